@@ -1,0 +1,336 @@
+"""Cross-checks of the oracle against brute force, closed forms and invariants.
+
+The oracle's minimisers (Hopcroft, Moore), its table filling, its pointer
+jumping and its equivalence/inclusion deciders are compared with each other
+and with exhaustive word enumeration (the plain definition of language
+equivalence, Section 2), on every DFA of the smallest shapes and on random
+ones.  A dropped term, a wrong index or a transposed operand in any of them
+breaks at least one of these agreements.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import words
+from paper_2508_20735_amd import workloads as W
+
+
+def all_dfas(n, k):
+    """Every complete DFA with n states and k letters: deltas [M, n, k] and
+    accepting masks [M, n], M = n^(nk) * 2^n."""
+    m = n ** (n * k)
+    idx = np.arange(m, dtype=np.int64)
+    digits = np.empty((m, n * k), dtype=np.uint32)
+    for j in range(n * k):
+        digits[:, j] = idx % n
+        idx //= n
+    deltas = digits.reshape(m, n, k)
+    masks = ((np.arange(2 ** n)[:, None] >> np.arange(n)[None, :]) & 1).astype(np.uint8)
+    D = np.repeat(deltas, 2 ** n, axis=0)
+    A = np.tile(masks, (m, 1))
+    return D, A
+
+
+def stable_partition_certificate(delta, acc, block):
+    """True iff `block` refines {F, Q\\F} and every state agrees with its
+    block's leader on the block of every successor (stability)."""
+    block = np.asarray(block, dtype=np.int64)
+    acc = np.asarray(acc) != 0
+    if (acc != acc[block]).any():
+        return False
+    return bool((block[delta] == block[delta[block]]).all())
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)])
+def test_exhaustive_small(n, k):
+    """All DFAs with n <= 4, k <= 2: Hopcroft = Moore = word enumeration."""
+    D, A = all_dfas(n, k)
+    ref = words.partition_by_words(D, A)
+    hop = oracle.minimise_many(D, A, "hopcroft")
+    np.testing.assert_array_equal(hop, ref)
+    moo = oracle.minimise_many(D, A, "moore")
+    np.testing.assert_array_equal(moo, ref)
+
+
+@pytest.mark.parametrize("n,k", [(2, 2), (3, 1), (3, 2)])
+def test_exhaustive_table_fill(n, k):
+    """All DFAs with n <= 3: the Apart fixpoint equals 'in different blocks'
+    of the word-enumeration partition."""
+    D, A = all_dfas(n, k)
+    ref = words.partition_by_words(D, A)
+    for i in range(len(D)):
+        apart, _ = oracle.table_fill(D[i], A[i])
+        np.testing.assert_array_equal(apart, ref[i][:, None] != ref[i][None, :])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_minimisers_agree(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 3000))
+    k = int(rng.integers(1, 6))
+    p = float(rng.uniform(0, 1))
+    d = W.random_dfa(n, k, p, seed)
+    hb, hnb = oracle.hopcroft(d.delta, d.accepting)
+    mb, mnb, rounds, changing = oracle.moore(d.delta, d.accepting)
+    np.testing.assert_array_equal(hb, mb)
+    assert hnb == mnb == len(np.unique(hb))
+    assert rounds == changing + 1
+    assert stable_partition_certificate(d.delta, d.accepting, hb)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_table_fill_random(seed):
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(1, 60))
+    k = int(rng.integers(1, 4))
+    d = W.random_dfa(n, k, float(rng.uniform(0.1, 0.9)), seed)
+    # add structure: make some states copies of others so blocks are non-trivial
+    if n > 4:
+        src = rng.integers(0, n, size=n // 3)
+        dst = rng.integers(0, n, size=n // 3)
+        d.delta[dst] = d.delta[src]
+        d.accepting[dst] = d.accepting[src]
+    hb, _ = oracle.hopcroft(d.delta, d.accepting)
+    apart, sweeps = oracle.table_fill(d.delta, d.accepting)
+    np.testing.assert_array_equal(apart, hb[:, None] != hb[None, :])
+    _, _, _, changing = oracle.moore(d.delta, d.accepting)
+    # both compute the same chain of relations; the table marks pairs in the
+    # same number of Jacobi-free sweeps or fewer (Gauss-Seidel order)
+    assert sweeps <= changing
+
+
+def test_degenerate_partitions():
+    """F empty or F = Q: a single block, no refining round, one confirming round."""
+    for acc_value in (0, 1):
+        d = W.random_dfa(50, 3, 0.5, 7)
+        d.accepting[:] = acc_value
+        block, nb, rounds, changing = oracle.moore(d.delta, d.accepting)
+        assert nb == 1 and rounds == 1 and changing == 0
+        assert (block == 0).all()
+        hb, hnb = oracle.hopcroft(d.delta, d.accepting)
+        assert hnb == 1 and (hb == 0).all()
+    one = np.zeros((1, 2), dtype=np.uint32)
+    for a in (0, 1):
+        block, nb, rounds, changing = oracle.moore(one, [a])
+        assert list(block) == [0] and nb == 1 and rounds == 1 and changing == 0
+
+
+def test_invalid_inputs_rejected():
+    d = W.random_dfa(8, 2, 0.5, 1)
+    bad = d.delta.copy()
+    bad[3, 1] = 8
+    with pytest.raises(oracle.OracleError):
+        oracle.hopcroft(bad, d.accepting)
+    with pytest.raises(oracle.OracleError):
+        oracle.moore(bad, d.accepting)
+    with pytest.raises(oracle.OracleError):
+        oracle.equiv_hk(d.delta, d.accepting, 0, d.delta[:, :1], d.accepting, 0)
+
+
+# ---------------------------------------------------------------- pointer jumping
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pointer_jump_is_iterated_letter(seed):
+    """Algorithm 5: column (i, a) maps q to delta applied 2^i times with a."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 200))
+    k = int(rng.integers(1, 4))
+    d = W.random_dfa(n, k, 0.5, seed)
+    ext = oracle.pointer_jump(d.delta)
+    L = oracle.floor_log2(n)
+    assert ext.shape == (n, k * (L + 1))
+    for a in range(k):
+        cur = np.arange(n)
+        steps = 0
+        for i in range(L + 1):
+            while steps < 2 ** i:
+                cur = d.delta[cur, a]
+                steps += 1
+            np.testing.assert_array_equal(ext[:, i * k + a], cur)
+
+
+def test_floor_log2():
+    assert [oracle.floor_log2(x) for x in (1, 2, 3, 4, 7, 8, 10, 1023, 1024, 2 ** 21)] == \
+        [0, 1, 1, 2, 2, 3, 3, 9, 10, 21]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_closure_preserves_equivalence(seed):
+    """Section 3.4: adding the letters a^(2^i) does not change which states are
+    equivalent, so refinement on the extended DFA gives the same partition."""
+    rng = np.random.default_rng(50 + seed)
+    n = int(rng.integers(2, 800))
+    k = int(rng.integers(1, 4))
+    d = W.random_dfa(n, k, float(rng.uniform(0.05, 0.95)), seed)
+    hb, _ = oracle.hopcroft(d.delta, d.accepting)
+    tb, _, _, _ = oracle.minimise_tc(d.delta, d.accepting)
+    np.testing.assert_array_equal(hb, tb)
+
+
+@pytest.mark.parametrize("i", range(4, 12))
+def test_closure_on_fibonacci(i):
+    d = W.fibonacci(i)
+    tb, nb, _, changing = oracle.minimise_tc(d.delta, d.accepting)
+    assert nb == d.n
+    # the closure shortens the n - 2 plain rounds (Table 2, transPR column)
+    assert changing < d.n - 2
+
+
+@pytest.mark.parametrize("M", [3, 4, 6, 8, 10])
+def test_chain_round_counts_closed_form(M):
+    """The chain a: i -> min(i+1, N-1) with only N-1 accepting (and an identity
+    letter b): states i < j are first told apart by a^(N-1-j), so plain
+    refinement needs N-2 refining rounds.  With the closure letters a word of
+    length l moves the chain by a sum of l powers of two, so the deepest pair
+    needs max popcount(m) over m in [0, N-2] = M-1 letters for N = 2^M."""
+    N = 2 ** M
+    d = W.chain_with_tail(N, 0, seed=0)
+    _, nb, _, changing = oracle.moore(d.delta, d.accepting)
+    assert nb == N and changing == N - 2
+    _, nb_tc, _, changing_tc = oracle.minimise_tc(d.delta, d.accepting)
+    assert nb_tc == N
+    assert changing_tc == max(bin(m).count("1") for m in range(N - 1)) == M - 1
+
+
+def test_chain_with_tail_small():
+    """The chain-plus-random-tail workload at reduced size: all states
+    distinct, plain rounds = N - 2 from the chain, and the closure agrees."""
+    N = 256
+    d = W.chain_with_tail(N, N, seed=3)
+    hb, hnb = oracle.hopcroft(d.delta, d.accepting)
+    mb, nb, _, changing = oracle.moore(d.delta, d.accepting)
+    np.testing.assert_array_equal(hb, mb)
+    assert changing >= N - 2
+    tb, _, _, changing_tc = oracle.minimise_tc(d.delta, d.accepting)
+    np.testing.assert_array_equal(hb, tb)
+    assert changing_tc < 20
+
+
+# ---------------------------------------------------------------- equivalence / inclusion
+
+def _tiny_pair(rng):
+    nA = int(rng.integers(1, 5))
+    nB = int(rng.integers(1, 5))
+    k = int(rng.integers(1, 3))
+    A = W.DFA(rng.integers(0, nA, (nA, k)).astype(np.uint32),
+              rng.integers(0, 2, nA).astype(np.uint8), int(rng.integers(0, nA)))
+    B = W.DFA(rng.integers(0, nB, (nB, k)).astype(np.uint32),
+              rng.integers(0, 2, nB).astype(np.uint8), int(rng.integers(0, nB)))
+    return A, B
+
+
+def _union_verdict(A, B):
+    d, acc = oracle.union(A.delta, A.accepting, B.delta, B.accepting)
+    hb, _ = oracle.hopcroft(d, acc)
+    return bool(hb[A.start] == hb[A.n + B.start])
+
+
+def test_equivalence_deciders_agree_tiny():
+    rng = np.random.default_rng(77)
+    seen = {True: 0, False: 0}
+    for _ in range(3000):
+        A, B = _tiny_pair(rng)
+        ref = words.equivalent_by_words(A.delta, A.accepting, A.start, B.delta, B.accepting,
+                                        B.start)
+        hk = oracle.equiv_hk(A.delta, A.accepting, A.start, B.delta, B.accepting, B.start)
+        bfs, _ = oracle.product_bfs(A.delta, A.accepting, A.start, B.delta, B.accepting,
+                                    B.start, "equivalence")
+        assert hk == bfs == _union_verdict(A, B) == ref
+        assert hk == oracle.equiv_hk(B.delta, B.accepting, B.start, A.delta, A.accepting,
+                                     A.start)
+        seen[ref] += 1
+    assert seen[True] > 100 and seen[False] > 100
+
+
+def test_inclusion_decider_tiny():
+    rng = np.random.default_rng(78)
+    seen = {True: 0, False: 0}
+    for _ in range(3000):
+        A, B = _tiny_pair(rng)
+        ref = words.included_by_words(A.delta, A.accepting, A.start, B.delta, B.accepting,
+                                      B.start)
+        inc = oracle.included(A.delta, A.accepting, A.start, B.delta, B.accepting, B.start)
+        assert inc == ref
+        back = oracle.included(B.delta, B.accepting, B.start, A.delta, A.accepting, A.start)
+        eq = oracle.equiv_hk(A.delta, A.accepting, A.start, B.delta, B.accepting, B.start)
+        assert (inc and back) == eq
+        assert oracle.included(A.delta, A.accepting, A.start, A.delta, A.accepting, A.start)
+        seen[ref] += 1
+    assert seen[True] > 100 and seen[False] > 100
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_equivalence_random_pairs(seed):
+    """Permuted copies are equivalent; one-transition mutations are decided
+    identically by all deciders."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(2, 3000))
+    k = int(rng.integers(1, 5))
+    d = W.random_dfa(n, k, float(rng.uniform(0.05, 0.6)), seed)
+    perm, _ = W.permuted_copy(d, seed + 1)
+    assert oracle.equiv_hk(d.delta, d.accepting, d.start, perm.delta, perm.accepting, perm.start)
+    assert _union_verdict(d, perm)
+    mut, _ = W.mutate_one(d, seed + 2)
+    v = oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting, mut.start)
+    bfs, _ = oracle.product_bfs(d.delta, d.accepting, d.start, mut.delta, mut.accepting,
+                                mut.start, "equivalence")
+    assert v == bfs == _union_verdict(d, mut)
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("seed", range(8))
+def test_quotient_invariants(seed):
+    """Idempotence (the quotient is minimal), language preservation (the
+    quotient is equivalent to the input), permutation equivariance of the
+    partition, and the stability certificate."""
+    rng = np.random.default_rng(400 + seed)
+    n = int(rng.integers(1, 2000))
+    k = int(rng.integers(1, 4))
+    d = W.random_dfa(n, k, float(rng.uniform(0.05, 0.95)), seed)
+    # duplicate some rows so that blocks are non-trivial
+    if n > 3:
+        src = rng.integers(0, n, size=n // 2)
+        dst = rng.integers(0, n, size=n // 2)
+        d.delta[dst] = d.delta[src]
+        d.accepting[dst] = d.accepting[src]
+    block, nb = oracle.hopcroft(d.delta, d.accepting)
+    assert stable_partition_certificate(d.delta, d.accepting, block)
+    B, qd, qa, qs = oracle.quotient(d.delta, d.accepting, block, d.start)
+    assert B == nb
+    qb, qnb = oracle.hopcroft(qd, qa)
+    assert qnb == B and (qb == np.arange(B)).all()
+    assert oracle.equiv_hk(d.delta, d.accepting, d.start, qd, qa, qs)
+    perm, pi = W.permuted_copy(d, seed)
+    pb, pnb = oracle.hopcroft(perm.delta, perm.accepting)
+    assert pnb == nb
+    # same relation: pi(p) ~ pi(q) iff p ~ q
+    np.testing.assert_array_equal(oracle.canonicalise(pb[pi]), block)
+
+
+def test_canonicalise():
+    ids = np.array([7, 3, 7, 9, 3, 9, 1], dtype=np.uint32)
+    np.testing.assert_array_equal(oracle.canonicalise(ids), [0, 1, 0, 3, 1, 3, 6])
+
+
+def test_quotient_example():
+    """Hand-checkable: states 0 and 2 equivalent, 1 and 3 equivalent."""
+    delta = np.array([[1], [2], [3], [0]], dtype=np.uint32)
+    acc = np.array([1, 0, 1, 0], dtype=np.uint8)
+    block, nb = oracle.hopcroft(delta, acc)
+    assert list(block) == [0, 1, 0, 1] and nb == 2
+    B, qd, qa, qs = oracle.quotient(delta, acc, block, 2)
+    assert B == 2 and qd.tolist() == [[1], [0]] and qa.tolist() == [1, 0] and qs == 0
+
+
+def test_moore_round_counts_random_small():
+    """Random uniform DFAs need few rounds (Section 3.3: polylogarithmic
+    distinguishing depth on average); the small workload is minimal."""
+    d = W.cfg_small()
+    block, nb, rounds, changing = oracle.moore(d.delta, d.accepting)
+    hb, _ = oracle.hopcroft(d.delta, d.accepting)
+    np.testing.assert_array_equal(block, hb)
+    assert changing <= 8
+    assert list(itertools.islice(iter(block), 3)) == list(hb[:3])
