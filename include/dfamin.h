@@ -1,0 +1,205 @@
+/*
+ * dfamin.h -- C ABI of libdfamin, parallel partition refinement for DFA
+ * minimisation, equivalence and inclusion checking on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Heemstra, Martens, Wijs, "Evaluating Massively Parallel Algorithms
+ * for DFA Minimisation, Equivalence Checking and Inclusion Checking".
+ *
+ *   - A DFA is the 5-tuple (Q, Sigma, delta, F, q0) of Section 2 (Definition
+ *     "Deterministic Finite Automaton"); states and letters are dense indices
+ *     (Section 2, "Representation").
+ *   - Minimisation computes the coarsest partition of Q that refines
+ *     {F, Q\F} and is stable under every letter (Section 2; Section 3.3,
+ *     Algorithm 4 computes it by signature rounds).  No unreachable states
+ *     are removed: every one of the n states is partitioned (Section 2 treats
+ *     reachability pruning as a separate pre-processing step).
+ *   - Equivalence decides L(A) = L(B) (Section 4, Algorithm 6; here decided by
+ *     refining the disjoint union, which Section 4 names as the alternative).
+ *   - Inclusion decides L(A) <= L(B) (Section 4: the Hopcroft-Karp loop with
+ *     the acceptance test changed to "q_A in F_A and q_B not in F_B", over the
+ *     plain set of reached pairs).
+ *
+ * Conventions shared by every call:
+ *   - delta is row-major: delta[q*k + a] = delta(q, a), uint32, every target
+ *     < n.  (The paper stores |Sigma| arrays delta[a][q]; the library
+ *     re-lays the table out itself.)
+ *   - accepting[q] != 0 iff q is in F.
+ *   - Block ids are canonical: block_out[q] = the smallest state index in q's
+ *     block, so results do not depend on thread scheduling.
+ *   - Indices are uint32 (n < 2^32 - 1); sizes of n*k are 64-bit internally.
+ *   - Every call returns DFA_OK (0) or a negative status; nothing is thrown
+ *     across the ABI.  dfa_last_error() describes the last failure on the
+ *     calling thread.
+ *   - Calls block until their results are ready.  Calls on one device are
+ *     serialised inside the library (it keeps one grow-only device workspace
+ *     per device).
+ *   - The caller owns every buffer it passes; the library keeps no pointer
+ *     after a call returns.
+ *   - Host-pointer calls (dfa_minimise, dfa_equivalent, dfa_included) copy the
+ *     inputs to the device and the results back.  The *_device variants take
+ *     device pointers (memory of the current HIP device) and a hipStream_t
+ *     (passed as void*, NULL = the library's own stream); their inputs must
+ *     stay unchanged until the call returns.
+ */
+#ifndef DFAMIN_H
+#define DFAMIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define DFA_OK 0
+#define DFA_EINVAL (-1)  /* bad argument: n == 0, k == 0, target >= n, start >= n,
+                            k mismatch, NULL required pointer */
+#define DFA_ENOMEM (-2)  /* device allocation failed / request exceeds the budget */
+#define DFA_EDEVICE (-3) /* a HIP runtime error */
+#define DFA_ELIMIT (-5)  /* options.max_rounds reached before the partition was stable */
+
+/* ---- partial transitive closure (Section 3.4, Algorithm 5) ---- */
+#define DFA_TC_OFF 0  /* refine on the input letters only */
+#define DFA_TC_ON 1   /* add the letters a^(2^i), i = 1..floor(log2 n), first */
+#define DFA_TC_AUTO 2 /* start plain; switch to the closure when splitting stalls */
+
+/* ---- round-loop driver ---- */
+#define DFA_LOOP_HOST 0  /* the host reads the block count after every round */
+#define DFA_LOOP_CHUNK 1 /* rounds are enqueued in chunks; kernels turn into no-ops
+                            on the device once the partition is stable; the host
+                            checks once per chunk */
+#define DFA_LOOP_GRAPH 2 /* like CHUNK, each chunk replayed from a captured hipGraph */
+
+typedef struct dfa_options {
+    int32_t tc_mode;      /* DFA_TC_*, default DFA_TC_AUTO */
+    int32_t loop_mode;    /* DFA_LOOP_*, default DFA_LOOP_GRAPH */
+    uint32_t start;       /* start state used for the quotient's start (default 0) */
+    uint32_t max_rounds;  /* 0 = until stable */
+    uint32_t chunk;       /* rounds per chunk in CHUNK/GRAPH mode (0 = library default) */
+    int32_t lds_stage;    /* 1 = pre-group keys in LDS before the global table (default),
+                             0 = insert every key into the global table */
+    int32_t reserved[4];
+} dfa_options;
+
+typedef struct dfa_stats {
+    uint32_t rounds;          /* signature rounds executed; the last one confirms stability */
+    uint32_t changing_rounds; /* rounds that split at least one block */
+    uint32_t num_blocks;      /* blocks of the final partition */
+    uint32_t k_eff;           /* letters per signature in the last round (k, or closure letters) */
+    uint32_t tc_used;         /* 1 if the closure letters were built */
+    uint32_t tc_levels;       /* floor(log2 n) when tc_used */
+    uint32_t plain_rounds;    /* rounds run on the input letters before switching to the closure */
+    uint32_t reserved0;
+    double h2d_ms;            /* host-pointer calls: copy of the inputs */
+    double device_ms;         /* device work of the call (HIP events) */
+    double d2h_ms;            /* host-pointer calls: copy of the results */
+    uint64_t transitions_refined; /* sum over rounds of n * k_eff (nominal) */
+    uint64_t algorithmic_bytes;   /* sum over rounds of n * (8*k_eff + 8) */
+} dfa_stats;
+
+/* Quotient DFA: caller-provided arrays of capacity n*k (delta) and n
+ * (accepting); the library fills the first num_blocks rows.  Blocks are
+ * numbered densely in increasing order of their smallest member;
+ * start = the block of options.start. */
+typedef struct dfa_quotient {
+    uint32_t *delta;
+    uint8_t *accepting;
+    uint32_t num_blocks; /* out */
+    uint32_t start;      /* out */
+} dfa_quotient;
+
+/* One DFA operand of a two-DFA call. */
+typedef struct dfa_view {
+    uint32_t n, k, start;
+    const uint32_t *delta;    /* n*k, row-major */
+    const uint8_t *accepting; /* n */
+} dfa_view;
+
+/* Fill *opt with the defaults (TC AUTO, graph loop, LDS staging, start 0). */
+void dfa_options_default(dfa_options *opt);
+
+/*
+ * Kernel tuning of the current device (launch shapes and kernel variants; no
+ * effect on results).  Set by the autotuner or by hand; read by every later
+ * call on that device.  dfa_set_tuning returns DFA_EINVAL for out-of-range
+ * values.
+ */
+typedef struct dfa_tuning {
+    uint32_t round_grid_cap; /* workgroups of the signature/grouping kernels (grid-stride
+                                beyond); 0 = one workgroup per 256 states */
+    uint32_t label_grid_cap; /* workgroups of the label rounds; 0 = one per 256 states */
+    uint32_t label_rounds;   /* 0: every round uses the table; 1: round 0 groups by the bit
+                                pattern of acceptance of q and its successors when
+                                k_eff + 1 <= 16; 2: round 1 then groups by the packed
+                                round-0 labels when (k_eff + 1)^2 <= 25 */
+    uint32_t cached_probe;   /* 1: probe the grouping table with cached loads first */
+    uint32_t chunk;          /* rounds per chunk when options.chunk is 0 (1..4096) */
+    uint32_t reserved[11];
+} dfa_tuning;
+
+void dfa_tuning_default(dfa_tuning *t);
+int dfa_get_tuning(dfa_tuning *t);
+int dfa_set_tuning(const dfa_tuning *t);
+
+/*
+ * Minimise one DFA (Section 2 problem statement; Section 3.3, Algorithm 4
+ * signature rounds; Section 3.4, Algorithm 5 closure).
+ *   n, k        states and letters (both >= 1)
+ *   delta       host, n*k uint32, row-major, every entry < n
+ *   accepting   host, n bytes
+ *   block_out   host, n uint32: canonical block id per state
+ *   q_out       optional quotient (host arrays), NULL to skip
+ *   opt, stats  optional (NULL = defaults / not reported)
+ * Errors: DFA_EINVAL (bad sizes, target >= n, start >= n, NULL required
+ * pointer), DFA_ENOMEM, DFA_EDEVICE, DFA_ELIMIT (block_out then holds the
+ * partition reached so far).
+ */
+int dfa_minimise(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *accepting,
+                 uint32_t *block_out, dfa_quotient *q_out, const dfa_options *opt,
+                 dfa_stats *stats);
+
+/* As dfa_minimise with device pointers (delta, accepting, block_out and the
+ * quotient arrays) on `stream`. */
+int dfa_minimise_device(uint32_t n, uint32_t k, const uint32_t *delta,
+                        const uint8_t *accepting, uint32_t *block_out, dfa_quotient *q_out,
+                        const dfa_options *opt, dfa_stats *stats, void *stream);
+
+/*
+ * Equivalence L(a) = L(b) (Section 4, Algorithm 6's result; decided by
+ * minimising the disjoint union and comparing the blocks of the two start
+ * states, with an early exit as soon as they separate).
+ *   a, b     host views; a->k must equal b->k
+ *   verdict  out: 1 if equivalent, 0 otherwise
+ */
+int dfa_equivalent(const dfa_view *a, const dfa_view *b, int *verdict,
+                   const dfa_options *opt, dfa_stats *stats);
+int dfa_equivalent_device(const dfa_view *a, const dfa_view *b, int *verdict,
+                          const dfa_options *opt, dfa_stats *stats, void *stream);
+
+/*
+ * Inclusion L(a) <= L(b) (Section 4: breadth-first exploration of the pairs
+ * reachable from (start_a, start_b) in the synchronous product, stopping at a
+ * pair (p, q) with p accepting in a and q not accepting in b).
+ *   verdict          out: 1 if included, 0 otherwise
+ *   pairs_visited    optional out: distinct pairs reached (the whole
+ *                    reachable product when the verdict is 1)
+ */
+int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *pairs_visited,
+                 const dfa_options *opt, dfa_stats *stats);
+int dfa_included_device(const dfa_view *a, const dfa_view *b, int *verdict,
+                        uint64_t *pairs_visited, const dfa_options *opt, dfa_stats *stats,
+                        void *stream);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *dfa_last_error(void);
+
+/* Name, compute-unit count and memory of the current HIP device. */
+int dfa_device_info(char *name, size_t name_cap, int *compute_units, size_t *hbm_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFAMIN_H */

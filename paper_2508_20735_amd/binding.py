@@ -1,0 +1,339 @@
+"""ctypes binding of libdfamin (include/dfamin.h).
+
+Argument marshalling only: every step of minimisation, equivalence and
+inclusion runs in the library's HIP kernels.  Importing this module does not
+load the library; the first call does, and it raises DfaError if the library
+is missing (it never falls back to another implementation).
+
+Host variants take numpy arrays; ``*_device`` variants take torch tensors on
+the GPU (torch provides device memory and the stream only).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+DFA_OK = 0
+DFA_EINVAL = -1
+DFA_ENOMEM = -2
+DFA_EDEVICE = -3
+DFA_ELIMIT = -5
+
+TC = {"off": 0, "on": 1, "auto": 2}
+LOOP = {"host": 0, "chunk": 1, "graph": 2}
+
+
+class DfaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libdfamin status {status}: {message}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tc_mode", ctypes.c_int32), ("loop_mode", ctypes.c_int32),
+                ("start", ctypes.c_uint32), ("max_rounds", ctypes.c_uint32),
+                ("chunk", ctypes.c_uint32), ("lds_stage", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint32), ("changing_rounds", ctypes.c_uint32),
+                ("num_blocks", ctypes.c_uint32), ("k_eff", ctypes.c_uint32),
+                ("tc_used", ctypes.c_uint32), ("tc_levels", ctypes.c_uint32),
+                ("plain_rounds", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("h2d_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("d2h_ms", ctypes.c_double), ("transitions_refined", ctypes.c_uint64),
+                ("algorithmic_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved0"}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("round_grid_cap", ctypes.c_uint32), ("label_grid_cap", ctypes.c_uint32),
+                ("label_rounds", ctypes.c_uint32), ("cached_probe", ctypes.c_uint32),
+                ("chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 11)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class Quotient(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_void_p), ("accepting", ctypes.c_void_p),
+                ("num_blocks", ctypes.c_uint32), ("start", ctypes.c_uint32)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("k", ctypes.c_uint32), ("start", ctypes.c_uint32),
+                ("delta", ctypes.c_void_p), ("accepting", ctypes.c_void_p)]
+
+
+EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
+                  "dfa_equivalent", "dfa_equivalent_device", "dfa_included",
+                  "dfa_included_device", "dfa_last_error", "dfa_device_info",
+                  "dfa_tuning_default", "dfa_get_tuning", "dfa_set_tuning"])
+
+_lock = threading.Lock()
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load(build_if_missing: bool = True):
+    """Load libdfamin.so (building it first only if it does not exist)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_build.LIB):
+            if not build_if_missing:
+                raise DfaError(DFA_EDEVICE, f"{_build.LIB} is not built")
+            _build.build()
+        # torch ships its own HIP runtime with the same soname as ROCm's; load
+        # it first so that libdfamin binds to it and the process keeps one
+        # HIP runtime (two runtimes in one process do not share the device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        lib = ctypes.CDLL(_build.LIB)
+        vp, u32, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
+        P = ctypes.POINTER
+        lib.dfa_options_default.argtypes = [P(Options)]
+        lib.dfa_options_default.restype = None
+        lib.dfa_minimise.argtypes = [u32, u32, vp, vp, vp, P(Quotient), P(Options), P(Stats)]
+        lib.dfa_minimise_device.argtypes = [u32, u32, vp, vp, vp, P(Quotient), P(Options),
+                                            P(Stats), vp]
+        lib.dfa_equivalent.argtypes = [P(View), P(View), P(i32), P(Options), P(Stats)]
+        lib.dfa_equivalent_device.argtypes = [P(View), P(View), P(i32), P(Options), P(Stats), vp]
+        lib.dfa_included.argtypes = [P(View), P(View), P(i32), P(ctypes.c_uint64), P(Options),
+                                     P(Stats)]
+        lib.dfa_included_device.argtypes = [P(View), P(View), P(i32), P(ctypes.c_uint64),
+                                            P(Options), P(Stats), vp]
+        lib.dfa_last_error.argtypes = []
+        lib.dfa_last_error.restype = ctypes.c_char_p
+        lib.dfa_device_info.argtypes = [ctypes.c_char_p, ctypes.c_size_t, P(i32),
+                                        P(ctypes.c_size_t)]
+        lib.dfa_tuning_default.argtypes = [P(Tuning)]
+        lib.dfa_tuning_default.restype = None
+        lib.dfa_get_tuning.argtypes = [P(Tuning)]
+        lib.dfa_set_tuning.argtypes = [P(Tuning)]
+        for fn in ("dfa_minimise", "dfa_minimise_device", "dfa_equivalent",
+                   "dfa_equivalent_device", "dfa_included", "dfa_included_device",
+                   "dfa_device_info", "dfa_get_tuning", "dfa_set_tuning"):
+            getattr(lib, fn).restype = i32
+        _lib = lib
+        return lib
+
+
+def _check(rc: int, allow=()) -> int:
+    if rc != DFA_OK and rc not in allow:
+        msg = load().dfa_last_error().decode(errors="replace")
+        raise DfaError(rc, msg)
+    return rc
+
+
+def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: int = 0,
+            chunk: int = 0, lds_stage: bool = True) -> Options:
+    o = Options()
+    load().dfa_options_default(ctypes.byref(o))
+    o.tc_mode = TC[tc]
+    o.loop_mode = LOOP[loop]
+    o.start = start
+    o.max_rounds = max_rounds
+    o.chunk = chunk
+    o.lds_stage = 1 if lds_stage else 0
+    return o
+
+
+def default_tuning() -> dict:
+    t = Tuning()
+    load().dfa_tuning_default(ctypes.byref(t))
+    return t.as_dict()
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(load().dfa_get_tuning(ctypes.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(**values) -> dict:
+    """Update fields of the current device's tuning; returns the new tuning."""
+    t = Tuning()
+    _check(load().dfa_get_tuning(ctypes.byref(t)))
+    for key, value in values.items():
+        if key not in t.as_dict():
+            raise KeyError(key)
+        setattr(t, key, int(value))
+    _check(load().dfa_set_tuning(ctypes.byref(t)))
+    return t.as_dict()
+
+
+def device_info() -> dict:
+    name = ctypes.create_string_buffer(256)
+    cu = ctypes.c_int()
+    mem = ctypes.c_size_t()
+    _check(load().dfa_device_info(name, 256, ctypes.byref(cu), ctypes.byref(mem)))
+    return {"name": name.value.decode(), "compute_units": cu.value, "hbm_bytes": mem.value}
+
+
+def _host_arrays(delta, accepting):
+    d = np.ascontiguousarray(delta, dtype=np.uint32)
+    if d.ndim != 2:
+        raise ValueError("delta must be [n, k]")
+    a = np.ascontiguousarray(np.asarray(accepting) != 0, dtype=np.uint8)
+    if a.shape != (d.shape[0],):
+        raise ValueError("accepting must have n entries")
+    return d, a
+
+
+@dataclass
+class MinimiseResult:
+    block: object          # numpy array (host call) or torch tensor (device call)
+    stats: dict
+    quotient: tuple | None = None  # (num_blocks, qdelta [B,k], qacc [B], qstart)
+
+
+def minimise(delta, accepting, *, tc: str = "auto", loop: str = "graph", start: int = 0,
+             max_rounds: int = 0, chunk: int = 0, lds_stage: bool = True,
+             quotient: bool = False) -> MinimiseResult:
+    """dfa_minimise on host arrays."""
+    d, a = _host_arrays(delta, accepting)
+    n, k = d.shape
+    block = np.empty(n, dtype=np.uint32)
+    o = options(tc, loop, start, max_rounds, chunk, lds_stage)
+    st = Stats()
+    q = None
+    if quotient:
+        qd = np.empty((n, k), dtype=np.uint32)
+        qa = np.empty(n, dtype=np.uint8)
+        q = Quotient(qd.ctypes.data, qa.ctypes.data, 0, 0)
+    rc = load().dfa_minimise(n, k, d.ctypes.data, a.ctypes.data, block.ctypes.data,
+                             ctypes.byref(q) if q is not None else None, ctypes.byref(o),
+                             ctypes.byref(st))
+    _check(rc)
+    res = MinimiseResult(block, st.as_dict())
+    if q is not None:
+        B = q.num_blocks
+        res.quotient = (B, qd[:B].copy(), qa[:B].copy(), q.start)
+    return res
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _check_device_tensor(t, dtype_name: str, numel: int, what: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a torch tensor on the GPU")
+    if str(t.dtype) != dtype_name or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{what} must be a contiguous {dtype_name} tensor of {numel} elements")
+
+
+def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop: str = "graph",
+                    start: int = 0, max_rounds: int = 0, chunk: int = 0, lds_stage: bool = True,
+                    quotient: bool = False, stream=None) -> MinimiseResult:
+    """dfa_minimise_device on torch GPU tensors: delta int32/uint32 [n, k]
+    (row-major), accepting uint8 [n]; block_out int32 [n] (allocated if None)."""
+    import torch
+    n, k = delta.shape
+    if delta.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("delta must be int32 or uint32")
+    _check_device_tensor(delta, str(delta.dtype), n * k, "delta")
+    _check_device_tensor(accepting, "torch.uint8", n, "accepting")
+    if block_out is None:
+        block_out = torch.empty(n, dtype=torch.int32, device=delta.device)
+    _check_device_tensor(block_out, str(block_out.dtype), n, "block_out")
+    o = options(tc, loop, start, max_rounds, chunk, lds_stage)
+    st = Stats()
+    q = None
+    if quotient:
+        qd = torch.empty((n, k), dtype=torch.int32, device=delta.device)
+        qa = torch.empty(n, dtype=torch.uint8, device=delta.device)
+        q = Quotient(qd.data_ptr(), qa.data_ptr(), 0, 0)
+    rc = load().dfa_minimise_device(n, k, delta.data_ptr(), accepting.data_ptr(),
+                                    block_out.data_ptr(),
+                                    ctypes.byref(q) if q is not None else None, ctypes.byref(o),
+                                    ctypes.byref(st), _stream_ptr(stream))
+    _check(rc)
+    res = MinimiseResult(block_out, st.as_dict())
+    if q is not None:
+        B = q.num_blocks
+        res.quotient = (B, qd[:B], qa[:B], q.start)
+    return res
+
+
+def _view_host(dfa) -> tuple[View, tuple]:
+    d, a = _host_arrays(dfa.delta, dfa.accepting)
+    v = View(d.shape[0], d.shape[1], int(dfa.start), d.ctypes.data, a.ctypes.data)
+    return v, (d, a)
+
+
+def _view_device(delta, accepting, start) -> View:
+    n, k = delta.shape
+    _check_device_tensor(delta, str(delta.dtype), n * k, "delta")
+    _check_device_tensor(accepting, "torch.uint8", n, "accepting")
+    return View(n, k, int(start), delta.data_ptr(), accepting.data_ptr())
+
+
+def equivalent(A, B, *, tc: str = "auto", loop: str = "graph", max_rounds: int = 0,
+               chunk: int = 0, lds_stage: bool = True) -> tuple[bool, dict]:
+    """dfa_equivalent on two host DFAs (objects with delta, accepting, start)."""
+    va, keep_a = _view_host(A)
+    vb, keep_b = _view_host(B)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage)
+    v = ctypes.c_int()
+    st = Stats()
+    _check(load().dfa_equivalent(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
+                                 ctypes.byref(o), ctypes.byref(st)))
+    return bool(v.value), st.as_dict()
+
+
+def equivalent_device(dA, accA, sA, dB, accB, sB, *, tc: str = "auto", loop: str = "graph",
+                      max_rounds: int = 0, chunk: int = 0, lds_stage: bool = True,
+                      stream=None) -> tuple[bool, dict]:
+    va = _view_device(dA, accA, sA)
+    vb = _view_device(dB, accB, sB)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage)
+    v = ctypes.c_int()
+    st = Stats()
+    _check(load().dfa_equivalent_device(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
+                                        ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream)))
+    return bool(v.value), st.as_dict()
+
+
+def included(A, B) -> tuple[bool, int, dict]:
+    """dfa_included on two host DFAs: (verdict, pairs visited, stats)."""
+    va, keep_a = _view_host(A)
+    vb, keep_b = _view_host(B)
+    v = ctypes.c_int()
+    cnt = ctypes.c_uint64()
+    st = Stats()
+    _check(load().dfa_included(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
+                               ctypes.byref(cnt), None, ctypes.byref(st)))
+    return bool(v.value), int(cnt.value), st.as_dict()
+
+
+def included_device(dA, accA, sA, dB, accB, sB, stream=None) -> tuple[bool, int, dict]:
+    va = _view_device(dA, accA, sA)
+    vb = _view_device(dB, accB, sB)
+    v = ctypes.c_int()
+    cnt = ctypes.c_uint64()
+    st = Stats()
+    _check(load().dfa_included_device(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
+                                      ctypes.byref(cnt), None, ctypes.byref(st),
+                                      _stream_ptr(stream)))
+    return bool(v.value), int(cnt.value), st.as_dict()

@@ -1,0 +1,871 @@
+// C ABI of libdfamin: argument checks, device workspace, the round-loop
+// drivers and the host/device copies.  All compute runs in the kernels of
+// refine_kernels.hip and product_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dfamin.h"
+#include "dfamin_internal.h"
+
+namespace dfamin {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(DFA_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define DFA_TRY(expr)              \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != DFA_OK) return rc_; \
+    } while (0)
+
+// Grow-only device allocation.
+struct Buffer {
+    void *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes, const char *what) {
+        if (p && bytes <= cap) return DFA_OK;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 256);
+        want = (want + (2u << 20) - 1) & ~static_cast<size_t>((2u << 20) - 1);
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(DFA_ENOMEM, "device allocation of %zu bytes for %s failed: %s", want, what,
+                        hipGetErrorString(e));
+        }
+        cap = want;
+        return DFA_OK;
+    }
+    template <class T>
+    T *as() const {
+        return static_cast<T *>(p);
+    }
+};
+
+constexpr size_t kPinnedWords = 1u << 16;
+
+// A captured chunk is reused while the round arguments and the chunk length
+// are unchanged (RoundArgs values are built from zeroed storage, so they can
+// be compared bytewise).
+struct GraphKey {
+    RoundArgs args;
+    uint32_t chunk;
+    bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof *this) == 0; }
+};
+
+struct Ctx {
+    std::mutex mu;
+    bool inited = false;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_in = nullptr;
+    uint32_t *pinned = nullptr;  // host staging for small transfers
+    Buffer cols, tc_cols, colmap, blockA, blockB, sig, hash, table, ctl, flags, canon, dense,
+        leader_of, partials, scalars, multi, active, accbits, counters, presence, presence_packed,
+        lab8;
+    dfa_tuning tune{};
+    Buffer stage_delta, stage_acc, stage_block, stage_qdelta, stage_qacc, stage_delta_b,
+        stage_acc_b;
+    Buffer visited, visited2, front0, front1;
+    hipGraphExec_t graph = nullptr;
+    GraphKey graph_key{};
+};
+
+constexpr int kMaxDevices = 64;
+Ctx g_ctx[kMaxDevices];
+
+int get_ctx(Ctx *&out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DFA_EDEVICE, "device index %d out of range", dev);
+    out = &g_ctx[dev];
+    return DFA_OK;
+}
+
+int init_ctx(Ctx &c) {
+    if (c.inited) return DFA_OK;
+    HIP_TRY(hipGetDevice(&c.device));
+    // default priority; callers' streams are joined explicitly (join_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreate(&c.ev_start));
+    HIP_TRY(hipEventCreate(&c.ev_stop));
+    HIP_TRY(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c.pinned), kPinnedWords * sizeof(uint32_t),
+                          hipHostMallocDefault));
+    dfa_tuning_default(&c.tune);
+    c.inited = true;
+    return DFA_OK;
+}
+
+dfa_options resolve(const dfa_options *o) {
+    dfa_options r;
+    dfa_options_default(&r);
+    if (o) r = *o;
+    return r;
+}
+
+uint32_t floor_log2(uint64_t x) {
+    uint32_t l = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++l;
+    }
+    return l;
+}
+
+uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Copy `words` uint32 from device to the pinned buffer and wait.
+int read_back(Ctx &c, const void *dev, size_t bytes) {
+    if (bytes > kPinnedWords * sizeof(uint32_t)) return fail(DFA_EINVAL, "readback too large");
+    HIP_TRY(hipMemcpyAsync(c.pinned, dev, bytes, hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    return DFA_OK;
+}
+
+int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
+    if (bytes > kPinnedWords * sizeof(uint32_t)) return fail(DFA_EINVAL, "upload too large");
+    // the pinned buffer may still be read by an earlier async copy
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    std::memcpy(c.pinned, host, bytes);
+    HIP_TRY(hipMemcpyAsync(dev, c.pinned, bytes, hipMemcpyHostToDevice, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    return DFA_OK;
+}
+
+// flags layout (uint32 words): [0] target >= n, [1] some state accepts,
+// [2] some state rejects, [3 .. 3+ncols) column is not the identity,
+// [3+ncols .. 3+2*ncols) column differs from the previous closure level.
+constexpr size_t kFlagErr = 0, kFlagClass = 1, kFlagNonid = 3;
+
+struct RefineResult {
+    RoundCtl ctl{};
+    uint32_t label_rounds = 0;  // rounds 0..label_rounds-1 produced labels, not state ids
+    uint32_t k_eff = 0;
+    uint32_t tc_used = 0, tc_levels = 0, plain_rounds = 0;
+    const uint32_t *final_block = nullptr;
+    uint64_t transitions = 0, bytes = 0;
+};
+
+// Builds the closure columns (all levels) from level 0 in c.cols, and the
+// signature column list.  Returns DFA_ENOMEM if the table does not fit.
+int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, uint32_t &levels) {
+    const uint32_t L = floor_log2(N);
+    const size_t ncols = static_cast<size_t>(L + 1) * k;
+    DFA_TRY(c.tc_cols.ensure(ncols * N * sizeof(uint32_t), "closure columns"));
+    DFA_TRY(c.flags.ensure((kFlagNonid + 2 * ncols) * sizeof(uint32_t), "flags"));
+    uint32_t *flags = c.flags.as<uint32_t>();
+    uint32_t *nonid = flags + kFlagNonid;
+    uint32_t *diff = nonid + ncols;
+    HIP_TRY(hipMemcpyAsync(c.tc_cols.p, c.cols.p, static_cast<size_t>(k) * N * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, c.stream));
+    HIP_TRY(hipMemsetAsync(nonid + k, 0, (ncols - k) * sizeof(uint32_t), c.stream));
+    HIP_TRY(hipMemsetAsync(diff, 0, ncols * sizeof(uint32_t), c.stream));
+    for (uint32_t i = 1; i <= L; ++i)
+        launch_jump(c.tc_cols.as<uint32_t>(), N, k, i, diff, nonid, c.stream);
+    HIP_TRY(hipGetLastError());
+    DFA_TRY(read_back(c, nonid, 2 * ncols * sizeof(uint32_t)));
+    const uint32_t *h_nonid = c.pinned, *h_diff = c.pinned + ncols;
+    colmap.clear();
+    for (uint32_t i = 0; i <= L; ++i)
+        for (uint32_t a = 0; a < k; ++a) {
+            const size_t col = static_cast<size_t>(i) * k + a;
+            // an identity letter repeats the leading block id; a level equal
+            // to the previous one (and all above it) repeats that letter
+            if (h_nonid[col] && (i == 0 || h_diff[col])) colmap.push_back(static_cast<uint32_t>(col));
+        }
+    levels = L;
+    return DFA_OK;
+}
+
+int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
+    DFA_TRY(c.colmap.ensure(std::max<size_t>(colmap.size(), 1) * sizeof(uint32_t), "colmap"));
+    if (!colmap.empty())
+        DFA_TRY(upload(c, c.colmap.p, colmap.data(), colmap.size() * sizeof(uint32_t)));
+    return DFA_OK;
+}
+
+int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode) {
+    if (mode == DFA_LOOP_GRAPH) {
+        GraphKey key;
+        std::memset(&key, 0, sizeof key);
+        std::memcpy(&key.args, &ra, sizeof ra);
+        key.chunk = rounds;
+        if (!c.graph || !(c.graph_key == key)) {
+            if (c.graph) {
+                (void)hipGraphExecDestroy(c.graph);
+                c.graph = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+            for (uint32_t i = 0; i < rounds; ++i) launch_round(ra, c.stream);
+            HIP_TRY(hipStreamEndCapture(c.stream, &g));
+            hipError_t e = hipGraphInstantiate(&c.graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c.graph = nullptr;
+                return fail(DFA_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            c.graph_key = key;
+        }
+        HIP_TRY(hipGraphLaunch(c.graph, c.stream));
+    } else {
+        for (uint32_t i = 0; i < rounds; ++i) launch_round(ra, c.stream);
+        HIP_TRY(hipGetLastError());
+    }
+    return DFA_OK;
+}
+
+// Signature rounds over N states whose level-0 columns are in c.cols and
+// whose initial labels are in c.blockA (flags already written by the ingest
+// and init kernels).
+RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff, uint64_t cap,
+                          int lds_stage, bool packed) {
+    RoundArgs ra;
+    std::memset(&ra, 0, sizeof ra);
+    ra.cols = cols;
+    ra.colmap = c.colmap.as<uint32_t>();
+    ra.N = N;
+    ra.k_eff = k_eff;
+    ra.blockA = c.blockA.as<uint32_t>();
+    ra.blockB = c.blockB.as<uint32_t>();
+    ra.sig = c.sig.as<uint32_t>();
+    ra.hash = c.hash.as<uint64_t>();
+    ra.table = c.table.as<unsigned long long>();
+    ra.table_cap = cap;
+    ra.multi = c.multi.as<uint32_t>();
+    ra.active = c.active.as<unsigned long long>();
+    ra.accbits = c.accbits.as<unsigned long long>();
+    ra.counters = c.counters.as<uint32_t>();
+    ra.presence = c.presence.as<uint32_t>();
+    ra.presence_packed = packed ? c.presence_packed.as<uint32_t>() : nullptr;
+    ra.lab8 = packed ? c.lab8.as<uint8_t>() : nullptr;
+    ra.ctl = c.ctl.as<RoundCtl>();
+    ra.lds_stage = lds_stage;
+    ra.round_grid_cap = c.tune.round_grid_cap;
+    ra.pattern_grid_cap = c.tune.label_grid_cap;
+    ra.cached_probe = c.tune.cached_probe;
+    return ra;
+}
+
+// Signature rounds over N states whose level-0 columns are in c.cols and
+// whose initial labels are in c.blockA (flags already written by the ingest
+// and init kernels).  With state_ids, a partition that ends in label ids
+// (a stable partition found by a label round) gets one more table round,
+// which keeps the partition and turns the labels into state ids.
+int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq, uint32_t eq_a,
+           uint32_t eq_b, bool state_ids, RefineResult &res) {
+    // target check, classes, identity letters (one readback)
+    DFA_TRY(read_back(c, c.flags.p, (kFlagNonid + k) * sizeof(uint32_t)));
+    if (c.pinned[kFlagErr]) return fail(DFA_EINVAL, "a transition target is >= n");
+    std::vector<uint32_t> colmap;
+    for (uint32_t a = 0; a < k; ++a)
+        if (c.pinned[kFlagNonid + a]) colmap.push_back(a);
+
+    const uint64_t cap = next_pow2(std::max<uint64_t>(2 * N, 1024));
+    DFA_TRY(c.table.ensure(cap * sizeof(unsigned long long), "hash table"));
+    HIP_TRY(hipMemsetAsync(c.table.p, 0, cap * sizeof(unsigned long long), c.stream));
+    DFA_TRY(c.ctl.ensure(sizeof(RoundCtl), "round state"));
+    RoundCtl *ctl = c.ctl.as<RoundCtl>();
+
+    const uint32_t *cols = c.cols.as<uint32_t>();
+    res.tc_used = 0;
+    res.tc_levels = 0;
+    if (o.tc_mode == DFA_TC_ON) {
+        DFA_TRY(build_closure(c, N, k, colmap, res.tc_levels));
+        cols = c.tc_cols.as<uint32_t>();
+        res.tc_used = 1;
+    }
+    DFA_TRY(set_colmap(c, colmap));
+    uint32_t k_eff = static_cast<uint32_t>(colmap.size());
+    DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
+    DFA_TRY(c.hash.ensure(N * sizeof(uint64_t), "hashes"));
+    // label rounds need at least three rounds of budget (ids become state
+    // ids in the round after them)
+    const bool budget = o.max_rounds == 0 || o.max_rounds > 2;
+    const uint32_t pattern_first =
+        (c.tune.label_rounds >= 1 && budget && k_eff + 1 <= kPatternMaxBits) ? 1u : 0u;
+    const uint32_t packed_second =
+        (pattern_first && c.tune.label_rounds >= 2 && (k_eff + 1) * (k_eff + 1) <= kPackedMaxBits)
+            ? 1u
+            : 0u;
+    if (packed_second) {
+        DFA_TRY(c.lab8.ensure(N, "byte labels"));
+        DFA_TRY(c.presence_packed.ensure((size_t(1) << kPackedMaxBits) / 8, "label bitmap"));
+        HIP_TRY(hipMemsetAsync(c.presence_packed.p, 0, (size_t(1) << kPackedMaxBits) / 8,
+                               c.stream));
+    }
+    res.label_rounds = pattern_first + packed_second;
+    launch_ctl_reset(ctl, c.flags.as<uint32_t>() + kFlagClass, o.max_rounds, check_eq, eq_a, eq_b,
+                     pattern_first, packed_second, c.stream);
+
+    const int mode = o.loop_mode;
+    const uint32_t chunk = o.chunk ? o.chunk : c.tune.chunk;
+    uint32_t last_round = 0;
+    unsigned long long last_active_sum = 0;
+    bool tc_failed = false;
+    res.transitions = 0;
+    res.bytes = 0;
+    bool first = true;
+    for (;;) {
+        const RoundArgs ra = make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second);
+        if (first) {
+            // rounds 0 (and 1) run on their own: label rounds when the
+            // signatures are short enough
+            if (pattern_first)
+                launch_pattern_round(ra, c.stream);
+            else
+                launch_round(ra, c.stream);
+            if (packed_second) launch_packed_round(ra, c.stream);
+            HIP_TRY(hipGetLastError());
+            first = false;
+        }
+        DFA_TRY(run_chunk(c, ra, mode == DFA_LOOP_HOST ? 1u : chunk, mode));
+        DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
+        std::memcpy(&res.ctl, c.pinned, sizeof(RoundCtl));
+        const uint32_t done_rounds = res.ctl.round - last_round;
+        res.transitions += static_cast<uint64_t>(done_rounds) * N * k_eff;
+        res.bytes += (res.ctl.active_sum - last_active_sum) * (8ull * k_eff + 8ull);
+        last_round = res.ctl.round;
+        last_active_sum = res.ctl.active_sum;
+        if (res.ctl.done) break;
+        // closure on demand: progress has stalled relative to what is left
+        const uint64_t left = N - res.ctl.prev_count;
+        if (o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed && res.ctl.round >= 4 &&
+            left >= 4096 && static_cast<uint64_t>(res.ctl.last_gain) * 1024 < left) {
+            std::vector<uint32_t> tcmap;
+            uint32_t levels = 0;
+            int rc = build_closure(c, N, k, tcmap, levels);
+            if (rc == DFA_ENOMEM) {  // stay on the plain letters
+                tc_failed = true;
+                g_last_error.clear();
+                continue;
+            }
+            DFA_TRY(rc);
+            DFA_TRY(set_colmap(c, tcmap));
+            k_eff = static_cast<uint32_t>(tcmap.size());
+            DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
+            cols = c.tc_cols.as<uint32_t>();
+            res.tc_used = 1;
+            res.tc_levels = levels;
+            res.plain_rounds = res.ctl.round;
+        }
+    }
+    res.k_eff = k_eff;
+    uint32_t rounds_run = res.ctl.round;
+    if (state_ids && res.ctl.stable && res.ctl.round <= res.label_rounds) {
+        launch_ctl_resume(ctl, c.stream);
+        launch_round(make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second), c.stream);
+        HIP_TRY(hipGetLastError());
+        DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
+        const RoundCtl *after = reinterpret_cast<const RoundCtl *>(c.pinned);
+        if (!after->stable || after->prev_count != res.ctl.prev_count)
+            return fail(DFA_EDEVICE, "internal: relabelling round changed the partition");
+        rounds_run = after->round;
+    }
+    const uint32_t r_last = rounds_run - 1;
+    res.final_block = (r_last & 1u) ? c.blockA.as<uint32_t>() : c.blockB.as<uint32_t>();
+    return DFA_OK;
+}
+
+void fill_stats(dfa_stats *st, const RefineResult &r) {
+    if (!st) return;
+    st->rounds = r.ctl.round;
+    st->changing_rounds = r.ctl.changing;
+    st->num_blocks = r.ctl.prev_count;
+    st->k_eff = r.k_eff;
+    st->tc_used = r.tc_used;
+    st->tc_levels = r.tc_levels;
+    st->plain_rounds = r.tc_used ? r.plain_rounds : r.ctl.round;
+    st->transitions_refined = r.transitions;
+    st->algorithmic_bytes = r.bytes;
+}
+
+int check_options(const dfa_options &o) {
+    if (o.tc_mode < DFA_TC_OFF || o.tc_mode > DFA_TC_AUTO) return fail(DFA_EINVAL, "bad tc_mode");
+    if (o.loop_mode < DFA_LOOP_HOST || o.loop_mode > DFA_LOOP_GRAPH)
+        return fail(DFA_EINVAL, "bad loop_mode");
+    return DFA_OK;
+}
+
+int prepare_refinement(Ctx &c, size_t N, uint32_t k) {
+    const uint32_t L = floor_log2(N);
+    const size_t ncols = static_cast<size_t>(L + 1) * k;
+    const size_t words64 = (N + 63) / 64;
+    DFA_TRY(c.cols.ensure(static_cast<size_t>(k) * N * sizeof(uint32_t), "columns"));
+    DFA_TRY(c.flags.ensure((kFlagNonid + 2 * ncols) * sizeof(uint32_t), "flags"));
+    DFA_TRY(c.blockA.ensure(N * sizeof(uint32_t), "blocks"));
+    DFA_TRY(c.blockB.ensure(N * sizeof(uint32_t), "blocks"));
+    DFA_TRY(c.multi.ensure(N * sizeof(uint32_t), "block marks"));
+    DFA_TRY(c.active.ensure(words64 * sizeof(unsigned long long), "active masks"));
+    DFA_TRY(c.accbits.ensure(words64 * sizeof(unsigned long long), "acceptance bits"));
+    DFA_TRY(c.counters.ensure(kSpread * kSpreadStride * sizeof(uint32_t), "counters"));
+    DFA_TRY(c.presence.ensure((1u << kPatternMaxBits) / 8, "pattern bitmap"));
+    HIP_TRY(hipMemsetAsync(c.flags.p, 0, (kFlagNonid + k) * sizeof(uint32_t), c.stream));
+    HIP_TRY(hipMemsetAsync(c.multi.p, 0, N * sizeof(uint32_t), c.stream));
+    HIP_TRY(hipMemsetAsync(c.accbits.p, 0, words64 * sizeof(unsigned long long), c.stream));
+    HIP_TRY(hipMemsetAsync(c.counters.p, 0, kSpread * kSpreadStride * sizeof(uint32_t), c.stream));
+    HIP_TRY(hipMemsetAsync(c.presence.p, 0, (1u << kPatternMaxBits) / 8, c.stream));
+    return DFA_OK;
+}
+
+int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *acc,
+                  uint32_t *block_out, dfa_quotient *q, const dfa_options &o, dfa_stats *st) {
+    DFA_TRY(prepare_refinement(c, n, k));
+    const size_t id_range = n;  // refine() returns state ids
+    DFA_TRY(c.canon.ensure(id_range * sizeof(uint32_t), "canonical ids"));
+    HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    uint32_t *flags = c.flags.as<uint32_t>();
+    launch_ingest(delta, n, k, c.cols.as<uint32_t>(), n, 0, 0, flags + kFlagErr, flags + kFlagNonid,
+                  c.stream);
+    launch_init_blocks(acc, n, 0, c.blockA.as<uint32_t>(), c.accbits.as<unsigned long long>(),
+                       flags + kFlagClass, c.stream);
+    HIP_TRY(hipGetLastError());
+    RefineResult r;
+    int rc = refine(c, n, k, o, 0, 0, 0, true, r);
+    if (rc != DFA_OK) return rc;
+    launch_canonicalise(r.final_block, n, id_range, c.canon.as<uint32_t>(), block_out, c.stream);
+    if (q) {
+        const size_t ntiles = (static_cast<size_t>(n) + kScanTile - 1) / kScanTile;
+        DFA_TRY(c.partials.ensure((ntiles + 1) * sizeof(uint32_t), "scan partials"));
+        DFA_TRY(c.dense.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "dense ids"));
+        DFA_TRY(c.leader_of.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "leaders"));
+        DFA_TRY(c.scalars.ensure(16 * sizeof(uint32_t), "scalars"));
+        uint32_t *sc = c.scalars.as<uint32_t>();
+        launch_dense_leaders(block_out, n, c.partials.as<uint32_t>(), c.dense.as<uint32_t>(),
+                             c.leader_of.as<uint32_t>(), sc, c.stream);
+        launch_quotient(delta, acc, k, block_out, c.dense.as<uint32_t>(),
+                        c.leader_of.as<uint32_t>(), sc, n, o.start, q->delta, q->accepting,
+                        sc + 1, c.stream);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
+    if (q) {
+        DFA_TRY(read_back(c, c.scalars.p, 2 * sizeof(uint32_t)));
+        q->num_blocks = c.pinned[0];
+        q->start = c.pinned[1];
+    } else {
+        HIP_TRY(hipStreamSynchronize(c.stream));
+    }
+    if (r.ctl.limit) {
+        fill_stats(st, r);
+        return fail(DFA_ELIMIT, "max_rounds (%u) reached before the partition was stable",
+                    o.max_rounds);
+    }
+    if (st) {
+        fill_stats(st, r);
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
+        st->device_ms = ms;
+    }
+    return DFA_OK;
+}
+
+int equivalent_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict,
+                    const dfa_options &o, dfa_stats *st) {
+    const size_t N = static_cast<size_t>(a.n) + b.n;
+    if (N >= 0xFFFFFFFFull) return fail(DFA_EINVAL, "nA + nB must be < 2^32 - 1");
+    const uint32_t k = a.k;
+    DFA_TRY(prepare_refinement(c, N, k));
+    HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    uint32_t *flags = c.flags.as<uint32_t>();
+    uint32_t *cols = c.cols.as<uint32_t>();
+    // two separate target checks: A's targets < nA, B's < nB
+    launch_ingest(a.delta, a.n, k, cols, N, 0, 0, flags + kFlagErr, flags + kFlagNonid, c.stream);
+    launch_ingest(b.delta, b.n, k, cols, N, a.n, a.n, flags + kFlagErr, flags + kFlagNonid,
+                  c.stream);
+    launch_init_blocks(a.accepting, a.n, 0, c.blockA.as<uint32_t>(),
+                       c.accbits.as<unsigned long long>(), flags + kFlagClass, c.stream);
+    launch_init_blocks(b.accepting, b.n, a.n, c.blockA.as<uint32_t>(),
+                       c.accbits.as<unsigned long long>(), flags + kFlagClass, c.stream);
+    HIP_TRY(hipGetLastError());
+    RefineResult r;
+    DFA_TRY(refine(c, N, k, o, 1, a.start, a.n + b.start, false, r));
+    HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    fill_stats(st, r);
+    if (st) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
+        st->device_ms = ms;
+    }
+    if (r.ctl.separated) {
+        *verdict = 0;
+        return DFA_OK;
+    }
+    if (r.ctl.limit)
+        return fail(DFA_ELIMIT, "max_rounds (%u) reached before the verdict was known",
+                    o.max_rounds);
+    *verdict = 1;
+    return DFA_OK;
+}
+
+int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, uint64_t *visited,
+                  dfa_stats *st) {
+    const uint32_t k = a.k;
+    // reuse the flag buffer for the target checks (no refinement here)
+    DFA_TRY(c.flags.ensure((kFlagNonid + k) * sizeof(uint32_t), "flags"));
+    const size_t N = static_cast<size_t>(a.n) + b.n;
+    DFA_TRY(c.cols.ensure(static_cast<size_t>(k) * N * sizeof(uint32_t), "columns"));
+    HIP_TRY(hipMemsetAsync(c.flags.p, 0, (kFlagNonid + k) * sizeof(uint32_t), c.stream));
+    HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    uint32_t *flags = c.flags.as<uint32_t>();
+    launch_ingest(a.delta, a.n, k, c.cols.as<uint32_t>(), N, 0, 0, flags + kFlagErr,
+                  flags + kFlagNonid, c.stream);
+    launch_ingest(b.delta, b.n, k, c.cols.as<uint32_t>(), N, a.n, a.n, flags + kFlagErr,
+                  flags + kFlagNonid, c.stream);
+    HIP_TRY(hipGetLastError());
+    DFA_TRY(read_back(c, flags, sizeof(uint32_t)));
+    if (c.pinned[0]) return fail(DFA_EINVAL, "a transition target is >= n");
+
+    uint64_t cap = next_pow2(std::max<uint64_t>(4 * N, 4096));
+    DFA_TRY(c.visited.ensure(cap * sizeof(unsigned long long), "visited set"));
+    launch_visited_clear(c.visited.as<unsigned long long>(), cap, c.stream);
+    const unsigned long long start = (static_cast<unsigned long long>(a.start) << 32) | b.start;
+    launch_visited_insert_start(c.visited.as<unsigned long long>(), cap, start, c.stream);
+    DFA_TRY(c.front0.ensure(sizeof(unsigned long long), "frontier"));
+    DFA_TRY(upload(c, c.front0.p, &start, sizeof start));
+    DFA_TRY(c.scalars.ensure(16 * sizeof(uint32_t), "scalars"));
+    uint32_t *sc = c.scalars.as<uint32_t>();
+    Buffer *cur = &c.front0, *nxt = &c.front1;
+    uint64_t count = 1, fsize = 1;
+    int v = 1;
+    while (fsize > 0) {
+        const uint64_t need = fsize * k;
+        if (need >= 0xFFFFFFFFull) return fail(DFA_ENOMEM, "frontier too large");
+        DFA_TRY(nxt->ensure(need * sizeof(unsigned long long), "frontier"));
+        if ((count + need) * 2 > cap) {
+            const uint64_t ncap = next_pow2((count + need) * 2);
+            DFA_TRY(c.visited2.ensure(ncap * sizeof(unsigned long long), "visited set"));
+            launch_visited_clear(c.visited2.as<unsigned long long>(), ncap, c.stream);
+            launch_rehash(c.visited.as<unsigned long long>(), cap,
+                          c.visited2.as<unsigned long long>(), ncap, c.stream);
+            std::swap(c.visited, c.visited2);
+            cap = ncap;
+        }
+        HIP_TRY(hipMemsetAsync(sc, 0, 3 * sizeof(uint32_t), c.stream));
+        ProductArgs pa{a.delta, b.delta, a.accepting, b.accepting, k, 0,
+                       cur->as<unsigned long long>(), static_cast<uint32_t>(fsize),
+                       nxt->as<unsigned long long>(), static_cast<uint32_t>(need), sc,
+                       c.visited.as<unsigned long long>(), cap, sc + 1, sc + 2};
+        launch_product_level(pa, c.stream);
+        HIP_TRY(hipGetLastError());
+        DFA_TRY(read_back(c, sc, 3 * sizeof(uint32_t)));
+        if (c.pinned[2]) return fail(DFA_EDEVICE, "internal: frontier overflow");
+        if (c.pinned[1]) {
+            v = 0;
+            break;
+        }
+        fsize = c.pinned[0];
+        count += fsize;
+        std::swap(cur, nxt);
+    }
+    HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    *verdict = v;
+    if (visited) *visited = count;
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
+        st->device_ms = ms;
+    }
+    return DFA_OK;
+}
+
+// ---- argument checks ----
+
+int check_view(const dfa_view *v, const char *name) {
+    if (!v) return fail(DFA_EINVAL, "%s is NULL", name);
+    if (v->n == 0 || v->k == 0) return fail(DFA_EINVAL, "%s: n and k must be >= 1", name);
+    if (v->n == 0xFFFFFFFFu) return fail(DFA_EINVAL, "%s: n must be < 2^32 - 1", name);
+    if (!v->delta || !v->accepting) return fail(DFA_EINVAL, "%s: NULL delta/accepting", name);
+    if (v->start >= v->n) return fail(DFA_EINVAL, "%s: start %u >= n %u", name, v->start, v->n);
+    return DFA_OK;
+}
+
+int check_pair(const dfa_view *a, const dfa_view *b, const int *verdict) {
+    DFA_TRY(check_view(a, "a"));
+    DFA_TRY(check_view(b, "b"));
+    if (a->k != b->k) return fail(DFA_EINVAL, "alphabet sizes differ (%u vs %u)", a->k, b->k);
+    if (!verdict) return fail(DFA_EINVAL, "verdict is NULL");
+    return DFA_OK;
+}
+
+int check_minimise(uint32_t n, uint32_t k, const void *delta, const void *acc, const void *out,
+                   const dfa_quotient *q, const dfa_options &o) {
+    if (n == 0 || k == 0) return fail(DFA_EINVAL, "n and k must be >= 1");
+    if (n == 0xFFFFFFFFu) return fail(DFA_EINVAL, "n must be < 2^32 - 1");
+    if (!delta || !acc || !out) return fail(DFA_EINVAL, "NULL delta/accepting/block_out");
+    if (q && (!q->delta || !q->accepting)) return fail(DFA_EINVAL, "NULL quotient arrays");
+    if (o.start >= n) return fail(DFA_EINVAL, "start %u >= n %u", o.start, n);
+    return check_options(o);
+}
+
+// Orders the work already queued on the caller's stream (NULL = the legacy
+// default stream) before the library's own stream.
+int join_stream(Ctx &c, void *stream) {
+    auto s = static_cast<hipStream_t>(stream);
+    if (s == c.stream) return DFA_OK;
+    HIP_TRY(hipEventRecord(c.ev_in, s));
+    HIP_TRY(hipStreamWaitEvent(c.stream, c.ev_in, 0));
+    return DFA_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace dfamin
+
+using namespace dfamin;
+
+extern "C" {
+
+void dfa_tuning_default(dfa_tuning *t) {
+    if (!t) return;
+    std::memset(t, 0, sizeof *t);
+    t->round_grid_cap = 8192;
+    t->label_grid_cap = 2048;
+    t->label_rounds = 2;
+    t->cached_probe = 1;
+    t->chunk = 4;
+}
+
+int dfa_get_tuning(dfa_tuning *t) {
+    if (!t) return fail(DFA_EINVAL, "tuning is NULL");
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    *t = c->tune;
+    return DFA_OK;
+}
+
+int dfa_set_tuning(const dfa_tuning *t) {
+    if (!t) return fail(DFA_EINVAL, "tuning is NULL");
+    if (t->label_rounds > 2 || t->cached_probe > 1 || t->chunk == 0 || t->chunk > 4096 ||
+        t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24))
+        return fail(DFA_EINVAL, "tuning value out of range");
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    c->tune = *t;
+    return DFA_OK;
+}
+
+void dfa_options_default(dfa_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->tc_mode = DFA_TC_AUTO;
+    opt->loop_mode = DFA_LOOP_GRAPH;
+    opt->start = 0;
+    opt->max_rounds = 0;
+    opt->chunk = 0;
+    opt->lds_stage = 1;
+}
+
+const char *dfa_last_error(void) { return g_last_error.c_str(); }
+
+int dfa_device_info(char *name, size_t name_cap, int *compute_units, size_t *hbm_bytes) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, dev));
+    if (name && name_cap) {
+        std::snprintf(name, name_cap, "%s (%s)", p.name, p.gcnArchName);
+    }
+    if (compute_units) *compute_units = p.multiProcessorCount;
+    if (hbm_bytes) *hbm_bytes = p.totalGlobalMem;
+    return DFA_OK;
+}
+
+int dfa_minimise_device(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *accepting,
+                        uint32_t *block_out, dfa_quotient *q_out, const dfa_options *opt,
+                        dfa_stats *stats, void *stream) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    DFA_TRY(join_stream(*c, stream));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return minimise_impl(*c, n, k, delta, accepting, block_out, q_out, o, stats);
+}
+
+int dfa_minimise(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *accepting,
+                 uint32_t *block_out, dfa_quotient *q_out, const dfa_options *opt,
+                 dfa_stats *stats) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    const size_t nk = static_cast<size_t>(n) * k;
+    DFA_TRY(c->stage_delta.ensure(nk * sizeof(uint32_t), "input copy"));
+    DFA_TRY(c->stage_acc.ensure(n, "input copy"));
+    DFA_TRY(c->stage_block.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "output copy"));
+    if (q_out) {
+        DFA_TRY(c->stage_qdelta.ensure(nk * sizeof(uint32_t), "quotient copy"));
+        DFA_TRY(c->stage_qacc.ensure(n, "quotient copy"));
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_TRY(hipMemcpyAsync(c->stage_delta.p, delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->stage_acc.p, accepting, n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double h2d = ms_since(t0);
+    dfa_quotient dq{};
+    if (q_out) {
+        dq.delta = c->stage_qdelta.as<uint32_t>();
+        dq.accepting = c->stage_qacc.as<uint8_t>();
+    }
+    int rc = minimise_impl(*c, n, k, c->stage_delta.as<uint32_t>(), c->stage_acc.as<uint8_t>(),
+                           c->stage_block.as<uint32_t>(), q_out ? &dq : nullptr, o, stats);
+    if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
+    t0 = std::chrono::steady_clock::now();
+    HIP_TRY(hipMemcpyAsync(block_out, c->stage_block.p, static_cast<size_t>(n) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    if (q_out) {
+        HIP_TRY(hipMemcpyAsync(q_out->delta, dq.delta,
+                               static_cast<size_t>(dq.num_blocks) * k * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(q_out->accepting, dq.accepting, dq.num_blocks,
+                               hipMemcpyDeviceToHost, c->stream));
+        q_out->num_blocks = dq.num_blocks;
+        q_out->start = dq.start;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (stats) {
+        stats->h2d_ms = h2d;
+        stats->d2h_ms = ms_since(t0);
+    }
+    return rc;
+}
+
+static int stage_view(Buffer &bd, Buffer &ba, const dfa_view *v, dfa_view &out, hipStream_t s) {
+    const size_t nk = static_cast<size_t>(v->n) * v->k;
+    DFA_TRY(bd.ensure(nk * sizeof(uint32_t), "input copy"));
+    DFA_TRY(ba.ensure(v->n, "input copy"));
+    HIP_TRY(hipMemcpyAsync(bd.p, v->delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ba.p, v->accepting, v->n, hipMemcpyHostToDevice, s));
+    out = *v;
+    out.delta = bd.as<uint32_t>();
+    out.accepting = ba.as<uint8_t>();
+    return DFA_OK;
+}
+
+int dfa_equivalent_device(const dfa_view *a, const dfa_view *b, int *verdict,
+                          const dfa_options *opt, dfa_stats *stats, void *stream) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_pair(a, b, verdict));
+    DFA_TRY(check_options(o));
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    DFA_TRY(join_stream(*c, stream));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return equivalent_impl(*c, *a, *b, verdict, o, stats);
+}
+
+int dfa_equivalent(const dfa_view *a, const dfa_view *b, int *verdict, const dfa_options *opt,
+                   dfa_stats *stats) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_pair(a, b, verdict));
+    DFA_TRY(check_options(o));
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    auto t0 = std::chrono::steady_clock::now();
+    dfa_view da, db;
+    DFA_TRY(stage_view(c->stage_delta, c->stage_acc, a, da, c->stream));
+    DFA_TRY(stage_view(c->stage_delta_b, c->stage_acc_b, b, db, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double h2d = ms_since(t0);
+    int rc = equivalent_impl(*c, da, db, verdict, o, stats);
+    if (stats) stats->h2d_ms = h2d;
+    return rc;
+}
+
+int dfa_included_device(const dfa_view *a, const dfa_view *b, int *verdict,
+                        uint64_t *pairs_visited, const dfa_options *opt, dfa_stats *stats,
+                        void *stream) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_pair(a, b, verdict));
+    DFA_TRY(check_options(o));
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    DFA_TRY(join_stream(*c, stream));
+    return included_impl(*c, *a, *b, verdict, pairs_visited, stats);
+}
+
+int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *pairs_visited,
+                 const dfa_options *opt, dfa_stats *stats) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_pair(a, b, verdict));
+    DFA_TRY(check_options(o));
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    auto t0 = std::chrono::steady_clock::now();
+    dfa_view da, db;
+    DFA_TRY(stage_view(c->stage_delta, c->stage_acc, a, da, c->stream));
+    DFA_TRY(stage_view(c->stage_delta_b, c->stage_acc_b, b, db, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double h2d = ms_since(t0);
+    int rc = included_impl(*c, da, db, verdict, pairs_visited, stats);
+    if (stats) stats->h2d_ms = h2d;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations of libdfamin (not part of the public ABI).
+//
+// Device data layout (one refinement over N states, N = n or nA + nB):
+//   cols     uint32 [ncols][N]   symbol-major transition columns; column c,
+//                                state q -> cols[c*N + q].  Plain refinement
+//                                uses the k input letters; the closure adds
+//                                the letters a^(2^i) at column i*k + a.
+//   colmap   uint32 [k_eff]      the columns that enter the signature
+//   blockA/B uint32 [N]          block ids, double-buffered by round parity
+//   sig      uint32 [N][k_eff+1] the signature of every state (row-major)
+//   hash     uint64 [N]          64-bit hash of each signature
+//   table    uint64 [cap]        lock-free open-addressing table
+//                                (epoch:8 | tag:24 | representative:32)
+//   multi    uint32 [N]          multi[b] = r + 1 when block b had two or more
+//                                members after round r (singleton blocks
+//                                never split again and are skipped)
+//   active   uint64 [N/64]       per-wave bitmask of the states refined in
+//                                the current round
+//   accbits  uint64 [N/64]       acceptance, one bit per state (first round)
+//   ctl      RoundCtl            round counter / stop flag on the device
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dfamin {
+
+constexpr int kBlock = 256;        // threads per workgroup
+constexpr uint32_t kEpochs = 255;  // table epochs before it is cleared
+constexpr int kSpread = 64;        // per-round counters, one per 128-byte line
+constexpr int kSpreadStride = 32;  // uint32 words between two counters
+constexpr uint32_t kPatternMaxBits = 16;  // first round by bit patterns if k_eff + 1 <= 16
+constexpr uint32_t kPackedMaxBits = 25;   // round 1 by packed labels if (k_eff + 1)^2 <= 25
+
+// Round-loop state kept on the device so that rounds can be enqueued (or
+// replayed from a graph) without the host in the loop.
+struct RoundCtl {
+    uint32_t round;       // rounds completed
+    uint32_t done;        // stop flag: stable, decided or limit reached
+    uint32_t prev_count;  // blocks before the current round
+    uint32_t last_gain;   // blocks added by the last round
+    uint32_t changing;    // rounds that added blocks
+    uint32_t stable;      // 1 once a round added no block
+    uint32_t separated;   // equivalence: the two start states were split
+    uint32_t limit;       // max_rounds reached
+    uint32_t max_rounds;  // 0 = unbounded
+    uint32_t eq_a, eq_b;  // equivalence: states whose blocks are compared
+    uint32_t check_eq;    // 1 = stop as soon as eq_a and eq_b separate
+    uint32_t pattern_first;  // round 0 grouped by acceptance bit patterns
+    uint32_t packed_second;  // round 1 grouped by packed round-0 labels
+    uint32_t all_active_until;  // rounds <= this refine every state
+    uint32_t last_active;    // states refined by the last round
+    unsigned long long active_sum;  // states refined, summed over rounds
+};
+
+// ---- launchers (defined in refine_kernels.hip); all enqueue on `s` ----
+
+// Transpose row-major delta (n x k, targets < n) into cols[a*N + offset + q]
+// adding `target_offset` to every target; sets *err = 1 on a target >= n and
+// nonid[a] = 1 when letter a is not the identity on these states.
+void launch_ingest(const uint32_t *delta, uint32_t n, uint32_t k, uint32_t *cols, size_t N,
+                   uint32_t offset, uint32_t target_offset, uint32_t *err, uint32_t *nonid,
+                   hipStream_t s);
+
+// block[q] = accepting[q] ? 1 : 0 for q in [offset, offset + n), the
+// acceptance bits (accbits, zeroed beforehand), and class_flags[0] / [1] = 1
+// if some state accepts / rejects.
+void launch_init_blocks(const uint8_t *acc, uint32_t n, uint32_t offset, uint32_t *block,
+                        unsigned long long *accbits, uint32_t *class_flags, hipStream_t s);
+
+// ctl := fresh state with prev_count = initial class count (read from
+// class_flags on the device).
+void launch_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t max_rounds,
+                      uint32_t check_eq, uint32_t eq_a, uint32_t eq_b, uint32_t pattern_first,
+                      uint32_t packed_second, hipStream_t s);
+// Clears the stop flag so that one more round can run (relabelling).
+void launch_ctl_resume(RoundCtl *ctl, hipStream_t s);
+
+// One signature round: signatures + hashes (and the periodic table clear),
+// then grouping through the table, then the round-end bookkeeping.
+struct RoundArgs {
+    const uint32_t *cols;
+    const uint32_t *colmap;
+    size_t N;
+    uint32_t k_eff;
+    uint32_t *blockA, *blockB;
+    uint32_t *sig;
+    uint64_t *hash;
+    unsigned long long *table;
+    uint64_t table_cap;  // power of two
+    uint32_t *multi;
+    unsigned long long *active;
+    const unsigned long long *accbits;
+    uint32_t *counters;  // kSpread * kSpreadStride words, zero between rounds
+    uint32_t *presence;  // 2^kPatternMaxBits bits, zero between calls
+    uint32_t *presence_packed;  // 2^kPackedMaxBits bits, zero between calls
+    uint8_t *lab8;       // round-0 labels as bytes (packed round 1 only)
+    RoundCtl *ctl;
+    int lds_stage;
+    uint32_t round_grid_cap;    // workgroups of the round kernels (0 = one per 256 states)
+    uint32_t pattern_grid_cap;  // workgroups of the label rounds
+    uint32_t cached_probe;      // probe the table with cached loads first
+    uint32_t pad;
+};
+void launch_round(const RoundArgs &a, hipStream_t s);
+// Round 0 from acceptance bit patterns (requires k_eff + 1 <= kPatternMaxBits).
+void launch_pattern_round(const RoundArgs &a, hipStream_t s);
+// Round 1 from the packed round-0 labels of q and its successors (requires
+// (k_eff + 1)^2 <= kPackedMaxBits and lab8 written by the pattern round).
+void launch_packed_round(const RoundArgs &a, hipStream_t s);
+
+// Pointer jumping, level i >= 1, all k letters:
+// cols[(i*k+a)*N + q] = cols[((i-1)*k+a)*N + cols[((i-1)*k+a)*N + q]];
+// diff[i*k+a] = 1 if the level differs from level i-1 somewhere,
+// nonid[i*k+a] = 1 if it is not the identity.
+void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t *diff,
+                 uint32_t *nonid, hipStream_t s);
+
+// Canonical renumbering: out[q] = min{ q' : ids[q'] == ids[q] } for ids <
+// id_range; scratch_min holds id_range words.
+void launch_canonicalise(const uint32_t *ids, size_t N, size_t id_range, uint32_t *scratch_min,
+                         uint32_t *out, hipStream_t s);
+
+// Dense quotient numbering of a canonical partition: dense[l] for every
+// leader l (block[l] == l) in increasing order; leader_of[b] = l;
+// *num_blocks = B.  partials needs ceil(N / kScanTile) + 1 words.
+constexpr uint32_t kScanTile = 1024;
+void launch_dense_leaders(const uint32_t *block, size_t N, uint32_t *partials, uint32_t *dense,
+                          uint32_t *leader_of, uint32_t *num_blocks, hipStream_t s);
+
+// qdelta[b*k + a] = dense[block[delta[l*k + a]]], qacc[b] = acc[l] for
+// l = leader_of[b]; *qstart = dense[block[start]].
+void launch_quotient(const uint32_t *delta, const uint8_t *acc, uint32_t k,
+                     const uint32_t *block, const uint32_t *dense, const uint32_t *leader_of,
+                     const uint32_t *num_blocks, uint32_t B_max, uint32_t start,
+                     uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart, hipStream_t s);
+
+// ---- product exploration (product_kernels.hip) ----
+struct ProductArgs {
+    const uint32_t *dA, *dB;   // row-major
+    const uint8_t *accA, *accB;
+    uint32_t k;
+    int mode;                  // 0 inclusion, 1 equivalence
+    const unsigned long long *frontier;
+    uint32_t frontier_size;
+    unsigned long long *next;  // capacity next_cap
+    uint32_t next_cap;
+    uint32_t *next_size;       // atomic counter
+    unsigned long long *visited;
+    uint64_t visited_cap;      // power of two
+    uint32_t *bad;             // set to 1 when a refuting pair is reached
+    uint32_t *overflow;        // set to 1 when `next` overflows
+};
+void launch_product_level(const ProductArgs &a, hipStream_t s);
+void launch_visited_clear(unsigned long long *visited, uint64_t cap, hipStream_t s);
+void launch_visited_insert_start(unsigned long long *visited, uint64_t cap,
+                                 unsigned long long key, hipStream_t s);
+void launch_rehash(const unsigned long long *old_tab, uint64_t old_cap,
+                   unsigned long long *new_tab, uint64_t new_cap, hipStream_t s);
+
+}  // namespace dfamin

@@ -1,0 +1,121 @@
+// Breadth-first exploration of the synchronous product of two DFAs on the
+// GPU: the naive Hopcroft-Karp of Section 4, where the relation is the plain
+// set of reached pairs (a lock-free hash set of 64-bit keys p << 32 | q in
+// HBM) and no transitive closure is maintained.  Inclusion L(A) <= L(B) is
+// refuted by a reached pair with p accepting in A and q rejecting in B;
+// equivalence by a pair with exactly one accepting side.
+#include "dfamin_internal.h"
+
+namespace dfamin {
+namespace {
+
+constexpr unsigned long long kEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+// Inserts key; returns true if it was not present.
+__device__ __forceinline__ bool set_insert(unsigned long long *tab, uint64_t mask,
+                                           unsigned long long key) {
+    uint64_t s = mix64(key) & mask;
+    for (;;) {
+        unsigned long long e = __hip_atomic_load(tab + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (e == key) return false;
+        if (e == kEmpty) {
+            const unsigned long long prev = atomicCAS(tab + s, kEmpty, key);
+            if (prev == kEmpty) return true;
+            if (prev == key) return false;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_product_level(ProductArgs a) {
+    const uint32_t lane = __lane_id();
+    const uint64_t mask = a.visited_cap - 1;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+         i < a.frontier_size; i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const unsigned long long key = a.frontier[i];
+        const uint32_t p = static_cast<uint32_t>(key >> 32), q = static_cast<uint32_t>(key);
+        const bool fa = a.accA[p] != 0, fb = a.accB[q] != 0;
+        const bool bad = a.mode == 0 ? (fa && !fb) : (fa != fb);
+        if (bad) atomicOr(a.bad, 1u);
+        for (uint32_t c = 0; c < a.k; ++c) {
+            const unsigned long long nk =
+                (static_cast<unsigned long long>(a.dA[static_cast<size_t>(p) * a.k + c]) << 32) |
+                a.dB[static_cast<size_t>(q) * a.k + c];
+            const bool fresh = !bad && set_insert(a.visited, mask, nk);
+            // wave-aggregated append to the next frontier
+            const unsigned long long m = __ballot(fresh);
+            if (m == 0) continue;
+            const int leader = __ffsll(m) - 1;
+            uint32_t base = 0;
+            if (static_cast<int>(lane) == leader) base = atomicAdd(a.next_size, static_cast<uint32_t>(__popcll(m)));
+            base = __shfl(base, leader, 64);
+            if (fresh) {
+                const unsigned long long below = lane ? (m & ((1ull << lane) - 1ull)) : 0ull;
+                const uint32_t slot = base + static_cast<uint32_t>(__popcll(below));
+                if (slot < a.next_cap)
+                    a.next[slot] = nk;
+                else
+                    atomicOr(a.overflow, 1u);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_visited_clear(unsigned long long *tab, uint64_t cap) {
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < cap;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        tab[i] = kEmpty;
+}
+
+__global__ void k_visited_insert_start(unsigned long long *tab, uint64_t cap,
+                                       unsigned long long key) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_insert(tab, cap - 1, key);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rehash(const unsigned long long *old_tab, uint64_t old_cap,
+                                                    unsigned long long *new_tab, uint64_t new_cap) {
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < old_cap;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const unsigned long long key = old_tab[i];
+        if (key != kEmpty) set_insert(new_tab, new_cap - 1, key);
+    }
+}
+
+unsigned grid_for(size_t work) {
+    size_t g = (work + kBlock - 1) / kBlock;
+    if (g == 0) g = 1;
+    if (g > (1u << 20)) g = 1u << 20;
+    return static_cast<unsigned>(g);
+}
+
+}  // namespace
+
+void launch_product_level(const ProductArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_product_level, dim3(grid_for(a.frontier_size)), dim3(kBlock), 0, s, a);
+}
+
+void launch_visited_clear(unsigned long long *visited, uint64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_visited_clear, dim3(grid_for(cap)), dim3(kBlock), 0, s, visited, cap);
+}
+
+void launch_visited_insert_start(unsigned long long *visited, uint64_t cap,
+                                 unsigned long long key, hipStream_t s) {
+    hipLaunchKernelGGL(k_visited_insert_start, dim3(1), dim3(64), 0, s, visited, cap, key);
+}
+
+void launch_rehash(const unsigned long long *old_tab, uint64_t old_cap,
+                   unsigned long long *new_tab, uint64_t new_cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_rehash, dim3(grid_for(old_cap)), dim3(kBlock), 0, s, old_tab, old_cap,
+                       new_tab, new_cap);
+}
+
+}  // namespace dfamin

@@ -1,0 +1,835 @@
+// HIP kernels of the partition-refinement path for gfx950 (wave64).
+//
+// One refinement round (the signature rounds of Section 3.3, Algorithm 4,
+// with grouping by hashing instead of sorting):
+//   k_signature  every state q writes its signature
+//                  ( block[q], block[col_0[q]], ..., block[col_{k_eff-1}[q]] )
+//                into a row of `sig` and a 64-bit hash of it.  Column reads are
+//                coalesced (symbol-major layout); the block ids are gathers.
+//   k_insert     groups equal signatures in a lock-free open-addressing table
+//                in HBM.  The hash only picks the slot and a 24-bit tag; keys
+//                are always compared in full, so grouping is exact.  The first
+//                state to claim a slot becomes the representative, and its
+//                index is the new block id of every state with that signature.
+//                The LDS variant first groups the 256 states of a workgroup in
+//                an LDS table, so only one state per distinct signature and
+//                workgroup touches the HBM table.
+//   k_round_end  one workgroup: the block count of the round is the number
+//                of claimed slots plus the singleton states that were not
+//                refined; an unchanged count means the partition is stable
+//                (the block id leads the signature, so each round refines the
+//                previous one).
+// A block with a single state never splits again: states whose block was a
+// singleton after the previous round skip the signature and grouping work
+// (their id is final).  Round 0 groups by the bit pattern of acceptance of q
+// and its successors when that pattern is short enough, without a table.
+// Block ids during the rounds are representatives chosen by the hardware's
+// atomic order; the final partition is renumbered canonically (smallest state
+// of each block) once, by k_canon_min / k_canon_apply.
+#include "dfamin_internal.h"
+
+namespace dfamin {
+namespace {
+
+constexpr unsigned long long kEmptyPair = ~0ull;
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Multiply-xorshift mixing of 32-bit words into a 64-bit hash.
+__device__ __forceinline__ uint64_t mix_step(uint64_t h, uint32_t w) {
+    h ^= w;
+    h *= 0x9E3779B97F4A7C15ull;
+    h ^= h >> 32;
+    return h;
+}
+__device__ __forceinline__ uint64_t mix_final(uint64_t h) {
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 32;
+    return h;
+}
+constexpr uint64_t kHashSeed = 0x6A09E667F3BCC909ull;
+
+__device__ __forceinline__ size_t global_tid() {
+    return static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+}
+__device__ __forceinline__ size_t grid_stride() {
+    return static_cast<size_t>(gridDim.x) * blockDim.x;
+}
+
+// Workgroup sum of per-thread values, added with one atomic per workgroup to
+// one of kSpread counters (consecutive workgroups use different lines).
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void wg_add_spread(uint32_t *counters, int word, uint32_t v) {
+    __shared__ uint32_t part[kBlock / 64];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    __syncthreads();
+    if (lane_id() == 0) part[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+        if (s) atomicAdd(counters + (blockIdx.x % kSpread) * kSpreadStride + word, s);
+    }
+}
+
+// Sets *flag = 1 (a plain store: every writer stores the same value) if any
+// active lane has `pred`; skips the store once the flag reads as set.
+__device__ __forceinline__ void wave_set_flag(uint32_t *flag, bool pred) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    if (static_cast<int>(lane_id()) == leader && *flag == 0u) *flag = 1u;
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
+    uint32_t lo = static_cast<uint32_t>(v), hi = static_cast<uint32_t>(v >> 32);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        lo |= __shfl_xor(lo, d, 64);
+        hi |= __shfl_xor(hi, d, 64);
+    }
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// ---------------------------------------------------------------- ingest
+
+// One thread per state: reads its row of delta, writes one entry per column.
+__global__ __launch_bounds__(kBlock) void k_ingest(const uint32_t *__restrict__ delta, uint32_t n,
+                                                    uint32_t k, uint32_t *__restrict__ cols,
+                                                    size_t N, uint32_t offset, uint32_t toff,
+                                                    uint32_t *err, uint32_t *nonid) {
+    bool bad = false;
+    unsigned long long moves = 0;  // letters 0..63 that move some state
+    for (size_t q = global_tid(); q < n; q += grid_stride()) {
+        const uint32_t *row = delta + q * k;
+        for (uint32_t a = 0; a < k; ++a) {
+            const uint32_t t = row[a];
+            bad |= t >= n;
+            if (t != q) {
+                if (a < 64)
+                    moves |= 1ull << a;
+                else if (nonid[a] == 0u)
+                    nonid[a] = 1u;
+            }
+            cols[static_cast<size_t>(a) * N + offset + q] = t + toff;
+        }
+    }
+    wave_set_flag(err, bad);
+    moves = wave_or64(moves);
+    if (lane_id() == 0) {
+        while (moves) {
+            const int a = __ffsll(moves) - 1;
+            moves &= moves - 1;
+            if (nonid[a] == 0u) nonid[a] = 1u;
+        }
+    }
+}
+
+// Initial labels (accepting ? 1 : 0), packed acceptance bits, class flags.
+__global__ __launch_bounds__(kBlock) void k_init_blocks(const uint8_t *__restrict__ acc, uint32_t n,
+                                                         uint32_t offset,
+                                                         uint32_t *__restrict__ block,
+                                                         unsigned long long *accbits,
+                                                         uint32_t *class_flags) {
+    bool any_acc = false, any_rej = false;
+    const bool aligned = (offset & 63u) == 0;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < n;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        const size_t q = base + threadIdx.x;
+        const bool valid = q < n;
+        const bool f = valid && acc[q] != 0;
+        if (valid) block[offset + q] = f ? 1u : 0u;
+        any_acc |= f;
+        any_rej |= valid && !f;
+        if (aligned) {
+            const unsigned long long m = __ballot(f);
+            const size_t first = base + (threadIdx.x & ~63u);
+            if (lane_id() == 0 && first < n && m) accbits[(offset + first) >> 6] = m;
+        } else if (f) {
+            const size_t g = offset + q;
+            atomicOr(accbits + (g >> 6), 1ull << (g & 63));
+        }
+    }
+    wave_set_flag(class_flags + 0, any_acc);
+    wave_set_flag(class_flags + 1, any_rej);
+}
+
+__global__ void k_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t max_rounds,
+                            uint32_t check_eq, uint32_t eq_a, uint32_t eq_b,
+                            uint32_t pattern_first, uint32_t packed_second) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    RoundCtl c{};
+    c.prev_count = (class_flags[0] ? 1u : 0u) + (class_flags[1] ? 1u : 0u);
+    c.max_rounds = max_rounds;
+    c.check_eq = check_eq;
+    c.eq_a = eq_a;
+    c.eq_b = eq_b;
+    c.pattern_first = pattern_first;
+    c.packed_second = packed_second;
+    // ids produced by label rounds are not state indices: the round after
+    // them refines every state
+    c.all_active_until = pattern_first + packed_second;
+    *ctl = c;
+}
+
+__global__ void k_ctl_resume(RoundCtl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->done = 0;
+}
+
+// ---------------------------------------------------------------- round kernels
+
+struct SigParams {
+    const uint32_t *cols;
+    const uint32_t *colmap;
+    size_t N;
+    uint32_t k_eff;
+    uint32_t *blockA, *blockB;
+    uint32_t *sig;
+    uint64_t *hash;
+    unsigned long long *table;
+    uint64_t table_cap;
+    const uint32_t *multi;
+    unsigned long long *active;
+    const unsigned long long *accbits;
+    uint32_t *presence;
+    uint32_t *presence_packed;
+    uint8_t *lab8;
+    uint32_t *counters;
+    const RoundCtl *ctl;
+};
+
+__device__ __forceinline__ uint32_t acc_bit(const unsigned long long *accbits, uint32_t t) {
+    return static_cast<uint32_t>(accbits[t >> 6] >> (t & 63)) & 1u;
+}
+
+// Round 0 when k_eff + 1 <= kPatternMaxBits: the signature of q is the bit
+// pattern (q accepting, successor 0 accepting, ...), which is itself an exact
+// label of q's new block; no table is needed.  Distinct patterns are counted
+// by the workgroups that set a bit first in a presence bitmap (deduplicated
+// in LDS per workgroup, then OR-ed into HBM).
+__global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
+    __shared__ uint32_t pres[(1u << kPatternMaxBits) / 32];
+    if (p.ctl->done) return;
+    const uint32_t bits = p.k_eff + 1;
+    const uint32_t words = bits >= 5 ? (1u << bits) / 32 : 1u;
+    for (uint32_t i = threadIdx.x; i < words; i += kBlock) pres[i] = 0;
+    __syncthreads();
+    uint32_t *__restrict__ out = p.blockB;
+    for (size_t q = global_tid(); q < p.N; q += grid_stride()) {
+        uint32_t label = acc_bit(p.accbits, static_cast<uint32_t>(q));
+        for (uint32_t j = 0; j < p.k_eff; ++j) {
+            const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+            label |= acc_bit(p.accbits, t) << (j + 1);
+        }
+        out[q] = label;
+        if (p.lab8) p.lab8[q] = static_cast<uint8_t>(label);
+        atomicOr(pres + (label >> 5), 1u << (label & 31));
+    }
+    __syncthreads();
+    uint32_t fresh = 0;
+    for (uint32_t i = threadIdx.x; i < words; i += kBlock) {
+        const uint32_t m = pres[i];
+        if (m == 0) continue;
+        const uint32_t seen =
+            __hip_atomic_load(p.presence + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (m & ~seen) fresh += __popc(m & ~atomicOr(p.presence + i, m));
+    }
+    wg_add_spread(p.counters, 0, fresh);
+}
+
+// Round 1 after a pattern round when (k_eff + 1)^2 <= kPackedMaxBits: the
+// signature (label of q, labels of its successors) packs exactly into one
+// word, which becomes the new label.  Labels are gathered from the byte copy
+// written by round 0 (small enough to stay in L2); distinct labels are
+// counted by first setters in a presence bitmap.
+__global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
+    if (p.ctl->done) return;
+    const uint32_t r = p.ctl->round;
+    uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
+    const uint32_t bits = p.k_eff + 1;
+    uint32_t fresh = 0;
+    for (size_t q = global_tid(); q < p.N; q += grid_stride()) {
+        uint32_t key = p.lab8[q];
+        for (uint32_t j = 0; j < p.k_eff; ++j) {
+            const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+            key |= static_cast<uint32_t>(p.lab8[t]) << (bits * (j + 1));
+        }
+        Y[q] = key;
+        uint32_t *word = p.presence_packed + (key >> 5);
+        const uint32_t bit = 1u << (key & 31);
+        // a cached read first: only a word that does not show the bit yet
+        // needs the atomic (which is exact either way)
+        if (!(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) & bit))
+            fresh += (atomicOr(word, bit) & bit) ? 0u : 1u;
+    }
+    wg_add_spread(p.counters, 0, fresh);
+}
+
+// Signatures of the states refined this round.  A state is refined if the
+// round refines everything (the first rounds) or if its block had two or
+// more members after the previous round; the others are singletons, keep
+// their id and are copied to the output buffer.
+// KC > 0: k_eff known at compile time (fully unrolled gathers);
+// KC == 0: runtime k_eff, gathers issued in batches of 8.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
+    if (p.ctl->done) return;
+    const uint32_t r = p.ctl->round;
+    const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
+    uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
+    const bool all = r <= p.ctl->all_active_until;
+    const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
+    const size_t W = keff + 1;
+
+    // the table is cleared every kEpochs rounds (its entries carry the epoch)
+    if (r > 0 && r % kEpochs == 0) {
+        for (size_t i = global_tid(); i < p.table_cap; i += grid_stride()) p.table[i] = 0ull;
+    }
+
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        const size_t q = base + threadIdx.x;
+        const bool valid = q < p.N;
+        const uint32_t w0 = valid ? X[q] : 0u;
+        const bool act = valid && (all || p.multi[w0] == r);
+        const unsigned long long am = __ballot(act);
+        const size_t first = base + (threadIdx.x & ~63u);
+        if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
+        if (valid && !act) Y[q] = w0;
+        if (!act) continue;
+        uint32_t *__restrict__ row = p.sig + q * W;
+        row[0] = w0;
+        uint64_t h = mix_step(kHashSeed, w0);
+        if constexpr (KC > 0) {
+            uint32_t t[KC], w[KC];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) w[j] = X[t[j]];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) {
+                row[1 + j] = w[j];
+                h = mix_step(h, w[j]);
+            }
+        } else {
+            for (uint32_t j0 = 0; j0 < keff; j0 += 8) {
+                const uint32_t m = keff - j0 < 8 ? keff - j0 : 8;
+                uint32_t t[8], w[8];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j)
+                    if (j < m) t[j] = p.cols[static_cast<size_t>(p.colmap[j0 + j]) * p.N + q];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j)
+                    if (j < m) w[j] = X[t[j]];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j)
+                    if (j < m) {
+                        row[1 + j0 + j] = w[j];
+                        h = mix_step(h, w[j]);
+                    }
+            }
+        }
+        p.hash[q] = mix_final(h);
+    }
+}
+
+// ---------------------------------------------------------------- grouping
+
+struct InsParams {
+    const uint32_t *sig;
+    const uint64_t *hash;
+    size_t N;
+    uint32_t W;
+    unsigned long long *table;
+    uint64_t mask;
+    uint32_t *blockA, *blockB;
+    uint32_t *multi;
+    const unsigned long long *active;
+    uint32_t *counters;
+    const RoundCtl *ctl;
+    uint32_t cached_probe;
+};
+
+__device__ __forceinline__ bool rows_equal(const uint32_t *__restrict__ sig, size_t W, size_t a,
+                                           size_t b) {
+    const uint32_t *ra = sig + a * W;
+    const uint32_t *rb = sig + b * W;
+    for (size_t i = 0; i < W; ++i)
+        if (ra[i] != rb[i]) return false;
+    return true;
+}
+
+__device__ __forceinline__ unsigned long long load_entry(const unsigned long long *p, bool cached) {
+    return cached ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)
+                  : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Finds the slot holding q's signature or claims an empty one for it.
+// Entry = (epoch:8 | tag:24) << 32 | representative; entries of older
+// epochs count as empty.  Lock-free: a slot only ever changes from "empty" to
+// a final value within an epoch, and every decision is confirmed by a CAS or
+// by reading such a final value.  A cached read may show an older "empty"
+// value; the CAS then fails and returns the value actually stored, which is
+// examined next without reading the cache again.  The load factor stays
+// <= 1/2, so the probe always reaches an empty slot.
+__device__ __forceinline__ uint32_t find_or_claim(unsigned long long *table, uint64_t mask,
+                                                  uint32_t epoch, uint64_t h, uint32_t self,
+                                                  const uint32_t *sig, size_t W, bool cached,
+                                                  bool &claimed) {
+    const uint32_t tag = (epoch << 24) | static_cast<uint32_t>(h >> 40);
+    const unsigned long long want = (static_cast<unsigned long long>(tag) << 32) | self;
+    uint64_t s = h & mask;
+    unsigned long long e = load_entry(table + s, cached);
+    for (;;) {
+        if (static_cast<uint32_t>(e >> 56) != epoch) {
+            const unsigned long long prev = atomicCAS(table + s, e, want);
+            if (prev == e) {
+                claimed = true;
+                return self;
+            }
+            e = prev;
+            continue;
+        }
+        if (static_cast<uint32_t>(e >> 32) == tag) {
+            const uint32_t rep = static_cast<uint32_t>(e);
+            if (rows_equal(sig, W, self, rep)) {
+                claimed = false;
+                return rep;
+            }
+        }
+        s = (s + 1) & mask;
+        e = load_entry(table + s, cached);
+    }
+}
+
+// Marks block `id` as having two or more members after round r.
+__device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_t tag) {
+    if (multi[id] != tag) multi[id] = tag;
+}
+
+// Counter words: [0] blocks after the round, [1] states not refined.
+__global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
+    if (p.ctl->done) return;
+    const uint32_t r = p.ctl->round;
+    const uint32_t epoch = r % kEpochs + 1;
+    uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
+    uint32_t blocks = 0, idle = 0;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        const size_t q = base + threadIdx.x;
+        const size_t first = base + (threadIdx.x & ~63u);
+        const unsigned long long am = first < p.N ? p.active[first >> 6] : 0ull;
+        const bool valid = q < p.N;
+        const bool act = valid && ((am >> lane_id()) & 1ull);
+        idle += (valid && !act) ? 1u : 0u;
+        if (!act) continue;
+        bool claimed = false;
+        const uint32_t id = find_or_claim(p.table, p.mask, epoch, p.hash[q],
+                                          static_cast<uint32_t>(q), p.sig, p.W,
+                                          p.cached_probe != 0, claimed);
+        Y[q] = id;
+        if (claimed)
+            ++blocks;
+        else
+            mark_multi(p.multi, id, r + 1);
+    }
+    wg_add_spread(p.counters, 0, blocks + idle);
+    wg_add_spread(p.counters, 1, idle);
+}
+
+// LDS-staged grouping: a workgroup first groups the refined states of its
+// tile of kBlock states in an LDS table (full-key compare), then only the
+// first state of each local group goes to the HBM table; the others copy its
+// result through LDS.
+constexpr uint32_t kLdsSlots = 2 * kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
+    __shared__ unsigned long long ltab[kLdsSlots];
+    __shared__ uint32_t gid[kBlock];
+    __shared__ uint32_t lsize[kBlock];
+    if (p.ctl->done) return;
+    const uint32_t r = p.ctl->round;
+    const uint32_t epoch = r % kEpochs + 1;
+    uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
+    const uint32_t tx = threadIdx.x;
+    uint32_t blocks = 0, idle = 0;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        const size_t q = base + tx;
+        const size_t first = base + (tx & ~63u);
+        const unsigned long long am = first < p.N ? p.active[first >> 6] : 0ull;
+        const bool valid = q < p.N;
+        const bool act = valid && ((am >> lane_id()) & 1ull);
+        idle += (valid && !act) ? 1u : 0u;
+        // whole tile idle: nothing to group (uniform across the workgroup)
+        if (__syncthreads_or(act) == 0) continue;
+        for (uint32_t i = tx; i < kLdsSlots; i += kBlock) ltab[i] = kEmptyPair;
+        lsize[tx] = 0;
+        __syncthreads();
+        const uint64_t h = act ? p.hash[q] : 0;
+        uint32_t lead = tx;
+        if (act) {
+            const uint32_t ltag = static_cast<uint32_t>(h >> 32);
+            uint32_t s = static_cast<uint32_t>(h) & (kLdsSlots - 1);
+            for (;;) {
+                unsigned long long e =
+                    __hip_atomic_load(ltab + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (e == kEmptyPair) {
+                    const unsigned long long want = (static_cast<unsigned long long>(ltag) << 32) | tx;
+                    const unsigned long long prev = atomicCAS(ltab + s, kEmptyPair, want);
+                    if (prev == kEmptyPair) {
+                        lead = tx;
+                        break;
+                    }
+                    e = prev;
+                }
+                if (static_cast<uint32_t>(e >> 32) == ltag) {
+                    const uint32_t other = static_cast<uint32_t>(e);
+                    if (rows_equal(p.sig, p.W, q, base + other)) {
+                        lead = other;
+                        break;
+                    }
+                }
+                s = (s + 1) & (kLdsSlots - 1);
+            }
+            atomicAdd(lsize + lead, 1u);
+        }
+        __syncthreads();
+        if (act && lead == tx) {
+            bool claimed = false;
+            const uint32_t id = find_or_claim(p.table, p.mask, epoch, h, static_cast<uint32_t>(q),
+                                              p.sig, p.W, p.cached_probe != 0, claimed);
+            gid[tx] = id;
+            if (claimed) ++blocks;
+            if (!claimed || lsize[tx] > 1) mark_multi(p.multi, id, r + 1);
+        }
+        __syncthreads();
+        if (act) Y[q] = gid[lead];
+        __syncthreads();
+    }
+    wg_add_spread(p.counters, 0, blocks + idle);
+    wg_add_spread(p.counters, 1, idle);
+}
+
+// One workgroup: the round's block count (spread counters), the stop tests,
+// and the counter reset.
+__global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint32_t *blockA,
+                                                       const uint32_t *blockB, uint32_t *counters,
+                                                       uint32_t N) {
+    __shared__ uint32_t red[2][kBlock / 64];
+    if (ctl->done) return;
+    const uint32_t r = ctl->round;
+    uint32_t c = 0, idle = 0;
+    for (uint32_t i = threadIdx.x; i < kSpread; i += kBlock) {
+        c += counters[i * kSpreadStride + 0];
+        idle += counters[i * kSpreadStride + 1];
+        counters[i * kSpreadStride + 0] = 0;
+        counters[i * kSpreadStride + 1] = 0;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        c += __shfl_xor(c, d, 64);
+        idle += __shfl_xor(idle, d, 64);
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / 64] = c;
+        red[1][threadIdx.x / 64] = idle;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    c = 0;
+    idle = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        c += red[0][w];
+        idle += red[1][w];
+    }
+    const uint32_t *out = (r & 1u) ? blockA : blockB;
+    ctl->last_gain = c - ctl->prev_count;
+    ctl->last_active = N - idle;
+    ctl->active_sum += N - idle;
+    if (c == ctl->prev_count) {
+        ctl->stable = 1;
+        ctl->done = 1;
+    } else {
+        ctl->changing += 1;
+        ctl->prev_count = c;
+    }
+    if (ctl->check_eq && out[ctl->eq_a] != out[ctl->eq_b]) {
+        ctl->separated = 1;
+        ctl->done = 1;
+    }
+    ctl->round = r + 1;
+    if (!ctl->done && ctl->max_rounds && r + 1 >= ctl->max_rounds) {
+        ctl->limit = 1;
+        ctl->done = 1;
+    }
+}
+
+// ---------------------------------------------------------------- pointer jumping
+
+__global__ __launch_bounds__(kBlock) void k_jump(uint32_t *__restrict__ cols, size_t N,
+                                                  uint32_t k, uint32_t level,
+                                                  uint32_t *diff, uint32_t *nonid) {
+    const uint32_t a = blockIdx.y;
+    const uint32_t *__restrict__ prev = cols + (static_cast<size_t>(level - 1) * k + a) * N;
+    uint32_t *__restrict__ cur = cols + (static_cast<size_t>(level) * k + a) * N;
+    bool d = false, moves = false;
+    for (size_t q = global_tid(); q < N; q += grid_stride()) {
+        const uint32_t m = prev[q];
+        const uint32_t t = prev[m];
+        cur[q] = t;
+        d |= t != m;
+        moves |= t != q;
+    }
+    wave_set_flag(diff + static_cast<size_t>(level) * k + a, d);
+    wave_set_flag(nonid + static_cast<size_t>(level) * k + a, moves);
+}
+
+// ---------------------------------------------------------------- canonical ids
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
+    for (size_t i = global_tid(); i < n; i += grid_stride()) p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_canon_min(const uint32_t *__restrict__ ids, size_t N,
+                                                       uint32_t *mins) {
+    for (size_t q = global_tid(); q < N; q += grid_stride())
+        atomicMin(mins + ids[q], static_cast<uint32_t>(q));
+}
+
+__global__ __launch_bounds__(kBlock) void k_canon_apply(const uint32_t *__restrict__ ids, size_t N,
+                                                         const uint32_t *__restrict__ mins,
+                                                         uint32_t *__restrict__ out) {
+    for (size_t q = global_tid(); q < N; q += grid_stride()) out[q] = mins[ids[q]];
+}
+
+// ---------------------------------------------------------------- dense leader numbering
+
+constexpr int kScanThreads = static_cast<int>(kScanTile);  // one element per thread
+
+// Per-tile leader counts: ballot of "block[q] == q" and popcount per wave.
+__global__ __launch_bounds__(kScanThreads) void k_leader_partials(const uint32_t *__restrict__ block,
+                                                                   size_t N, uint32_t *partials) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const size_t q = static_cast<size_t>(blockIdx.x) * kScanTile + threadIdx.x;
+    const bool lead = q < N && block[q] == q;
+    const unsigned long long m = __ballot(lead);
+    if (lane_id() == 0) wsum[threadIdx.x / 64] = static_cast<uint32_t>(__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) s += wsum[w];
+        partials[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of the tile counts in one workgroup; partials[ntiles] and
+// *total receive the sum.
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t *partials, uint32_t ntiles,
+                                                                 uint32_t *total) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < ntiles; base += kScanThreads) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < ntiles ? partials[i] : 0u;
+        // inclusive scan within the wave by shuffles
+        uint32_t x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (static_cast<int>(lane_id()) >= d) x += y;
+        }
+        if (lane_id() == 63) wsum[threadIdx.x / 64] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t s = 0;
+            for (int w = 0; w < kScanThreads / 64; ++w) {
+                const uint32_t t = wsum[w];
+                wsum[w] = s;
+                s += t;
+            }
+        }
+        __syncthreads();
+        const uint32_t excl = carry + wsum[threadIdx.x / 64] + x - v;
+        __syncthreads();
+        if (i < ntiles) partials[i] = excl;
+        if (threadIdx.x == kScanThreads - 1) carry = excl + v;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[ntiles] = carry;
+        *total = carry;
+    }
+}
+
+// dense[q] for leaders: tile offset + leaders before q in the tile (ballot
+// rank within the wave + wave offsets).
+__global__ __launch_bounds__(kScanThreads) void k_leader_rank(const uint32_t *__restrict__ block,
+                                                               size_t N,
+                                                               const uint32_t *__restrict__ partials,
+                                                               uint32_t *__restrict__ dense,
+                                                               uint32_t *__restrict__ leader_of) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const size_t q = static_cast<size_t>(blockIdx.x) * kScanTile + threadIdx.x;
+    const bool lead = q < N && block[q] == q;
+    const unsigned long long m = __ballot(lead);
+    const uint32_t lane = lane_id();
+    if (lane == 0) wsum[threadIdx.x / 64] = static_cast<uint32_t>(__popcll(m));
+    __syncthreads();
+    uint32_t woff = 0;
+    for (uint32_t w = 0; w < threadIdx.x / 64; ++w) woff += wsum[w];
+    if (lead) {
+        const unsigned long long below = lane ? (m & ((1ull << lane) - 1ull)) : 0ull;
+        const uint32_t d = partials[blockIdx.x] + woff + static_cast<uint32_t>(__popcll(below));
+        dense[q] = d;
+        leader_of[d] = static_cast<uint32_t>(q);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_quotient(const uint32_t *__restrict__ delta,
+                                                      const uint8_t *__restrict__ acc, uint32_t k,
+                                                      const uint32_t *__restrict__ block,
+                                                      const uint32_t *__restrict__ dense,
+                                                      const uint32_t *__restrict__ leader_of,
+                                                      const uint32_t *num_blocks, uint32_t start,
+                                                      uint32_t *__restrict__ qdelta,
+                                                      uint8_t *__restrict__ qacc, uint32_t *qstart) {
+    const uint32_t B = *num_blocks;
+    if (global_tid() == 0) *qstart = dense[block[start]];
+    for (size_t b = global_tid(); b < B; b += grid_stride()) {
+        const size_t l = leader_of[b];
+        for (uint32_t a = 0; a < k; ++a) qdelta[b * k + a] = dense[block[delta[l * k + a]]];
+        qacc[b] = acc[l] ? 1 : 0;
+    }
+}
+
+unsigned grid_for(size_t work, unsigned cap = 1u << 20) {
+    size_t g = (work + kBlock - 1) / kBlock;
+    if (g == 0) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<unsigned>(g);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+namespace {
+constexpr unsigned kDefaultGridCap = 8192;
+
+SigParams sig_params(const RoundArgs &a) {
+    return SigParams{a.cols,     a.colmap, a.N,      a.k_eff,    a.blockA,  a.blockB,
+                     a.sig,      a.hash,   a.table,  a.table_cap, a.multi, a.active,
+                     a.accbits,  a.presence, a.presence_packed, a.lab8, a.counters, a.ctl};
+}
+
+unsigned round_grid(const RoundArgs &a, unsigned cap) {
+    return grid_for(a.N, cap ? cap : (1u << 30));
+}
+
+void launch_round_end(const RoundArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(kBlock), 0, s, a.ctl, a.blockA, a.blockB,
+                       a.counters, static_cast<uint32_t>(a.N));
+}
+}  // namespace
+
+void launch_ingest(const uint32_t *delta, uint32_t n, uint32_t k, uint32_t *cols, size_t N,
+                   uint32_t offset, uint32_t target_offset, uint32_t *err, uint32_t *nonid,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_ingest, dim3(grid_for(n)), dim3(kBlock), 0, s, delta, n, k, cols, N,
+                       offset, target_offset, err, nonid);
+}
+
+void launch_init_blocks(const uint8_t *acc, uint32_t n, uint32_t offset, uint32_t *block,
+                        unsigned long long *accbits, uint32_t *class_flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_blocks, dim3(grid_for(n, kDefaultGridCap)), dim3(kBlock), 0, s, acc,
+                       n, offset, block, accbits, class_flags);
+}
+
+void launch_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t max_rounds,
+                      uint32_t check_eq, uint32_t eq_a, uint32_t eq_b, uint32_t pattern_first,
+                      uint32_t packed_second, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, class_flags, max_rounds,
+                       check_eq, eq_a, eq_b, pattern_first, packed_second);
+}
+
+void launch_ctl_resume(RoundCtl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, s, ctl);
+}
+
+void launch_pattern_round(const RoundArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_pattern_round, dim3(round_grid(a, a.pattern_grid_cap)), dim3(kBlock), 0,
+                       s, sig_params(a));
+    launch_round_end(a, s);
+}
+
+void launch_packed_round(const RoundArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_packed_round, dim3(round_grid(a, a.pattern_grid_cap)), dim3(kBlock), 0, s,
+                       sig_params(a));
+    launch_round_end(a, s);
+}
+
+void launch_round(const RoundArgs &a, hipStream_t s) {
+    const SigParams sp = sig_params(a);
+    const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
+    switch (a.k_eff) {
+        case 1: hipLaunchKernelGGL(k_signature<1>, grid, block, 0, s, sp); break;
+        case 2: hipLaunchKernelGGL(k_signature<2>, grid, block, 0, s, sp); break;
+        case 3: hipLaunchKernelGGL(k_signature<3>, grid, block, 0, s, sp); break;
+        case 4: hipLaunchKernelGGL(k_signature<4>, grid, block, 0, s, sp); break;
+        case 5: hipLaunchKernelGGL(k_signature<5>, grid, block, 0, s, sp); break;
+        case 6: hipLaunchKernelGGL(k_signature<6>, grid, block, 0, s, sp); break;
+        case 7: hipLaunchKernelGGL(k_signature<7>, grid, block, 0, s, sp); break;
+        case 8: hipLaunchKernelGGL(k_signature<8>, grid, block, 0, s, sp); break;
+        default: hipLaunchKernelGGL(k_signature<0>, grid, block, 0, s, sp); break;
+    }
+    const InsParams ip{a.sig,    a.hash,   a.N,     a.k_eff + 1, a.table,    a.table_cap - 1,
+                       a.blockA, a.blockB, a.multi, a.active,    a.counters, a.ctl,
+                       a.cached_probe};
+    if (a.lds_stage)
+        hipLaunchKernelGGL(k_insert_lds, grid, block, 0, s, ip);
+    else
+        hipLaunchKernelGGL(k_insert, grid, block, 0, s, ip);
+    launch_round_end(a, s);
+}
+
+void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t *diff,
+                 uint32_t *nonid, hipStream_t s) {
+    dim3 grid(grid_for(N, kDefaultGridCap), k);
+    hipLaunchKernelGGL(k_jump, grid, dim3(kBlock), 0, s, cols, N, k, level, diff, nonid);
+}
+
+void launch_canonicalise(const uint32_t *ids, size_t N, size_t id_range, uint32_t *scratch_min,
+                         uint32_t *out, hipStream_t s) {
+    const dim3 grid(grid_for(N)), block(kBlock);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(id_range, kDefaultGridCap)), block, 0, s,
+                       scratch_min, id_range, ~0u);
+    hipLaunchKernelGGL(k_canon_min, grid, block, 0, s, ids, N, scratch_min);
+    hipLaunchKernelGGL(k_canon_apply, grid, block, 0, s, ids, N, scratch_min, out);
+}
+
+void launch_dense_leaders(const uint32_t *block, size_t N, uint32_t *partials, uint32_t *dense,
+                          uint32_t *leader_of, uint32_t *num_blocks, hipStream_t s) {
+    const uint32_t ntiles = static_cast<uint32_t>((N + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_leader_partials, dim3(ntiles), dim3(kScanThreads), 0, s, block, N,
+                       partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, ntiles,
+                       num_blocks);
+    hipLaunchKernelGGL(k_leader_rank, dim3(ntiles), dim3(kScanThreads), 0, s, block, N, partials,
+                       dense, leader_of);
+}
+
+void launch_quotient(const uint32_t *delta, const uint8_t *acc, uint32_t k,
+                     const uint32_t *block, const uint32_t *dense, const uint32_t *leader_of,
+                     const uint32_t *num_blocks, uint32_t B_max, uint32_t start,
+                     uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart, hipStream_t s) {
+    hipLaunchKernelGGL(k_quotient, dim3(grid_for(B_max)), dim3(kBlock), 0, s, delta, acc, k, block,
+                       dense, leader_of, num_blocks, start, qdelta, qacc, qstart);
+}
+
+}  // namespace dfamin

@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function declared in include/dfamin.h, fills default options, and
+rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2508_20735_amd import binding as B
+from paper_2508_20735_amd import build as hip_build
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "dfamin.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfa_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not hip_build.is_built():
+        hip_build.build()
+    return B.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert B.EXPORTS == names
+
+
+def test_default_options(lib):
+    o = B.Options()
+    lib.dfa_options_default(ctypes.byref(o))
+    assert o.tc_mode == B.TC["auto"] and o.loop_mode == B.LOOP["graph"]
+    assert o.start == 0 and o.max_rounds == 0 and o.lds_stage == 1
+
+
+def test_struct_sizes_match_header():
+    # the binding's structures mirror the header's field by field
+    assert ctypes.sizeof(B.Options) == 40
+    assert ctypes.sizeof(B.Stats) == 32 + 3 * 8 + 2 * 8
+    assert ctypes.sizeof(B.View) == 12 + 4 + 16
+    assert ctypes.sizeof(B.Tuning) == 64
+
+
+def test_default_tuning(lib):
+    t = B.Tuning()
+    lib.dfa_tuning_default(ctypes.byref(t))
+    assert t.label_rounds == 2 and t.chunk >= 1 and t.cached_probe in (0, 1)
+
+
+def test_bad_arguments_rejected_on_host(lib):
+    d = np.zeros((4, 2), dtype=np.uint32)
+    a = np.zeros(4, dtype=np.uint8)
+    out = np.zeros(4, dtype=np.uint32)
+    # n == 0 and k == 0 are rejected before any device call
+    assert lib.dfa_minimise(0, 2, d.ctypes.data, a.ctypes.data, out.ctypes.data, None, None,
+                            None) == B.DFA_EINVAL
+    assert lib.dfa_minimise(4, 0, d.ctypes.data, a.ctypes.data, out.ctypes.data, None, None,
+                            None) == B.DFA_EINVAL
+    assert b"n and k" in lib.dfa_last_error()
+    assert lib.dfa_minimise(4, 2, None, a.ctypes.data, out.ctypes.data, None, None,
+                            None) == B.DFA_EINVAL
+    o = B.Options()
+    lib.dfa_options_default(ctypes.byref(o))
+    o.start = 4
+    assert lib.dfa_minimise(4, 2, d.ctypes.data, a.ctypes.data, out.ctypes.data, None,
+                            ctypes.byref(o), None) == B.DFA_EINVAL
+    o.start = 0
+    o.tc_mode = 7
+    assert lib.dfa_minimise(4, 2, d.ctypes.data, a.ctypes.data, out.ctypes.data, None,
+                            ctypes.byref(o), None) == B.DFA_EINVAL
+    va = B.View(4, 2, 0, d.ctypes.data, a.ctypes.data)
+    vb = B.View(4, 3, 0, d.ctypes.data, a.ctypes.data)
+    v = ctypes.c_int()
+    assert lib.dfa_equivalent(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v), None,
+                              None) == B.DFA_EINVAL
+    vb = B.View(4, 2, 9, d.ctypes.data, a.ctypes.data)
+    assert lib.dfa_included(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v), None, None,
+                            None) == B.DFA_EINVAL
+    assert b"start" in lib.dfa_last_error()

@@ -1,0 +1,380 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Partitions are compared element by element after canonical renumbering (block
+id = smallest state of the block), which both sides produce; round counts are
+compared with the oracle's Moore rounds (plain letters, or the closure letters
+built by Algorithm 5); verdicts with union-find Hopcroft-Karp and the oracle's
+product exploration.  Integer work: every comparison is exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_20735_amd import binding as B
+from paper_2508_20735_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+LOOPS = ["host", "chunk", "graph"]
+
+
+def _ref(d):
+    block, nb, rounds, changing = oracle.moore(d.delta, d.accepting)
+    return block, nb, rounds, changing
+
+
+def _ref_tc(d):
+    return oracle.minimise_tc(d.delta, d.accepting)
+
+
+def check_minimise(d, tc="off", loop="graph", lds=True, quotient=False, ref=None):
+    res = B.minimise(d.delta, d.accepting, tc=tc, loop=loop, lds_stage=lds, quotient=quotient,
+                     start=d.start)
+    block, nb, rounds, changing = ref if ref is not None else _ref(d)
+    np.testing.assert_array_equal(res.block, block)
+    st = res.stats
+    assert st["num_blocks"] == nb
+    if tc == "off":
+        assert st["changing_rounds"] == changing and st["rounds"] == rounds
+        assert st["tc_used"] == 0
+    if quotient:
+        qn, qd, qa, qs = oracle.quotient(d.delta, d.accepting, block, d.start)
+        gn, gd, ga, gs = res.quotient
+        assert gn == qn and gs == qs
+        np.testing.assert_array_equal(gd, qd)
+        np.testing.assert_array_equal(ga, qa)
+    return res
+
+
+# ---------------------------------------------------------------- small / ragged
+
+@pytest.mark.parametrize("n,k,p,seed", [
+    (1, 1, 0.5, 1), (2, 1, 0.5, 2), (3, 2, 0.5, 3), (63, 2, 0.3, 4), (64, 3, 0.5, 5),
+    (65, 2, 0.5, 6), (255, 4, 0.1, 7), (256, 2, 0.5, 8), (257, 5, 0.5, 9),
+    (1000, 3, 0.2, 10), (4097, 8, 0.4, 11), (12345, 9, 0.3, 12), (5000, 17, 0.5, 13),
+])
+@pytest.mark.parametrize("loop", LOOPS)
+def test_random_small(n, k, p, seed, loop):
+    d = W.random_dfa(n, k, p, seed)
+    check_minimise(d, tc="off", loop=loop, quotient=True)
+
+
+@pytest.mark.parametrize("lds", [True, False])
+def test_lds_and_global_grouping_agree(lds):
+    d = W.random_dfa(30000, 3, 0.3, 99)
+    # duplicate rows: many states share signatures, stressing the grouping
+    rng = np.random.default_rng(5)
+    src = rng.integers(0, d.n, 20000)
+    dst = rng.integers(0, d.n, 20000)
+    d.delta[dst] = d.delta[src]
+    d.accepting[dst] = d.accepting[src]
+    check_minimise(d, tc="off", loop="chunk", lds=lds, quotient=True)
+
+
+def test_config_small_all_modes():
+    """n = 10,000, k = 2, p = 0.5, seed 1."""
+    d = W.cfg_small()
+    ref = _ref(d)
+    for loop in LOOPS:
+        for tc in ("off", "auto"):
+            for lds in (True, False):
+                check_minimise(d, tc=tc, loop=loop, lds=lds, ref=ref)
+    res = check_minimise(d, tc="on", loop="graph", ref=ref)
+    block, nb, rounds, changing = _ref_tc(d)
+    assert res.stats["changing_rounds"] == changing and res.stats["tc_used"] == 1
+
+
+def test_degenerate_inputs():
+    # all accepting / none accepting: one block, one confirming round
+    for v in (0, 1):
+        d = W.random_dfa(777, 3, 0.5, 3)
+        d.accepting[:] = v
+        res = check_minimise(d, tc="off", quotient=True)
+        assert (res.block == 0).all() and res.stats["rounds"] == 1
+    # every letter the identity: the signature is the block id alone
+    n = 300
+    d = W.DFA(np.tile(np.arange(n, dtype=np.uint32)[:, None], (1, 3)),
+              (np.arange(n) % 3 == 0).astype(np.uint8), 0)
+    for tc in ("off", "on", "auto"):
+        res = check_minimise(d, tc=tc)
+        assert res.stats["k_eff"] == 0
+    # a single state
+    d = W.DFA(np.zeros((1, 4), dtype=np.uint32), np.ones(1, dtype=np.uint8), 0)
+    for tc in ("off", "on"):
+        check_minimise(d, tc=tc, quotient=True)
+
+
+def test_invalid_arguments():
+    d = W.random_dfa(100, 2, 0.5, 1)
+    bad = d.delta.copy()
+    bad[57, 1] = 100
+    with pytest.raises(B.DfaError) as e:
+        B.minimise(bad, d.accepting)
+    assert e.value.status == B.DFA_EINVAL
+    with pytest.raises(B.DfaError) as e:
+        B.minimise(d.delta, d.accepting, start=100)
+    assert e.value.status == B.DFA_EINVAL
+    other = W.random_dfa(50, 3, 0.5, 2)
+    with pytest.raises(B.DfaError) as e:
+        B.equivalent(d, other)
+    assert e.value.status == B.DFA_EINVAL
+    # the library is still usable afterwards
+    check_minimise(d)
+
+
+def test_max_rounds_limit():
+    d = W.fibonacci(12)  # 233 states, 231 refining rounds
+    with pytest.raises(B.DfaError) as e:
+        B.minimise(d.delta, d.accepting, tc="off", max_rounds=10)
+    assert e.value.status == B.DFA_ELIMIT
+
+
+def test_deterministic_repeats():
+    d = W.random_dfa(50000, 4, 0.1, 8)
+    first = B.minimise(d.delta, d.accepting, tc="off").block
+    for loop in LOOPS:
+        np.testing.assert_array_equal(B.minimise(d.delta, d.accepting, tc="off",
+                                                 loop=loop).block, first)
+
+
+# ---------------------------------------------------------------- the paper's families
+
+@pytest.mark.parametrize("i", [5, 8, 12, 16])
+def test_fibonacci(i):
+    d = W.fibonacci(i)
+    ref = _ref(d)
+    check_minimise(d, tc="off", loop="chunk", ref=ref)
+    res = check_minimise(d, tc="on", ref=ref)
+    _, _, _, changing_tc = _ref_tc(d)
+    assert res.stats["changing_rounds"] == changing_tc
+    check_minimise(d, tc="auto", ref=ref)
+
+
+@pytest.mark.parametrize("n", [2, 3, 8, 14])
+def test_bitsplitter(n):
+    d = W.bitsplitter(n)
+    res = check_minimise(d, tc="off", loop="graph")
+    assert res.stats["changing_rounds"] == n - 1
+    check_minimise(d, tc="on")
+
+
+def test_fig1_chain_closure():
+    d = W.fig1_chain()
+    res = check_minimise(d, tc="off", loop="host")
+    assert res.stats["changing_rounds"] == 8
+    res = check_minimise(d, tc="on")
+    _, _, _, changing_tc = _ref_tc(d)
+    assert res.stats["changing_rounds"] == changing_tc
+
+
+@pytest.mark.parametrize("M", [6, 10, 14])
+def test_chain_round_counts(M):
+    N = 2 ** M
+    d = W.chain_with_tail(N, 0, seed=0)
+    hb, nb = oracle.hopcroft(d.delta, d.accepting)
+    # closed forms (derived in the oracle tests): N - 2 plain rounds, M - 1 with the closure
+    ref = (hb, nb, N - 1, N - 2)
+    res = check_minimise(d, tc="off", loop="chunk", ref=ref)
+    assert res.stats["changing_rounds"] == N - 2
+    res = check_minimise(d, tc="on", ref=ref)
+    assert res.stats["changing_rounds"] == M - 1
+
+
+def test_chain_with_tail_medium_auto():
+    d = W.chain_with_tail(1 << 14, 1 << 14, seed=3)
+    hb, nb = oracle.hopcroft(d.delta, d.accepting)
+    for tc in ("on", "auto"):
+        res = B.minimise(d.delta, d.accepting, tc=tc)
+        np.testing.assert_array_equal(res.block, hb)
+        assert res.stats["tc_used"] == 1
+    tb, _, _, changing_tc = _ref_tc(d)
+    res = B.minimise(d.delta, d.accepting, tc="on")
+    assert res.stats["changing_rounds"] == changing_tc
+
+
+@pytest.mark.parametrize("i", [5, 12])
+def test_cycle_and_extended_bitsplitter(i):
+    for d in (W.cycle(i + 10), W.extended_bitsplitter(i)):
+        check_minimise(d, tc="off", quotient=True)
+        check_minimise(d, tc="auto")
+
+
+# ---------------------------------------------------------------- equivalence
+
+def test_equivalence_tiny_random_pairs():
+    rng = np.random.default_rng(7)
+    seen = {True: 0, False: 0}
+    for _ in range(300):
+        nA, nB, k = int(rng.integers(1, 6)), int(rng.integers(1, 6)), int(rng.integers(1, 3))
+        A = W.DFA(rng.integers(0, nA, (nA, k)).astype(np.uint32),
+                  rng.integers(0, 2, nA).astype(np.uint8), int(rng.integers(0, nA)))
+        Bd = W.DFA(rng.integers(0, nB, (nB, k)).astype(np.uint32),
+                   rng.integers(0, 2, nB).astype(np.uint8), int(rng.integers(0, nB)))
+        ref = oracle.equiv_hk(A.delta, A.accepting, A.start, Bd.delta, Bd.accepting, Bd.start)
+        got, _ = B.equivalent(A, Bd, loop="chunk")
+        assert got == ref
+        seen[ref] += 1
+    assert seen[True] > 10 and seen[False] > 10
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_equivalence_permuted_and_mutated(seed):
+    d = W.random_dfa(20000 + 1111 * seed, 2 + seed, 0.2, seed)
+    perm, _ = W.permuted_copy(d, seed + 10)
+    mut, _ = W.mutate_one(d, seed + 20)
+    for loop in LOOPS:
+        got, st = B.equivalent(d, perm, loop=loop)
+        assert got
+        got, _ = B.equivalent(d, mut, loop=loop)
+        assert got == oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting,
+                                      mut.start)
+
+
+def test_equivalence_families():
+    for d in (W.cycle(15), W.extended_bitsplitter(6), W.fibonacci(10)):
+        perm, _ = W.permuted_copy(d, 3)
+        assert B.equivalent(d, perm)[0]
+        assert B.equivalent(d, perm, tc="on")[0]
+    F, P = W.memory(8, True), W.memory(8, False)
+    assert not B.equivalent(F, P)[0]
+
+
+# ---------------------------------------------------------------- inclusion
+
+@pytest.mark.parametrize("n", [3, 5, 9, 12])
+def test_inclusion_memory_table5(n):
+    """Table 5: forgetful memory_n is included in perfect memory_n, and the
+    explored product has (2n+1) 2^(n-2) states; the converse fails."""
+    F, P = W.memory(n, True), W.memory(n, False)
+    ok, visited, _ = B.included(F, P)
+    ref_ok, ref_visited = oracle.product_bfs(F.delta, F.accepting, 0, P.delta, P.accepting, 0)
+    assert ok and ref_ok and visited == ref_visited
+    ok, _, _ = B.included(P, F)
+    assert not ok
+
+
+def test_inclusion_tiny_random_pairs():
+    rng = np.random.default_rng(11)
+    seen = {True: 0, False: 0}
+    for _ in range(300):
+        nA, nB, k = int(rng.integers(1, 6)), int(rng.integers(1, 6)), int(rng.integers(1, 3))
+        A = W.DFA(rng.integers(0, nA, (nA, k)).astype(np.uint32),
+                  rng.integers(0, 2, nA).astype(np.uint8), int(rng.integers(0, nA)))
+        Bd = W.DFA(rng.integers(0, nB, (nB, k)).astype(np.uint32),
+                   rng.integers(0, 2, nB).astype(np.uint8), int(rng.integers(0, nB)))
+        ref, ref_visited = oracle.product_bfs(A.delta, A.accepting, A.start, Bd.delta,
+                                              Bd.accepting, Bd.start)
+        got, visited, _ = B.included(A, Bd)
+        assert got == ref
+        if ref:
+            assert visited == ref_visited
+        seen[ref] += 1
+    assert seen[True] > 10 and seen[False] > 10
+
+
+def test_inclusion_self_products():
+    """Table 4: self-products of B'_n and C_n have 2^(n+1) and fib(n) pairs."""
+    d = W.extended_bitsplitter(10)
+    ok, visited, _ = B.included(d, d)
+    assert ok and visited == 2 ** 11
+    c = W.cycle(20)
+    ok, visited, _ = B.included(c, c)
+    assert ok and visited == W.fib_numbers(20)
+
+
+# ---------------------------------------------------------------- device API
+
+def test_device_api_matches_host_api():
+    import torch
+    d = W.random_dfa(70000, 4, 0.1, 31)
+    ref = _ref(d)
+    dev = torch.device("cuda:0")
+    delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
+    acc = torch.from_numpy(d.accepting).to(dev)
+    res = B.minimise_device(delta, acc, tc="off", quotient=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(res.block.cpu().numpy().view(np.uint32), ref[0])
+    qn, qd, qa, qs = oracle.quotient(d.delta, d.accepting, ref[0], 0)
+    gn, gd, ga, gs = res.quotient
+    assert gn == qn and gs == qs
+    np.testing.assert_array_equal(gd.cpu().numpy().view(np.uint32), qd)
+    np.testing.assert_array_equal(ga.cpu().numpy(), qa)
+    perm, _ = W.permuted_copy(d, 1)
+    pdelta = torch.from_numpy(perm.delta.view(np.int32)).to(dev)
+    pacc = torch.from_numpy(perm.accepting).to(dev)
+    assert B.equivalent_device(delta, acc, 0, pdelta, pacc, perm.start)[0]
+    ok, visited, _ = B.included_device(delta, acc, 0, pdelta, pacc, perm.start)
+    assert ok
+
+
+# ---------------------------------------------------------------- full-size workloads
+
+@pytest.fixture(scope="module")
+def large():
+    d = W.cfg_large()
+    block, nb, rounds, changing = oracle.moore(d.delta, d.accepting)
+    return d, (block, nb, rounds, changing)
+
+
+def test_config_large_minimise(large):
+    """n = 2^22, k = 4, p = 0.1: every state compared with the oracle."""
+    d, ref = large
+    for loop in ("graph", "host"):
+        res = check_minimise(d, tc="auto", loop=loop, ref=ref)
+        assert res.stats["tc_used"] == 0
+        assert res.stats["changing_rounds"] == ref[3]
+
+
+def test_config_large_equivalence(large):
+    d, _ = large
+    perm, _ = W.permuted_copy(d, W.CFG_LARGE_PERM_SEED)
+    mut, _ = W.mutate_one(d, W.CFG_LARGE_MUT_SEED)
+    assert B.equivalent(d, perm)[0]
+    expected = oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting, mut.start)
+    assert B.equivalent(d, mut)[0] == expected
+
+
+def test_config_chain_closure():
+    """Chain of 2^20 states plus a 2^20-state random tail: the closure path
+    (on and auto) against Hopcroft, and the closed-form round count of the
+    chain part (19 = log2(2^20) - 1) as a lower bound."""
+    d = W.cfg_chain()
+    hb, nb = oracle.hopcroft(d.delta, d.accepting)
+    for tc in ("on", "auto"):
+        res = B.minimise(d.delta, d.accepting, tc=tc)
+        np.testing.assert_array_equal(res.block, hb)
+        assert res.stats["num_blocks"] == nb == d.n
+    res = B.minimise(d.delta, d.accepting, tc="on")
+    assert res.stats["changing_rounds"] >= 19
+
+
+# ---------------------------------------------------------------- kernel variants
+
+@pytest.fixture
+def restore_tuning():
+    saved = B.get_tuning()
+    yield
+    B.set_tuning(**saved)
+
+
+@pytest.mark.parametrize("label_rounds", [0, 1, 2])
+@pytest.mark.parametrize("cached_probe", [0, 1])
+@pytest.mark.parametrize("grid_cap", [0, 64, 8192])
+def test_tuning_variants_agree(restore_tuning, label_rounds, cached_probe, grid_cap):
+    """Every launch shape and kernel variant gives the oracle's partition."""
+    B.set_tuning(label_rounds=label_rounds, cached_probe=cached_probe, round_grid_cap=grid_cap,
+                 label_grid_cap=grid_cap)
+    cases = [W.random_dfa(20011, 4, 0.1, 5), W.random_dfa(3001, 2, 0.5, 6),
+             W.random_dfa(5003, 7, 0.3, 7), W.fibonacci(11), W.bitsplitter(9)]
+    # stable after round 0 and after round 1 (label ids turned into state ids)
+    cases.append(W.DFA(np.array([[1], [1]], dtype=np.uint32), np.array([0, 1], np.uint8), 0))
+    cases.append(W.DFA(np.array([[2], [1], [2]], dtype=np.uint32), np.array([0, 0, 1], np.uint8), 0))
+    for d in cases:
+        for lds in (True, False):
+            check_minimise(d, tc="off", loop="chunk", lds=lds, quotient=True)
+    d = cases[0]
+    perm, _ = W.permuted_copy(d, 3)
+    assert B.equivalent(d, perm)[0]
+    mut, _ = W.mutate_one(d, 4)
+    assert B.equivalent(d, mut)[0] == oracle.equiv_hk(d.delta, d.accepting, 0, mut.delta,
+                                                     mut.accepting, mut.start)
