@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the partition-refinement hot path on one MI355X.
+
+One step = the whole path over one synthetic workload already resident in HBM:
+  * minimise a random complete DFA with n = 2^22 states, |Sigma| = 4,
+    acceptance p = 0.1 (seed 2): ingest, initial partition, signature rounds
+    (closure on demand), canonical block ids and the quotient DFA;
+  * decide its equivalence with a state-permuted copy (seed 20) and with a
+    copy where one transition is redirected (seed 21), by refining the
+    disjoint unions.
+The metric is transitions refined per second: the sum over the step's
+refinements of n * k_eff * rounds, divided by the step time.
+
+Prints one JSON line.  Kernel timing (HIP events inside the library, on the
+stream the kernels run on) gives the dominant kernel's average launch time
+for the roofline entry; the CPU baseline runs the sequential oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "transitions refined/sec (n·|Σ|·rounds/s) and achieved HBM GB/s; batched vs plain"
+UNIT = "transitions/s"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2508_20735_amd", "csrc", f)
+                  for f in ("refine_kernels.hip", "dfamin_internal.h")]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha1()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--loop", default="graph", choices=["host", "chunk", "graph"])
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing on the host cores")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the steps without per-kernel events (roofline omitted)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it is missing or the kernels changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha1") != kernel_source_digest():
+        return None
+    entry = t.get("kernels", {}).get(kernel)
+    if not entry:
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(d, perm):
+    """The oracle (sequential C, one thread) on a bounded sample of the same
+    workload: Moore signature refinement of the DFA and of its union with the
+    permuted copy.  Returns transitions refined per second."""
+    import oracle
+    t0 = time.perf_counter()
+    _, _, rounds_a, _ = oracle.moore(d.delta, d.accepting)
+    t1 = time.perf_counter()
+    ud, ua = oracle.union(d.delta, d.accepting, perm.delta, perm.accepting)
+    t2 = time.perf_counter()
+    _, _, rounds_u, _ = oracle.moore(ud, ua)
+    t3 = time.perf_counter()
+    work = d.n * d.k * rounds_a + 2 * d.n * d.k * rounds_u
+    secs = (t1 - t0) + (t3 - t2)
+    return {"value": work / secs, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": (f"Moore rounds on the n=2^22 DFA ({rounds_a} rounds) and on its union "
+                       f"with the permuted copy ({rounds_u} rounds), {secs:.1f} s")}
+
+
+def main() -> int:
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent DFAs would shard one queue per GPU)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2508_20735_amd import binding as B
+    from paper_2508_20735_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    B.load(build_if_missing=True)
+    dev = torch.device("cuda:0")
+
+    d = W.cfg_large()
+    perm, _ = W.permuted_copy(d, W.CFG_LARGE_PERM_SEED)
+    mut, _ = W.mutate_one(d, W.CFG_LARGE_MUT_SEED)
+
+    def to_dev(x):
+        return (torch.from_numpy(x.delta.view(np.int32)).to(dev),
+                torch.from_numpy(x.accepting).to(dev))
+
+    A_d, A_a = to_dev(d)
+    P_d, P_a = to_dev(perm)
+    M_d, M_a = to_dev(mut)
+    block = torch.empty(d.n, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    loop = "chunk" if not args.no_kernel_timing and args.loop == "graph" else args.loop
+
+    def step():
+        r = B.minimise_device(A_d, A_a, block, quotient=True, loop=loop)
+        e1, s1 = B.equivalent_device(A_d, A_a, d.start, P_d, P_a, perm.start, loop=loop)
+        e2, s2 = B.equivalent_device(A_d, A_a, d.start, M_d, M_a, mut.start, loop=loop)
+        if not e1:
+            raise RuntimeError("permuted copy reported inequivalent")
+        work = (r.stats["transitions_refined"] + s1["transitions_refined"]
+                + s2["transitions_refined"])
+        return work, (r.stats, s1, s2, e2)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if not args.no_kernel_timing:
+        B.profile_enable(True)
+    total = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        work, last = step()
+        total += work
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    kernels = {}
+    if not args.no_kernel_timing:
+        kernels = B.profile_read()
+        B.profile_enable(False)
+
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    stats_min, stats_perm, stats_mut, verdict_mut = last
+    out = {
+        "metric": METRIC,
+        "value": total / elapsed,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("random complete DFA n=2^22 |Sigma|=4 p=0.1 seed 2: minimise "
+                         "(+quotient) and equivalence vs permuted copy (seed 20) and vs "
+                         "one-transition mutation (seed 21)"),
+            "n": d.n, "k": d.k, "tc": "auto", "loop": loop,
+            "rounds": [stats_min["rounds"], stats_perm["rounds"], stats_mut["rounds"]],
+            "mutation_equivalent": bool(verdict_mut),
+            "device_ms": [round(stats_min["device_ms"], 3), round(stats_perm["device_ms"], 3),
+                          round(stats_mut["device_ms"], 3)],
+            "tuning": B.get_tuning(),
+        },
+    }
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+        kd = kernels[dom]
+        avg_s = kd["total_ms"] / kd["launches"] / 1e3
+        bytes_per_launch = kd["algorithmic_bytes"] / kd["launches"]
+        achieved = bytes_per_launch / avg_s / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom),
+            "avg_launch_us": avg_s * 1e6, "launches": kd["launches"],
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        }
+        out["kernels"] = {
+            k: {"launches": v["launches"], "avg_us": v["total_ms"] / v["launches"] * 1e3,
+                "share": v["total_ms"] / sum(x["total_ms"] for x in kernels.values()),
+                "algorithmic_GBps": (v["algorithmic_bytes"] / (v["total_ms"] / 1e3) / 1e9
+                                     if v["total_ms"] else 0.0)}
+            for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"])}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d, perm)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

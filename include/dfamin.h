@@ -78,8 +78,10 @@ typedef struct dfa_options {
     uint32_t start;       /* start state used for the quotient's start (default 0) */
     uint32_t max_rounds;  /* 0 = until stable */
     uint32_t chunk;       /* rounds per chunk in CHUNK/GRAPH mode (0 = library default) */
-    int32_t lds_stage;    /* 1 = pre-group keys in LDS before the global table (default),
-                             0 = insert every key into the global table */
+    int32_t lds_stage;    /* 1 = pre-group keys in LDS before the global table,
+                             0 = insert every key into the global table,
+                             2 = LDS only in rounds after one that formed at most one
+                                 block per eight refined states (default) */
     int32_t reserved[4];
 } dfa_options;
 
@@ -142,6 +144,26 @@ typedef struct dfa_tuning {
 void dfa_tuning_default(dfa_tuning *t);
 int dfa_get_tuning(dfa_tuning *t);
 int dfa_set_tuning(const dfa_tuning *t);
+
+/*
+ * Kernel timing for benchmarks.  While enabled on the current device, every
+ * launch of a round kernel (signature, grouping, round end, label rounds) is
+ * bracketed by HIP events on the library's stream, and chunks are launched
+ * without graphs.  dfa_profile_enable(1) also clears the totals.
+ * dfa_profile_read copies up to cap entries and sets *count to the number of
+ * kernels seen.  algorithmic_bytes sums, over the launches, the states the
+ * launch refined times the kernel's bytes per refined state (k = k_eff):
+ * signature 8k + 4, grouping 4, label rounds 5k + 5, round end 0.
+ */
+typedef struct dfa_kernel_time {
+    char name[32];
+    uint64_t launches;
+    double total_ms;
+    uint64_t algorithmic_bytes;
+} dfa_kernel_time;
+
+int dfa_profile_enable(int on);
+int dfa_profile_read(dfa_kernel_time *out, int cap, int *count);
 
 /*
  * Minimise one DFA (Section 2 problem statement; Section 3.3, Algorithm 4

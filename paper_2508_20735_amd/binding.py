@@ -64,6 +64,11 @@ class Tuning(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("algorithmic_bytes", ctypes.c_uint64)]
+
+
 class Quotient(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_void_p), ("accepting", ctypes.c_void_p),
                 ("num_blocks", ctypes.c_uint32), ("start", ctypes.c_uint32)]
@@ -77,7 +82,8 @@ class View(ctypes.Structure):
 EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
                   "dfa_equivalent", "dfa_equivalent_device", "dfa_included",
                   "dfa_included_device", "dfa_last_error", "dfa_device_info",
-                  "dfa_tuning_default", "dfa_get_tuning", "dfa_set_tuning"])
+                  "dfa_tuning_default", "dfa_get_tuning", "dfa_set_tuning",
+                  "dfa_profile_enable", "dfa_profile_read"])
 
 _lock = threading.Lock()
 _lib = None
@@ -126,9 +132,12 @@ def load(build_if_missing: bool = True):
         lib.dfa_tuning_default.restype = None
         lib.dfa_get_tuning.argtypes = [P(Tuning)]
         lib.dfa_set_tuning.argtypes = [P(Tuning)]
+        lib.dfa_profile_enable.argtypes = [i32]
+        lib.dfa_profile_read.argtypes = [P(KernelTime), i32, P(i32)]
         for fn in ("dfa_minimise", "dfa_minimise_device", "dfa_equivalent",
                    "dfa_equivalent_device", "dfa_included", "dfa_included_device",
-                   "dfa_device_info", "dfa_get_tuning", "dfa_set_tuning"):
+                   "dfa_device_info", "dfa_get_tuning", "dfa_set_tuning",
+                   "dfa_profile_enable", "dfa_profile_read"):
             getattr(lib, fn).restype = i32
         _lib = lib
         return lib
@@ -142,7 +151,7 @@ def _check(rc: int, allow=()) -> int:
 
 
 def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: int = 0,
-            chunk: int = 0, lds_stage: bool = True) -> Options:
+            chunk: int = 0, lds_stage=2) -> Options:
     o = Options()
     load().dfa_options_default(ctypes.byref(o))
     o.tc_mode = TC[tc]
@@ -150,7 +159,8 @@ def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: i
     o.start = start
     o.max_rounds = max_rounds
     o.chunk = chunk
-    o.lds_stage = 1 if lds_stage else 0
+    # True/False select always/never; 2 (the default) lets each round decide
+    o.lds_stage = int(lds_stage) if not isinstance(lds_stage, bool) else (1 if lds_stage else 0)
     return o
 
 
@@ -176,6 +186,24 @@ def set_tuning(**values) -> dict:
         setattr(t, key, int(value))
     _check(load().dfa_set_tuning(ctypes.byref(t)))
     return t.as_dict()
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (and clear) or stop per-kernel event timing in the library."""
+    _check(load().dfa_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel name: {launches, total_ms, algorithmic_bytes}} since profile_enable(True)."""
+    lib = load()
+    count = ctypes.c_int()
+    _check(lib.dfa_profile_read(None, 0, ctypes.byref(count)))
+    buf = (KernelTime * max(count.value, 1))()
+    _check(lib.dfa_profile_read(buf, count.value, ctypes.byref(count)))
+    return {buf[i].name.decode(): {"launches": int(buf[i].launches),
+                                   "total_ms": float(buf[i].total_ms),
+                                   "algorithmic_bytes": int(buf[i].algorithmic_bytes)}
+            for i in range(count.value)}
 
 
 def device_info() -> dict:
@@ -204,7 +232,7 @@ class MinimiseResult:
 
 
 def minimise(delta, accepting, *, tc: str = "auto", loop: str = "graph", start: int = 0,
-             max_rounds: int = 0, chunk: int = 0, lds_stage: bool = True,
+             max_rounds: int = 0, chunk: int = 0, lds_stage=2,
              quotient: bool = False) -> MinimiseResult:
     """dfa_minimise on host arrays."""
     d, a = _host_arrays(delta, accepting)
@@ -244,7 +272,7 @@ def _check_device_tensor(t, dtype_name: str, numel: int, what: str):
 
 
 def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop: str = "graph",
-                    start: int = 0, max_rounds: int = 0, chunk: int = 0, lds_stage: bool = True,
+                    start: int = 0, max_rounds: int = 0, chunk: int = 0, lds_stage=2,
                     quotient: bool = False, stream=None) -> MinimiseResult:
     """dfa_minimise_device on torch GPU tensors: delta int32/uint32 [n, k]
     (row-major), accepting uint8 [n]; block_out int32 [n] (allocated if None)."""
@@ -290,7 +318,7 @@ def _view_device(delta, accepting, start) -> View:
 
 
 def equivalent(A, B, *, tc: str = "auto", loop: str = "graph", max_rounds: int = 0,
-               chunk: int = 0, lds_stage: bool = True) -> tuple[bool, dict]:
+               chunk: int = 0, lds_stage=2) -> tuple[bool, dict]:
     """dfa_equivalent on two host DFAs (objects with delta, accepting, start)."""
     va, keep_a = _view_host(A)
     vb, keep_b = _view_host(B)
@@ -303,7 +331,7 @@ def equivalent(A, B, *, tc: str = "auto", loop: str = "graph", max_rounds: int =
 
 
 def equivalent_device(dA, accA, sA, dB, accB, sB, *, tc: str = "auto", loop: str = "graph",
-                      max_rounds: int = 0, chunk: int = 0, lds_stage: bool = True,
+                      max_rounds: int = 0, chunk: int = 0, lds_stage=2,
                       stream=None) -> tuple[bool, dict]:
     va = _view_device(dA, accA, sA)
     vb = _view_device(dB, accB, sB)

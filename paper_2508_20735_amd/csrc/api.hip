@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -98,6 +99,24 @@ struct Ctx {
     Buffer visited, visited2, front0, front1;
     hipGraphExec_t graph = nullptr;
     GraphKey graph_key{};
+    // kernel timing (dfa_profile_enable): event pairs around the round
+    // kernels, folded into per-kernel totals after every readback
+    bool profiling = false;
+    struct KernelTime {
+        uint64_t launches = 0;
+        double ms = 0;
+        uint64_t bytes = 0;
+    };
+    std::map<std::string, KernelTime> ktimes;
+    struct Pending {
+        const char *name;
+        size_t ev0, ev1;
+        uint32_t round;
+        uint32_t bytes_per_state;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> evpool;
+    size_t ev_used = 0;
 };
 
 constexpr int kMaxDevices = 64;
@@ -166,6 +185,89 @@ int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
     return DFA_OK;
 }
 
+// ---- kernel timing ----
+
+enum class Kern { Signature, Insert, RoundEnd, Pattern, Packed };
+
+int prof_event(Ctx &c, size_t &idx) {
+    if (c.ev_used == c.evpool.size()) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        c.evpool.push_back(e);
+    }
+    idx = c.ev_used++;
+    return DFA_OK;
+}
+
+// Algorithmic bytes per refined state of each round kernel (k = k_eff):
+//   signature  4k (column entries) + 4 (own block id) + 4k (successor ids)
+//   insert     4 (the new block id)
+//   pattern    4k (columns) + (k + 1) (acceptance of q and successors) + 4 (label)
+//   packed     4k (columns) + (k + 1) (byte labels) + 4 (label)
+uint32_t kern_bytes(Kern kind, uint32_t k_eff) {
+    switch (kind) {
+        case Kern::Signature: return 8 * k_eff + 4;
+        case Kern::Insert: return 4;
+        case Kern::Pattern:
+        case Kern::Packed: return 5 * k_eff + 5;
+        default: return 0;
+    }
+}
+
+const char *kern_name(Kern kind, const RoundArgs &a) {
+    switch (kind) {
+        case Kern::Signature: return "k_signature";
+        case Kern::Insert: return "k_insert";
+        case Kern::RoundEnd: return "k_round_end";
+        case Kern::Pattern: return "k_pattern_round";
+        default: return "k_packed_round";
+    }
+}
+
+// Launches one round kernel, bracketed by events when timing is on.
+int launch_kern(Ctx &c, Kern kind, const RoundArgs &a, uint32_t round) {
+    size_t e0 = 0, e1 = 0;
+    if (c.profiling) {
+        DFA_TRY(prof_event(c, e0));
+        HIP_TRY(hipEventRecord(c.evpool[e0], c.stream));
+    }
+    switch (kind) {
+        case Kern::Signature: launch_signature(a, c.stream); break;
+        case Kern::Insert: launch_insert(a, c.stream); break;
+        case Kern::RoundEnd: launch_round_end(a, c.stream); break;
+        case Kern::Pattern: launch_pattern_kernel(a, c.stream); break;
+        case Kern::Packed: launch_packed_kernel(a, c.stream); break;
+    }
+    if (c.profiling) {
+        DFA_TRY(prof_event(c, e1));
+        HIP_TRY(hipEventRecord(c.evpool[e1], c.stream));
+        c.pending.push_back({kern_name(kind, a), e0, e1, round, kern_bytes(kind, a.k_eff)});
+    }
+    return DFA_OK;
+}
+
+int launch_full_round(Ctx &c, const RoundArgs &a, uint32_t round) {
+    DFA_TRY(launch_kern(c, Kern::Signature, a, round));
+    DFA_TRY(launch_kern(c, Kern::Insert, a, round));
+    return launch_kern(c, Kern::RoundEnd, a, round);
+}
+
+// Folds the timed launches into the totals (the stream has been synchronised).
+int prof_collect(Ctx &c, const RoundCtl &ctl) {
+    for (const auto &p : c.pending) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c.evpool[p.ev0], c.evpool[p.ev1]));
+        auto &t = c.ktimes[p.name];
+        t.launches += 1;
+        t.ms += ms;
+        if (p.round < ctl.round && ctl.round - p.round <= kActiveHist)
+            t.bytes += static_cast<uint64_t>(ctl.active_hist[p.round % kActiveHist]) * p.bytes_per_state;
+    }
+    c.pending.clear();
+    c.ev_used = 0;
+    return DFA_OK;
+}
+
 // flags layout (uint32 words): [0] target >= n, [1] some state accepts,
 // [2] some state rejects, [3 .. 3+ncols) column is not the identity,
 // [3+ncols .. 3+2*ncols) column differs from the previous closure level.
@@ -218,8 +320,8 @@ int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
     return DFA_OK;
 }
 
-int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode) {
-    if (mode == DFA_LOOP_GRAPH) {
+int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t first_round) {
+    if (mode == DFA_LOOP_GRAPH && !c.profiling) {
         GraphKey key;
         std::memset(&key, 0, sizeof key);
         std::memcpy(&key.args, &ra, sizeof ra);
@@ -243,7 +345,7 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode) {
         }
         HIP_TRY(hipGraphLaunch(c.graph, c.stream));
     } else {
-        for (uint32_t i = 0; i < rounds; ++i) launch_round(ra, c.stream);
+        for (uint32_t i = 0; i < rounds; ++i) DFA_TRY(launch_full_round(c, ra, first_round + i));
         HIP_TRY(hipGetLastError());
     }
     return DFA_OK;
@@ -333,7 +435,8 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
                      pattern_first, packed_second, c.stream);
 
     const int mode = o.loop_mode;
-    const uint32_t chunk = o.chunk ? o.chunk : c.tune.chunk;
+    uint32_t chunk = o.chunk ? o.chunk : c.tune.chunk;
+    if (c.profiling) chunk = std::min(chunk, kActiveHist);
     uint32_t last_round = 0;
     unsigned long long last_active_sum = 0;
     bool tc_failed = false;
@@ -345,27 +448,41 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         if (first) {
             // rounds 0 (and 1) run on their own: label rounds when the
             // signatures are short enough
-            if (pattern_first)
-                launch_pattern_round(ra, c.stream);
-            else
-                launch_round(ra, c.stream);
-            if (packed_second) launch_packed_round(ra, c.stream);
+            if (pattern_first) {
+                DFA_TRY(launch_kern(c, Kern::Pattern, ra, 0));
+                DFA_TRY(launch_kern(c, Kern::RoundEnd, ra, 0));
+            } else {
+                DFA_TRY(launch_full_round(c, ra, 0));
+            }
+            if (packed_second) {
+                DFA_TRY(launch_kern(c, Kern::Packed, ra, 1));
+                DFA_TRY(launch_kern(c, Kern::RoundEnd, ra, 1));
+            }
             HIP_TRY(hipGetLastError());
             first = false;
         }
-        DFA_TRY(run_chunk(c, ra, mode == DFA_LOOP_HOST ? 1u : chunk, mode));
+        // rounds launched so far: the label rounds, then last_round onwards
+        const uint32_t next_round = std::max(last_round, res.label_rounds ? res.label_rounds : 1u);
+        DFA_TRY(run_chunk(c, ra, mode == DFA_LOOP_HOST ? 1u : chunk, mode, next_round));
         DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
         std::memcpy(&res.ctl, c.pinned, sizeof(RoundCtl));
+        if (c.profiling) DFA_TRY(prof_collect(c, res.ctl));
         const uint32_t done_rounds = res.ctl.round - last_round;
         res.transitions += static_cast<uint64_t>(done_rounds) * N * k_eff;
         res.bytes += (res.ctl.active_sum - last_active_sum) * (8ull * k_eff + 8ull);
         last_round = res.ctl.round;
         last_active_sum = res.ctl.active_sum;
         if (res.ctl.done) break;
-        // closure on demand: progress has stalled relative to what is left
+        // closure on demand: over the last four rounds no round added more
+        // than 1/4096 of the states still to be separated (the chain-like
+        // regime where plain rounds each split only a few blocks)
         const uint64_t left = N - res.ctl.prev_count;
-        if (o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed && res.ctl.round >= 4 &&
-            left >= 4096 && static_cast<uint64_t>(res.ctl.last_gain) * 1024 < left) {
+        uint64_t recent_gain = 0;
+        for (uint32_t i = 1; i <= 4 && i <= res.ctl.round; ++i)
+            recent_gain = std::max<uint64_t>(
+                recent_gain, res.ctl.gain_hist[(res.ctl.round - i) % kActiveHist]);
+        if (o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed && res.ctl.round >= 8 &&
+            left >= 4096 && recent_gain * 4096 < left) {
             std::vector<uint32_t> tcmap;
             uint32_t levels = 0;
             int rc = build_closure(c, N, k, tcmap, levels);
@@ -388,10 +505,13 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     uint32_t rounds_run = res.ctl.round;
     if (state_ids && res.ctl.stable && res.ctl.round <= res.label_rounds) {
         launch_ctl_resume(ctl, c.stream);
-        launch_round(make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second), c.stream);
+        DFA_TRY(launch_full_round(c, make_round_args(c, cols, N, k_eff, cap, o.lds_stage,
+                                                     packed_second),
+                                  res.ctl.round));
         HIP_TRY(hipGetLastError());
         DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
         const RoundCtl *after = reinterpret_cast<const RoundCtl *>(c.pinned);
+        if (c.profiling) DFA_TRY(prof_collect(c, *after));
         if (!after->stable || after->prev_count != res.ctl.prev_count)
             return fail(DFA_EDEVICE, "internal: relabelling round changed the partition");
         rounds_run = after->round;
@@ -418,6 +538,7 @@ int check_options(const dfa_options &o) {
     if (o.tc_mode < DFA_TC_OFF || o.tc_mode > DFA_TC_AUTO) return fail(DFA_EINVAL, "bad tc_mode");
     if (o.loop_mode < DFA_LOOP_HOST || o.loop_mode > DFA_LOOP_GRAPH)
         return fail(DFA_EINVAL, "bad loop_mode");
+    if (o.lds_stage < 0 || o.lds_stage > 2) return fail(DFA_EINVAL, "bad lds_stage");
     return DFA_OK;
 }
 
@@ -459,17 +580,25 @@ int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const u
     if (rc != DFA_OK) return rc;
     launch_canonicalise(r.final_block, n, id_range, c.canon.as<uint32_t>(), block_out, c.stream);
     if (q) {
-        const size_t ntiles = (static_cast<size_t>(n) + kScanTile - 1) / kScanTile;
-        DFA_TRY(c.partials.ensure((ntiles + 1) * sizeof(uint32_t), "scan partials"));
-        DFA_TRY(c.dense.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "dense ids"));
-        DFA_TRY(c.leader_of.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "leaders"));
         DFA_TRY(c.scalars.ensure(16 * sizeof(uint32_t), "scalars"));
         uint32_t *sc = c.scalars.as<uint32_t>();
-        launch_dense_leaders(block_out, n, c.partials.as<uint32_t>(), c.dense.as<uint32_t>(),
-                             c.leader_of.as<uint32_t>(), sc, c.stream);
-        launch_quotient(delta, acc, k, block_out, c.dense.as<uint32_t>(),
-                        c.leader_of.as<uint32_t>(), sc, n, o.start, q->delta, q->accepting,
-                        sc + 1, c.stream);
+        if (r.ctl.prev_count == n) {
+            // every block is one state: the quotient is the input itself
+            HIP_TRY(hipMemsetD32Async(sc, n, 1, c.stream));
+            launch_quotient_identity(delta, acc, n, k, o.start, q->delta, q->accepting, sc + 1,
+                                     c.stream);
+        } else {
+            const size_t ntiles = (static_cast<size_t>(n) + kScanTile - 1) / kScanTile;
+            DFA_TRY(c.partials.ensure((ntiles + 1) * sizeof(uint32_t), "scan partials"));
+            DFA_TRY(c.dense.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "dense ids"));
+            DFA_TRY(c.leader_of.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "leaders"));
+            launch_dense_leaders(block_out, n, c.partials.as<uint32_t>(), c.dense.as<uint32_t>(),
+                                 c.leader_of.as<uint32_t>(), sc, c.stream);
+            // the canonicalisation scratch is free again: it holds dq
+            launch_quotient(delta, acc, k, block_out, c.dense.as<uint32_t>(),
+                            c.leader_of.as<uint32_t>(), sc, n, o.start, c.canon.as<uint32_t>(),
+                            q->delta, q->accepting, sc + 1, c.stream);
+        }
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
@@ -656,6 +785,39 @@ using namespace dfamin;
 
 extern "C" {
 
+int dfa_profile_enable(int on) {
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    c->profiling = on != 0;
+    c->ktimes.clear();
+    c->pending.clear();
+    c->ev_used = 0;
+    return DFA_OK;
+}
+
+int dfa_profile_read(dfa_kernel_time *out, int cap, int *count) {
+    if (!count || (cap > 0 && !out)) return fail(DFA_EINVAL, "NULL profile buffer");
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    int i = 0;
+    for (const auto &kv : c->ktimes) {
+        if (i < cap) {
+            std::memset(&out[i], 0, sizeof out[i]);
+            std::snprintf(out[i].name, sizeof out[i].name, "%s", kv.first.c_str());
+            out[i].launches = kv.second.launches;
+            out[i].total_ms = kv.second.ms;
+            out[i].algorithmic_bytes = kv.second.bytes;
+        }
+        ++i;
+    }
+    *count = i;
+    return DFA_OK;
+}
+
 void dfa_tuning_default(dfa_tuning *t) {
     if (!t) return;
     std::memset(t, 0, sizeof *t);
@@ -697,7 +859,7 @@ void dfa_options_default(dfa_options *opt) {
     opt->start = 0;
     opt->max_rounds = 0;
     opt->chunk = 0;
-    opt->lds_stage = 1;
+    opt->lds_stage = 2;
 }
 
 const char *dfa_last_error(void) { return g_last_error.c_str(); }

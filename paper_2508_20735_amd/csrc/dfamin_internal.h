@@ -33,6 +33,7 @@ constexpr int kSpread = 64;        // per-round counters, one per 128-byte line
 constexpr int kSpreadStride = 32;  // uint32 words between two counters
 constexpr uint32_t kPatternMaxBits = 16;  // first round by bit patterns if k_eff + 1 <= 16
 constexpr uint32_t kPackedMaxBits = 25;   // round 1 by packed labels if (k_eff + 1)^2 <= 25
+constexpr uint32_t kActiveHist = 64;      // rounds of refined-state counts kept in RoundCtl
 
 // Round-loop state kept on the device so that rounds can be enqueued (or
 // replayed from a graph) without the host in the loop.
@@ -53,6 +54,9 @@ struct RoundCtl {
     uint32_t all_active_until;  // rounds <= this refine every state
     uint32_t last_active;    // states refined by the last round
     unsigned long long active_sum;  // states refined, summed over rounds
+    uint32_t active_hist[kActiveHist];  // states refined by round r, at r % kActiveHist
+    uint32_t gain_hist[kActiveHist];    // blocks added by round r, at r % kActiveHist
+    uint32_t last_claims;               // blocks formed among the refined states
 };
 
 // ---- launchers (defined in refine_kernels.hip); all enqueue on `s` ----
@@ -98,13 +102,20 @@ struct RoundArgs {
     uint32_t *presence_packed;  // 2^kPackedMaxBits bits, zero between calls
     uint8_t *lab8;       // round-0 labels as bytes (packed round 1 only)
     RoundCtl *ctl;
-    int lds_stage;
+    int lds_stage;              // 0 never, 1 always, 2 when the last round grouped >= 8 states per block
     uint32_t round_grid_cap;    // workgroups of the round kernels (0 = one per 256 states)
     uint32_t pattern_grid_cap;  // workgroups of the label rounds
     uint32_t cached_probe;      // probe the table with cached loads first
     uint32_t pad;
 };
 void launch_round(const RoundArgs &a, hipStream_t s);
+// The three launches of launch_round, separately (for kernel timing).
+void launch_signature(const RoundArgs &a, hipStream_t s);
+void launch_insert(const RoundArgs &a, hipStream_t s);
+void launch_round_end(const RoundArgs &a, hipStream_t s);
+// The label-round kernels without their round end.
+void launch_pattern_kernel(const RoundArgs &a, hipStream_t s);
+void launch_packed_kernel(const RoundArgs &a, hipStream_t s);
 // Round 0 from acceptance bit patterns (requires k_eff + 1 <= kPatternMaxBits).
 void launch_pattern_round(const RoundArgs &a, hipStream_t s);
 // Round 1 from the packed round-0 labels of q and its successors (requires
@@ -131,11 +142,15 @@ void launch_dense_leaders(const uint32_t *block, size_t N, uint32_t *partials, u
                           uint32_t *leader_of, uint32_t *num_blocks, hipStream_t s);
 
 // qdelta[b*k + a] = dense[block[delta[l*k + a]]], qacc[b] = acc[l] for
-// l = leader_of[b]; *qstart = dense[block[start]].
+// l = leader_of[b]; *qstart = dense[block[start]].  dq: n words of scratch.
 void launch_quotient(const uint32_t *delta, const uint8_t *acc, uint32_t k,
                      const uint32_t *block, const uint32_t *dense, const uint32_t *leader_of,
-                     const uint32_t *num_blocks, uint32_t B_max, uint32_t start,
+                     const uint32_t *num_blocks, uint32_t n, uint32_t start, uint32_t *dq,
                      uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart, hipStream_t s);
+// Quotient of a discrete partition (num_blocks == n): a copy of the input.
+void launch_quotient_identity(const uint32_t *delta, const uint8_t *acc, uint32_t n, uint32_t k,
+                              uint32_t start, uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart,
+                              hipStream_t s);
 
 // ---- product exploration (product_kernels.hip) ----
 struct ProductArgs {

@@ -243,27 +243,59 @@ __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
 // Round 1 after a pattern round when (k_eff + 1)^2 <= kPackedMaxBits: the
 // signature (label of q, labels of its successors) packs exactly into one
 // word, which becomes the new label.  Labels are gathered from the byte copy
-// written by round 0 (small enough to stay in L2); distinct labels are
-// counted by first setters in a presence bitmap.
+// written by round 0 (small enough to stay in L2).  Distinct labels are
+// counted by first setters in a presence bitmap; each tile of kBlock states
+// first removes its own duplicates in an LDS set, so a frequent label costs
+// one bitmap access per tile, not one per state.
+constexpr uint32_t kLdsSlots = 2 * kBlock;
+
 __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
+    __shared__ uint32_t lset[kLdsSlots];
     if (p.ctl->done) return;
     const uint32_t r = p.ctl->round;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
     const uint32_t bits = p.k_eff + 1;
+    const uint32_t tx = threadIdx.x;
     uint32_t fresh = 0;
-    for (size_t q = global_tid(); q < p.N; q += grid_stride()) {
-        uint32_t key = p.lab8[q];
-        for (uint32_t j = 0; j < p.k_eff; ++j) {
-            const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
-            key |= static_cast<uint32_t>(p.lab8[t]) << (bits * (j + 1));
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        for (uint32_t i = tx; i < kLdsSlots; i += kBlock) lset[i] = ~0u;
+        __syncthreads();
+        const size_t q = base + tx;
+        bool first = false;
+        uint32_t key = 0;
+        if (q < p.N) {
+            key = p.lab8[q];
+            for (uint32_t j = 0; j < p.k_eff; ++j) {
+                const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+                key |= static_cast<uint32_t>(p.lab8[t]) << (bits * (j + 1));
+            }
+            Y[q] = key;
+            // keys are < 2^kPackedMaxBits, so ~0u marks an empty LDS slot
+            uint32_t slot = (key * 0x9E3779B1u) >> 23;  // 9 bits
+            for (;;) {
+                const uint32_t e =
+                    __hip_atomic_load(lset + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (e == key) break;
+                if (e == ~0u) {
+                    const uint32_t prev = atomicCAS(lset + slot, ~0u, key);
+                    if (prev == ~0u) {
+                        first = true;
+                        break;
+                    }
+                    if (prev == key) break;
+                }
+                slot = (slot + 1) & (kLdsSlots - 1);
+            }
         }
-        Y[q] = key;
-        uint32_t *word = p.presence_packed + (key >> 5);
-        const uint32_t bit = 1u << (key & 31);
-        // a cached read first: only a word that does not show the bit yet
-        // needs the atomic (which is exact either way)
-        if (!(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) & bit))
-            fresh += (atomicOr(word, bit) & bit) ? 0u : 1u;
+        if (first) {
+            uint32_t *word = p.presence_packed + (key >> 5);
+            const uint32_t bit = 1u << (key & 31);
+            const uint32_t seen =
+                __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!(seen & bit)) fresh += (atomicOr(word, bit) & bit) ? 0u : 1u;
+        }
+        __syncthreads();
     }
     wg_add_spread(p.counters, 0, fresh);
 }
@@ -287,6 +319,51 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
     // the table is cleared every kEpochs rounds (its entries carry the epoch)
     if (r > 0 && r % kEpochs == 0) {
         for (size_t i = global_tid(); i < p.table_cap; i += grid_stride()) p.table[i] = 0ull;
+    }
+
+    if constexpr (KC > 0) {
+        if (all) {
+            // every state is refined: two states per thread, all independent
+            // loads issued before their values are used
+            for (size_t base = static_cast<size_t>(blockIdx.x) * (2 * kBlock); base < p.N;
+                 base += static_cast<size_t>(gridDim.x) * (2 * kBlock)) {
+                const size_t q[2] = {base + threadIdx.x, base + kBlock + threadIdx.x};
+                bool v[2];
+                uint32_t w0[2], t[2][KC], w[2][KC];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    v[i] = q[i] < p.N;
+                    const size_t first = q[i] - lane_id();
+                    const unsigned long long am = __ballot(v[i]);
+                    if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    w0[i] = v[i] ? X[q[i]] : 0u;
+#pragma unroll
+                    for (int j = 0; j < KC; ++j)
+                        t[i][j] = v[i] ? p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q[i]] : 0u;
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) w[i][j] = v[i] ? X[t[i][j]] : 0u;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    if (!v[i]) continue;
+                    uint32_t *__restrict__ row = p.sig + q[i] * W;
+                    row[0] = w0[i];
+                    uint64_t h = mix_step(kHashSeed, w0[i]);
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) {
+                        row[1 + j] = w[i][j];
+                        h = mix_step(h, w[i][j]);
+                    }
+                    p.hash[q[i]] = mix_final(h);
+                }
+            }
+            return;
+        }
     }
 
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
@@ -351,6 +428,7 @@ struct InsParams {
     uint32_t *counters;
     const RoundCtl *ctl;
     uint32_t cached_probe;
+    int lds_stage;
 };
 
 __device__ __forceinline__ bool rows_equal(const uint32_t *__restrict__ sig, size_t W, size_t a,
@@ -410,9 +488,19 @@ __device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_
     if (multi[id] != tag) multi[id] = tag;
 }
 
+// Whether this round stages keys in LDS (uniform across the grid).
+__device__ __forceinline__ bool stage_in_lds(const InsParams &p) {
+    if (p.lds_stage == 1) return true;
+    if (p.lds_stage != 2) return false;
+    const RoundCtl *c = p.ctl;
+    // the round after the initial partition, or a previous round that formed
+    // at most one block per eight refined states
+    return c->round == 0 || static_cast<uint64_t>(c->last_claims) * 8 <= c->last_active;
+}
+
 // Counter words: [0] blocks after the round, [1] states not refined.
 __global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
-    if (p.ctl->done) return;
+    if (p.ctl->done || stage_in_lds(p)) return;
     const uint32_t r = p.ctl->round;
     const uint32_t epoch = r % kEpochs + 1;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
@@ -444,13 +532,12 @@ __global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
 // tile of kBlock states in an LDS table (full-key compare), then only the
 // first state of each local group goes to the HBM table; the others copy its
 // result through LDS.
-constexpr uint32_t kLdsSlots = 2 * kBlock;
 
 __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
     __shared__ unsigned long long ltab[kLdsSlots];
     __shared__ uint32_t gid[kBlock];
     __shared__ uint32_t lsize[kBlock];
-    if (p.ctl->done) return;
+    if (p.ctl->done || !stage_in_lds(p)) return;
     const uint32_t r = p.ctl->round;
     const uint32_t epoch = r % kEpochs + 1;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
@@ -549,7 +636,10 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint3
     const uint32_t *out = (r & 1u) ? blockA : blockB;
     ctl->last_gain = c - ctl->prev_count;
     ctl->last_active = N - idle;
+    ctl->last_claims = c - idle;
     ctl->active_sum += N - idle;
+    ctl->active_hist[r % kActiveHist] = N - idle;
+    ctl->gain_hist[r % kActiveHist] = c - ctl->prev_count;
     if (c == ctl->prev_count) {
         ctl->stable = 1;
         ctl->done = 1;
@@ -691,21 +781,45 @@ __global__ __launch_bounds__(kScanThreads) void k_leader_rank(const uint32_t *__
     }
 }
 
+// dq[q] = dense id of q's block.
+__global__ __launch_bounds__(kBlock) void k_dense_of_state(const uint32_t *__restrict__ block,
+                                                            const uint32_t *__restrict__ dense,
+                                                            size_t N, uint32_t *__restrict__ dq) {
+    for (size_t q = global_tid(); q < N; q += grid_stride()) dq[q] = dense[block[q]];
+}
+
+// One thread per quotient transition (b, a): qdelta[b*k + a] = dq[delta(l, a)]
+// with l the leader of block b; qacc[b] = accepting[l] as 0/1.
 __global__ __launch_bounds__(kBlock) void k_quotient(const uint32_t *__restrict__ delta,
                                                       const uint8_t *__restrict__ acc, uint32_t k,
-                                                      const uint32_t *__restrict__ block,
-                                                      const uint32_t *__restrict__ dense,
+                                                      const uint32_t *__restrict__ dq,
                                                       const uint32_t *__restrict__ leader_of,
                                                       const uint32_t *num_blocks, uint32_t start,
                                                       uint32_t *__restrict__ qdelta,
                                                       uint8_t *__restrict__ qacc, uint32_t *qstart) {
-    const uint32_t B = *num_blocks;
-    if (global_tid() == 0) *qstart = dense[block[start]];
-    for (size_t b = global_tid(); b < B; b += grid_stride()) {
+    const size_t total = static_cast<size_t>(*num_blocks) * k;
+    if (global_tid() == 0) *qstart = dq[start];
+    for (size_t i = global_tid(); i < total; i += grid_stride()) {
+        const size_t b = i / k;
+        const uint32_t a = static_cast<uint32_t>(i - b * k);
         const size_t l = leader_of[b];
-        for (uint32_t a = 0; a < k; ++a) qdelta[b * k + a] = dense[block[delta[l * k + a]]];
-        qacc[b] = acc[l] ? 1 : 0;
+        qdelta[i] = dq[delta[l * k + a]];
+        if (a == 0) qacc[b] = acc[l] ? 1 : 0;
     }
+}
+
+// Discrete partition (every block a single state): the quotient is the input.
+__global__ __launch_bounds__(kBlock) void k_quotient_identity(const uint32_t *__restrict__ delta,
+                                                               const uint8_t *__restrict__ acc,
+                                                               size_t n, uint32_t k,
+                                                               uint32_t start,
+                                                               uint32_t *__restrict__ qdelta,
+                                                               uint8_t *__restrict__ qacc,
+                                                               uint32_t *qstart) {
+    if (global_tid() == 0) *qstart = start;
+    const size_t total = n * k;
+    for (size_t i = global_tid(); i < total; i += grid_stride()) qdelta[i] = delta[i];
+    for (size_t q = global_tid(); q < n; q += grid_stride()) qacc[q] = acc[q] ? 1 : 0;
 }
 
 unsigned grid_for(size_t work, unsigned cap = 1u << 20) {
@@ -732,10 +846,6 @@ unsigned round_grid(const RoundArgs &a, unsigned cap) {
     return grid_for(a.N, cap ? cap : (1u << 30));
 }
 
-void launch_round_end(const RoundArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(kBlock), 0, s, a.ctl, a.blockA, a.blockB,
-                       a.counters, static_cast<uint32_t>(a.N));
-}
 }  // namespace
 
 void launch_ingest(const uint32_t *delta, uint32_t n, uint32_t k, uint32_t *cols, size_t N,
@@ -762,19 +872,32 @@ void launch_ctl_resume(RoundCtl *ctl, hipStream_t s) {
     hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, s, ctl);
 }
 
-void launch_pattern_round(const RoundArgs &a, hipStream_t s) {
+void launch_round_end(const RoundArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(kBlock), 0, s, a.ctl, a.blockA, a.blockB,
+                       a.counters, static_cast<uint32_t>(a.N));
+}
+
+void launch_pattern_kernel(const RoundArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_pattern_round, dim3(round_grid(a, a.pattern_grid_cap)), dim3(kBlock), 0,
                        s, sig_params(a));
+}
+
+void launch_packed_kernel(const RoundArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_packed_round, dim3(round_grid(a, a.pattern_grid_cap)), dim3(kBlock), 0, s,
+                       sig_params(a));
+}
+
+void launch_pattern_round(const RoundArgs &a, hipStream_t s) {
+    launch_pattern_kernel(a, s);
     launch_round_end(a, s);
 }
 
 void launch_packed_round(const RoundArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_packed_round, dim3(round_grid(a, a.pattern_grid_cap)), dim3(kBlock), 0, s,
-                       sig_params(a));
+    launch_packed_kernel(a, s);
     launch_round_end(a, s);
 }
 
-void launch_round(const RoundArgs &a, hipStream_t s) {
+void launch_signature(const RoundArgs &a, hipStream_t s) {
     const SigParams sp = sig_params(a);
     const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
     switch (a.k_eff) {
@@ -788,13 +911,22 @@ void launch_round(const RoundArgs &a, hipStream_t s) {
         case 8: hipLaunchKernelGGL(k_signature<8>, grid, block, 0, s, sp); break;
         default: hipLaunchKernelGGL(k_signature<0>, grid, block, 0, s, sp); break;
     }
+}
+
+void launch_insert(const RoundArgs &a, hipStream_t s) {
+    const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
     const InsParams ip{a.sig,    a.hash,   a.N,     a.k_eff + 1, a.table,    a.table_cap - 1,
                        a.blockA, a.blockB, a.multi, a.active,    a.counters, a.ctl,
-                       a.cached_probe};
-    if (a.lds_stage)
-        hipLaunchKernelGGL(k_insert_lds, grid, block, 0, s, ip);
-    else
-        hipLaunchKernelGGL(k_insert, grid, block, 0, s, ip);
+                       a.cached_probe, a.lds_stage};
+    // the two grouping variants; exactly one of them works in a given round
+    // (lds_stage 2 decides on the device from the previous round)
+    if (a.lds_stage != 0) hipLaunchKernelGGL(k_insert_lds, grid, block, 0, s, ip);
+    if (a.lds_stage != 1) hipLaunchKernelGGL(k_insert, grid, block, 0, s, ip);
+}
+
+void launch_round(const RoundArgs &a, hipStream_t s) {
+    launch_signature(a, s);
+    launch_insert(a, s);
     launch_round_end(a, s);
 }
 
@@ -826,10 +958,21 @@ void launch_dense_leaders(const uint32_t *block, size_t N, uint32_t *partials, u
 
 void launch_quotient(const uint32_t *delta, const uint8_t *acc, uint32_t k,
                      const uint32_t *block, const uint32_t *dense, const uint32_t *leader_of,
-                     const uint32_t *num_blocks, uint32_t B_max, uint32_t start,
+                     const uint32_t *num_blocks, uint32_t n, uint32_t start, uint32_t *dq,
                      uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart, hipStream_t s) {
-    hipLaunchKernelGGL(k_quotient, dim3(grid_for(B_max)), dim3(kBlock), 0, s, delta, acc, k, block,
-                       dense, leader_of, num_blocks, start, qdelta, qacc, qstart);
+    hipLaunchKernelGGL(k_dense_of_state, dim3(grid_for(n, kDefaultGridCap)), dim3(kBlock), 0, s,
+                       block, dense, static_cast<size_t>(n), dq);
+    hipLaunchKernelGGL(k_quotient, dim3(grid_for(static_cast<size_t>(n) * k, kDefaultGridCap)),
+                       dim3(kBlock), 0, s, delta, acc, k, dq, leader_of, num_blocks, start, qdelta,
+                       qacc, qstart);
+}
+
+void launch_quotient_identity(const uint32_t *delta, const uint8_t *acc, uint32_t n, uint32_t k,
+                              uint32_t start, uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_quotient_identity,
+                       dim3(grid_for(static_cast<size_t>(n) * k, kDefaultGridCap)), dim3(kBlock),
+                       0, s, delta, acc, static_cast<size_t>(n), k, start, qdelta, qacc, qstart);
 }
 
 }  // namespace dfamin

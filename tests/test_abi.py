@@ -30,7 +30,7 @@ def lib():
 
 def test_exports_every_declared_function(lib):
     names = declared_functions()
-    assert len(names) >= 12
+    assert len(names) >= 14
     for name in names:
         assert hasattr(lib, name), name
     assert B.EXPORTS == names
@@ -40,7 +40,7 @@ def test_default_options(lib):
     o = B.Options()
     lib.dfa_options_default(ctypes.byref(o))
     assert o.tc_mode == B.TC["auto"] and o.loop_mode == B.LOOP["graph"]
-    assert o.start == 0 and o.max_rounds == 0 and o.lds_stage == 1
+    assert o.start == 0 and o.max_rounds == 0 and o.lds_stage == 2
 
 
 def test_struct_sizes_match_header():

@@ -27,7 +27,7 @@ def _ref_tc(d):
     return oracle.minimise_tc(d.delta, d.accepting)
 
 
-def check_minimise(d, tc="off", loop="graph", lds=True, quotient=False, ref=None):
+def check_minimise(d, tc="off", loop="graph", lds=2, quotient=False, ref=None):
     res = B.minimise(d.delta, d.accepting, tc=tc, loop=loop, lds_stage=lds, quotient=quotient,
                      start=d.start)
     block, nb, rounds, changing = ref if ref is not None else _ref(d)
@@ -59,7 +59,7 @@ def test_random_small(n, k, p, seed, loop):
     check_minimise(d, tc="off", loop=loop, quotient=True)
 
 
-@pytest.mark.parametrize("lds", [True, False])
+@pytest.mark.parametrize("lds", [True, False, 2])
 def test_lds_and_global_grouping_agree(lds):
     d = W.random_dfa(30000, 3, 0.3, 99)
     # duplicate rows: many states share signatures, stressing the grouping
@@ -77,7 +77,7 @@ def test_config_small_all_modes():
     ref = _ref(d)
     for loop in LOOPS:
         for tc in ("off", "auto"):
-            for lds in (True, False):
+            for lds in (True, False, 2):
                 check_minimise(d, tc=tc, loop=loop, lds=lds, ref=ref)
     res = check_minimise(d, tc="on", loop="graph", ref=ref)
     block, nb, rounds, changing = _ref_tc(d)
@@ -331,7 +331,10 @@ def test_config_large_equivalence(large):
     mut, _ = W.mutate_one(d, W.CFG_LARGE_MUT_SEED)
     assert B.equivalent(d, perm)[0]
     expected = oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting, mut.start)
-    assert B.equivalent(d, mut)[0] == expected
+    got, st = B.equivalent(d, mut)
+    assert got == expected
+    # twins (q and its copy) separate in a few rounds: no closure is built
+    assert st["tc_used"] == 0
 
 
 def test_config_chain_closure():
@@ -370,7 +373,7 @@ def test_tuning_variants_agree(restore_tuning, label_rounds, cached_probe, grid_
     cases.append(W.DFA(np.array([[1], [1]], dtype=np.uint32), np.array([0, 1], np.uint8), 0))
     cases.append(W.DFA(np.array([[2], [1], [2]], dtype=np.uint32), np.array([0, 0, 1], np.uint8), 0))
     for d in cases:
-        for lds in (True, False):
+        for lds in (True, False, 2):
             check_minimise(d, tc="off", loop="chunk", lds=lds, quotient=True)
     d = cases[0]
     perm, _ = W.permuted_copy(d, 3)
