@@ -56,6 +56,9 @@ def parse_args():
                     help="time the steps without per-kernel events (roofline omitted)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-plain comparison on the 4,096-DFA workload")
+    ap.add_argument("--batch-count", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -92,6 +95,67 @@ def cpu_baseline(d, perm):
     return {"value": work / secs, "unit": UNIT, "cores": 1, "kind": "oracle",
             "sample": (f"Moore rounds on the n=2^22 DFA ({rounds_a} rounds) and on its union "
                        f"with the permuted copy ({rounds_u} rounds), {secs:.1f} s")}
+
+
+def batch_leg(B, W, torch, np, count: int) -> dict:
+    """Batched vs plain on the same GPU: `count` random DFAs (n log-uniform in
+    [64, 65536], k in 2..8, p in [0.05, 0.5]); the upper half also checked for
+    equivalence (even: permuted copy, odd: one-transition mutation).  Batched =
+    one dfa_minimise_batch_device + one dfa_equivalent_batch_device call;
+    plain = one dfa_minimise_device / dfa_equivalent_device call per DFA/pair."""
+    dev = torch.device("cuda:0")
+    items = W.batch_workload(count=count, paired_from=count // 2)
+
+    def up(d):
+        return (torch.from_numpy(d.delta.view(np.int32)).to(dev),
+                torch.from_numpy(d.accepting).to(dev), d.start)
+
+    A = [up(it.dfa) for it in items]
+    pairs = [(i, up(it.pair)) for i, it in enumerate(items) if it.pair is not None]
+    total = sum(it.dfa.n for it in items)
+    out = torch.empty(total, dtype=torch.int32, device=dev)
+    blocks = [torch.empty(it.dfa.n, dtype=torch.int32, device=dev) for it in items]
+    torch.cuda.synchronize()
+
+    def batched():
+        nb, rounds, st = B.minimise_batch_device([a[0] for a in A], [a[1] for a in A], out)
+        v, st2 = B.equivalent_batch_device([A[i] for i, _ in pairs], [p for _, p in pairs])
+        return st["transitions_refined"] + st2["transitions_refined"], v
+
+    def plain():
+        work = 0
+        for a, blk in zip(A, blocks):
+            r = B.minimise_device(a[0], a[1], blk, tc="off")
+            work += r.stats["transitions_refined"]
+        verdicts = []
+        for i, p in pairs:
+            v, s2 = B.equivalent_device(A[i][0], A[i][1], A[i][2], p[0], p[1], p[2], tc="off")
+            verdicts.append(v)
+            work += s2["transitions_refined"]
+        return work, verdicts
+
+    batched()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        work_b, vb = batched()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work_p, vp = plain()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    if list(vb) != list(vp):
+        raise RuntimeError("batched and plain equivalence verdicts differ")
+    return {"workload": f"{count} random DFAs, n log-uniform [64, 65536], k in 2..8, "
+                        f"{len(pairs)} equivalence pairs",
+            "states": total, "batched_ms": tb * 1e3, "plain_ms": tp * 1e3,
+            "speedup": tp / tb,
+            "batched_transitions_per_s": work_b / tb,
+            "plain_transitions_per_s": work_p / tp}
 
 
 def main() -> int:
@@ -210,6 +274,8 @@ def main() -> int:
                 "algorithmic_GBps": (v["algorithmic_bytes"] / (v["total_ms"] / 1e3) / 1e9
                                      if v["total_ms"] else 0.0)}
             for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"])}
+    if not args.no_batch:
+        out["batched"] = batch_leg(B, W, torch, np, args.batch_count)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, perm)
     print(json.dumps(out), flush=True)

@@ -214,6 +214,55 @@ int dfa_included_device(const dfa_view *a, const dfa_view *b, int *verdict,
                         uint64_t *pairs_visited, const dfa_options *opt, dfa_stats *stats,
                         void *stream);
 
+/*
+ * Batches: many independent DFAs refined together in one set of launches
+ * (one refinement over their disjoint union; each DFA's states start in its
+ * own two classes, so no block spans two DFAs; DFAs with fewer letters are
+ * padded with identity letters, which change no partition).  Results are the
+ * same as those of the single-DFA calls.  The closure is built only with
+ * tc_mode ON (AUTO acts as OFF in batches).
+ */
+typedef struct dfa_batch_stats {
+    uint32_t count;           /* DFAs (or pairs) in the batch */
+    uint32_t rounds;          /* rounds of the joint refinement (max over DFAs) */
+    uint32_t k_eff;           /* letters per signature of the joint refinement */
+    uint32_t reserved0;
+    double h2d_ms, device_ms, d2h_ms;
+    uint64_t states;              /* states in the union */
+    uint64_t transitions_refined; /* sum over DFAs of n * k * (their own rounds) */
+    uint64_t algorithmic_bytes;   /* as dfa_stats, for the joint refinement */
+} dfa_batch_stats;
+
+/*
+ * Minimise count DFAs (Section 3.3, Algorithm 4, per DFA).
+ *   dfas           count host views (n, k, start, delta, accepting); start unused
+ *   blocks_concat  host; DFA i's canonical block ids (local state indices) at
+ *                  block_offsets[i] (NULL: packed back to back in order)
+ *   num_blocks     optional, count entries: blocks of each DFA
+ *   rounds         optional, count entries: each DFA's own rounds (as dfa_stats.rounds)
+ * Errors as dfa_minimise; "dfas[i]: ..." names the offending DFA.
+ */
+int dfa_minimise_batch(uint32_t count, const dfa_view *dfas, uint32_t *blocks_concat,
+                       const uint64_t *block_offsets, uint32_t *num_blocks, uint32_t *rounds,
+                       const dfa_options *opt, dfa_batch_stats *stats);
+/* Device variant: views and blocks_concat point to device memory;
+ * block_offsets, num_blocks and rounds stay host arrays. */
+int dfa_minimise_batch_device(uint32_t count, const dfa_view *dfas, uint32_t *blocks_concat,
+                              const uint64_t *block_offsets, uint32_t *num_blocks,
+                              uint32_t *rounds, const dfa_options *opt, dfa_batch_stats *stats,
+                              void *stream);
+
+/*
+ * Decide count equivalences L(a[i]) = L(b[i]) (Section 4) in one refinement
+ * of the union of all pairs.  verdicts: host, count entries, 1 = equivalent.
+ * a[i].k must equal b[i].k.
+ */
+int dfa_equivalent_batch(uint32_t count, const dfa_view *a, const dfa_view *b, int32_t *verdicts,
+                         const dfa_options *opt, dfa_batch_stats *stats);
+int dfa_equivalent_batch_device(uint32_t count, const dfa_view *a, const dfa_view *b,
+                                int32_t *verdicts, const dfa_options *opt,
+                                dfa_batch_stats *stats, void *stream);
+
 /* Description of the last failure on the calling thread ("" if none). */
 const char *dfa_last_error(void);
 

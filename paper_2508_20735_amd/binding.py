@@ -69,6 +69,17 @@ class KernelTime(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("algorithmic_bytes", ctypes.c_uint64)]
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+                ("k_eff", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("h2d_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("d2h_ms", ctypes.c_double), ("states", ctypes.c_uint64),
+                ("transitions_refined", ctypes.c_uint64), ("algorithmic_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved0"}
+
+
 class Quotient(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_void_p), ("accepting", ctypes.c_void_p),
                 ("num_blocks", ctypes.c_uint32), ("start", ctypes.c_uint32)]
@@ -83,7 +94,9 @@ EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
                   "dfa_equivalent", "dfa_equivalent_device", "dfa_included",
                   "dfa_included_device", "dfa_last_error", "dfa_device_info",
                   "dfa_tuning_default", "dfa_get_tuning", "dfa_set_tuning",
-                  "dfa_profile_enable", "dfa_profile_read"])
+                  "dfa_profile_enable", "dfa_profile_read", "dfa_minimise_batch",
+                  "dfa_minimise_batch_device", "dfa_equivalent_batch",
+                  "dfa_equivalent_batch_device"])
 
 _lock = threading.Lock()
 _lib = None
@@ -132,12 +145,22 @@ def load(build_if_missing: bool = True):
         lib.dfa_tuning_default.restype = None
         lib.dfa_get_tuning.argtypes = [P(Tuning)]
         lib.dfa_set_tuning.argtypes = [P(Tuning)]
+        lib.dfa_minimise_batch.argtypes = [u32, P(View), vp, vp, vp, vp, P(Options),
+                                           P(BatchStats)]
+        lib.dfa_minimise_batch_device.argtypes = [u32, P(View), vp, vp, vp, vp, P(Options),
+                                                  P(BatchStats), vp]
+        lib.dfa_equivalent_batch.argtypes = [u32, P(View), P(View), vp, P(Options),
+                                             P(BatchStats)]
+        lib.dfa_equivalent_batch_device.argtypes = [u32, P(View), P(View), vp, P(Options),
+                                                    P(BatchStats), vp]
         lib.dfa_profile_enable.argtypes = [i32]
         lib.dfa_profile_read.argtypes = [P(KernelTime), i32, P(i32)]
         for fn in ("dfa_minimise", "dfa_minimise_device", "dfa_equivalent",
                    "dfa_equivalent_device", "dfa_included", "dfa_included_device",
                    "dfa_device_info", "dfa_get_tuning", "dfa_set_tuning",
-                   "dfa_profile_enable", "dfa_profile_read"):
+                   "dfa_profile_enable", "dfa_profile_read", "dfa_minimise_batch",
+                   "dfa_minimise_batch_device", "dfa_equivalent_batch",
+                   "dfa_equivalent_batch_device"):
             getattr(lib, fn).restype = i32
         _lib = lib
         return lib
@@ -365,3 +388,89 @@ def included_device(dA, accA, sA, dB, accB, sB, stream=None) -> tuple[bool, int,
                                       ctypes.byref(cnt), None, ctypes.byref(st),
                                       _stream_ptr(stream)))
     return bool(v.value), int(cnt.value), st.as_dict()
+
+
+# --------------------------------------------------------------------------- batches
+
+def _views_host(dfas):
+    keep, views = [], (View * len(dfas))()
+    for i, d in enumerate(dfas):
+        v, arrays = _view_host(d)
+        views[i] = v
+        keep.append(arrays)
+    return views, keep
+
+
+def minimise_batch(dfas, *, tc: str = "auto", loop: str = "graph", max_rounds: int = 0,
+                   chunk: int = 0, lds_stage=2, offsets=None):
+    """dfa_minimise_batch on host DFAs.  Returns (list of block arrays,
+    num_blocks array, rounds array, stats)."""
+    count = len(dfas)
+    views, keep = _views_host(dfas)
+    sizes = np.array([int(v.n) for v in views], dtype=np.uint64)
+    if offsets is None:
+        offs = None
+        total = int(sizes.sum())
+    else:
+        offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+        total = int((offs + sizes).max())
+    out = np.zeros(total, dtype=np.uint32)
+    nb = np.empty(count, dtype=np.uint32)
+    rounds = np.empty(count, dtype=np.uint32)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage)
+    st = BatchStats()
+    _check(load().dfa_minimise_batch(count, views, out.ctypes.data,
+                                     None if offs is None else offs.ctypes.data, nb.ctypes.data,
+                                     rounds.ctypes.data, ctypes.byref(o), ctypes.byref(st)))
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.uint64) if offs is None \
+        else offs
+    blocks = [out[int(starts[i]):int(starts[i]) + int(sizes[i])] for i in range(count)]
+    return blocks, nb, rounds, st.as_dict()
+
+
+def minimise_batch_device(deltas, accs, out, *, tc: str = "auto", loop: str = "graph",
+                          lds_stage=2, stream=None):
+    """dfa_minimise_batch_device: deltas / accs are lists of GPU tensors, out a
+    GPU int32 tensor with room for all states (packed in order)."""
+    count = len(deltas)
+    views = (View * count)()
+    for i, (d, a) in enumerate(zip(deltas, accs)):
+        views[i] = _view_device(d, a, 0)
+    nb = np.empty(count, dtype=np.uint32)
+    rounds = np.empty(count, dtype=np.uint32)
+    o = options(tc, loop, 0, 0, 0, lds_stage)
+    st = BatchStats()
+    _check(load().dfa_minimise_batch_device(count, views, out.data_ptr(), None, nb.ctypes.data,
+                                            rounds.ctypes.data, ctypes.byref(o),
+                                            ctypes.byref(st), _stream_ptr(stream)))
+    return nb, rounds, st.as_dict()
+
+
+def equivalent_batch(pairs, *, tc: str = "auto", loop: str = "graph", max_rounds: int = 0,
+                     lds_stage=2):
+    """dfa_equivalent_batch on host DFA pairs: (verdict array, stats)."""
+    count = len(pairs)
+    va, keep_a = _views_host([p[0] for p in pairs])
+    vb, keep_b = _views_host([p[1] for p in pairs])
+    verdicts = np.empty(count, dtype=np.int32)
+    o = options(tc, loop, 0, max_rounds, 0, lds_stage)
+    st = BatchStats()
+    _check(load().dfa_equivalent_batch(count, va, vb, verdicts.ctypes.data, ctypes.byref(o),
+                                       ctypes.byref(st)))
+    return verdicts.astype(bool), st.as_dict()
+
+
+def equivalent_batch_device(a_list, b_list, *, loop: str = "graph", lds_stage=2, stream=None):
+    """a_list / b_list: lists of (delta tensor, accepting tensor, start)."""
+    count = len(a_list)
+    va, vb = (View * count)(), (View * count)()
+    for i in range(count):
+        va[i] = _view_device(*a_list[i])
+        vb[i] = _view_device(*b_list[i])
+    verdicts = np.empty(count, dtype=np.int32)
+    o = options("auto", loop, 0, 0, 0, lds_stage)
+    st = BatchStats()
+    _check(load().dfa_equivalent_batch_device(count, va, vb, verdicts.ctypes.data,
+                                              ctypes.byref(o), ctypes.byref(st),
+                                              _stream_ptr(stream)))
+    return verdicts.astype(bool), st.as_dict()

@@ -97,6 +97,9 @@ struct Ctx {
     Buffer stage_delta, stage_acc, stage_block, stage_qdelta, stage_qacc, stage_delta_b,
         stage_acc_b;
     Buffer visited, visited2, front0, front1;
+    Buffer parts, tile_part, seg_words, batch_in, batch_out;
+    uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
+    size_t pinned_batch_cap = 0;
     hipGraphExec_t graph = nullptr;
     GraphKey graph_key{};
     // kernel timing (dfa_profile_enable): event pairs around the round
@@ -249,6 +252,7 @@ int launch_kern(Ctx &c, Kern kind, const RoundArgs &a, uint32_t round) {
 int launch_full_round(Ctx &c, const RoundArgs &a, uint32_t round) {
     DFA_TRY(launch_kern(c, Kern::Signature, a, round));
     DFA_TRY(launch_kern(c, Kern::Insert, a, round));
+    if (a.seg.nseg) launch_seg_round(a, c.stream);
     return launch_kern(c, Kern::RoundEnd, a, round);
 }
 
@@ -355,9 +359,10 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t f
 // whose initial labels are in c.blockA (flags already written by the ingest
 // and init kernels).
 RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff, uint64_t cap,
-                          int lds_stage, bool packed) {
+                          int lds_stage, bool packed, const SegArgs *seg) {
     RoundArgs ra;
     std::memset(&ra, 0, sizeof ra);
+    if (seg) ra.seg = *seg;
     ra.cols = cols;
     ra.colmap = c.colmap.as<uint32_t>();
     ra.N = N;
@@ -389,7 +394,7 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
 // (a stable partition found by a label round) gets one more table round,
 // which keeps the partition and turns the labels into state ids.
 int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq, uint32_t eq_a,
-           uint32_t eq_b, bool state_ids, RefineResult &res) {
+           uint32_t eq_b, bool state_ids, RefineResult &res, const SegArgs *seg = nullptr) {
     // target check, classes, identity letters (one readback)
     DFA_TRY(read_back(c, c.flags.p, (kFlagNonid + k) * sizeof(uint32_t)));
     if (c.pinned[kFlagErr]) return fail(DFA_EINVAL, "a transition target is >= n");
@@ -417,7 +422,8 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     DFA_TRY(c.hash.ensure(N * sizeof(uint64_t), "hashes"));
     // label rounds need at least three rounds of budget (ids become state
     // ids in the round after them)
-    const bool budget = o.max_rounds == 0 || o.max_rounds > 2;
+    // (segmented refinements keep their segment labels: no label rounds)
+    const bool budget = (o.max_rounds == 0 || o.max_rounds > 2) && !seg;
     const uint32_t pattern_first =
         (c.tune.label_rounds >= 1 && budget && k_eff + 1 <= kPatternMaxBits) ? 1u : 0u;
     const uint32_t packed_second =
@@ -432,7 +438,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     }
     res.label_rounds = pattern_first + packed_second;
     launch_ctl_reset(ctl, c.flags.as<uint32_t>() + kFlagClass, o.max_rounds, check_eq, eq_a, eq_b,
-                     pattern_first, packed_second, c.stream);
+                     pattern_first, packed_second, seg ? seg->init_count : nullptr, c.stream);
 
     const int mode = o.loop_mode;
     uint32_t chunk = o.chunk ? o.chunk : c.tune.chunk;
@@ -444,7 +450,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     res.bytes = 0;
     bool first = true;
     for (;;) {
-        const RoundArgs ra = make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second);
+        const RoundArgs ra = make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second, seg);
         if (first) {
             // rounds 0 (and 1) run on their own: label rounds when the
             // signatures are short enough
@@ -481,7 +487,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         for (uint32_t i = 1; i <= 4 && i <= res.ctl.round; ++i)
             recent_gain = std::max<uint64_t>(
                 recent_gain, res.ctl.gain_hist[(res.ctl.round - i) % kActiveHist]);
-        if (o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed && res.ctl.round >= 8 &&
+        if (o.tc_mode == DFA_TC_AUTO && !seg && !res.tc_used && !tc_failed && res.ctl.round >= 8 &&
             left >= 4096 && recent_gain * 4096 < left) {
             std::vector<uint32_t> tcmap;
             uint32_t levels = 0;
@@ -506,7 +512,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     if (state_ids && res.ctl.stable && res.ctl.round <= res.label_rounds) {
         launch_ctl_resume(ctl, c.stream);
         DFA_TRY(launch_full_round(c, make_round_args(c, cols, N, k_eff, cap, o.lds_stage,
-                                                     packed_second),
+                                                     packed_second, seg),
                                   res.ctl.round));
         HIP_TRY(hipGetLastError());
         DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
@@ -778,6 +784,251 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// ---- batches: many DFAs in one segmented refinement ----
+
+int ensure_pinned_batch(Ctx &c, size_t bytes) {
+    if (c.pinned_batch && bytes <= c.pinned_batch_cap) return DFA_OK;
+    if (c.pinned_batch) {
+        HIP_TRY(hipStreamSynchronize(c.stream));
+        (void)hipHostFree(c.pinned_batch);
+        c.pinned_batch = nullptr;
+        c.pinned_batch_cap = 0;
+    }
+    const size_t want = std::max<size_t>(bytes, 1 << 20);
+    if (hipHostMalloc(reinterpret_cast<void **>(&c.pinned_batch), want, hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        c.pinned_batch = nullptr;
+        return fail(DFA_ENOMEM, "pinned host allocation of %zu bytes failed", want);
+    }
+    c.pinned_batch_cap = want;
+    return DFA_OK;
+}
+
+// parts (host vector, device pointers inside) -> device SegArgs.
+int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, size_t N, SegArgs &g) {
+    const size_t tiles = (N + kBlock - 1) / kBlock;
+    std::vector<uint32_t> tile_part(tiles);
+    uint32_t p = 0;
+    for (size_t t = 0; t < tiles; ++t) {
+        const size_t first = t * kBlock;
+        while (static_cast<size_t>(parts[p].off) + parts[p].n <= first) ++p;
+        tile_part[t] = p;
+    }
+    DFA_TRY(c.parts.ensure(parts.size() * sizeof(Part), "batch parts"));
+    DFA_TRY(c.tile_part.ensure(tiles * sizeof(uint32_t), "batch tiles"));
+    DFA_TRY(c.seg_words.ensure((4 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t),
+                               "segment counters"));
+    HIP_TRY(hipMemcpy(c.parts.p, parts.data(), parts.size() * sizeof(Part),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c.tile_part.p, tile_part.data(), tiles * sizeof(uint32_t),
+                      hipMemcpyHostToDevice));
+    uint32_t *w = c.seg_words.as<uint32_t>();
+    HIP_TRY(hipMemsetAsync(w, 0, (4 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t), c.stream));
+    g.parts = c.parts.as<Part>();
+    g.tile_part = c.tile_part.as<uint32_t>();
+    g.nparts = static_cast<uint32_t>(parts.size());
+    g.nseg = nseg;
+    g.seg_cnt = w;
+    g.seg_prev = w + nseg;
+    g.seg_changing = w + 2 * static_cast<size_t>(nseg);
+    g.seg_flags = w + 3 * static_cast<size_t>(nseg);
+    g.init_count = w + 4 * static_cast<size_t>(nseg);
+    return DFA_OK;
+}
+
+// Refines the union described by parts; fills per-segment block counts and
+// changing rounds (host vectors).
+int refine_segments(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, uint32_t kmax,
+                    const dfa_options &o, RefineResult &r, SegArgs &g,
+                    std::vector<uint32_t> &seg_blocks, std::vector<uint32_t> &seg_changing) {
+    const Part &last = parts.back();
+    const size_t N = static_cast<size_t>(last.off) + last.n;
+    if (N >= 0xFFFFFFFFull) return fail(DFA_EINVAL, "total number of states must be < 2^32 - 1");
+    DFA_TRY(upload_plan(c, parts, nseg, N, g));
+    DFA_TRY(prepare_refinement(c, N, kmax));
+    uint32_t *flags = c.flags.as<uint32_t>();
+    launch_ingest_parts(g, N, kmax, c.cols.as<uint32_t>(), flags + kFlagErr, flags + kFlagNonid,
+                        c.stream);
+    launch_init_parts(g, N, c.blockA.as<uint32_t>(), c.stream);
+    HIP_TRY(hipGetLastError());
+    dfa_options ob = o;
+    if (ob.tc_mode == DFA_TC_AUTO) ob.tc_mode = DFA_TC_OFF;  // no closure on demand in batches
+    DFA_TRY(refine(c, N, kmax, ob, 0, 0, 0, false, r, &g));
+    seg_blocks.resize(nseg);
+    seg_changing.resize(nseg);
+    HIP_TRY(hipMemcpyAsync(seg_blocks.data(), g.seg_prev, nseg * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipMemcpyAsync(seg_changing.data(), g.seg_changing, nseg * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    return DFA_OK;
+}
+
+void fill_batch_stats(dfa_batch_stats *st, uint32_t count, const RefineResult &r, size_t N,
+                      uint64_t transitions) {
+    if (!st) return;
+    st->count = count;
+    st->rounds = r.ctl.round;
+    st->k_eff = r.k_eff;
+    st->states = N;
+    st->transitions_refined = transitions;
+    st->algorithmic_bytes = r.bytes;
+}
+
+// Places the views' arrays (host memory) into one pinned buffer and copies
+// it to the device; returns device views.
+int stage_views(Ctx &c, uint32_t count, const dfa_view *const *lists, int nlists,
+                std::vector<dfa_view> &dev_views, double &h2d_ms) {
+    size_t bytes = 0;
+    for (int l = 0; l < nlists; ++l)
+        for (uint32_t i = 0; i < count; ++i) {
+            const dfa_view &v = lists[l][i];
+            bytes += ((static_cast<size_t>(v.n) * v.k * 4 + 255) & ~size_t(255)) +
+                     ((static_cast<size_t>(v.n) + 255) & ~size_t(255));
+        }
+    DFA_TRY(ensure_pinned_batch(c, bytes));
+    DFA_TRY(c.batch_in.ensure(bytes, "batched inputs"));
+    auto t0 = std::chrono::steady_clock::now();
+    size_t off = 0;
+    dev_views.clear();
+    uint8_t *dev = c.batch_in.as<uint8_t>();
+    for (int l = 0; l < nlists; ++l)
+        for (uint32_t i = 0; i < count; ++i) {
+            const dfa_view &v = lists[l][i];
+            dfa_view d = v;
+            const size_t db = static_cast<size_t>(v.n) * v.k * 4;
+            std::memcpy(c.pinned_batch + off, v.delta, db);
+            d.delta = reinterpret_cast<const uint32_t *>(dev + off);
+            off += (db + 255) & ~size_t(255);
+            std::memcpy(c.pinned_batch + off, v.accepting, v.n);
+            d.accepting = dev + off;
+            off += (static_cast<size_t>(v.n) + 255) & ~size_t(255);
+            dev_views.push_back(d);
+        }
+    HIP_TRY(hipMemcpyAsync(dev, c.pinned_batch, off, hipMemcpyHostToDevice, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    h2d_ms = ms_since(t0);
+    return DFA_OK;
+}
+
+int check_views(uint32_t count, const dfa_view *v, const char *name) {
+    if (count == 0) return fail(DFA_EINVAL, "count must be >= 1");
+    if (!v) return fail(DFA_EINVAL, "%s is NULL", name);
+    for (uint32_t i = 0; i < count; ++i) {
+        int rc = check_view(v + i, name);
+        if (rc != DFA_OK) return fail(rc, "%s[%u]: %s", name, i, g_last_error.c_str());
+    }
+    return DFA_OK;
+}
+
+// Batched minimisation on device views; out_dev receives the block ids,
+// part i at out_off[i].
+int minimise_batch_impl(Ctx &c, uint32_t count, const dfa_view *views, uint32_t *out_dev,
+                        const uint64_t *out_off, uint32_t *num_blocks, uint32_t *rounds,
+                        const dfa_options &o, dfa_batch_stats *st) {
+    std::vector<Part> parts(count);
+    uint64_t off = 0, out = 0;
+    uint32_t kmax = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const dfa_view &v = views[i];
+        Part &p = parts[i];
+        std::memset(&p, 0, sizeof p);
+        p.delta = v.delta;
+        p.accepting = v.accepting;
+        p.n = v.n;
+        p.k = v.k;
+        p.off = static_cast<uint32_t>(off);
+        p.seg = i;
+        p.start = v.start;
+        p.out = out_off ? out_off[i] : out;
+        out += v.n;
+        off += v.n;
+        kmax = std::max(kmax, v.k);
+        if (off >= 0xFFFFFFFFull) return fail(DFA_EINVAL, "total number of states must be < 2^32 - 1");
+    }
+    HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    RefineResult r;
+    SegArgs g{};
+    std::vector<uint32_t> blocks, changing;
+    DFA_TRY(refine_segments(c, parts, count, kmax, o, r, g, blocks, changing));
+    const size_t N = off;
+    DFA_TRY(c.canon.ensure(N * sizeof(uint32_t), "canonical ids"));
+    // canonical ids go to the block buffer that does not hold the result
+    uint32_t *canon_ids = c.blockA.as<uint32_t>() == r.final_block ? c.blockB.as<uint32_t>()
+                                                                   : c.blockA.as<uint32_t>();
+    launch_canonicalise(r.final_block, N, N, c.canon.as<uint32_t>(), canon_ids, c.stream);
+    launch_part_output(g, N, canon_ids, out_dev, c.stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    uint64_t transitions = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (num_blocks) num_blocks[i] = blocks[i];
+        if (rounds) rounds[i] = changing[i] + 1;
+        transitions += static_cast<uint64_t>(views[i].n) * views[i].k * (changing[i] + 1);
+    }
+    if (st) {
+        fill_batch_stats(st, count, r, N, transitions);
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
+        st->device_ms = ms;
+    }
+    if (r.ctl.limit)
+        return fail(DFA_ELIMIT, "max_rounds (%u) reached before every partition was stable",
+                    o.max_rounds);
+    return DFA_OK;
+}
+
+int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_view *b,
+                          int32_t *verdicts, const dfa_options &o, dfa_batch_stats *st) {
+    std::vector<Part> parts(2 * static_cast<size_t>(count));
+    uint64_t off = 0;
+    uint32_t kmax = 0;
+    for (uint32_t i = 0; i < count; ++i)
+        for (int side = 0; side < 2; ++side) {
+            const dfa_view &v = side ? b[i] : a[i];
+            Part &p = parts[2 * static_cast<size_t>(i) + side];
+            std::memset(&p, 0, sizeof p);
+            p.delta = v.delta;
+            p.accepting = v.accepting;
+            p.n = v.n;
+            p.k = v.k;
+            p.off = static_cast<uint32_t>(off);
+            p.seg = i;
+            p.start = v.start;
+            off += v.n;
+            kmax = std::max(kmax, v.k);
+            if (off >= 0xFFFFFFFFull)
+                return fail(DFA_EINVAL, "total number of states must be < 2^32 - 1");
+        }
+    HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    RefineResult r;
+    SegArgs g{};
+    std::vector<uint32_t> blocks, changing;
+    DFA_TRY(refine_segments(c, parts, count, kmax, o, r, g, blocks, changing));
+    DFA_TRY(c.batch_out.ensure(count * sizeof(int32_t), "verdicts"));
+    launch_pair_verdicts(g, r.final_block, c.batch_out.as<int32_t>(), c.stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(verdicts, c.batch_out.p, count * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c.stream));
+    HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    if (st) {
+        uint64_t transitions = 0;
+        for (uint32_t i = 0; i < count; ++i)
+            transitions += (static_cast<uint64_t>(a[i].n) + b[i].n) * a[i].k * (changing[i] + 1);
+        fill_batch_stats(st, count, r, off, transitions);
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
+        st->device_ms = ms;
+    }
+    if (r.ctl.limit)
+        return fail(DFA_ELIMIT, "max_rounds (%u) reached before every verdict was known",
+                    o.max_rounds);
+    return DFA_OK;
+}
+
 }  // namespace
 }  // namespace dfamin
 
@@ -1026,6 +1277,112 @@ int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *p
     HIP_TRY(hipStreamSynchronize(c->stream));
     const double h2d = ms_since(t0);
     int rc = included_impl(*c, da, db, verdict, pairs_visited, stats);
+    if (stats) stats->h2d_ms = h2d;
+    return rc;
+}
+
+
+int dfa_minimise_batch_device(uint32_t count, const dfa_view *dfas, uint32_t *blocks_concat,
+                              const uint64_t *block_offsets, uint32_t *num_blocks,
+                              uint32_t *rounds, const dfa_options *opt, dfa_batch_stats *stats,
+                              void *stream) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_views(count, dfas, "dfas"));
+    DFA_TRY(check_options(o));
+    if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    DFA_TRY(join_stream(*c, stream));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return minimise_batch_impl(*c, count, dfas, blocks_concat, block_offsets, num_blocks, rounds,
+                               o, stats);
+}
+
+int dfa_minimise_batch(uint32_t count, const dfa_view *dfas, uint32_t *blocks_concat,
+                       const uint64_t *block_offsets, uint32_t *num_blocks, uint32_t *rounds,
+                       const dfa_options *opt, dfa_batch_stats *stats) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_views(count, dfas, "dfas"));
+    DFA_TRY(check_options(o));
+    if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    std::vector<dfa_view> dev;
+    double h2d = 0;
+    const dfa_view *lists[1] = {dfas};
+    DFA_TRY(stage_views(*c, count, lists, 1, dev, h2d));
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < count; ++i) total += dfas[i].n;
+    DFA_TRY(c->batch_out.ensure(total * sizeof(uint32_t), "batched outputs"));
+    int rc = minimise_batch_impl(*c, count, dev.data(), c->batch_out.as<uint32_t>(), nullptr,
+                                 num_blocks, rounds, o, stats);
+    if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
+    auto t0 = std::chrono::steady_clock::now();
+    DFA_TRY(ensure_pinned_batch(*c, total * sizeof(uint32_t)));
+    HIP_TRY(hipMemcpyAsync(c->pinned_batch, c->batch_out.p, total * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    uint64_t pos = 0;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(c->pinned_batch);
+    for (uint32_t i = 0; i < count; ++i) {
+        const uint64_t dst = block_offsets ? block_offsets[i] : pos;
+        std::memcpy(blocks_concat + dst, src + pos, dfas[i].n * sizeof(uint32_t));
+        pos += dfas[i].n;
+    }
+    if (stats) {
+        stats->h2d_ms = h2d;
+        stats->d2h_ms = ms_since(t0);
+    }
+    return rc;
+}
+
+int dfa_equivalent_batch_device(uint32_t count, const dfa_view *a, const dfa_view *b,
+                                int32_t *verdicts, const dfa_options *opt,
+                                dfa_batch_stats *stats, void *stream) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_views(count, a, "a"));
+    DFA_TRY(check_views(count, b, "b"));
+    DFA_TRY(check_options(o));
+    if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
+    for (uint32_t i = 0; i < count; ++i)
+        if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    DFA_TRY(join_stream(*c, stream));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return equivalent_batch_impl(*c, count, a, b, verdicts, o, stats);
+}
+
+int dfa_equivalent_batch(uint32_t count, const dfa_view *a, const dfa_view *b, int32_t *verdicts,
+                         const dfa_options *opt, dfa_batch_stats *stats) {
+    g_last_error.clear();
+    dfa_options o = resolve(opt);
+    DFA_TRY(check_views(count, a, "a"));
+    DFA_TRY(check_views(count, b, "b"));
+    DFA_TRY(check_options(o));
+    if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
+    for (uint32_t i = 0; i < count; ++i)
+        if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    DFA_TRY(init_ctx(*c));
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    std::vector<dfa_view> dev;
+    double h2d = 0;
+    const dfa_view *lists[2] = {a, b};
+    DFA_TRY(stage_views(*c, count, lists, 2, dev, h2d));
+    int rc = equivalent_batch_impl(*c, count, dev.data(), dev.data() + count, verdicts, o, stats);
     if (stats) stats->h2d_ms = h2d;
     return rc;
 }

@@ -76,11 +76,57 @@ void launch_init_blocks(const uint8_t *acc, uint32_t n, uint32_t offset, uint32_
 
 // ctl := fresh state with prev_count = initial class count (read from
 // class_flags on the device).
+// With init_count != nullptr the initial block count is read from it
+// instead of the two class flags.
 void launch_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t max_rounds,
                       uint32_t check_eq, uint32_t eq_a, uint32_t eq_b, uint32_t pattern_first,
-                      uint32_t packed_second, hipStream_t s);
+                      uint32_t packed_second, const uint32_t *init_count, hipStream_t s);
 // Clears the stop flag so that one more round can run (relabelling).
 void launch_ctl_resume(RoundCtl *ctl, hipStream_t s);
+
+// ---- segmented refinement (many DFAs in one refinement) ----
+//
+// The DFAs ("parts") are laid out back to back over the N states; a
+// "segment" is a set of consecutive parts refined as one automaton (one DFA
+// for batched minimisation, the two operands for batched equivalence).
+// Initial labels are 2 * segment + accepting, so no block ever spans two
+// segments; parts with fewer letters than the refinement are padded with
+// identity letters, which do not change the partition.
+struct Part {
+    const uint32_t *delta;    // device, row-major n x k
+    const uint8_t *accepting; // device, n
+    uint32_t n, k;            // states, letters of this part
+    uint32_t off;             // first state of the part in the union
+    uint32_t seg;             // segment of the part
+    uint32_t start;           // start state (local index)
+    uint32_t pad;
+    uint64_t out;             // output offset of the part's block ids
+};
+
+struct SegArgs {
+    const Part *parts;        // nparts entries, ordered by off
+    const uint32_t *tile_part;  // first part of every tile of kBlock states
+    uint32_t nparts, nseg;
+    uint32_t *seg_cnt;        // blocks per segment in the current round
+    uint32_t *seg_prev;       // blocks per segment after the last round
+    uint32_t *seg_changing;   // rounds that split a block of the segment
+    uint32_t *seg_flags;      // acceptance classes per segment (bit 0/1)
+    uint32_t *init_count;     // sum over segments of their class counts
+};
+
+// Transposes every part into cols (targets offset by the part's first
+// state; letters >= part.k become the identity); err / nonid as launch_ingest.
+void launch_ingest_parts(const SegArgs &g, size_t N, uint32_t k, uint32_t *cols, uint32_t *err,
+                         uint32_t *nonid, hipStream_t s);
+// Initial labels 2 * seg + accepting, per-segment classes, their total.
+void launch_init_parts(const SegArgs &g, size_t N, uint32_t *block, hipStream_t s);
+// Writes every part's canonical block ids (local: global id - part offset)
+// to out + part.out.
+void launch_part_output(const SegArgs &g, size_t N, const uint32_t *canon, uint32_t *out,
+                        hipStream_t s);
+// verdict[s] = 1 iff the start states of parts 2s and 2s+1 share a block.
+void launch_pair_verdicts(const SegArgs &g, const uint32_t *block, int32_t *verdicts,
+                          hipStream_t s);
 
 // One signature round: signatures + hashes (and the periodic table clear),
 // then grouping through the table, then the round-end bookkeeping.
@@ -107,8 +153,12 @@ struct RoundArgs {
     uint32_t pattern_grid_cap;  // workgroups of the label rounds
     uint32_t cached_probe;      // probe the table with cached loads first
     uint32_t pad;
+    SegArgs seg;                // nseg == 0: a single automaton
 };
 void launch_round(const RoundArgs &a, hipStream_t s);
+// Per-segment block counts of the round, then the per-segment bookkeeping
+// (both no-ops once the refinement has stopped); run before the round end.
+void launch_seg_round(const RoundArgs &a, hipStream_t s);
 // The three launches of launch_round, separately (for kernel timing).
 void launch_signature(const RoundArgs &a, hipStream_t s);
 void launch_insert(const RoundArgs &a, hipStream_t s);

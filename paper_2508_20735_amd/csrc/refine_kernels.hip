@@ -159,10 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_init_blocks(const uint8_t *__restric
 
 __global__ void k_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t max_rounds,
                             uint32_t check_eq, uint32_t eq_a, uint32_t eq_b,
-                            uint32_t pattern_first, uint32_t packed_second) {
+                            uint32_t pattern_first, uint32_t packed_second,
+                            const uint32_t *init_count) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     RoundCtl c{};
-    c.prev_count = (class_flags[0] ? 1u : 0u) + (class_flags[1] ? 1u : 0u);
+    c.prev_count = init_count ? *init_count
+                              : (class_flags[0] ? 1u : 0u) + (class_flags[1] ? 1u : 0u);
     c.max_rounds = max_rounds;
     c.check_eq = check_eq;
     c.eq_a = eq_a;
@@ -658,6 +660,137 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint3
     }
 }
 
+// ---------------------------------------------------------------- segmented refinement
+
+__device__ __forceinline__ uint32_t find_part(const SegArgs &g, size_t q) {
+    uint32_t p = g.tile_part[q / kBlock];
+    while (static_cast<size_t>(g.parts[p].off) + g.parts[p].n <= q) ++p;
+    return p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ingest_parts(SegArgs g, size_t N, uint32_t k,
+                                                          uint32_t *__restrict__ cols,
+                                                          uint32_t *err, uint32_t *nonid) {
+    bool bad = false;
+    unsigned long long moves = 0;
+    for (size_t q = global_tid(); q < N; q += grid_stride()) {
+        const Part P = g.parts[find_part(g, q)];
+        const size_t i = q - P.off;
+        for (uint32_t a = 0; a < k; ++a) {
+            uint32_t t = static_cast<uint32_t>(i);  // padding letters are the identity
+            if (a < P.k) {
+                t = P.delta[i * P.k + a];
+                if (t >= P.n) {
+                    bad = true;
+                    t = 0;
+                }
+            }
+            if (t != i) {
+                if (a < 64)
+                    moves |= 1ull << a;
+                else if (nonid[a] == 0u)
+                    nonid[a] = 1u;
+            }
+            cols[static_cast<size_t>(a) * N + q] = t + P.off;
+        }
+    }
+    wave_set_flag(err, bad);
+    moves = wave_or64(moves);
+    if (lane_id() == 0) {
+        while (moves) {
+            const int a = __ffsll(moves) - 1;
+            moves &= moves - 1;
+            if (nonid[a] == 0u) nonid[a] = 1u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_parts(SegArgs g, size_t N,
+                                                        uint32_t *__restrict__ block) {
+    for (size_t q = global_tid(); q < N; q += grid_stride()) {
+        const Part P = g.parts[find_part(g, q)];
+        const bool f = P.accepting[q - P.off] != 0;
+        block[q] = 2u * P.seg + (f ? 1u : 0u);
+        const uint32_t bit = f ? 1u : 2u;
+        uint32_t *w = g.seg_flags + P.seg;
+        if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) & bit))
+            atomicOr(w, bit);
+    }
+}
+
+// seg_prev[s] = classes of segment s; *init_count = their sum.
+__global__ __launch_bounds__(kBlock) void k_seg_init(SegArgs g) {
+    uint32_t sum = 0;
+    for (size_t s = global_tid(); s < g.nseg; s += grid_stride()) {
+        const uint32_t c = __popc(g.seg_flags[s]);
+        g.seg_prev[s] = c;
+        g.seg_changing[s] = 0;
+        g.seg_cnt[s] = 0;
+        sum += c;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d, 64);
+    if (lane_id() == 0 && sum) atomicAdd(g.init_count, sum);
+}
+
+// Blocks per segment after the round: the states that are their block's id
+// (a block's id is the state that first claimed its signature).  Counts are
+// aggregated per tile in LDS (a tile spans at most kBlock segments).
+__global__ __launch_bounds__(kBlock) void k_seg_count(SegArgs g, size_t N, const RoundCtl *ctl,
+                                                       const uint32_t *blockA,
+                                                       const uint32_t *blockB) {
+    __shared__ uint32_t lcnt[kBlock];
+    __shared__ uint32_t seg_first;
+    if (ctl->done) return;
+    const uint32_t r = ctl->round;
+    const uint32_t *__restrict__ Y = (r & 1u) ? blockA : blockB;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        lcnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) seg_first = g.parts[g.tile_part[base / kBlock]].seg;
+        __syncthreads();
+        const size_t q = base + threadIdx.x;
+        if (q < N && Y[q] == q) {
+            const uint32_t seg = g.parts[find_part(g, q)].seg;
+            atomicAdd(lcnt + (seg - seg_first), 1u);
+        }
+        __syncthreads();
+        const uint32_t c = lcnt[threadIdx.x];
+        if (c) atomicAdd(g.seg_cnt + seg_first + threadIdx.x, c);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_end(SegArgs g, const RoundCtl *ctl) {
+    if (ctl->done) return;
+    for (size_t s = global_tid(); s < g.nseg; s += grid_stride()) {
+        const uint32_t c = g.seg_cnt[s];
+        if (c != g.seg_prev[s]) {
+            g.seg_changing[s] += 1;
+            g.seg_prev[s] = c;
+        }
+        g.seg_cnt[s] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_output(SegArgs g, size_t N,
+                                                         const uint32_t *__restrict__ canon,
+                                                         uint32_t *__restrict__ out) {
+    for (size_t q = global_tid(); q < N; q += grid_stride()) {
+        const Part P = g.parts[find_part(g, q)];
+        out[P.out + (q - P.off)] = canon[q] - P.off;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_verdicts(SegArgs g,
+                                                           const uint32_t *__restrict__ block,
+                                                           int32_t *verdicts) {
+    for (size_t s = global_tid(); s < g.nseg; s += grid_stride()) {
+        const Part A = g.parts[2 * s], B = g.parts[2 * s + 1];
+        verdicts[s] = block[A.off + A.start] == block[B.off + B.start] ? 1 : 0;
+    }
+}
+
 // ---------------------------------------------------------------- pointer jumping
 
 __global__ __launch_bounds__(kBlock) void k_jump(uint32_t *__restrict__ cols, size_t N,
@@ -863,9 +996,40 @@ void launch_init_blocks(const uint8_t *acc, uint32_t n, uint32_t offset, uint32_
 
 void launch_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t max_rounds,
                       uint32_t check_eq, uint32_t eq_a, uint32_t eq_b, uint32_t pattern_first,
-                      uint32_t packed_second, hipStream_t s) {
+                      uint32_t packed_second, const uint32_t *init_count, hipStream_t s) {
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, class_flags, max_rounds,
-                       check_eq, eq_a, eq_b, pattern_first, packed_second);
+                       check_eq, eq_a, eq_b, pattern_first, packed_second, init_count);
+}
+
+void launch_ingest_parts(const SegArgs &g, size_t N, uint32_t k, uint32_t *cols, uint32_t *err,
+                         uint32_t *nonid, hipStream_t s) {
+    hipLaunchKernelGGL(k_ingest_parts, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g,
+                       N, k, cols, err, nonid);
+}
+
+void launch_init_parts(const SegArgs &g, size_t N, uint32_t *block, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_parts, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g, N,
+                       block);
+    hipLaunchKernelGGL(k_seg_init, dim3(grid_for(g.nseg, kDefaultGridCap)), dim3(kBlock), 0, s, g);
+}
+
+void launch_seg_round(const RoundArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_count, dim3(grid_for(a.N, kDefaultGridCap)), dim3(kBlock), 0, s,
+                       a.seg, a.N, a.ctl, a.blockA, a.blockB);
+    hipLaunchKernelGGL(k_seg_end, dim3(grid_for(a.seg.nseg, kDefaultGridCap)), dim3(kBlock), 0, s,
+                       a.seg, a.ctl);
+}
+
+void launch_part_output(const SegArgs &g, size_t N, const uint32_t *canon, uint32_t *out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_part_output, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g, N,
+                       canon, out);
+}
+
+void launch_pair_verdicts(const SegArgs &g, const uint32_t *block, int32_t *verdicts,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_verdicts, dim3(grid_for(g.nseg, kDefaultGridCap)), dim3(kBlock), 0,
+                       s, g, block, verdicts);
 }
 
 void launch_ctl_resume(RoundCtl *ctl, hipStream_t s) {
@@ -927,6 +1091,7 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
 void launch_round(const RoundArgs &a, hipStream_t s) {
     launch_signature(a, s);
     launch_insert(a, s);
+    if (a.seg.nseg) launch_seg_round(a, s);
     launch_round_end(a, s);
 }
 

@@ -30,7 +30,7 @@ def lib():
 
 def test_exports_every_declared_function(lib):
     names = declared_functions()
-    assert len(names) >= 14
+    assert len(names) >= 18
     for name in names:
         assert hasattr(lib, name), name
     assert B.EXPORTS == names
@@ -49,6 +49,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(B.Stats) == 32 + 3 * 8 + 2 * 8
     assert ctypes.sizeof(B.View) == 12 + 4 + 16
     assert ctypes.sizeof(B.Tuning) == 64
+    assert ctypes.sizeof(B.BatchStats) == 16 + 24 + 24
 
 
 def test_default_tuning(lib):

@@ -381,3 +381,92 @@ def test_tuning_variants_agree(restore_tuning, label_rounds, cached_probe, grid_
     mut, _ = W.mutate_one(d, 4)
     assert B.equivalent(d, mut)[0] == oracle.equiv_hk(d.delta, d.accepting, 0, mut.delta,
                                                      mut.accepting, mut.start)
+
+
+# ---------------------------------------------------------------- batches
+
+def _mixed_batch(seed, count):
+    rng = np.random.default_rng(seed)
+    dfas = []
+    for i in range(count):
+        n = int(np.exp(rng.uniform(0, np.log(6000))))
+        k = int(rng.integers(1, 9))
+        d = W.random_dfa(n, k, float(rng.uniform(0.0, 0.6)), int(rng.integers(1 << 30)))
+        if i % 5 == 0 and n > 4:  # duplicated rows: non-trivial blocks
+            src = rng.integers(0, n, n // 2)
+            dst = rng.integers(0, n, n // 2)
+            d.delta[dst] = d.delta[src]
+            d.accepting[dst] = d.accepting[src]
+        dfas.append(d)
+    dfas.append(W.DFA(np.zeros((1, 3), np.uint32), np.ones(1, np.uint8), 0))   # one state
+    dfas.append(W.fibonacci(9))                                                  # 55 rounds
+    dfas.append(W.bitsplitter(7))
+    return dfas
+
+
+@pytest.mark.parametrize("loop", ["chunk", "graph"])
+def test_minimise_batch_matches_single(loop):
+    dfas = _mixed_batch(3, 150)
+    blocks, nb, rounds, st = B.minimise_batch(dfas, loop=loop)
+    assert st["count"] == len(dfas)
+    for i, d in enumerate(dfas):
+        ref, rnb, rrounds, rchanging = oracle.moore(d.delta, d.accepting)
+        np.testing.assert_array_equal(blocks[i], ref, err_msg=f"dfa {i}")
+        assert nb[i] == rnb and rounds[i] == rrounds, i
+    assert st["rounds"] == max(rounds)
+
+
+def test_minimise_batch_offsets_and_errors():
+    dfas = _mixed_batch(4, 20)
+    sizes = [d.n for d in dfas]
+    # reversed placement with gaps
+    offsets, pos = [0] * len(dfas), 0
+    for i in reversed(range(len(dfas))):
+        offsets[i] = pos
+        pos += sizes[i] + 3
+    blocks, nb, rounds, _ = B.minimise_batch(dfas, offsets=offsets)
+    for i, d in enumerate(dfas):
+        np.testing.assert_array_equal(blocks[i], oracle.hopcroft(d.delta, d.accepting)[0])
+    bad = [W.random_dfa(10, 2, 0.5, 1), W.random_dfa(20, 2, 0.5, 2)]
+    bad[1].delta[3, 1] = 20
+    with pytest.raises(B.DfaError) as e:
+        B.minimise_batch(bad)
+    assert e.value.status == B.DFA_EINVAL
+
+
+def test_equivalent_batch():
+    rng = np.random.default_rng(9)
+    pairs, expected = [], []
+    for i in range(120):
+        n = int(rng.integers(1, 3000))
+        k = int(rng.integers(1, 7))
+        d = W.random_dfa(n, k, float(rng.uniform(0.05, 0.6)), 1000 + i)
+        if i % 3 == 0:
+            other, _ = W.permuted_copy(d, i)
+        elif i % 3 == 1:
+            other, _ = W.mutate_one(d, i)
+        else:
+            m = int(rng.integers(1, 40))
+            other = W.random_dfa(m, k, 0.5, 5000 + i)
+        pairs.append((d, other))
+        expected.append(oracle.equiv_hk(d.delta, d.accepting, d.start, other.delta,
+                                        other.accepting, other.start))
+    verdicts, st = B.equivalent_batch(pairs)
+    assert list(verdicts) == expected
+    assert sum(expected) > 20 and len(expected) - sum(expected) > 20
+
+
+def test_batch_workload_small_slice():
+    """The first DFAs of the 4,096-DFA batch workload (sizes log-uniform in
+    [64, 65536], k in 2..8) and their equivalence pairs."""
+    items = W.batch_workload(count=64, paired_from=32)
+    dfas = [it.dfa for it in items]
+    blocks, nb, rounds, _ = B.minimise_batch(dfas)
+    for i, d in enumerate(dfas):
+        ref, rnb, rrounds, _ = oracle.moore(d.delta, d.accepting)
+        np.testing.assert_array_equal(blocks[i], ref)
+        assert rounds[i] == rrounds
+    pairs = [(it.dfa, it.pair) for it in items if it.pair is not None]
+    verdicts, _ = B.equivalent_batch(pairs)
+    for (a, b), v in zip(pairs, verdicts):
+        assert v == oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
