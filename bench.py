@@ -59,6 +59,9 @@ def parse_args():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-plain comparison on the 4,096-DFA workload")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served request stream")
+    ap.add_argument("--serve-requests", type=int, default=96)
     return ap.parse_args()
 
 
@@ -156,6 +159,66 @@ def batch_leg(B, W, torch, np, count: int) -> dict:
             "speedup": tp / tb,
             "batched_transitions_per_s": work_b / tb,
             "plain_transitions_per_s": work_p / tp}
+
+
+def serve_leg(B, W, count: int) -> dict:
+    """Served requests: n log-uniform in [1,000, 4,194,304], k in {2,4,8,16},
+    80% minimise / 20% equivalence, 10% chain DFAs.  First a burst (all
+    requests submitted at once) gives the capacity; then a Poisson stream at
+    0.7x that rate gives p50/p99 latency; plain = the same requests one by
+    one through the single-request calls."""
+    reqs = W.serving_workload(count, rate=1.0)
+
+    def submit(srv, r):
+        return srv.submit_minimise(r.dfa) if r.kind == "minimise" else \
+            srv.submit_equivalent(r.dfa, r.other)
+
+    def plain_one(r):
+        if r.kind == "minimise":
+            B.minimise(r.dfa.delta, r.dfa.accepting)
+        else:
+            B.equivalent(r.dfa, r.other)
+
+    with B.Server(lanes=2) as srv:
+        for r in reqs[:4]:  # warm the lanes
+            srv.wait(submit(srv, r))
+        t0 = time.perf_counter()
+        tickets = [submit(srv, r) for r in reqs]
+        for t in tickets:
+            srv.wait(t)
+        burst_s = time.perf_counter() - t0
+    capacity = count / burst_s
+    rate = 0.7 * capacity
+    gaps = W._rng(55).exponential(1.0 / rate, size=count)
+    with B.Server(lanes=2) as srv:
+        for r in reqs[:4]:
+            srv.wait(submit(srv, r))
+        t0 = time.perf_counter()
+        tickets = []
+        due = t0
+        for r, g in zip(reqs, gaps):
+            due += g
+            delay = due - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(submit(srv, r))
+        lat = [srv.wait(t)["latency_ms"] for t in tickets]
+        stream_s = time.perf_counter() - t0
+    for r in reqs[:2]:
+        plain_one(r)
+    t0 = time.perf_counter()
+    for r in reqs:
+        plain_one(r)
+    plain_s = time.perf_counter() - t0
+    lat_sorted = sorted(lat)
+    pick = lambda q: lat_sorted[min(len(lat_sorted) - 1, int(q * (len(lat_sorted) - 1) + 0.5))]
+    return {"workload": (f"{count} requests, n log-uniform [1000, 4194304], k in {{2,4,8,16}}, "
+                         "80% minimise / 20% equivalence, 10% chain"),
+            "burst_requests_per_s": capacity,
+            "plain_requests_per_s": count / plain_s,
+            "speedup": (count / burst_s) / (count / plain_s),
+            "poisson_rate": rate, "p50_ms": pick(0.5), "p99_ms": pick(0.99),
+            "stream_requests_per_s": count / stream_s, "lanes": 2}
 
 
 def main() -> int:
@@ -276,6 +339,8 @@ def main() -> int:
             for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"])}
     if not args.no_batch:
         out["batched"] = batch_leg(B, W, torch, np, args.batch_count)
+    if not args.no_serve:
+        out["served"] = serve_leg(B, W, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, perm)
     print(json.dumps(out), flush=True)

@@ -58,7 +58,9 @@ extern "C" {
                             k mismatch, NULL required pointer */
 #define DFA_ENOMEM (-2)  /* device allocation failed / request exceeds the budget */
 #define DFA_EDEVICE (-3) /* a HIP runtime error */
+#define DFA_EAGAIN (-4)  /* served request not finished yet */
 #define DFA_ELIMIT (-5)  /* options.max_rounds reached before the partition was stable */
+#define DFA_ECANCELED (-6) /* served request cancelled when its server was destroyed */
 
 /* ---- partial transitive closure (Section 3.4, Algorithm 5) ---- */
 #define DFA_TC_OFF 0  /* refine on the input letters only */
@@ -262,6 +264,78 @@ int dfa_equivalent_batch(uint32_t count, const dfa_view *a, const dfa_view *b, i
 int dfa_equivalent_batch_device(uint32_t count, const dfa_view *a, const dfa_view *b,
                                 int32_t *verdicts, const dfa_options *opt,
                                 dfa_batch_stats *stats, void *stream);
+
+/*
+ * Served requests (continuous batching).  A server runs `lanes` workers,
+ * each with its own HIP stream and device workspace.  Submitted requests
+ * wait in FIFO order and are admitted while their device-memory footprint
+ * fits hbm_budget.  A free lane takes the head request: requests with more
+ * than batch_max_states states run alone (closure per tc_mode); smaller ones
+ * of the same kind are refined together (up to max_group, one segmented
+ * refinement, at most batch_round_budget rounds), and any that are not stable
+ * by then run again alone with the closure.  Lanes overlap on the device, so
+ * requests arriving while others run start as soon as a lane and memory are
+ * free.  Results are the same as the single-request calls and do not depend
+ * on the other requests in the mix.
+ */
+#define DFA_REQ_MINIMISE 0
+#define DFA_REQ_EQUIVALENT 1
+
+typedef struct dfa_server dfa_server;
+
+typedef struct dfa_server_config {
+    size_t hbm_budget;           /* device bytes for admitted requests (0 = half the free memory) */
+    uint32_t lanes;              /* concurrent workers / streams (1..16, default 2) */
+    uint32_t max_group;          /* requests per batched refinement (default 512) */
+    uint32_t batch_max_states;   /* larger requests run alone (default 2^18) */
+    uint32_t batch_round_budget; /* rounds of a batched refinement (>= 3, default 64) */
+    int32_t tc_mode;             /* closure for requests run alone (default DFA_TC_AUTO) */
+    uint32_t reserved[9];
+} dfa_server_config;
+
+typedef struct dfa_request {
+    int32_t kind;      /* DFA_REQ_MINIMISE or DFA_REQ_EQUIVALENT */
+    uint32_t reserved;
+    dfa_view a;        /* host view; copied by dfa_server_submit */
+    dfa_view b;        /* second operand of an equivalence request */
+} dfa_request;
+
+typedef struct dfa_result {
+    int32_t status;           /* DFA_OK or the request's error */
+    int32_t verdict;          /* equivalence: 1 if equivalent */
+    uint32_t num_blocks;      /* minimise */
+    uint32_t rounds;          /* rounds of the request's own refinement */
+    const uint32_t *blocks;   /* minimise: n canonical block ids, owned by the server
+                                 until dfa_result_release */
+    uint32_t n;
+    uint32_t batched;         /* 1 if it ran in a batched refinement */
+    double queue_ms;          /* submit -> start */
+    double service_ms;        /* start -> done (of its group) */
+    double latency_ms;        /* submit -> done */
+} dfa_result;
+
+typedef struct dfa_server_stats {
+    uint64_t submitted, completed, rejected, pending;
+    uint64_t batched_groups, solo_runs;
+    double p50_ms, p99_ms, mean_ms; /* latency of completed requests */
+    double uptime_s, requests_per_s;
+    uint64_t hbm_in_use, hbm_budget;
+} dfa_server_stats;
+
+void dfa_server_config_default(dfa_server_config *cfg);
+/* NULL on failure (see dfa_last_error).  Uses the current HIP device. */
+dfa_server *dfa_server_create(const dfa_server_config *cfg);
+/* Copies the request's arrays; DFA_ENOMEM if it can never fit the budget. */
+int dfa_server_submit(dfa_server *s, const dfa_request *req, uint64_t *ticket);
+/* DFA_EAGAIN while the request runs or waits. */
+int dfa_server_poll(dfa_server *s, uint64_t ticket, dfa_result *out);
+int dfa_server_wait(dfa_server *s, uint64_t ticket, dfa_result *out);
+/* Frees a finished request's result (the blocks pointer becomes invalid). */
+int dfa_result_release(dfa_server *s, uint64_t ticket);
+int dfa_server_get_stats(dfa_server *s, dfa_server_stats *out);
+/* Cancels waiting requests (status DFA_ECANCELED), waits for running ones,
+ * frees the lanes.  Results not released are freed too. */
+void dfa_server_destroy(dfa_server *s);
 
 /* Description of the last failure on the calling thread ("" if none). */
 const char *dfa_last_error(void);

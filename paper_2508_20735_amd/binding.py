@@ -23,7 +23,11 @@ DFA_OK = 0
 DFA_EINVAL = -1
 DFA_ENOMEM = -2
 DFA_EDEVICE = -3
+DFA_EAGAIN = -4
 DFA_ELIMIT = -5
+DFA_ECANCELED = -6
+REQ_MINIMISE = 0
+REQ_EQUIVALENT = 1
 
 TC = {"off": 0, "on": 1, "auto": 2}
 LOOP = {"host": 0, "chunk": 1, "graph": 2}
@@ -90,13 +94,49 @@ class View(ctypes.Structure):
                 ("delta", ctypes.c_void_p), ("accepting", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("lanes", ctypes.c_uint32),
+                ("max_group", ctypes.c_uint32), ("batch_max_states", ctypes.c_uint32),
+                ("batch_round_budget", ctypes.c_uint32), ("tc_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 9)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_uint32), ("a", View),
+                ("b", View)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("verdict", ctypes.c_int32),
+                ("num_blocks", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+                ("blocks", ctypes.POINTER(ctypes.c_uint32)), ("n", ctypes.c_uint32),
+                ("batched", ctypes.c_uint32), ("queue_ms", ctypes.c_double),
+                ("service_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+                ("batched_groups", ctypes.c_uint64), ("solo_runs", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("uptime_s", ctypes.c_double),
+                ("requests_per_s", ctypes.c_double), ("hbm_in_use", ctypes.c_uint64),
+                ("hbm_budget", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
                   "dfa_equivalent", "dfa_equivalent_device", "dfa_included",
                   "dfa_included_device", "dfa_last_error", "dfa_device_info",
                   "dfa_tuning_default", "dfa_get_tuning", "dfa_set_tuning",
                   "dfa_profile_enable", "dfa_profile_read", "dfa_minimise_batch",
                   "dfa_minimise_batch_device", "dfa_equivalent_batch",
-                  "dfa_equivalent_batch_device"])
+                  "dfa_equivalent_batch_device", "dfa_server_config_default",
+                  "dfa_server_create", "dfa_server_submit", "dfa_server_poll",
+                  "dfa_server_wait", "dfa_result_release", "dfa_server_get_stats",
+                  "dfa_server_destroy"])
 
 _lock = threading.Lock()
 _lib = None
@@ -153,6 +193,17 @@ def load(build_if_missing: bool = True):
                                              P(BatchStats)]
         lib.dfa_equivalent_batch_device.argtypes = [u32, P(View), P(View), vp, P(Options),
                                                     P(BatchStats), vp]
+        lib.dfa_server_config_default.argtypes = [P(ServerConfig)]
+        lib.dfa_server_config_default.restype = None
+        lib.dfa_server_create.argtypes = [P(ServerConfig)]
+        lib.dfa_server_create.restype = vp
+        lib.dfa_server_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
+        lib.dfa_server_poll.argtypes = [vp, ctypes.c_uint64, P(Result)]
+        lib.dfa_server_wait.argtypes = [vp, ctypes.c_uint64, P(Result)]
+        lib.dfa_result_release.argtypes = [vp, ctypes.c_uint64]
+        lib.dfa_server_get_stats.argtypes = [vp, P(ServerStats)]
+        lib.dfa_server_destroy.argtypes = [vp]
+        lib.dfa_server_destroy.restype = None
         lib.dfa_profile_enable.argtypes = [i32]
         lib.dfa_profile_read.argtypes = [P(KernelTime), i32, P(i32)]
         for fn in ("dfa_minimise", "dfa_minimise_device", "dfa_equivalent",
@@ -160,7 +211,8 @@ def load(build_if_missing: bool = True):
                    "dfa_device_info", "dfa_get_tuning", "dfa_set_tuning",
                    "dfa_profile_enable", "dfa_profile_read", "dfa_minimise_batch",
                    "dfa_minimise_batch_device", "dfa_equivalent_batch",
-                   "dfa_equivalent_batch_device"):
+                   "dfa_equivalent_batch_device", "dfa_server_submit", "dfa_server_poll",
+                   "dfa_server_wait", "dfa_result_release", "dfa_server_get_stats"):
             getattr(lib, fn).restype = i32
         _lib = lib
         return lib
@@ -474,3 +526,95 @@ def equivalent_batch_device(a_list, b_list, *, loop: str = "graph", lds_stage=2,
                                               ctypes.byref(o), ctypes.byref(st),
                                               _stream_ptr(stream)))
     return verdicts.astype(bool), st.as_dict()
+
+
+# --------------------------------------------------------------------------- serving
+
+class Server:
+    """dfa_server_*: continuous batching of minimise / equivalence requests."""
+
+    def __init__(self, hbm_budget: int = 0, lanes: int = 2, max_group: int = 512,
+                 batch_max_states: int = 1 << 18, batch_round_budget: int = 64,
+                 tc: str = "auto"):
+        lib = load()
+        cfg = ServerConfig()
+        lib.dfa_server_config_default(ctypes.byref(cfg))
+        cfg.hbm_budget = hbm_budget
+        cfg.lanes = lanes
+        cfg.max_group = max_group
+        cfg.batch_max_states = batch_max_states
+        cfg.batch_round_budget = batch_round_budget
+        cfg.tc_mode = TC[tc]
+        h = lib.dfa_server_create(ctypes.byref(cfg))
+        if not h:
+            raise DfaError(DFA_EINVAL, lib.dfa_last_error().decode(errors="replace"))
+        self._h = h
+        self._lib = lib
+
+    def submit_minimise(self, dfa) -> int:
+        return self._submit(REQ_MINIMISE, dfa, None)
+
+    def submit_equivalent(self, a, b) -> int:
+        return self._submit(REQ_EQUIVALENT, a, b)
+
+    def _submit(self, kind, a, b) -> int:
+        req = Request()
+        req.kind = kind
+        va, keep_a = _view_host(a)
+        req.a = va
+        if b is not None:
+            vb, keep_b = _view_host(b)
+            req.b = vb
+        t = ctypes.c_uint64()
+        _check(self._lib.dfa_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        return int(t.value)
+
+    def _convert(self, r: Result) -> dict:
+        out = {"status": r.status, "verdict": bool(r.verdict), "num_blocks": r.num_blocks,
+               "rounds": r.rounds, "batched": bool(r.batched), "queue_ms": r.queue_ms,
+               "service_ms": r.service_ms, "latency_ms": r.latency_ms, "blocks": None}
+        if r.blocks:
+            out["blocks"] = np.ctypeslib.as_array(r.blocks, shape=(r.n,)).copy()
+        return out
+
+    def poll(self, ticket: int):
+        """Result dict, or None while the request is not finished."""
+        r = Result()
+        rc = self._lib.dfa_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc == DFA_EAGAIN:
+            return None
+        _check(rc)
+        return self._convert(r)
+
+    def wait(self, ticket: int, release: bool = True) -> dict:
+        r = Result()
+        _check(self._lib.dfa_server_wait(self._h, ticket, ctypes.byref(r)))
+        out = self._convert(r)
+        if release:
+            self.release(ticket)
+        return out
+
+    def release(self, ticket: int) -> None:
+        _check(self._lib.dfa_result_release(self._h, ticket))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.dfa_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.dfa_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,7 +9,13 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <memory>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -981,7 +987,8 @@ int minimise_batch_impl(Ctx &c, uint32_t count, const dfa_view *views, uint32_t 
 }
 
 int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_view *b,
-                          int32_t *verdicts, const dfa_options &o, dfa_batch_stats *st) {
+                          int32_t *verdicts, const dfa_options &o, dfa_batch_stats *st,
+                          uint32_t *rounds_out = nullptr) {
     std::vector<Part> parts(2 * static_cast<size_t>(count));
     uint64_t off = 0;
     uint32_t kmax = 0;
@@ -1014,6 +1021,8 @@ int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_v
                            c.stream));
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
     HIP_TRY(hipStreamSynchronize(c.stream));
+    if (rounds_out)
+        for (uint32_t i = 0; i < count; ++i) rounds_out[i] = changing[i] + 1;
     if (st) {
         uint64_t transitions = 0;
         for (uint32_t i = 0; i < count; ++i)
@@ -1027,6 +1036,378 @@ int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_v
         return fail(DFA_ELIMIT, "max_rounds (%u) reached before every verdict was known",
                     o.max_rounds);
     return DFA_OK;
+}
+
+// dfa_minimise on an initialised context (host pointers in and out).
+int minimise_host(Ctx &c_, uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *accepting,
+                  uint32_t *block_out, dfa_quotient *q_out, const dfa_options &o,
+                  dfa_stats *stats) {
+    Ctx *c = &c_;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    const size_t nk = static_cast<size_t>(n) * k;
+    DFA_TRY(c->stage_delta.ensure(nk * sizeof(uint32_t), "input copy"));
+    DFA_TRY(c->stage_acc.ensure(n, "input copy"));
+    DFA_TRY(c->stage_block.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "output copy"));
+    if (q_out) {
+        DFA_TRY(c->stage_qdelta.ensure(nk * sizeof(uint32_t), "quotient copy"));
+        DFA_TRY(c->stage_qacc.ensure(n, "quotient copy"));
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_TRY(hipMemcpyAsync(c->stage_delta.p, delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->stage_acc.p, accepting, n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double h2d = ms_since(t0);
+    dfa_quotient dq{};
+    if (q_out) {
+        dq.delta = c->stage_qdelta.as<uint32_t>();
+        dq.accepting = c->stage_qacc.as<uint8_t>();
+    }
+    int rc = minimise_impl(*c, n, k, c->stage_delta.as<uint32_t>(), c->stage_acc.as<uint8_t>(),
+                           c->stage_block.as<uint32_t>(), q_out ? &dq : nullptr, o, stats);
+    if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
+    t0 = std::chrono::steady_clock::now();
+    HIP_TRY(hipMemcpyAsync(block_out, c->stage_block.p, static_cast<size_t>(n) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    if (q_out) {
+        HIP_TRY(hipMemcpyAsync(q_out->delta, dq.delta,
+                               static_cast<size_t>(dq.num_blocks) * k * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(q_out->accepting, dq.accepting, dq.num_blocks,
+                               hipMemcpyDeviceToHost, c->stream));
+        q_out->num_blocks = dq.num_blocks;
+        q_out->start = dq.start;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (stats) {
+        stats->h2d_ms = h2d;
+        stats->d2h_ms = ms_since(t0);
+    }
+    return rc;
+}
+
+
+int stage_view(Buffer &bd, Buffer &ba, const dfa_view *v, dfa_view &out, hipStream_t s) {
+    const size_t nk = static_cast<size_t>(v->n) * v->k;
+    DFA_TRY(bd.ensure(nk * sizeof(uint32_t), "input copy"));
+    DFA_TRY(ba.ensure(v->n, "input copy"));
+    HIP_TRY(hipMemcpyAsync(bd.p, v->delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ba.p, v->accepting, v->n, hipMemcpyHostToDevice, s));
+    out = *v;
+    out.delta = bd.as<uint32_t>();
+    out.accepting = ba.as<uint8_t>();
+    return DFA_OK;
+}
+
+
+// dfa_equivalent on an initialised context (host views).
+int equivalent_host(Ctx &c, const dfa_view *a, const dfa_view *b, int *verdict,
+                    const dfa_options &o, dfa_stats *stats) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    auto t0 = std::chrono::steady_clock::now();
+    dfa_view da, db;
+    DFA_TRY(stage_view(c.stage_delta, c.stage_acc, a, da, c.stream));
+    DFA_TRY(stage_view(c.stage_delta_b, c.stage_acc_b, b, db, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    const double h2d = ms_since(t0);
+    int rc = equivalent_impl(c, da, db, verdict, o, stats);
+    if (stats) stats->h2d_ms = h2d;
+    return rc;
+}
+
+
+// ---- served requests ----
+//
+// A server owns `lanes` workers; each has its own stream and workspace (a
+// private Ctx).  Requests wait in a FIFO and are admitted while their HBM
+// footprint fits the budget.  A free lane takes the head request: a large
+// one runs alone (closure on demand); small ones of the same kind are taken
+// together, up to max_group, and refined as one segmented union with a
+// round budget; any that are not stable within it (chain-like DFAs) are run
+// again alone with the closure.  Lanes run concurrently, so requests that
+// arrive while others are on the GPU start as soon as a lane and memory are
+// free, and their kernels overlap on the device.  Results are canonical, so
+// a request's result does not depend on the requests it ran with.
+
+void release_ctx(Ctx &c) {
+    Buffer *bufs[] = {&c.cols, &c.tc_cols, &c.colmap, &c.blockA, &c.blockB, &c.sig, &c.hash,
+                      &c.table, &c.ctl, &c.flags, &c.canon, &c.dense, &c.leader_of, &c.partials,
+                      &c.scalars, &c.multi, &c.active, &c.accbits, &c.counters, &c.presence,
+                      &c.presence_packed, &c.lab8, &c.stage_delta, &c.stage_acc, &c.stage_block,
+                      &c.stage_qdelta, &c.stage_qacc, &c.stage_delta_b, &c.stage_acc_b,
+                      &c.visited, &c.visited2, &c.front0, &c.front1, &c.parts, &c.tile_part,
+                      &c.seg_words, &c.batch_in, &c.batch_out};
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    for (Buffer *b : bufs) {
+        if (b->p) (void)hipFree(b->p);
+        b->p = nullptr;
+        b->cap = 0;
+    }
+    if (c.graph) (void)hipGraphExecDestroy(c.graph);
+    c.graph = nullptr;
+    for (hipEvent_t e : c.evpool) (void)hipEventDestroy(e);
+    c.evpool.clear();
+    if (c.ev_start) (void)hipEventDestroy(c.ev_start);
+    if (c.ev_stop) (void)hipEventDestroy(c.ev_stop);
+    if (c.ev_in) (void)hipEventDestroy(c.ev_in);
+    if (c.pinned) (void)hipHostFree(c.pinned);
+    if (c.pinned_batch) (void)hipHostFree(c.pinned_batch);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    c.ev_start = c.ev_stop = c.ev_in = nullptr;
+    c.pinned = nullptr;
+    c.pinned_batch = nullptr;
+    c.pinned_batch_cap = 0;
+    c.stream = nullptr;
+    c.inited = false;
+}
+
+using Clock = std::chrono::steady_clock;
+
+struct ServedRequest {
+    uint64_t ticket = 0;
+    int kind = DFA_REQ_MINIMISE;
+    dfa_view a{}, b{};
+    std::vector<uint32_t> da, db;
+    std::vector<uint8_t> aa, ab;
+    size_t footprint = 0;
+    size_t states = 0;
+    Clock::time_point t_submit, t_start, t_done;
+    bool done = false;
+    int status = DFA_OK;
+    int verdict = 0;
+    uint32_t num_blocks = 0, rounds = 0;
+    bool batched = false;
+    std::vector<uint32_t> blocks;
+};
+
+struct Server {
+    int device = 0;
+    dfa_server_config cfg{};
+    dfa_tuning tune{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<ServedRequest *> pending;
+    std::unordered_map<uint64_t, std::unique_ptr<ServedRequest>> requests;
+    size_t in_use = 0;
+    bool stopping = false;
+    uint64_t next_ticket = 1;
+    uint64_t submitted = 0, completed = 0, rejected = 0, groups = 0, solo = 0;
+    std::vector<double> latencies;
+    Clock::time_point t_created;
+    std::vector<std::thread> workers;
+    std::vector<std::unique_ptr<Ctx>> lanes;
+};
+
+// Device bytes a request may occupy while it runs (inputs, columns,
+// signatures, hashes, table, block buffers and marks, outputs).
+size_t request_footprint(uint64_t n, uint32_t k, bool closure) {
+    uint64_t bytes = n * (4ull * k + 1)        // input copy
+                     + n * 4ull * k            // columns
+                     + n * 4ull * (k + 1)      // signature rows
+                     + n * 8ull                // hashes
+                     + n * 32ull               // table (2n slots of 8 bytes, rounded up)
+                     + n * 4ull * 6            // blocks A/B, marks, canonical ids, output, scratch
+                     + (1u << 22);             // fixed buffers
+    if (closure) {
+        uint32_t L = floor_log2(std::max<uint64_t>(n, 1));
+        bytes += n * 4ull * k * (L + 1);
+    }
+    return bytes;
+}
+
+void finish(Server &s, ServedRequest *r, const std::lock_guard<std::mutex> &) {
+    r->t_done = Clock::now();
+    r->done = true;
+    s.completed++;
+    s.latencies.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+}
+
+// Runs one request alone on a lane (closure on demand).
+void run_solo(Server &s, Ctx &c, ServedRequest *r) {
+    dfa_options o;
+    dfa_options_default(&o);
+    o.tc_mode = s.cfg.tc_mode;
+    o.loop_mode = DFA_LOOP_CHUNK;
+    dfa_stats st{};
+    if (r->kind == DFA_REQ_MINIMISE) {
+        r->blocks.resize(r->a.n);
+        r->status = minimise_host(c, r->a.n, r->a.k, r->a.delta, r->a.accepting, r->blocks.data(),
+                                  nullptr, o, &st);
+        r->num_blocks = st.num_blocks;
+        r->rounds = st.rounds;
+    } else {
+        int v = 0;
+        r->status = equivalent_host(c, &r->a, &r->b, &v, o, &st);
+        r->verdict = v;
+        r->rounds = st.rounds;
+    }
+    r->batched = false;
+}
+
+// Runs a group of small requests of one kind as one segmented refinement;
+// the ones that are not stable within the round budget run again alone.
+void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
+    dfa_options o;
+    dfa_options_default(&o);
+    o.tc_mode = DFA_TC_OFF;
+    o.loop_mode = DFA_LOOP_CHUNK;
+    o.max_rounds = s.cfg.batch_round_budget;
+    const uint32_t count = static_cast<uint32_t>(grp.size());
+    std::vector<uint32_t> rounds(count), nb(count);
+    dfa_batch_stats bs{};
+    std::vector<bool> redo(count, false);
+    int rc;
+    if (grp[0]->kind == DFA_REQ_MINIMISE) {
+        std::vector<dfa_view> views(count);
+        for (uint32_t i = 0; i < count; ++i) views[i] = grp[i]->a;
+        std::vector<dfa_view> dev;
+        double h2d = 0;
+        const dfa_view *lists[1] = {views.data()};
+        rc = stage_views(c, count, lists, 1, dev, h2d);
+        uint64_t total = 0;
+        for (auto *r : grp) total += r->a.n;
+        if (rc == DFA_OK) rc = c.batch_out.ensure(total * sizeof(uint32_t), "batched outputs");
+        if (rc == DFA_OK)
+            rc = minimise_batch_impl(c, count, dev.data(), c.batch_out.as<uint32_t>(), nullptr,
+                                     nb.data(), rounds.data(), o, &bs);
+        if (rc == DFA_OK || rc == DFA_ELIMIT) {
+            int rc2 = ensure_pinned_batch(c, total * sizeof(uint32_t));
+            if (rc2 == DFA_OK && hipMemcpyAsync(c.pinned_batch, c.batch_out.p,
+                                                total * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                                c.stream) == hipSuccess &&
+                hipStreamSynchronize(c.stream) == hipSuccess) {
+                const uint32_t *src = reinterpret_cast<const uint32_t *>(c.pinned_batch);
+                uint64_t pos = 0;
+                for (uint32_t i = 0; i < count; ++i) {
+                    ServedRequest *r = grp[i];
+                    // a DFA that changed in every round may not be stable yet
+                    redo[i] = rc == DFA_ELIMIT && rounds[i] > bs.rounds;
+                    if (!redo[i]) {
+                        r->blocks.assign(src + pos, src + pos + r->a.n);
+                        r->num_blocks = nb[i];
+                        r->rounds = rounds[i];
+                        r->status = DFA_OK;
+                        r->batched = true;
+                    }
+                    pos += r->a.n;
+                }
+                rc = DFA_OK;
+            } else {
+                rc = rc2 != DFA_OK ? rc2 : fail(DFA_EDEVICE, "copy of batched results failed");
+            }
+        }
+    } else {
+        std::vector<dfa_view> va(count), vb(count);
+        for (uint32_t i = 0; i < count; ++i) {
+            va[i] = grp[i]->a;
+            vb[i] = grp[i]->b;
+        }
+        std::vector<dfa_view> dev;
+        double h2d = 0;
+        const dfa_view *lists[2] = {va.data(), vb.data()};
+        rc = stage_views(c, count, lists, 2, dev, h2d);
+        std::vector<int32_t> verdicts(count);
+        if (rc == DFA_OK)
+            rc = equivalent_batch_impl(c, count, dev.data(), dev.data() + count, verdicts.data(),
+                                       o, &bs, rounds.data());
+        if (rc == DFA_OK || rc == DFA_ELIMIT) {
+            for (uint32_t i = 0; i < count; ++i) {
+                redo[i] = rc == DFA_ELIMIT && rounds[i] > bs.rounds;
+                if (!redo[i]) {
+                    grp[i]->verdict = verdicts[i];
+                    grp[i]->rounds = rounds[i];
+                    grp[i]->status = DFA_OK;
+                    grp[i]->batched = true;
+                }
+            }
+            rc = DFA_OK;
+        }
+    }
+    for (uint32_t i = 0; i < count; ++i) {
+        if (rc != DFA_OK) {
+            grp[i]->status = rc;
+        } else if (redo[i]) {
+            run_solo(s, c, grp[i]);
+        }
+    }
+}
+
+void lane_main(Server *sp, size_t lane) {
+    Server &s = *sp;
+    (void)hipSetDevice(s.device);
+    Ctx &c = *s.lanes[lane];
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        if (init_ctx(c) == DFA_OK) c.tune = s.tune;
+    }
+    for (;;) {
+        std::vector<ServedRequest *> grp;
+        size_t fp = 0;
+        {
+            std::unique_lock<std::mutex> lk(s.mu);
+            s.cv_work.wait(lk, [&] {
+                return s.stopping ||
+                       (!s.pending.empty() && s.in_use + s.pending.front()->footprint <= s.cfg.hbm_budget);
+            });
+            if (s.stopping) return;
+            ServedRequest *head = s.pending.front();
+            s.pending.pop_front();
+            grp.push_back(head);
+            fp = head->footprint;
+            const bool small = head->states <= s.cfg.batch_max_states;
+            if (small) {
+                for (auto it = s.pending.begin();
+                     it != s.pending.end() && grp.size() < s.cfg.max_group;) {
+                    ServedRequest *r = *it;
+                    if (r->kind == head->kind && r->states <= s.cfg.batch_max_states &&
+                        s.in_use + fp + r->footprint <= s.cfg.hbm_budget) {
+                        grp.push_back(r);
+                        fp += r->footprint;
+                        it = s.pending.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            s.in_use += fp;
+            const auto now = Clock::now();
+            for (auto *r : grp) r->t_start = now;
+            if (grp.size() > 1 || small) s.groups++;
+        }
+        {
+            std::lock_guard<std::mutex> g(c.mu);
+            g_last_error.clear();
+            if (grp.size() == 1 && grp[0]->states > s.cfg.batch_max_states) {
+                run_solo(s, c, grp[0]);
+            } else {
+                run_group(s, c, grp);
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(s.mu);
+            s.in_use -= fp;
+            for (auto *r : grp) {
+                if (!r->batched) s.solo++;
+                finish(s, r, lk);
+            }
+        }
+        s.cv_done.notify_all();
+        s.cv_work.notify_all();
+    }
+}
+
+void fill_result(const ServedRequest &r, dfa_result *out) {
+    std::memset(out, 0, sizeof *out);
+    out->status = r.status;
+    out->verdict = r.verdict;
+    out->num_blocks = r.num_blocks;
+    out->rounds = r.rounds;
+    out->blocks = r.kind == DFA_REQ_MINIMISE && r.status == DFA_OK ? r.blocks.data() : nullptr;
+    out->n = r.a.n;
+    out->batched = r.batched ? 1 : 0;
+    out->queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
+    out->service_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_start).count();
+    out->latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
 }
 
 }  // namespace
@@ -1153,59 +1534,7 @@ int dfa_minimise(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *a
     DFA_TRY(get_ctx(c));
     std::lock_guard<std::mutex> lock(c->mu);
     DFA_TRY(init_ctx(*c));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    const size_t nk = static_cast<size_t>(n) * k;
-    DFA_TRY(c->stage_delta.ensure(nk * sizeof(uint32_t), "input copy"));
-    DFA_TRY(c->stage_acc.ensure(n, "input copy"));
-    DFA_TRY(c->stage_block.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "output copy"));
-    if (q_out) {
-        DFA_TRY(c->stage_qdelta.ensure(nk * sizeof(uint32_t), "quotient copy"));
-        DFA_TRY(c->stage_qacc.ensure(n, "quotient copy"));
-    }
-    auto t0 = std::chrono::steady_clock::now();
-    HIP_TRY(hipMemcpyAsync(c->stage_delta.p, delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice,
-                           c->stream));
-    HIP_TRY(hipMemcpyAsync(c->stage_acc.p, accepting, n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    const double h2d = ms_since(t0);
-    dfa_quotient dq{};
-    if (q_out) {
-        dq.delta = c->stage_qdelta.as<uint32_t>();
-        dq.accepting = c->stage_qacc.as<uint8_t>();
-    }
-    int rc = minimise_impl(*c, n, k, c->stage_delta.as<uint32_t>(), c->stage_acc.as<uint8_t>(),
-                           c->stage_block.as<uint32_t>(), q_out ? &dq : nullptr, o, stats);
-    if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
-    t0 = std::chrono::steady_clock::now();
-    HIP_TRY(hipMemcpyAsync(block_out, c->stage_block.p, static_cast<size_t>(n) * sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, c->stream));
-    if (q_out) {
-        HIP_TRY(hipMemcpyAsync(q_out->delta, dq.delta,
-                               static_cast<size_t>(dq.num_blocks) * k * sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipMemcpyAsync(q_out->accepting, dq.accepting, dq.num_blocks,
-                               hipMemcpyDeviceToHost, c->stream));
-        q_out->num_blocks = dq.num_blocks;
-        q_out->start = dq.start;
-    }
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (stats) {
-        stats->h2d_ms = h2d;
-        stats->d2h_ms = ms_since(t0);
-    }
-    return rc;
-}
-
-static int stage_view(Buffer &bd, Buffer &ba, const dfa_view *v, dfa_view &out, hipStream_t s) {
-    const size_t nk = static_cast<size_t>(v->n) * v->k;
-    DFA_TRY(bd.ensure(nk * sizeof(uint32_t), "input copy"));
-    DFA_TRY(ba.ensure(v->n, "input copy"));
-    HIP_TRY(hipMemcpyAsync(bd.p, v->delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ba.p, v->accepting, v->n, hipMemcpyHostToDevice, s));
-    out = *v;
-    out.delta = bd.as<uint32_t>();
-    out.accepting = ba.as<uint8_t>();
-    return DFA_OK;
+    return minimise_host(*c, n, k, delta, accepting, block_out, q_out, o, stats);
 }
 
 int dfa_equivalent_device(const dfa_view *a, const dfa_view *b, int *verdict,
@@ -1233,16 +1562,7 @@ int dfa_equivalent(const dfa_view *a, const dfa_view *b, int *verdict, const dfa
     DFA_TRY(get_ctx(c));
     std::lock_guard<std::mutex> lock(c->mu);
     DFA_TRY(init_ctx(*c));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    auto t0 = std::chrono::steady_clock::now();
-    dfa_view da, db;
-    DFA_TRY(stage_view(c->stage_delta, c->stage_acc, a, da, c->stream));
-    DFA_TRY(stage_view(c->stage_delta_b, c->stage_acc_b, b, db, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    const double h2d = ms_since(t0);
-    int rc = equivalent_impl(*c, da, db, verdict, o, stats);
-    if (stats) stats->h2d_ms = h2d;
-    return rc;
+    return equivalent_host(*c, a, b, verdict, o, stats);
 }
 
 int dfa_included_device(const dfa_view *a, const dfa_view *b, int *verdict,
@@ -1385,6 +1705,192 @@ int dfa_equivalent_batch(uint32_t count, const dfa_view *a, const dfa_view *b, i
     int rc = equivalent_batch_impl(*c, count, dev.data(), dev.data() + count, verdicts, o, stats);
     if (stats) stats->h2d_ms = h2d;
     return rc;
+}
+
+
+void dfa_server_config_default(dfa_server_config *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->hbm_budget = 0;
+    cfg->lanes = 2;
+    cfg->max_group = 512;
+    cfg->batch_max_states = 1u << 18;
+    cfg->batch_round_budget = 64;
+    cfg->tc_mode = DFA_TC_AUTO;
+}
+
+dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
+    g_last_error.clear();
+    dfa_server_config cfg;
+    dfa_server_config_default(&cfg);
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.lanes == 0 || cfg.lanes > 16 || cfg.max_group == 0 || cfg.batch_round_budget < 3 ||
+        cfg.tc_mode < DFA_TC_OFF || cfg.tc_mode > DFA_TC_AUTO) {
+        fail(DFA_EINVAL, "bad server configuration");
+        return nullptr;
+    }
+    auto s = std::make_unique<Server>();
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        fail(DFA_EDEVICE, "no HIP device");
+        return nullptr;
+    }
+    if (cfg.hbm_budget == 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            fail(DFA_EDEVICE, "hipMemGetInfo failed");
+            return nullptr;
+        }
+        cfg.hbm_budget = free_b / 2;
+    }
+    s->cfg = cfg;
+    {
+        Ctx *dc = nullptr;
+        if (get_ctx(dc) != DFA_OK) return nullptr;
+        std::lock_guard<std::mutex> lock(dc->mu);
+        if (init_ctx(*dc) != DFA_OK) return nullptr;
+        s->tune = dc->tune;
+    }
+    s->t_created = Clock::now();
+    for (uint32_t i = 0; i < cfg.lanes; ++i) s->lanes.push_back(std::make_unique<Ctx>());
+    Server *raw = s.get();
+    for (uint32_t i = 0; i < cfg.lanes; ++i) s->workers.emplace_back(lane_main, raw, i);
+    return reinterpret_cast<dfa_server *>(s.release());
+}
+
+int dfa_server_submit(dfa_server *handle, const dfa_request *req, uint64_t *ticket) {
+    g_last_error.clear();
+    Server *s = reinterpret_cast<Server *>(handle);
+    if (!s || !req || !ticket) return fail(DFA_EINVAL, "NULL server, request or ticket");
+    if (req->kind != DFA_REQ_MINIMISE && req->kind != DFA_REQ_EQUIVALENT)
+        return fail(DFA_EINVAL, "unknown request kind %d", req->kind);
+    DFA_TRY(check_view(&req->a, "a"));
+    if (req->kind == DFA_REQ_EQUIVALENT) {
+        DFA_TRY(check_view(&req->b, "b"));
+        if (req->a.k != req->b.k) return fail(DFA_EINVAL, "alphabet sizes differ");
+    }
+    auto r = std::make_unique<ServedRequest>();
+    r->kind = req->kind;
+    const size_t na = static_cast<size_t>(req->a.n) * req->a.k;
+    r->da.assign(req->a.delta, req->a.delta + na);
+    r->aa.assign(req->a.accepting, req->a.accepting + req->a.n);
+    r->a = req->a;
+    r->a.delta = r->da.data();
+    r->a.accepting = r->aa.data();
+    r->states = req->a.n;
+    if (req->kind == DFA_REQ_EQUIVALENT) {
+        const size_t nb = static_cast<size_t>(req->b.n) * req->b.k;
+        r->db.assign(req->b.delta, req->b.delta + nb);
+        r->ab.assign(req->b.accepting, req->b.accepting + req->b.n);
+        r->b = req->b;
+        r->b.delta = r->db.data();
+        r->b.accepting = r->ab.data();
+        r->states += req->b.n;
+    }
+    r->footprint = request_footprint(r->states, req->a.k, s->cfg.tc_mode != DFA_TC_OFF);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (r->footprint > s->cfg.hbm_budget) {
+        s->rejected++;
+        return fail(DFA_ENOMEM, "request needs ~%zu bytes of device memory, budget is %zu",
+                    r->footprint, s->cfg.hbm_budget);
+    }
+    r->ticket = s->next_ticket++;
+    r->t_submit = Clock::now();
+    *ticket = r->ticket;
+    s->pending.push_back(r.get());
+    s->requests.emplace(r->ticket, std::move(r));
+    s->submitted++;
+    s->cv_work.notify_one();
+    return DFA_OK;
+}
+
+int dfa_server_poll(dfa_server *handle, uint64_t ticket, dfa_result *out) {
+    Server *s = reinterpret_cast<Server *>(handle);
+    if (!s || !out) return fail(DFA_EINVAL, "NULL server or result");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return fail(DFA_EINVAL, "unknown ticket %llu",
+                                             static_cast<unsigned long long>(ticket));
+    if (!it->second->done) return DFA_EAGAIN;
+    fill_result(*it->second, out);
+    return DFA_OK;
+}
+
+int dfa_server_wait(dfa_server *handle, uint64_t ticket, dfa_result *out) {
+    Server *s = reinterpret_cast<Server *>(handle);
+    if (!s || !out) return fail(DFA_EINVAL, "NULL server or result");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return fail(DFA_EINVAL, "unknown ticket %llu",
+                                             static_cast<unsigned long long>(ticket));
+    ServedRequest *r = it->second.get();
+    s->cv_done.wait(lk, [&] { return r->done; });
+    fill_result(*r, out);
+    return DFA_OK;
+}
+
+int dfa_result_release(dfa_server *handle, uint64_t ticket) {
+    Server *s = reinterpret_cast<Server *>(handle);
+    if (!s) return fail(DFA_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end() || !it->second->done)
+        return fail(DFA_EINVAL, "ticket %llu is unknown or not finished",
+                    static_cast<unsigned long long>(ticket));
+    s->requests.erase(it);
+    return DFA_OK;
+}
+
+int dfa_server_get_stats(dfa_server *handle, dfa_server_stats *out) {
+    Server *s = reinterpret_cast<Server *>(handle);
+    if (!s || !out) return fail(DFA_EINVAL, "NULL server or stats");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof *out);
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->rejected = s->rejected;
+    out->batched_groups = s->groups;
+    out->solo_runs = s->solo;
+    out->pending = s->pending.size();
+    out->hbm_in_use = s->in_use;
+    out->hbm_budget = s->cfg.hbm_budget;
+    std::vector<double> lat = s->latencies;
+    if (!lat.empty()) {
+        std::sort(lat.begin(), lat.end());
+        auto pct = [&](double p) {
+            size_t i = static_cast<size_t>(p * (lat.size() - 1) + 0.5);
+            return lat[std::min(i, lat.size() - 1)];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double sum = 0;
+        for (double v : lat) sum += v;
+        out->mean_ms = sum / lat.size();
+    }
+    out->uptime_s = std::chrono::duration<double>(Clock::now() - s->t_created).count();
+    out->requests_per_s = out->uptime_s > 0 ? s->completed / out->uptime_s : 0.0;
+    return DFA_OK;
+}
+
+void dfa_server_destroy(dfa_server *handle) {
+    Server *s = reinterpret_cast<Server *>(handle);
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        for (ServedRequest *r : s->pending) {
+            r->status = DFA_ECANCELED;
+            r->t_start = Clock::now();
+            r->done = true;
+            r->t_done = r->t_start;
+        }
+        s->pending.clear();
+    }
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+    for (auto &t : s->workers) t.join();
+    (void)hipSetDevice(s->device);
+    for (auto &c : s->lanes) release_ctx(*c);
+    delete s;
 }
 
 }  // extern "C"

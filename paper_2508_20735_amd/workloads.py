@@ -276,3 +276,43 @@ def batch_workload(count: int = 4096, seed: int = 4, nmin: int = 64, nmax: int =
                 item.pair, item.pair_kind = mutate_one(d, int(sub[i]) + 2)[0], "mutated"
         items.append(item)
     return items
+
+
+@dataclass
+class ServeRequest:
+    kind: str            # "minimise" or "equivalent"
+    dfa: DFA
+    other: DFA | None    # second operand of an equivalence request
+    arrival: float       # seconds after the start of the stream
+
+
+def serving_workload(count: int, rate: float, seed: int = 5, nmin: int = 1000,
+                     nmax: int = 4_194_304, letters=(2, 4, 8, 16), p_equivalent: float = 0.2,
+                     p_chain: float = 0.1) -> list[ServeRequest]:
+    """Request stream: Poisson arrivals at `rate` per second, 80% minimise /
+    20% equivalence (against a permuted copy or a one-transition mutation,
+    alternately), n log-uniform in [nmin, nmax], k uniform in `letters`, and
+    a fraction p_chain of chain DFAs (half chain, half random tail)."""
+    rng = _rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    ns = np.rint(np.exp(rng.uniform(math.log(nmin), math.log(nmax), size=count))).astype(np.int64)
+    ks = rng.choice(np.asarray(letters), size=count)
+    kinds = rng.random(count) < p_equivalent
+    chains = rng.random(count) < p_chain
+    ps = rng.uniform(0.05, 0.5, size=count)
+    sub = rng.integers(0, 2**62, size=count)
+    out = []
+    for i in range(count):
+        n, k = int(ns[i]), int(ks[i])
+        if chains[i]:
+            d = chain_with_tail(max(n // 2, 2), n - max(n // 2, 2), int(sub[i]))
+        else:
+            d = random_dfa(n, k, float(ps[i]), int(sub[i]))
+        if kinds[i]:
+            other = permuted_copy(d, int(sub[i]) + 1)[0] if i % 2 == 0 else \
+                mutate_one(d, int(sub[i]) + 2)[0]
+            out.append(ServeRequest("equivalent", d, other, float(arrivals[i])))
+        else:
+            out.append(ServeRequest("minimise", d, None, float(arrivals[i])))
+    return out

@@ -30,7 +30,7 @@ def lib():
 
 def test_exports_every_declared_function(lib):
     names = declared_functions()
-    assert len(names) >= 18
+    assert len(names) >= 26
     for name in names:
         assert hasattr(lib, name), name
     assert B.EXPORTS == names
@@ -50,6 +50,10 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(B.View) == 12 + 4 + 16
     assert ctypes.sizeof(B.Tuning) == 64
     assert ctypes.sizeof(B.BatchStats) == 16 + 24 + 24
+    assert ctypes.sizeof(B.ServerConfig) == 64
+    assert ctypes.sizeof(B.Request) == 8 + 2 * 32
+    assert ctypes.sizeof(B.Result) == 16 + 8 + 8 + 24
+    assert ctypes.sizeof(B.ServerStats) == 6 * 8 + 5 * 8 + 2 * 8
 
 
 def test_default_tuning(lib):

@@ -470,3 +470,95 @@ def test_batch_workload_small_slice():
     verdicts, _ = B.equivalent_batch(pairs)
     for (a, b), v in zip(pairs, verdicts):
         assert v == oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
+
+
+# ---------------------------------------------------------------- serving
+
+def _serving_mix(seed, count):
+    """Requests shaped like the serving workload at reduced sizes: 80%
+    minimise / 20% equivalence, n log-uniform, k in {2, 4, 8, 16}, 10% chain
+    with a random tail."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        n = int(np.exp(rng.uniform(np.log(100), np.log(40000))))
+        k = int(rng.choice([2, 4, 8, 16]))
+        if rng.random() < 0.1:
+            half = max(n // 2, 2)
+            d = W.chain_with_tail(half, n - half, int(rng.integers(1 << 30)))
+        else:
+            d = W.random_dfa(n, k, float(rng.uniform(0.05, 0.5)), int(rng.integers(1 << 30)))
+        if rng.random() < 0.2:
+            other = W.permuted_copy(d, i)[0] if i % 2 else W.mutate_one(d, i)[0]
+            reqs.append(("eq", d, other))
+        else:
+            reqs.append(("min", d, None))
+    return reqs
+
+
+def _expected(req):
+    kind, a, b = req
+    if kind == "min":
+        return oracle.hopcroft(a.delta, a.accepting)[0]
+    return oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
+
+
+def _submit(srv, req):
+    kind, a, b = req
+    return srv.submit_minimise(a) if kind == "min" else srv.submit_equivalent(a, b)
+
+
+def test_server_results_alone_and_in_mix():
+    reqs = _serving_mix(21, 60)
+    expected = [_expected(r) for r in reqs]
+    with B.Server(lanes=3, max_group=16, batch_max_states=20000) as srv:
+        tickets = [_submit(srv, r) for r in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["rejected"] == 0
+    assert st["batched_groups"] > 0 and st["p99_ms"] >= st["p50_ms"] > 0
+    for req, got, exp in zip(reqs, mixed, expected):
+        assert got["status"] == 0
+        if req[0] == "min":
+            np.testing.assert_array_equal(got["blocks"], exp)
+            assert got["num_blocks"] == len(np.unique(exp))
+        else:
+            assert got["verdict"] == exp
+    # each request alone on a fresh server: identical results
+    with B.Server(lanes=1) as srv:
+        for req, got in zip(reqs[:12], mixed[:12]):
+            alone = srv.wait(_submit(srv, req))
+            if req[0] == "min":
+                np.testing.assert_array_equal(alone["blocks"], got["blocks"])
+                assert alone["rounds"] == got["rounds"]
+            else:
+                assert alone["verdict"] == got["verdict"]
+
+
+def test_server_round_budget_fallback_to_closure():
+    """A chain request inside a group exceeds the round budget and is re-run
+    alone with the closure; its result is still exact."""
+    chain = W.chain_with_tail(3000, 3000, 7)
+    small = [W.random_dfa(500 + i, 3, 0.3, i) for i in range(5)]
+    with B.Server(lanes=1, max_group=8, batch_round_budget=16) as srv:
+        tickets = [srv.submit_minimise(d) for d in small + [chain]]
+        res = [srv.wait(t) for t in tickets]
+    for d, r in zip(small + [chain], res):
+        np.testing.assert_array_equal(r["blocks"], oracle.hopcroft(d.delta, d.accepting)[0])
+    assert res[-1]["batched"] is False and all(r["batched"] for r in res[:-1])
+
+
+def test_server_admission_and_errors():
+    with B.Server(lanes=1, hbm_budget=64 << 20) as srv:
+        too_big = W.random_dfa(1 << 20, 8, 0.5, 1)
+        with pytest.raises(B.DfaError) as e:
+            srv.submit_minimise(too_big)
+        assert e.value.status == B.DFA_ENOMEM
+        bad = W.random_dfa(50, 2, 0.5, 2)
+        bad.delta[3, 0] = 99
+        t = srv.submit_minimise(bad)
+        assert srv.wait(t)["status"] == B.DFA_EINVAL
+        good = W.random_dfa(1000, 2, 0.5, 3)
+        r = srv.wait(srv.submit_minimise(good))
+        np.testing.assert_array_equal(r["blocks"], oracle.hopcroft(good.delta, good.accepting)[0])
+        assert srv.stats()["rejected"] == 1
