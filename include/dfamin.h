@@ -67,6 +67,15 @@ extern "C" {
 #define DFA_TC_ON 1   /* add the letters a^(2^i), i = 1..floor(log2 n), first */
 #define DFA_TC_AUTO 2 /* start plain; switch to the closure when splitting stalls */
 
+/* ---- refinement algorithm ---- */
+#define DFA_ALGO_SIGNATURE 0 /* signature rounds with hashing: every block splits into
+                                all its classes at once (Section 3.3, Algorithm 4) */
+#define DFA_ALGO_LEADER 1    /* leader rounds, naivePR (Section 3.2, Algorithm 2): the
+                                states that differ from their block's leader leave it
+                                together; with DFA_TC_ON this is transPR (Algorithm 5
+                                followed by naivePR).  Same partition, more rounds,
+                                no hash table.  Single-DFA calls only. */
+
 /* ---- round-loop driver ---- */
 #define DFA_LOOP_HOST 0  /* the host reads the block count after every round */
 #define DFA_LOOP_CHUNK 1 /* rounds are enqueued in chunks; kernels turn into no-ops
@@ -84,11 +93,14 @@ typedef struct dfa_options {
                              0 = insert every key into the global table,
                              2 = LDS only in rounds after one that formed at most one
                                  block per eight refined states (default) */
-    int32_t reserved[4];
+    int32_t algorithm;    /* DFA_ALGO_*, default DFA_ALGO_SIGNATURE; the batched calls
+                             and the server accept only DFA_ALGO_SIGNATURE */
+    int32_t reserved[3];
 } dfa_options;
 
 typedef struct dfa_stats {
-    uint32_t rounds;          /* signature rounds executed; the last one confirms stability */
+    uint32_t rounds;          /* refinement rounds executed (signature or leader rounds);
+                                 the last one confirms stability */
     uint32_t changing_rounds; /* rounds that split at least one block */
     uint32_t num_blocks;      /* blocks of the final partition */
     uint32_t k_eff;           /* letters per signature in the last round (k, or closure letters) */
@@ -100,7 +112,9 @@ typedef struct dfa_stats {
     double device_ms;         /* device work of the call (HIP events) */
     double d2h_ms;            /* host-pointer calls: copy of the results */
     uint64_t transitions_refined; /* sum over rounds of n * k_eff (nominal) */
-    uint64_t algorithmic_bytes;   /* sum over rounds of n * (8*k_eff + 8) */
+    uint64_t algorithmic_bytes;   /* signature rounds: sum over rounds of the refined
+                                     states * (8*k_eff + 8); leader rounds: n * 4 per
+                                     round plus the compared states * 16*k_eff */
 } dfa_stats;
 
 /* Quotient DFA: caller-provided arrays of capacity n*k (delta) and n

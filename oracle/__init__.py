@@ -14,6 +14,9 @@ Inclusion Checking":
 
 * ``moore``          -- signature refinement with the semantics of sortPR
                         (Section 3.3, Algorithm 4), with round counts;
+* ``naive_pr``       -- leader-based refinement naivePR (Section 3.2,
+                        Algorithm 2), with iteration counts; ``naive_pr_tc`` is
+                        transPR (Algorithm 5 followed by naivePR);
 * ``hopcroft``       -- Hopcroft's n log n algorithm (cited in Section 1);
 * ``table_fill``     -- the Apart fixpoint computed by trans (Section 3.1,
                         Algorithm 1), sequentially;
@@ -74,6 +77,8 @@ def _load():
         lib.orc_moore_round.restype = ctypes.c_uint32
         lib.orc_moore.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u32p, _u8p, _u32p,
                                   _u32p, _u32p, _u32p, ctypes.c_uint32]
+        lib.orc_naive_pr.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u32p, _u8p, _u32p,
+                                     _u32p, _u32p, _u32p, ctypes.c_uint32]
         lib.orc_hopcroft.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u32p, _u8p, _u32p, _u32p]
         lib.orc_table_fill.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u32p, _u8p, _u8p, _u32p]
         lib.orc_pointer_jump.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u32p,
@@ -88,12 +93,15 @@ def _load():
             ctypes.c_int, ctypes.POINTER(ctypes.c_int), _u64p]
         lib.orc_minimise_many.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
                                           ctypes.c_uint32, _u32p, _u8p, _u32p]
-        for fn in ("orc_canonicalise", "orc_moore", "orc_hopcroft", "orc_table_fill",
+        for fn in ("orc_canonicalise", "orc_moore", "orc_naive_pr", "orc_hopcroft", "orc_table_fill",
                    "orc_pointer_jump", "orc_quotient", "orc_equiv_hk", "orc_product_bfs",
                    "orc_minimise_many"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
         return lib
+
+
+_ELIMIT = -3
 
 
 class OracleError(RuntimeError):
@@ -154,6 +162,29 @@ def moore(delta, acc, max_rounds: int = 0):
                            ctypes.byref(rounds), ctypes.byref(changing), max_rounds)
     _check(rc, "moore")
     return block, nb.value, rounds.value, changing.value
+
+
+def naive_pr(delta, acc, max_rounds: int = 0, partial: bool = False):
+    """Leader-based refinement (naivePR).  Returns (block, num_blocks, rounds,
+    changing_rounds); the leaders are the smallest members, so ``block`` is
+    canonical.  With ``partial``, reaching ``max_rounds`` returns the
+    partition after that many rounds instead of raising."""
+    d = _as_delta(delta)
+    a = _as_acc(acc)
+    n, k = d.shape
+    block = np.empty(n, dtype=np.uint32)
+    nb, rounds, changing = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    rc = _load().orc_naive_pr(n, k, _p32(d), _p8(a), _p32(block), ctypes.byref(nb),
+                              ctypes.byref(rounds), ctypes.byref(changing), max_rounds)
+    if not (partial and rc == _ELIMIT):
+        _check(rc, "naive_pr")
+    return block, nb.value, rounds.value, changing.value
+
+
+def naive_pr_tc(delta, acc, levels: int | None = None):
+    """The paper's transPR: naivePR over the closure letters."""
+    ext = pointer_jump(delta, levels)
+    return naive_pr(ext, acc)
 
 
 def hopcroft(delta, acc) -> tuple[np.ndarray, int]:
@@ -249,7 +280,7 @@ def minimise_many(deltas, accs, algo: str = "hopcroft") -> np.ndarray:
     a = np.ascontiguousarray(np.asarray(accs) != 0, dtype=np.uint8)
     count, n, k = d.shape
     out = np.empty((count, n), dtype=np.uint32)
-    code = {"hopcroft": 0, "moore": 1}[algo]
+    code = {"hopcroft": 0, "moore": 1, "naive_pr": 2}[algo]
     _check(_load().orc_minimise_many(code, count, n, k, _p32(d), _p8(a), _p32(out)),
            "minimise_many")
     return out

@@ -25,6 +25,8 @@
  *   orc_moore        signature refinement by sorting, the semantics of the
  *                    paper's sortPR (Section 3.3, Algorithm 4), sequential;
  *                    also reports the number of rounds;
+ *   orc_naive_pr     leader-based refinement, the paper's naivePR (Section
+ *                    3.2, Algorithm 2), sequential; reports its iterations;
  *   orc_hopcroft     Hopcroft's O(nk log n) algorithm (textbook, cited in the
  *                    paper's introduction);
  *   orc_table_fill   the fixpoint of the pair relation "Apart" that the
@@ -220,6 +222,95 @@ int orc_moore(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *acc,
         count = c;
     }
     free(next);
+    if (num_blocks)
+        *num_blocks = count;
+    if (rounds_out)
+        *rounds_out = rounds;
+    if (changing_out)
+        *changing_out = changing;
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Leader-based refinement, naivePR (Section 3.2, Algorithm 2).             */
+/*                                                                          */
+/* Every block is named by a leader state that belongs to it; initially the */
+/* leaders of F and Q\F.  One iteration: each state q whose successor block */
+/* differs from its leader's successor block on some letter is "separated"; */
+/* all separated states of one block move together to one new block, led by */
+/* one of them.  The iteration in which no state is separated ends the loop.*/
+/*                                                                          */
+/* Two readings fix what the paper leaves to the PRAM model:               */
+/*   - the concurrent leader write resolves to the smallest writer (the    */
+/*     priority rule), and the initial leaders are the smallest accepting  */
+/*     and the smallest rejecting state, so every leader is the smallest   */
+/*     member of its block and the ids are canonical without renumbering;  */
+/*   - the separation test of the second parallel loop reads the partition */
+/*     the iteration started from (lock-step evaluation), so moving one    */
+/*     state never changes the test of another in the same iteration.      */
+/* rounds_out counts every iteration including the last (no separation),   */
+/* changing_out those that separated some state.                           */
+/* ------------------------------------------------------------------------ */
+
+int orc_naive_pr(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *acc,
+                 uint32_t *block, uint32_t *num_blocks, uint32_t *rounds_out,
+                 uint32_t *changing_out, uint32_t max_rounds)
+{
+    int rc = check_dfa(n, k, delta, acc);
+    if (rc)
+        return rc;
+    uint32_t *new_leader = malloc((size_t)n * sizeof *new_leader);
+    uint8_t *separated = malloc(n);
+    if (!new_leader || !separated) {
+        free(new_leader);
+        free(separated);
+        return ORC_ENOMEM;
+    }
+    uint32_t count = initial_partition(n, acc, block);
+    uint32_t rounds = 0, changing = 0;
+    for (;;) {
+        if (max_rounds && rounds >= max_rounds) {
+            rc = ORC_ELIMIT;
+            break;
+        }
+        rounds++;
+        /* first parallel loop: test every state against its leader and
+         * elect the new leader of each block's separated states */
+        for (uint32_t q = 0; q < n; q++)
+            new_leader[q] = UINT32_MAX;
+        for (uint32_t q = 0; q < n; q++) {
+            const uint32_t leader = block[q];
+            separated[q] = 0;
+            for (uint32_t a = 0; a < k; a++) {
+                const uint32_t mine = block[delta[(size_t)q * k + a]];
+                const uint32_t theirs = block[delta[(size_t)leader * k + a]];
+                if (mine != theirs) {
+                    separated[q] = 1;
+                    break;
+                }
+            }
+            if (separated[q] && q < new_leader[leader])
+                new_leader[leader] = q;
+        }
+        /* second parallel loop: move the separated states (the test above
+         * was taken on the partition this iteration started from) */
+        uint32_t moved = 0, new_blocks = 0;
+        for (uint32_t q = 0; q < n; q++) {
+            if (!separated[q])
+                continue;
+            const uint32_t target = new_leader[block[q]];
+            if (target == q)
+                new_blocks++;
+            block[q] = target;
+            moved++;
+        }
+        if (moved == 0)
+            break;
+        changing++;
+        count += new_blocks;
+    }
+    free(new_leader);
+    free(separated);
     if (num_blocks)
         *num_blocks = count;
     if (rounds_out)
@@ -747,7 +838,7 @@ out:
 /* ------------------------------------------------------------------------ */
 /* Loops over many small DFAs of one shape (count instances, each n states,  */
 /* k letters, packed back to back) -- a convenience for exhaustive tests.   */
-/* algo 0 = Hopcroft, 1 = Moore.                                            */
+/* algo 0 = Hopcroft, 1 = Moore, 2 = naivePR.                               */
 /* ------------------------------------------------------------------------ */
 
 int orc_minimise_many(int algo, uint64_t count, uint32_t n, uint32_t k,
@@ -757,8 +848,9 @@ int orc_minimise_many(int algo, uint64_t count, uint32_t n, uint32_t k,
         const uint32_t *d = deltas + i * n * k;
         const uint8_t *a = accs + i * n;
         uint32_t *b = blocks + i * n;
-        int rc = algo == 0 ? orc_hopcroft(n, k, d, a, b, NULL)
-                           : orc_moore(n, k, d, a, b, NULL, NULL, NULL, 0);
+        int rc = algo == 0   ? orc_hopcroft(n, k, d, a, b, NULL)
+                 : algo == 1 ? orc_moore(n, k, d, a, b, NULL, NULL, NULL, 0)
+                             : orc_naive_pr(n, k, d, a, b, NULL, NULL, NULL, 0);
         if (rc)
             return rc;
     }

@@ -31,6 +31,8 @@ REQ_EQUIVALENT = 1
 
 TC = {"off": 0, "on": 1, "auto": 2}
 LOOP = {"host": 0, "chunk": 1, "graph": 2}
+# signature rounds (sortPR semantics, hashed) or leader rounds (naivePR)
+ALGO = {"signature": 0, "leader": 1}
 
 
 class DfaError(RuntimeError):
@@ -43,7 +45,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tc_mode", ctypes.c_int32), ("loop_mode", ctypes.c_int32),
                 ("start", ctypes.c_uint32), ("max_rounds", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("lds_stage", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("algorithm", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -226,7 +228,7 @@ def _check(rc: int, allow=()) -> int:
 
 
 def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: int = 0,
-            chunk: int = 0, lds_stage=2) -> Options:
+            chunk: int = 0, lds_stage=2, algorithm: str = "signature") -> Options:
     o = Options()
     load().dfa_options_default(ctypes.byref(o))
     o.tc_mode = TC[tc]
@@ -236,6 +238,7 @@ def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: i
     o.chunk = chunk
     # True/False select always/never; 2 (the default) lets each round decide
     o.lds_stage = int(lds_stage) if not isinstance(lds_stage, bool) else (1 if lds_stage else 0)
+    o.algorithm = ALGO[algorithm]
     return o
 
 
@@ -308,12 +311,12 @@ class MinimiseResult:
 
 def minimise(delta, accepting, *, tc: str = "auto", loop: str = "graph", start: int = 0,
              max_rounds: int = 0, chunk: int = 0, lds_stage=2,
-             quotient: bool = False) -> MinimiseResult:
+             quotient: bool = False, algorithm: str = "signature") -> MinimiseResult:
     """dfa_minimise on host arrays."""
     d, a = _host_arrays(delta, accepting)
     n, k = d.shape
     block = np.empty(n, dtype=np.uint32)
-    o = options(tc, loop, start, max_rounds, chunk, lds_stage)
+    o = options(tc, loop, start, max_rounds, chunk, lds_stage, algorithm)
     st = Stats()
     q = None
     if quotient:
@@ -348,7 +351,8 @@ def _check_device_tensor(t, dtype_name: str, numel: int, what: str):
 
 def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop: str = "graph",
                     start: int = 0, max_rounds: int = 0, chunk: int = 0, lds_stage=2,
-                    quotient: bool = False, stream=None) -> MinimiseResult:
+                    quotient: bool = False, stream=None,
+                    algorithm: str = "signature") -> MinimiseResult:
     """dfa_minimise_device on torch GPU tensors: delta int32/uint32 [n, k]
     (row-major), accepting uint8 [n]; block_out int32 [n] (allocated if None)."""
     import torch
@@ -360,7 +364,7 @@ def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop:
     if block_out is None:
         block_out = torch.empty(n, dtype=torch.int32, device=delta.device)
     _check_device_tensor(block_out, str(block_out.dtype), n, "block_out")
-    o = options(tc, loop, start, max_rounds, chunk, lds_stage)
+    o = options(tc, loop, start, max_rounds, chunk, lds_stage, algorithm)
     st = Stats()
     q = None
     if quotient:
@@ -393,11 +397,11 @@ def _view_device(delta, accepting, start) -> View:
 
 
 def equivalent(A, B, *, tc: str = "auto", loop: str = "graph", max_rounds: int = 0,
-               chunk: int = 0, lds_stage=2) -> tuple[bool, dict]:
+               chunk: int = 0, lds_stage=2, algorithm: str = "signature") -> tuple[bool, dict]:
     """dfa_equivalent on two host DFAs (objects with delta, accepting, start)."""
     va, keep_a = _view_host(A)
     vb, keep_b = _view_host(B)
-    o = options(tc, loop, 0, max_rounds, chunk, lds_stage)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage, algorithm)
     v = ctypes.c_int()
     st = Stats()
     _check(load().dfa_equivalent(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
@@ -407,10 +411,10 @@ def equivalent(A, B, *, tc: str = "auto", loop: str = "graph", max_rounds: int =
 
 def equivalent_device(dA, accA, sA, dB, accB, sB, *, tc: str = "auto", loop: str = "graph",
                       max_rounds: int = 0, chunk: int = 0, lds_stage=2,
-                      stream=None) -> tuple[bool, dict]:
+                      stream=None, algorithm: str = "signature") -> tuple[bool, dict]:
     va = _view_device(dA, accA, sA)
     vb = _view_device(dB, accB, sB)
-    o = options(tc, loop, 0, max_rounds, chunk, lds_stage)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage, algorithm)
     v = ctypes.c_int()
     st = Stats()
     _check(load().dfa_equivalent_device(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
@@ -454,7 +458,7 @@ def _views_host(dfas):
 
 
 def minimise_batch(dfas, *, tc: str = "auto", loop: str = "graph", max_rounds: int = 0,
-                   chunk: int = 0, lds_stage=2, offsets=None):
+                   chunk: int = 0, lds_stage=2, offsets=None, algorithm: str = "signature"):
     """dfa_minimise_batch on host DFAs.  Returns (list of block arrays,
     num_blocks array, rounds array, stats)."""
     count = len(dfas)
@@ -469,7 +473,7 @@ def minimise_batch(dfas, *, tc: str = "auto", loop: str = "graph", max_rounds: i
     out = np.zeros(total, dtype=np.uint32)
     nb = np.empty(count, dtype=np.uint32)
     rounds = np.empty(count, dtype=np.uint32)
-    o = options(tc, loop, 0, max_rounds, chunk, lds_stage)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage, algorithm)
     st = BatchStats()
     _check(load().dfa_minimise_batch(count, views, out.ctypes.data,
                                      None if offs is None else offs.ctypes.data, nb.ctypes.data,

@@ -9,12 +9,12 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
-#include <algorithm>
 #include <condition_variable>
 #include <deque>
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <string>
 #include <vector>
@@ -81,11 +81,13 @@ struct Buffer {
 constexpr size_t kPinnedWords = 1u << 16;
 
 // A captured chunk is reused while the round arguments and the chunk length
-// are unchanged (RoundArgs values are built from zeroed storage, so they can
-// be compared bytewise).
+// are unchanged (RoundArgs / LeaderArgs values are built from zeroed storage,
+// so they can be compared bytewise).
 struct GraphKey {
-    RoundArgs args;
+    RoundArgs args;      // signature rounds (zero for leader rounds)
+    LeaderArgs largs;    // leader rounds (zero for signature rounds)
     uint32_t chunk;
+    uint32_t leader;
     bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof *this) == 0; }
 };
 
@@ -103,6 +105,7 @@ struct Ctx {
     Buffer stage_delta, stage_acc, stage_block, stage_qdelta, stage_qacc, stage_delta_b,
         stage_acc_b;
     Buffer visited, visited2, front0, front1;
+    Buffer new_leader, moved;
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     size_t pinned_batch_cap = 0;
@@ -196,7 +199,7 @@ int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
 
 // ---- kernel timing ----
 
-enum class Kern { Signature, Insert, RoundEnd, Pattern, Packed };
+enum class Kern { Signature, Insert, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove, LeaderEnd };
 
 int prof_event(Ctx &c, size_t &idx) {
     if (c.ev_used == c.evpool.size()) {
@@ -213,44 +216,61 @@ int prof_event(Ctx &c, size_t &idx) {
 //   insert     4 (the new block id)
 //   pattern    4k (columns) + (k + 1) (acceptance of q and successors) + 4 (label)
 //   packed     4k (columns) + (k + 1) (byte labels) + 4 (label)
+//   elect      per compared (non-leader) state: 4k (own columns) + 4k (the
+//              leader's columns) + 8k (the two successor ids per letter)
 uint32_t kern_bytes(Kern kind, uint32_t k_eff) {
     switch (kind) {
         case Kern::Signature: return 8 * k_eff + 4;
         case Kern::Insert: return 4;
         case Kern::Pattern:
         case Kern::Packed: return 5 * k_eff + 5;
+        case Kern::LeaderElect: return 16 * k_eff;
         default: return 0;
     }
 }
 
-const char *kern_name(Kern kind, const RoundArgs &a) {
+const char *kern_name(Kern kind) {
     switch (kind) {
         case Kern::Signature: return "k_signature";
         case Kern::Insert: return "k_insert";
         case Kern::RoundEnd: return "k_round_end";
         case Kern::Pattern: return "k_pattern_round";
-        default: return "k_packed_round";
+        case Kern::Packed: return "k_packed_round";
+        case Kern::LeaderElect: return "k_leader_elect";
+        case Kern::LeaderMove: return "k_leader_move";
+        default: return "k_leader_end";
     }
 }
 
 // Launches one round kernel, bracketed by events when timing is on.
-int launch_kern(Ctx &c, Kern kind, const RoundArgs &a, uint32_t round) {
+template <class Args>
+int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
     size_t e0 = 0, e1 = 0;
     if (c.profiling) {
         DFA_TRY(prof_event(c, e0));
         HIP_TRY(hipEventRecord(c.evpool[e0], c.stream));
     }
-    switch (kind) {
-        case Kern::Signature: launch_signature(a, c.stream); break;
-        case Kern::Insert: launch_insert(a, c.stream); break;
-        case Kern::RoundEnd: launch_round_end(a, c.stream); break;
-        case Kern::Pattern: launch_pattern_kernel(a, c.stream); break;
-        case Kern::Packed: launch_packed_kernel(a, c.stream); break;
+    if constexpr (std::is_same_v<Args, RoundArgs>) {
+        switch (kind) {
+            case Kern::Signature: launch_signature(a, c.stream); break;
+            case Kern::Insert: launch_insert(a, c.stream); break;
+            case Kern::RoundEnd: launch_round_end(a, c.stream); break;
+            case Kern::Pattern: launch_pattern_kernel(a, c.stream); break;
+            case Kern::Packed: launch_packed_kernel(a, c.stream); break;
+            default: return fail(DFA_EDEVICE, "internal: leader kernel with round arguments");
+        }
+    } else {
+        switch (kind) {
+            case Kern::LeaderElect: launch_leader_elect(a, c.stream); break;
+            case Kern::LeaderMove: launch_leader_move(a, c.stream); break;
+            case Kern::LeaderEnd: launch_leader_end(a, c.stream); break;
+            default: return fail(DFA_EDEVICE, "internal: round kernel with leader arguments");
+        }
     }
     if (c.profiling) {
         DFA_TRY(prof_event(c, e1));
         HIP_TRY(hipEventRecord(c.evpool[e1], c.stream));
-        c.pending.push_back({kern_name(kind, a), e0, e1, round, kern_bytes(kind, a.k_eff)});
+        c.pending.push_back({kern_name(kind), e0, e1, round, kern_bytes(kind, a.k_eff)});
     }
     return DFA_OK;
 }
@@ -260,6 +280,12 @@ int launch_full_round(Ctx &c, const RoundArgs &a, uint32_t round) {
     DFA_TRY(launch_kern(c, Kern::Insert, a, round));
     if (a.seg.nseg) launch_seg_round(a, c.stream);
     return launch_kern(c, Kern::RoundEnd, a, round);
+}
+
+int launch_full_round(Ctx &c, const LeaderArgs &a, uint32_t round) {
+    DFA_TRY(launch_kern(c, Kern::LeaderElect, a, round));
+    DFA_TRY(launch_kern(c, Kern::LeaderMove, a, round));
+    return launch_kern(c, Kern::LeaderEnd, a, round);
 }
 
 // Folds the timed launches into the totals (the stream has been synchronised).
@@ -330,12 +356,19 @@ int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
     return DFA_OK;
 }
 
-int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t first_round) {
+// Enqueues `rounds` rounds of signature (ra) or leader (la != nullptr)
+// refinement, from a captured graph in GRAPH mode.
+int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t first_round,
+              const LeaderArgs *la = nullptr) {
     if (mode == DFA_LOOP_GRAPH && !c.profiling) {
         GraphKey key;
         std::memset(&key, 0, sizeof key);
-        std::memcpy(&key.args, &ra, sizeof ra);
+        if (la)
+            std::memcpy(&key.largs, la, sizeof *la);
+        else
+            std::memcpy(&key.args, &ra, sizeof ra);
         key.chunk = rounds;
+        key.leader = la ? 1u : 0u;
         if (!c.graph || !(c.graph_key == key)) {
             if (c.graph) {
                 (void)hipGraphExecDestroy(c.graph);
@@ -343,7 +376,12 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t f
             }
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
-            for (uint32_t i = 0; i < rounds; ++i) launch_round(ra, c.stream);
+            for (uint32_t i = 0; i < rounds; ++i) {
+                if (la)
+                    launch_leader_round(*la, c.stream);
+                else
+                    launch_round(ra, c.stream);
+            }
             HIP_TRY(hipStreamEndCapture(c.stream, &g));
             hipError_t e = hipGraphInstantiate(&c.graph, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -355,7 +393,12 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t f
         }
         HIP_TRY(hipGraphLaunch(c.graph, c.stream));
     } else {
-        for (uint32_t i = 0; i < rounds; ++i) DFA_TRY(launch_full_round(c, ra, first_round + i));
+        for (uint32_t i = 0; i < rounds; ++i) {
+            if (la)
+                DFA_TRY(launch_full_round(c, *la, first_round + i));
+            else
+                DFA_TRY(launch_full_round(c, ra, first_round + i));
+        }
         HIP_TRY(hipGetLastError());
     }
     return DFA_OK;
@@ -533,6 +576,112 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     return DFA_OK;
 }
 
+// Leader rounds (naivePR) over N states whose level-0 columns are in c.cols
+// and whose acceptance bits are in c.accbits (flags written by the ingest
+// and init kernels).  Block ids are leaders, i.e. state ids, throughout; the
+// result is in c.blockA.
+int refine_leader(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq,
+                  uint32_t eq_a, uint32_t eq_b, RefineResult &res) {
+    DFA_TRY(read_back(c, c.flags.p, (kFlagNonid + k) * sizeof(uint32_t)));
+    if (c.pinned[kFlagErr]) return fail(DFA_EINVAL, "a transition target is >= n");
+    std::vector<uint32_t> colmap;
+    // an identity letter never separates a state from its leader
+    for (uint32_t a = 0; a < k; ++a)
+        if (c.pinned[kFlagNonid + a]) colmap.push_back(a);
+    DFA_TRY(c.ctl.ensure(sizeof(RoundCtl), "round state"));
+    RoundCtl *ctl = c.ctl.as<RoundCtl>();
+    const uint32_t *cols = c.cols.as<uint32_t>();
+    res.tc_used = 0;
+    res.tc_levels = 0;
+    res.label_rounds = 0;
+    if (o.tc_mode == DFA_TC_ON) {
+        DFA_TRY(build_closure(c, N, k, colmap, res.tc_levels));
+        cols = c.tc_cols.as<uint32_t>();
+        res.tc_used = 1;
+    }
+    DFA_TRY(set_colmap(c, colmap));
+    uint32_t k_eff = static_cast<uint32_t>(colmap.size());
+    DFA_TRY(c.new_leader.ensure(N * sizeof(unsigned long long), "leader slots"));
+    DFA_TRY(c.moved.ensure((N + 63) / 64 * sizeof(unsigned long long), "separation masks"));
+    DFA_TRY(c.scalars.ensure(16 * sizeof(uint32_t), "scalars"));
+    HIP_TRY(hipMemsetAsync(c.new_leader.p, 0xFF, N * sizeof(unsigned long long), c.stream));
+    HIP_TRY(hipMemsetD32Async(c.scalars.as<uint32_t>(), 0xFFFFFFFFu, 2, c.stream));
+    launch_leader_init(c.accbits.as<unsigned long long>(), N, c.scalars.as<uint32_t>(),
+                       c.blockA.as<uint32_t>(), c.stream);
+    launch_ctl_reset(ctl, c.flags.as<uint32_t>() + kFlagClass, o.max_rounds, check_eq, eq_a, eq_b,
+                     0, 0, nullptr, c.stream);
+    HIP_TRY(hipGetLastError());
+
+    const int mode = o.loop_mode;
+    uint32_t chunk = o.chunk ? o.chunk : c.tune.chunk;
+    if (c.profiling) chunk = std::min(chunk, kActiveHist);
+    uint32_t last_round = 0;
+    unsigned long long last_active_sum = 0;
+    bool tc_failed = false;
+    res.transitions = 0;
+    res.bytes = 0;
+    RoundArgs none;
+    std::memset(&none, 0, sizeof none);
+    for (;;) {
+        LeaderArgs la;
+        std::memset(&la, 0, sizeof la);
+        la.cols = cols;
+        la.colmap = c.colmap.as<uint32_t>();
+        la.N = N;
+        la.k_eff = k_eff;
+        la.block = c.blockA.as<uint32_t>();
+        la.new_leader = c.new_leader.as<unsigned long long>();
+        la.moved = c.moved.as<unsigned long long>();
+        la.counters = c.counters.as<uint32_t>();
+        la.ctl = ctl;
+        DFA_TRY(run_chunk(c, none, mode == DFA_LOOP_HOST ? 1u : chunk, mode, last_round, &la));
+        DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
+        std::memcpy(&res.ctl, c.pinned, sizeof(RoundCtl));
+        if (c.profiling) DFA_TRY(prof_collect(c, res.ctl));
+        const uint32_t done_rounds = res.ctl.round - last_round;
+        res.transitions += static_cast<uint64_t>(done_rounds) * N * k_eff;
+        res.bytes += static_cast<uint64_t>(done_rounds) * N * 4 +
+                     (res.ctl.active_sum - last_active_sum) * (16ull * k_eff);
+        last_round = res.ctl.round;
+        last_active_sum = res.ctl.active_sum;
+        if (res.ctl.done) break;
+        // closure on demand, by the rule of the signature rounds
+        const uint64_t left = N - res.ctl.prev_count;
+        uint64_t recent_gain = 0;
+        for (uint32_t i = 1; i <= 4 && i <= res.ctl.round; ++i)
+            recent_gain = std::max<uint64_t>(
+                recent_gain, res.ctl.gain_hist[(res.ctl.round - i) % kActiveHist]);
+        if (o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed && res.ctl.round >= 8 &&
+            left >= 4096 && recent_gain * 4096 < left) {
+            std::vector<uint32_t> tcmap;
+            uint32_t levels = 0;
+            int rc = build_closure(c, N, k, tcmap, levels);
+            if (rc == DFA_ENOMEM) {
+                tc_failed = true;
+                g_last_error.clear();
+                continue;
+            }
+            DFA_TRY(rc);
+            DFA_TRY(set_colmap(c, tcmap));
+            k_eff = static_cast<uint32_t>(tcmap.size());
+            cols = c.tc_cols.as<uint32_t>();
+            res.tc_used = 1;
+            res.tc_levels = levels;
+            res.plain_rounds = res.ctl.round;
+        }
+    }
+    res.k_eff = k_eff;
+    res.final_block = c.blockA.as<uint32_t>();
+    return DFA_OK;
+}
+
+// Dispatch on the refinement algorithm of the options.
+int refine_any(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq,
+               uint32_t eq_a, uint32_t eq_b, bool state_ids, RefineResult &res) {
+    if (o.algorithm == DFA_ALGO_LEADER) return refine_leader(c, N, k, o, check_eq, eq_a, eq_b, res);
+    return refine(c, N, k, o, check_eq, eq_a, eq_b, state_ids, res);
+}
+
 void fill_stats(dfa_stats *st, const RefineResult &r) {
     if (!st) return;
     st->rounds = r.ctl.round;
@@ -551,6 +700,15 @@ int check_options(const dfa_options &o) {
     if (o.loop_mode < DFA_LOOP_HOST || o.loop_mode > DFA_LOOP_GRAPH)
         return fail(DFA_EINVAL, "bad loop_mode");
     if (o.lds_stage < 0 || o.lds_stage > 2) return fail(DFA_EINVAL, "bad lds_stage");
+    if (o.algorithm != DFA_ALGO_SIGNATURE && o.algorithm != DFA_ALGO_LEADER)
+        return fail(DFA_EINVAL, "bad algorithm");
+    return DFA_OK;
+}
+
+int check_batch_options(const dfa_options &o) {
+    DFA_TRY(check_options(o));
+    if (o.algorithm != DFA_ALGO_SIGNATURE)
+        return fail(DFA_EINVAL, "batched calls run signature rounds only");
     return DFA_OK;
 }
 
@@ -588,7 +746,7 @@ int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const u
                        flags + kFlagClass, c.stream);
     HIP_TRY(hipGetLastError());
     RefineResult r;
-    int rc = refine(c, n, k, o, 0, 0, 0, true, r);
+    int rc = refine_any(c, n, k, o, 0, 0, 0, true, r);
     if (rc != DFA_OK) return rc;
     launch_canonicalise(r.final_block, n, id_range, c.canon.as<uint32_t>(), block_out, c.stream);
     if (q) {
@@ -654,7 +812,7 @@ int equivalent_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict,
                        c.accbits.as<unsigned long long>(), flags + kFlagClass, c.stream);
     HIP_TRY(hipGetLastError());
     RefineResult r;
-    DFA_TRY(refine(c, N, k, o, 1, a.start, a.n + b.start, false, r));
+    DFA_TRY(refine_any(c, N, k, o, 1, a.start, a.n + b.start, false, r));
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
     HIP_TRY(hipStreamSynchronize(c.stream));
     fill_stats(st, r);
@@ -1609,7 +1767,7 @@ int dfa_minimise_batch_device(uint32_t count, const dfa_view *dfas, uint32_t *bl
     g_last_error.clear();
     dfa_options o = resolve(opt);
     DFA_TRY(check_views(count, dfas, "dfas"));
-    DFA_TRY(check_options(o));
+    DFA_TRY(check_batch_options(o));
     if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
@@ -1627,7 +1785,7 @@ int dfa_minimise_batch(uint32_t count, const dfa_view *dfas, uint32_t *blocks_co
     g_last_error.clear();
     dfa_options o = resolve(opt);
     DFA_TRY(check_views(count, dfas, "dfas"));
-    DFA_TRY(check_options(o));
+    DFA_TRY(check_batch_options(o));
     if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
@@ -1670,7 +1828,7 @@ int dfa_equivalent_batch_device(uint32_t count, const dfa_view *a, const dfa_vie
     dfa_options o = resolve(opt);
     DFA_TRY(check_views(count, a, "a"));
     DFA_TRY(check_views(count, b, "b"));
-    DFA_TRY(check_options(o));
+    DFA_TRY(check_batch_options(o));
     if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
     for (uint32_t i = 0; i < count; ++i)
         if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
@@ -1689,7 +1847,7 @@ int dfa_equivalent_batch(uint32_t count, const dfa_view *a, const dfa_view *b, i
     dfa_options o = resolve(opt);
     DFA_TRY(check_views(count, a, "a"));
     DFA_TRY(check_views(count, b, "b"));
-    DFA_TRY(check_options(o));
+    DFA_TRY(check_batch_options(o));
     if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
     for (uint32_t i = 0; i < count; ++i)
         if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);

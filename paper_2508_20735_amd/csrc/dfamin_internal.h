@@ -172,6 +172,36 @@ void launch_pattern_round(const RoundArgs &a, hipStream_t s);
 // (k_eff + 1)^2 <= kPackedMaxBits and lab8 written by the pattern round).
 void launch_packed_round(const RoundArgs &a, hipStream_t s);
 
+// ---- leader-based refinement (naivePR; leader_kernels.hip) ----
+//
+//   block       uint32 [N]          leader (smallest member) of q's block,
+//                                   updated in place by the move kernel
+//   new_leader  uint64 [N]          election slot of block b: (tag << 32) | q
+//                                   with tag = 2^32 - 1 - round; all ones
+//                                   before the first round of a call
+//   moved       uint64 [ceil(N/64)] states separated in the current round
+struct LeaderArgs {
+    const uint32_t *cols;
+    const uint32_t *colmap;
+    size_t N;
+    uint32_t k_eff;
+    uint32_t pad;
+    uint32_t *block;
+    unsigned long long *new_leader;
+    unsigned long long *moved;
+    uint32_t *counters;  // kSpread * kSpreadStride words, zero between rounds
+    RoundCtl *ctl;
+};
+// Initial leaders: block[q] = smallest accepting or smallest rejecting state
+// of q's class, from the acceptance bits; lead: 2 words preset to all ones.
+void launch_leader_init(const unsigned long long *accbits, size_t N, uint32_t *lead,
+                        uint32_t *block, hipStream_t s);
+// One round (elect, move, end); the three launches separately for timing.
+void launch_leader_round(const LeaderArgs &a, hipStream_t s);
+void launch_leader_elect(const LeaderArgs &a, hipStream_t s);
+void launch_leader_move(const LeaderArgs &a, hipStream_t s);
+void launch_leader_end(const LeaderArgs &a, hipStream_t s);
+
 // Pointer jumping, level i >= 1, all k letters:
 // cols[(i*k+a)*N + q] = cols[((i-1)*k+a)*N + cols[((i-1)*k+a)*N + q]];
 // diff[i*k+a] = 1 if the level differs from level i-1 somewhere,

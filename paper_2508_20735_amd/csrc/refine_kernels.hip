@@ -26,73 +26,12 @@
 // Block ids during the rounds are representatives chosen by the hardware's
 // atomic order; the final partition is renumbered canonically (smallest state
 // of each block) once, by k_canon_min / k_canon_apply.
-#include "dfamin_internal.h"
+#include "device_common.h"
 
 namespace dfamin {
 namespace {
 
 constexpr unsigned long long kEmptyPair = ~0ull;
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-
-// Multiply-xorshift mixing of 32-bit words into a 64-bit hash.
-__device__ __forceinline__ uint64_t mix_step(uint64_t h, uint32_t w) {
-    h ^= w;
-    h *= 0x9E3779B97F4A7C15ull;
-    h ^= h >> 32;
-    return h;
-}
-__device__ __forceinline__ uint64_t mix_final(uint64_t h) {
-    h ^= h >> 29;
-    h *= 0xBF58476D1CE4E5B9ull;
-    h ^= h >> 32;
-    return h;
-}
-constexpr uint64_t kHashSeed = 0x6A09E667F3BCC909ull;
-
-__device__ __forceinline__ size_t global_tid() {
-    return static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-}
-__device__ __forceinline__ size_t grid_stride() {
-    return static_cast<size_t>(gridDim.x) * blockDim.x;
-}
-
-// Workgroup sum of per-thread values, added with one atomic per workgroup to
-// one of kSpread counters (consecutive workgroups use different lines).
-// Every thread of the workgroup must call it.
-__device__ __forceinline__ void wg_add_spread(uint32_t *counters, int word, uint32_t v) {
-    __shared__ uint32_t part[kBlock / 64];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    __syncthreads();
-    if (lane_id() == 0) part[threadIdx.x / 64] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += part[w];
-        if (s) atomicAdd(counters + (blockIdx.x % kSpread) * kSpreadStride + word, s);
-    }
-}
-
-// Sets *flag = 1 (a plain store: every writer stores the same value) if any
-// active lane has `pred`; skips the store once the flag reads as set.
-__device__ __forceinline__ void wave_set_flag(uint32_t *flag, bool pred) {
-    const unsigned long long m = __ballot(pred);
-    if (m == 0) return;
-    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    if (static_cast<int>(lane_id()) == leader && *flag == 0u) *flag = 1u;
-}
-
-__device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
-    uint32_t lo = static_cast<uint32_t>(v), hi = static_cast<uint32_t>(v >> 32);
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        lo |= __shfl_xor(lo, d, 64);
-        hi |= __shfl_xor(hi, d, 64);
-    }
-    return (static_cast<unsigned long long>(hi) << 32) | lo;
-}
 
 // ---------------------------------------------------------------- ingest
 

@@ -45,13 +45,16 @@ def stable_partition_certificate(delta, acc, block):
 
 @pytest.mark.parametrize("n,k", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)])
 def test_exhaustive_small(n, k):
-    """All DFAs with n <= 4, k <= 2: Hopcroft = Moore = word enumeration."""
+    """All DFAs with n <= 4, k <= 2: Hopcroft = Moore = naivePR = word
+    enumeration."""
     D, A = all_dfas(n, k)
     ref = words.partition_by_words(D, A)
     hop = oracle.minimise_many(D, A, "hopcroft")
     np.testing.assert_array_equal(hop, ref)
     moo = oracle.minimise_many(D, A, "moore")
     np.testing.assert_array_equal(moo, ref)
+    nai = oracle.minimise_many(D, A, "naive_pr")
+    np.testing.assert_array_equal(nai, ref)
 
 
 @pytest.mark.parametrize("n,k", [(2, 2), (3, 1), (3, 2)])

@@ -113,7 +113,7 @@ def test_fibonacci_distinguishing_depth(i):
 def test_table2_fibonacci_sizes():
     """Table 2, N and output-size columns for Fib_18 .. Fib_30 (table index =
     word index - 1), and sortPR iterations = N - 1 where reported."""
-    for name, N, k, out, iters in load_table("table2.txt"):
+    for name, N, k, out, iters, _naive in load_table("table2.txt"):
         if not name.startswith("Fib"):
             continue
         i = int(name[3:]) + 1
@@ -159,7 +159,7 @@ def test_bitsplitter_halving(n):
 def test_table2_bitsplitter_rows():
     """Table 2, B_15 .. B_26: N = 2^n, |Sigma| = n - 1, output N, iterations
     n - 1 (checked by Moore up to B_16)."""
-    for name, N, k, out, iters in load_table("table2.txt"):
+    for name, N, k, out, iters, _naive in load_table("table2.txt"):
         if not name.startswith("B"):
             continue
         n = int(name[1:])
@@ -169,6 +169,115 @@ def test_table2_bitsplitter_rows():
             d = W.bitsplitter(n)
             _, nb, _, changing = oracle.moore(d.delta, d.accepting)
             assert nb == int(out) and changing == int(iters)
+
+
+# ---------------------------------------------------------------- naivePR (Algorithm 2)
+
+def test_table2_naive_pr_iterations_fibonacci():
+    """Table 2, naivePR iteration column: N - 1 for every Fib row (the N - 2
+    separating rounds plus the one that finds no difference), checked by the
+    oracle's naivePR for Fib_18 .. Fib_20; the output keeps all N states."""
+    rows = {r[0]: r for r in load_table("table2.txt")}
+    for name in ("Fib18", "Fib19", "Fib20"):
+        _, N, _, out, _, naive = rows[name]
+        d = W.fibonacci(int(name[3:]) + 1)
+        block, nb, rounds, changing = oracle.naive_pr(d.delta, d.accepting)
+        assert d.n == int(N) and nb == int(out)
+        assert rounds == int(naive) and changing == int(naive) - 1
+        np.testing.assert_array_equal(block, np.arange(d.n))
+    for name, N, _, _, _, naive in rows.values():
+        if name.startswith("Fib"):
+            assert int(naive) == int(N) - 1
+
+
+def test_table2_naive_pr_iterations_bitsplitter():
+    """Table 2, naivePR iteration column for B_15 and B_16: n - 1, the number
+    of rounds that split (the table's B rows count the separating rounds, its
+    Fib rows also the final one; both readings are checked here and above)."""
+    rows = {r[0]: r for r in load_table("table2.txt")}
+    for n in (15, 16):
+        _, N, k, out, _, naive = rows[f"B{n}"]
+        d = W.bitsplitter(n)
+        block, nb, rounds, changing = oracle.naive_pr(d.delta, d.accepting)
+        assert nb == int(out) == 2 ** n
+        assert changing == int(naive) == n - 1 and rounds == n
+    for name, _, _, _, _, naive in rows.values():
+        if name.startswith("B"):
+            assert int(naive) == int(name[1:]) - 1
+
+
+def test_naive_pr_worked_example():
+    """Worked by hand from Algorithm 2.  States 0, 1, 2 reject, 3 accepts;
+    letters a, b:  0 -a-> 3, 0 -b-> 0;  1 -a-> 0, 1 -b-> 3;  2 -a-> 0, 2 -b-> 0;
+    3 loops.  Leaders: 0 (rejecting), 3 (accepting).
+    Round 1: the leader 0 reaches blocks (3, 0); state 1 reaches (0, 3) and
+    state 2 reaches (0, 0): both differ, both leave block 0 together, led by
+    the smaller, 1.  Partition {0}, {1, 2}, {3}.
+    Round 2: leader 1 reaches (0, 3); state 2 reaches (0, 0): it leaves,
+    leading itself.  Round 3 separates nothing: 3 rounds, 2 separating.
+    Signature refinement (Moore) splits {0, 1, 2} three ways in its first
+    round: 2 rounds, 1 separating."""
+    delta = np.array([[3, 0], [0, 3], [0, 0], [3, 3]], dtype=np.uint32)
+    acc = np.array([0, 0, 0, 1], dtype=np.uint8)
+    b1, nb1, _, _ = oracle.naive_pr(delta, acc, max_rounds=1, partial=True)
+    assert b1.tolist() == [0, 1, 1, 3] and nb1 == 3
+    block, nb, rounds, changing = oracle.naive_pr(delta, acc)
+    assert block.tolist() == [0, 1, 2, 3] and nb == 4
+    assert (rounds, changing) == (3, 2)
+    _, _, mrounds, mchanging = oracle.moore(delta, acc)
+    assert (mrounds, mchanging) == (2, 1)
+
+
+def _naive_round_postconditions(delta, acc, before, after):
+    """What one round of Algorithm 2 guarantees, stated on its input and
+    output partitions: leaders keep their block; a state leaves iff some
+    letter leads it and its leader into different blocks of `before`; the
+    states leaving one block form one new block whose id is its smallest
+    member."""
+    before = np.asarray(before, dtype=np.int64)
+    after = np.asarray(after, dtype=np.int64)
+    differs = (before[delta] != before[delta[before]]).any(axis=1)
+    leaders = before == np.arange(len(before))
+    assert (after[leaders] == before[leaders]).all()
+    assert ((after != before) == differs).all()
+    for b in np.unique(before[differs]):
+        leaving = np.flatnonzero(differs & (before == b))
+        assert (after[leaving] == leaving.min()).all()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_naive_pr_round_by_round(seed):
+    """Every round of the oracle's naivePR meets the postconditions of one
+    round of Algorithm 2, on random DFAs (several leaders, many-way
+    differences inside one block)."""
+    d = W.random_dfa(300, 2 + seed % 3, 0.3, seed)
+    prev = np.where(d.accepting != 0, np.flatnonzero(d.accepting)[0],
+                    np.flatnonzero(d.accepting == 0)[0]).astype(np.uint32)
+    _, _, rounds, _ = oracle.naive_pr(d.delta, d.accepting)
+    for r in range(1, rounds + 1):
+        cur, _, _, _ = oracle.naive_pr(d.delta, d.accepting, max_rounds=r, partial=True)
+        _naive_round_postconditions(d.delta, d.accepting, prev, cur)
+        prev = cur
+    hb, _ = oracle.hopcroft(d.delta, d.accepting)
+    np.testing.assert_array_equal(prev, hb)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_naive_pr_never_faster_than_moore(seed):
+    """A naivePR round splits a block in at most two, a signature round into
+    all its classes: after r rounds the naivePR partition is coarser than (or
+    equal to) the Moore partition, so naivePR needs at least as many rounds."""
+    d = W.random_dfa(400, 3, 0.4, 100 + seed)
+    _, _, nrounds, nchanging = oracle.naive_pr(d.delta, d.accepting)
+    _, _, mrounds, mchanging = oracle.moore(d.delta, d.accepting)
+    assert nchanging >= mchanging
+    moore_block = oracle.canonicalise(np.asarray(d.accepting, dtype=np.uint32))
+    for r in range(1, mrounds + 1):
+        moore_block, _ = oracle.moore_round(d.delta, moore_block)
+        naive_block, _, _, _ = oracle.naive_pr(d.delta, d.accepting, max_rounds=r, partial=True)
+        # coarser: states together in Moore's partition are together here
+        together = moore_block[:, None] == moore_block[None, :]
+        assert (naive_block[:, None] == naive_block[None, :])[together].all()
 
 
 # ---------------------------------------------------------------- equivalence / inclusion
