@@ -106,6 +106,7 @@ struct Ctx {
         stage_acc_b;
     Buffer visited, visited2, front0, front1;
     Buffer new_leader, moved;
+    Buffer chg, single, touched;
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     size_t pinned_batch_cap = 0;
@@ -199,7 +200,9 @@ int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
 
 // ---- kernel timing ----
 
-enum class Kern { Signature, Insert, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove, LeaderEnd };
+enum class Kern {
+    Mark, Signature, Insert, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove, LeaderEnd
+};
 
 int prof_event(Ctx &c, size_t &idx) {
     if (c.ev_used == c.evpool.size()) {
@@ -231,6 +234,7 @@ uint32_t kern_bytes(Kern kind, uint32_t k_eff) {
 
 const char *kern_name(Kern kind) {
     switch (kind) {
+        case Kern::Mark: return "k_mark";
         case Kern::Signature: return "k_signature";
         case Kern::Insert: return "k_insert";
         case Kern::RoundEnd: return "k_round_end";
@@ -252,6 +256,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
     }
     if constexpr (std::is_same_v<Args, RoundArgs>) {
         switch (kind) {
+            case Kern::Mark: launch_mark(a, c.stream); break;
             case Kern::Signature: launch_signature(a, c.stream); break;
             case Kern::Insert: launch_insert(a, c.stream); break;
             case Kern::RoundEnd: launch_round_end(a, c.stream); break;
@@ -276,6 +281,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
 }
 
 int launch_full_round(Ctx &c, const RoundArgs &a, uint32_t round) {
+    DFA_TRY(launch_kern(c, Kern::Mark, a, round));
     DFA_TRY(launch_kern(c, Kern::Signature, a, round));
     DFA_TRY(launch_kern(c, Kern::Insert, a, round));
     if (a.seg.nseg) launch_seg_round(a, c.stream);
@@ -434,6 +440,9 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
     ra.round_grid_cap = c.tune.round_grid_cap;
     ra.pattern_grid_cap = c.tune.label_grid_cap;
     ra.cached_probe = c.tune.cached_probe;
+    ra.chg = c.chg.as<unsigned long long>();
+    ra.single = c.single.as<unsigned long long>();
+    ra.touched = c.touched.as<unsigned long long>();
     return ra;
 }
 
@@ -469,6 +478,12 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     uint32_t k_eff = static_cast<uint32_t>(colmap.size());
     DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
     DFA_TRY(c.hash.ensure(N * sizeof(uint64_t), "hashes"));
+    const size_t words64 = (N + 63) / 64;
+    DFA_TRY(c.chg.ensure(words64 * sizeof(unsigned long long), "changed-id bits"));
+    DFA_TRY(c.single.ensure(words64 * sizeof(unsigned long long), "singleton bits"));
+    DFA_TRY(c.touched.ensure(2 * words64 * sizeof(unsigned long long), "touched-block bits"));
+    HIP_TRY(hipMemsetAsync(c.single.p, 0, words64 * sizeof(unsigned long long), c.stream));
+    HIP_TRY(hipMemsetAsync(c.touched.p, 0, 2 * words64 * sizeof(unsigned long long), c.stream));
     // label rounds need at least three rounds of budget (ids become state
     // ids in the round after them)
     // (segmented refinements keep their segment labels: no label rounds)
@@ -550,6 +565,8 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             DFA_TRY(set_colmap(c, tcmap));
             k_eff = static_cast<uint32_t>(tcmap.size());
             DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
+            // new letters: the next round refines every multi-state block
+            launch_ctl_full(ctl, c.stream);
             cols = c.tc_cols.as<uint32_t>();
             res.tc_used = 1;
             res.tc_levels = levels;

@@ -17,6 +17,11 @@
 //   active   uint64 [N/64]       per-wave bitmask of the states refined in
 //                                the current round
 //   accbits  uint64 [N/64]       acceptance, one bit per state (first round)
+//   chg      uint64 [N/64]       state's block id changed in the last round
+//   single   uint64 [N/64]       state's block is known to be a singleton
+//   touched  uint64 [2][N/64]    per block id (bit b): the block has a member
+//                                with a successor whose id changed; one
+//                                bitmap per round parity
 //   ctl      RoundCtl            round counter / stop flag on the device
 #pragma once
 
@@ -52,6 +57,8 @@ struct RoundCtl {
     uint32_t pattern_first;  // round 0 grouped by acceptance bit patterns
     uint32_t packed_second;  // round 1 grouped by packed round-0 labels
     uint32_t all_active_until;  // rounds <= this refine every state
+    uint32_t full_until;     // rounds <= this refine every state of a multi-state block
+    uint32_t last_changed;   // states whose block id changed in the last round
     uint32_t last_active;    // states refined by the last round
     unsigned long long active_sum;  // states refined, summed over rounds
     uint32_t active_hist[kActiveHist];  // states refined by round r, at r % kActiveHist
@@ -153,9 +160,19 @@ struct RoundArgs {
     uint32_t pattern_grid_cap;  // workgroups of the label rounds
     uint32_t cached_probe;      // probe the table with cached loads first
     uint32_t pad;
+    unsigned long long *chg;      // N/64 words
+    unsigned long long *single;   // N/64 words, zero before the first round
+    unsigned long long *touched;  // 2 * (N/64) words, zero before the first round
     SegArgs seg;                // nseg == 0: a single automaton
 };
+// One round: marking of the blocks to refine, signatures, grouping, the
+// round end.
 void launch_round(const RoundArgs &a, hipStream_t s);
+// The marking kernel alone (also clears the table every kEpochs rounds).
+void launch_mark(const RoundArgs &a, hipStream_t s);
+// The next round refines every state of a multi-state block (used after the
+// signature letters change).
+void launch_ctl_full(RoundCtl *ctl, hipStream_t s);
 // Per-segment block counts of the round, then the per-segment bookkeeping
 // (both no-ops once the refinement has stopped); run before the round end.
 void launch_seg_round(const RoundArgs &a, hipStream_t s);

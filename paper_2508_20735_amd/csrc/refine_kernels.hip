@@ -113,6 +113,7 @@ __global__ void k_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t
     // ids produced by label rounds are not state indices: the round after
     // them refines every state
     c.all_active_until = pattern_first + packed_second;
+    c.full_until = c.all_active_until;
     *ctl = c;
 }
 
@@ -120,7 +121,99 @@ __global__ void k_ctl_resume(RoundCtl *ctl) {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->done = 0;
 }
 
+__global__ void k_ctl_full(RoundCtl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->full_until = ctl->round;
+}
+
 // ---------------------------------------------------------------- round kernels
+
+__device__ __forceinline__ bool rows_equal(const uint32_t *__restrict__ sig, size_t W, size_t a,
+                                           size_t b) {
+    const uint32_t *ra = sig + a * W;
+    const uint32_t *rb = sig + b * W;
+    for (size_t i = 0; i < W; ++i)
+        if (ra[i] != rb[i]) return false;
+    return true;
+}
+
+__device__ __forceinline__ unsigned long long load_entry(const unsigned long long *p, bool cached) {
+    return cached ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)
+                  : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Finds the slot holding q's signature or claims an empty one for it.
+// Entry = (epoch:8 | tag:24) << 32 | representative; entries of older
+// epochs count as empty.  Lock-free: a slot only ever changes from "empty" to
+// a final value within an epoch, and every decision is confirmed by a CAS or
+// by reading such a final value.  A cached read may show an older "empty"
+// value; the CAS then fails and returns the value actually stored, which is
+// examined next without reading the cache again.  The load factor stays
+// <= 1/2, so the probe always reaches an empty slot.
+__device__ __forceinline__ uint32_t find_or_claim(unsigned long long *table, uint64_t mask,
+                                                  uint32_t epoch, uint64_t h, uint32_t self,
+                                                  const uint32_t *sig, size_t W, bool cached,
+                                                  bool &claimed) {
+    const uint32_t tag = (epoch << 24) | static_cast<uint32_t>(h >> 40);
+    const unsigned long long want = (static_cast<unsigned long long>(tag) << 32) | self;
+    uint64_t s = h & mask;
+    unsigned long long e = load_entry(table + s, cached);
+    for (;;) {
+        if (static_cast<uint32_t>(e >> 56) != epoch) {
+            const unsigned long long prev = atomicCAS(table + s, e, want);
+            if (prev == e) {
+                claimed = true;
+                return self;
+            }
+            e = prev;
+            continue;
+        }
+        if (static_cast<uint32_t>(e >> 32) == tag) {
+            const uint32_t rep = static_cast<uint32_t>(e);
+            if (rows_equal(sig, W, self, rep)) {
+                claimed = false;
+                return rep;
+            }
+        }
+        s = (s + 1) & mask;
+        e = load_entry(table + s, cached);
+    }
+}
+
+// Marks block `id` as having two or more members after round r.
+__device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_t tag) {
+    if (multi[id] != tag) multi[id] = tag;
+}
+
+// Claims an empty slot for `self` without comparing keys: used when no
+// entry of the current epoch can hold an equal key (the states claiming this
+// way all have different block ids, which lead their keys).
+__device__ __forceinline__ void claim_slot(unsigned long long *table, uint64_t mask,
+                                           uint32_t epoch, uint64_t h, uint32_t self) {
+    const uint32_t tag = (epoch << 24) | static_cast<uint32_t>(h >> 40);
+    const unsigned long long want = (static_cast<unsigned long long>(tag) << 32) | self;
+    uint64_t s = h & mask;
+    unsigned long long e = load_entry(table + s, false);
+    for (;;) {
+        if (static_cast<uint32_t>(e >> 56) != epoch) {
+            const unsigned long long prev = atomicCAS(table + s, e, want);
+            if (prev == e) return;
+            e = prev;
+            continue;
+        }
+        s = (s + 1) & mask;
+        e = load_entry(table + s, false);
+    }
+}
+
+// Rounds after the first table round skip the blocks that cannot split:
+// once a round changed the ids of few states, a block is refined only if a
+// member has a successor whose id changed (the block is "touched").  Members
+// of one block had equal keys in the round that formed it; if no successor
+// id changed, their new keys are equal again.  Uniform over the grid.
+__device__ __forceinline__ bool incremental_round(const RoundCtl &c, size_t N, uint32_t r) {
+    return r > c.full_until && static_cast<uint64_t>(c.last_changed) * 8 < N;
+}
+
 
 struct SigParams {
     const uint32_t *cols;
@@ -140,6 +233,10 @@ struct SigParams {
     uint8_t *lab8;
     uint32_t *counters;
     const RoundCtl *ctl;
+    uint32_t cached_probe;
+    unsigned long long *chg;
+    unsigned long long *single;
+    unsigned long long *touched;
 };
 
 __device__ __forceinline__ uint32_t acc_bit(const unsigned long long *accbits, uint32_t t) {
@@ -179,6 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
         if (m & ~seen) fresh += __popc(m & ~atomicOr(p.presence + i, m));
     }
     wg_add_spread(p.counters, 0, fresh);
+    wg_add_spread(p.counters, 3, fresh);
 }
 
 // Round 1 after a pattern round when (k_eff + 1)^2 <= kPackedMaxBits: the
@@ -239,12 +337,57 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
         __syncthreads();
     }
     wg_add_spread(p.counters, 0, fresh);
+    wg_add_spread(p.counters, 3, fresh);
+}
+
+// First kernel of a round: clears the table every kEpochs rounds; in
+// incremental rounds it records, for the states refined last round, whether
+// their block is now a singleton, and marks the blocks with a member whose
+// successor changed id in the last round.  It also clears the touched bitmap
+// of the next round.
+__global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
+    if (p.ctl->done) return;
+    const uint32_t r = p.ctl->round;
+    // the table is cleared every kEpochs rounds (its entries carry the epoch)
+    if (r > 0 && r % kEpochs == 0) {
+        for (size_t i = global_tid(); i < p.table_cap; i += grid_stride()) p.table[i] = 0ull;
+    }
+    const size_t words = (p.N + 63) / 64;
+    unsigned long long *__restrict__ Tn = p.touched + ((r + 1) & 1u) * words;
+    for (size_t i = global_tid(); i < words; i += grid_stride()) Tn[i] = 0ull;
+    if (r <= p.ctl->all_active_until || !incremental_round(*p.ctl, p.N, r)) return;
+    unsigned long long *__restrict__ T = p.touched + (r & 1u) * words;
+    const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        const size_t q = base + threadIdx.x;
+        const bool valid = q < p.N;
+        const size_t first = base + (threadIdx.x & ~63u);
+        const size_t wd = first >> 6;
+        const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
+        const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
+        bool s = (sw >> lane_id()) & 1ull;
+        const uint32_t x = valid ? X[q] : 0u;
+        // a block formed last round with one member stays a singleton
+        if (valid && !s && ((aw >> lane_id()) & 1ull)) s = p.multi[x] != r;
+        const unsigned long long nsw = __ballot(s);
+        if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
+        if (!valid || s) continue;
+        bool dirty = false;
+        for (uint32_t j = 0; j < p.k_eff && !dirty; ++j) {
+            const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+            dirty = (p.chg[t >> 6] >> (t & 63)) & 1ull;
+        }
+        if (dirty) atomicOr(T + (x >> 6), 1ull << (x & 63));
+    }
 }
 
 // Signatures of the states refined this round.  A state is refined if the
-// round refines everything (the first rounds) or if its block had two or
-// more members after the previous round; the others are singletons, keep
-// their id and are copied to the output buffer.
+// round refines everything (the first rounds), or if its block is not a
+// singleton and, in incremental rounds, is touched; the others keep their id
+// and are copied to the output buffer.  A refined state that holds its
+// block's id claims a table slot for its key here, before any other state
+// looks its key up.
 // KC > 0: k_eff known at compile time (fully unrolled gathers);
 // KC == 0: runtime k_eff, gathers issued in batches of 8.
 template <int KC>
@@ -256,11 +399,6 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
     const bool all = r <= p.ctl->all_active_until;
     const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
     const size_t W = keff + 1;
-
-    // the table is cleared every kEpochs rounds (its entries carry the epoch)
-    if (r > 0 && r % kEpochs == 0) {
-        for (size_t i = global_tid(); i < p.table_cap; i += grid_stride()) p.table[i] = 0ull;
-    }
 
     if constexpr (KC > 0) {
         if (all) {
@@ -307,16 +445,39 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
         }
     }
 
+    const bool inc = !all && incremental_round(*p.ctl, p.N, r);
+    const size_t words = (p.N + 63) / 64;
+    const unsigned long long *__restrict__ T = p.touched + (r & 1u) * words;
+    const uint32_t epoch = r % kEpochs + 1;
+    uint32_t leaders = 0, claims = 0;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
         const size_t q = base + threadIdx.x;
         const bool valid = q < p.N;
-        const uint32_t w0 = valid ? X[q] : 0u;
-        const bool act = valid && (all || p.multi[w0] == r);
-        const unsigned long long am = __ballot(act);
         const size_t first = base + (threadIdx.x & ~63u);
-        if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
-        if (valid && !act) Y[q] = w0;
+        const size_t wd = first >> 6;
+        const uint32_t w0 = valid ? X[q] : 0u;
+        bool act = valid;
+        if (!all) {
+            const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
+            bool s = (sw >> lane_id()) & 1ull;
+            if (!inc) {
+                // states refined last round learn whether their block is now
+                // a singleton (the marking kernel does this in incremental
+                // rounds)
+                const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
+                if (valid && !s && ((aw >> lane_id()) & 1ull)) s = p.multi[w0] != r;
+                const unsigned long long nsw = __ballot(s);
+                if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
+            }
+            act = valid && !s && (!inc || ((T[w0 >> 6] >> (w0 & 63)) & 1ull));
+        }
+        const unsigned long long am = __ballot(act);
+        if (lane_id() == 0 && first < p.N) p.active[wd] = am;
+        if (valid && !act) {
+            Y[q] = w0;
+            leaders += w0 == q ? 1u : 0u;
+        }
         if (!act) continue;
         uint32_t *__restrict__ row = p.sig + q * W;
         row[0] = w0;
@@ -350,8 +511,18 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
                     }
             }
         }
-        p.hash[q] = mix_final(h);
+        h = mix_final(h);
+        p.hash[q] = h;
+        if (!all && w0 == q) {
+            // the state that holds its block's id claims its key before the
+            // others group, so a block that does not split keeps its id
+            claim_slot(p.table, p.table_cap - 1, epoch, h, static_cast<uint32_t>(q));
+            Y[q] = w0;
+            ++claims;
+        }
     }
+    wg_add_spread(p.counters, 0, leaders + claims);
+    wg_add_spread(p.counters, 3, claims);
 }
 
 // ---------------------------------------------------------------- grouping
@@ -370,64 +541,8 @@ struct InsParams {
     const RoundCtl *ctl;
     uint32_t cached_probe;
     int lds_stage;
+    unsigned long long *chg;
 };
-
-__device__ __forceinline__ bool rows_equal(const uint32_t *__restrict__ sig, size_t W, size_t a,
-                                           size_t b) {
-    const uint32_t *ra = sig + a * W;
-    const uint32_t *rb = sig + b * W;
-    for (size_t i = 0; i < W; ++i)
-        if (ra[i] != rb[i]) return false;
-    return true;
-}
-
-__device__ __forceinline__ unsigned long long load_entry(const unsigned long long *p, bool cached) {
-    return cached ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)
-                  : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Finds the slot holding q's signature or claims an empty one for it.
-// Entry = (epoch:8 | tag:24) << 32 | representative; entries of older
-// epochs count as empty.  Lock-free: a slot only ever changes from "empty" to
-// a final value within an epoch, and every decision is confirmed by a CAS or
-// by reading such a final value.  A cached read may show an older "empty"
-// value; the CAS then fails and returns the value actually stored, which is
-// examined next without reading the cache again.  The load factor stays
-// <= 1/2, so the probe always reaches an empty slot.
-__device__ __forceinline__ uint32_t find_or_claim(unsigned long long *table, uint64_t mask,
-                                                  uint32_t epoch, uint64_t h, uint32_t self,
-                                                  const uint32_t *sig, size_t W, bool cached,
-                                                  bool &claimed) {
-    const uint32_t tag = (epoch << 24) | static_cast<uint32_t>(h >> 40);
-    const unsigned long long want = (static_cast<unsigned long long>(tag) << 32) | self;
-    uint64_t s = h & mask;
-    unsigned long long e = load_entry(table + s, cached);
-    for (;;) {
-        if (static_cast<uint32_t>(e >> 56) != epoch) {
-            const unsigned long long prev = atomicCAS(table + s, e, want);
-            if (prev == e) {
-                claimed = true;
-                return self;
-            }
-            e = prev;
-            continue;
-        }
-        if (static_cast<uint32_t>(e >> 32) == tag) {
-            const uint32_t rep = static_cast<uint32_t>(e);
-            if (rows_equal(sig, W, self, rep)) {
-                claimed = false;
-                return rep;
-            }
-        }
-        s = (s + 1) & mask;
-        e = load_entry(table + s, cached);
-    }
-}
-
-// Marks block `id` as having two or more members after round r.
-__device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_t tag) {
-    if (multi[id] != tag) multi[id] = tag;
-}
 
 // Whether this round stages keys in LDS (uniform across the grid).
 __device__ __forceinline__ bool stage_in_lds(const InsParams &p) {
@@ -439,13 +554,17 @@ __device__ __forceinline__ bool stage_in_lds(const InsParams &p) {
     return c->round == 0 || static_cast<uint64_t>(c->last_claims) * 8 <= c->last_active;
 }
 
-// Counter words: [0] blocks after the round, [1] states not refined.
+// Counter words: [0] blocks after the round, [1] states not refined,
+// [2] states whose id changed, [3] blocks formed by claims.  The signature
+// kernel adds the unrefined block holders and its own claims.
 __global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
     if (p.ctl->done || stage_in_lds(p)) return;
     const uint32_t r = p.ctl->round;
     const uint32_t epoch = r % kEpochs + 1;
+    const bool all = r <= p.ctl->all_active_until;
+    const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
-    uint32_t blocks = 0, idle = 0;
+    uint32_t blocks = 0, idle = 0, changed = 0;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
         const size_t q = base + threadIdx.x;
@@ -454,19 +573,31 @@ __global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
         const bool valid = q < p.N;
         const bool act = valid && ((am >> lane_id()) & 1ull);
         idle += (valid && !act) ? 1u : 0u;
-        if (!act) continue;
-        bool claimed = false;
-        const uint32_t id = find_or_claim(p.table, p.mask, epoch, p.hash[q],
-                                          static_cast<uint32_t>(q), p.sig, p.W,
-                                          p.cached_probe != 0, claimed);
-        Y[q] = id;
-        if (claimed)
-            ++blocks;
-        else
-            mark_multi(p.multi, id, r + 1);
+        bool ch = false;
+        if (act) {
+            const uint32_t x = X[q];
+            // a state holding its block's id claimed in the signature kernel
+            if (all || x != q) {
+                bool claimed = false;
+                const uint32_t id = find_or_claim(p.table, p.mask, epoch, p.hash[q],
+                                                  static_cast<uint32_t>(q), p.sig, p.W,
+                                                  p.cached_probe != 0, claimed);
+                Y[q] = id;
+                if (claimed)
+                    ++blocks;
+                else
+                    mark_multi(p.multi, id, r + 1);
+                ch = id != x;
+            }
+        }
+        const unsigned long long cm = __ballot(ch);
+        if (lane_id() == 0 && first < p.N) p.chg[first >> 6] = cm;
+        changed += ch ? 1u : 0u;
     }
-    wg_add_spread(p.counters, 0, blocks + idle);
+    wg_add_spread(p.counters, 0, blocks);
     wg_add_spread(p.counters, 1, idle);
+    wg_add_spread(p.counters, 2, changed);
+    wg_add_spread(p.counters, 3, blocks);
 }
 
 // LDS-staged grouping: a workgroup first groups the refined states of its
@@ -481,9 +612,11 @@ __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
     if (p.ctl->done || !stage_in_lds(p)) return;
     const uint32_t r = p.ctl->round;
     const uint32_t epoch = r % kEpochs + 1;
+    const bool all = r <= p.ctl->all_active_until;
+    const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
     const uint32_t tx = threadIdx.x;
-    uint32_t blocks = 0, idle = 0;
+    uint32_t blocks = 0, idle = 0, changed = 0;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
         const size_t q = base + tx;
@@ -493,13 +626,20 @@ __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
         const bool act = valid && ((am >> lane_id()) & 1ull);
         idle += (valid && !act) ? 1u : 0u;
         // whole tile idle: nothing to group (uniform across the workgroup)
-        if (__syncthreads_or(act) == 0) continue;
+        if (__syncthreads_or(act) == 0) {
+            if (lane_id() == 0 && first < p.N) p.chg[first >> 6] = 0ull;
+            continue;
+        }
+        const uint32_t x = act ? X[q] : 0u;
+        // a state holding its block's id claimed in the signature kernel;
+        // the others group in LDS first
+        const bool grp = act && (all || x != q);
         for (uint32_t i = tx; i < kLdsSlots; i += kBlock) ltab[i] = kEmptyPair;
         lsize[tx] = 0;
         __syncthreads();
-        const uint64_t h = act ? p.hash[q] : 0;
+        const uint64_t h = grp ? p.hash[q] : 0;
         uint32_t lead = tx;
-        if (act) {
+        if (grp) {
             const uint32_t ltag = static_cast<uint32_t>(h >> 32);
             uint32_t s = static_cast<uint32_t>(h) & (kLdsSlots - 1);
             for (;;) {
@@ -526,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
             atomicAdd(lsize + lead, 1u);
         }
         __syncthreads();
-        if (act && lead == tx) {
+        if (grp && lead == tx) {
             bool claimed = false;
             const uint32_t id = find_or_claim(p.table, p.mask, epoch, h, static_cast<uint32_t>(q),
                                               p.sig, p.W, p.cached_probe != 0, claimed);
@@ -535,11 +675,21 @@ __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
             if (!claimed || lsize[tx] > 1) mark_multi(p.multi, id, r + 1);
         }
         __syncthreads();
-        if (act) Y[q] = gid[lead];
+        bool ch = false;
+        if (grp) {
+            const uint32_t id = gid[lead];
+            Y[q] = id;
+            ch = id != x;
+        }
+        const unsigned long long cm = __ballot(ch);
+        if (lane_id() == 0 && first < p.N) p.chg[first >> 6] = cm;
+        changed += ch ? 1u : 0u;
         __syncthreads();
     }
-    wg_add_spread(p.counters, 0, blocks + idle);
+    wg_add_spread(p.counters, 0, blocks);
     wg_add_spread(p.counters, 1, idle);
+    wg_add_spread(p.counters, 2, changed);
+    wg_add_spread(p.counters, 3, blocks);
 }
 
 // One workgroup: the round's block count (spread counters), the stop tests,
@@ -547,37 +697,33 @@ __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
 __global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint32_t *blockA,
                                                        const uint32_t *blockB, uint32_t *counters,
                                                        uint32_t N) {
-    __shared__ uint32_t red[2][kBlock / 64];
+    constexpr int kWords = 4;  // blocks, idle states, changed ids, claims
+    __shared__ uint32_t red[kWords][kBlock / 64];
     if (ctl->done) return;
     const uint32_t r = ctl->round;
-    uint32_t c = 0, idle = 0;
-    for (uint32_t i = threadIdx.x; i < kSpread; i += kBlock) {
-        c += counters[i * kSpreadStride + 0];
-        idle += counters[i * kSpreadStride + 1];
-        counters[i * kSpreadStride + 0] = 0;
-        counters[i * kSpreadStride + 1] = 0;
-    }
+    uint32_t v[kWords] = {0, 0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < kSpread; i += kBlock)
+        for (int w = 0; w < kWords; ++w) {
+            v[w] += counters[i * kSpreadStride + w];
+            counters[i * kSpreadStride + w] = 0;
+        }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        c += __shfl_xor(c, d, 64);
-        idle += __shfl_xor(idle, d, 64);
-    }
-    if (lane_id() == 0) {
-        red[0][threadIdx.x / 64] = c;
-        red[1][threadIdx.x / 64] = idle;
-    }
+    for (int d = 32; d >= 1; d >>= 1)
+        for (int w = 0; w < kWords; ++w) v[w] += __shfl_xor(v[w], d, 64);
+    if (lane_id() == 0)
+        for (int w = 0; w < kWords; ++w) red[w][threadIdx.x / 64] = v[w];
     __syncthreads();
     if (threadIdx.x != 0) return;
-    c = 0;
-    idle = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-        c += red[0][w];
-        idle += red[1][w];
+    for (int w = 0; w < kWords; ++w) {
+        v[w] = 0;
+        for (int i = 0; i < kBlock / 64; ++i) v[w] += red[w][i];
     }
+    const uint32_t c = v[0], idle = v[1];
     const uint32_t *out = (r & 1u) ? blockA : blockB;
     ctl->last_gain = c - ctl->prev_count;
     ctl->last_active = N - idle;
-    ctl->last_claims = c - idle;
+    ctl->last_claims = v[3];
+    ctl->last_changed = v[2];
     ctl->active_sum += N - idle;
     ctl->active_hist[r % kActiveHist] = N - idle;
     ctl->gain_hist[r % kActiveHist] = c - ctl->prev_count;
@@ -909,9 +1055,11 @@ namespace {
 constexpr unsigned kDefaultGridCap = 8192;
 
 SigParams sig_params(const RoundArgs &a) {
-    return SigParams{a.cols,     a.colmap, a.N,      a.k_eff,    a.blockA,  a.blockB,
-                     a.sig,      a.hash,   a.table,  a.table_cap, a.multi, a.active,
-                     a.accbits,  a.presence, a.presence_packed, a.lab8, a.counters, a.ctl};
+    return SigParams{a.cols,     a.colmap,     a.N,        a.k_eff,    a.blockA,
+                     a.blockB,   a.sig,        a.hash,     a.table,    a.table_cap,
+                     a.multi,    a.active,     a.accbits,  a.presence, a.presence_packed,
+                     a.lab8,     a.counters,   a.ctl,      a.cached_probe, a.chg,
+                     a.single,   a.touched};
 }
 
 unsigned round_grid(const RoundArgs &a, unsigned cap) {
@@ -1020,14 +1168,24 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
     const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
     const InsParams ip{a.sig,    a.hash,   a.N,     a.k_eff + 1, a.table,    a.table_cap - 1,
                        a.blockA, a.blockB, a.multi, a.active,    a.counters, a.ctl,
-                       a.cached_probe, a.lds_stage};
+                       a.cached_probe, a.lds_stage, a.chg};
     // the two grouping variants; exactly one of them works in a given round
     // (lds_stage 2 decides on the device from the previous round)
     if (a.lds_stage != 0) hipLaunchKernelGGL(k_insert_lds, grid, block, 0, s, ip);
     if (a.lds_stage != 1) hipLaunchKernelGGL(k_insert, grid, block, 0, s, ip);
 }
 
+void launch_mark(const RoundArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark, dim3(round_grid(a, a.round_grid_cap)), dim3(kBlock), 0, s,
+                       sig_params(a));
+}
+
+void launch_ctl_full(RoundCtl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_full, dim3(1), dim3(64), 0, s, ctl);
+}
+
 void launch_round(const RoundArgs &a, hipStream_t s) {
+    launch_mark(a, s);
     launch_signature(a, s);
     launch_insert(a, s);
     if (a.seg.nseg) launch_seg_round(a, s);
