@@ -163,10 +163,11 @@ def batch_leg(B, W, torch, np, count: int) -> dict:
 
 def serve_leg(B, W, count: int) -> dict:
     """Served requests: n log-uniform in [1,000, 4,194,304], k in {2,4,8,16},
-    80% minimise / 20% equivalence, 10% chain DFAs.  First a burst (all
-    requests submitted at once) gives the capacity; then a Poisson stream at
-    0.7x that rate gives p50/p99 latency; plain = the same requests one by
-    one through the single-request calls."""
+    80% minimise / 20% equivalence, 10% chain DFAs, host arrays.  First a
+    burst (all requests submitted at once, after one untimed burst on the same
+    server) gives the capacity; then a Poisson stream at 0.7x that rate gives
+    p50/p99 latency; plain = the same requests one by one through the
+    single-request host calls."""
     reqs = W.serving_workload(count, rate=1.0)
 
     def submit(srv, r):
@@ -179,20 +180,23 @@ def serve_leg(B, W, count: int) -> dict:
         else:
             B.equivalent(r.dfa, r.other)
 
-    with B.Server(lanes=2) as srv:
-        for r in reqs[:4]:  # warm the lanes
-            srv.wait(submit(srv, r))
+    def burst(srv):
         t0 = time.perf_counter()
         tickets = [submit(srv, r) for r in reqs]
         for t in tickets:
             srv.wait(t)
-        burst_s = time.perf_counter() - t0
+        return time.perf_counter() - t0
+
+    with B.Server() as srv:
+        # a long-running server: one untimed pass warms its page-locked
+        # input pool and the lanes' device workspaces
+        burst(srv)
+        burst_s = burst(srv)
     capacity = count / burst_s
     rate = 0.7 * capacity
     gaps = W._rng(55).exponential(1.0 / rate, size=count)
-    with B.Server(lanes=2) as srv:
-        for r in reqs[:4]:
-            srv.wait(submit(srv, r))
+    with B.Server() as srv:
+        burst(srv)
         t0 = time.perf_counter()
         tickets = []
         due = t0
@@ -218,7 +222,7 @@ def serve_leg(B, W, count: int) -> dict:
             "plain_requests_per_s": count / plain_s,
             "speedup": (count / burst_s) / (count / plain_s),
             "poisson_rate": rate, "p50_ms": pick(0.5), "p99_ms": pick(0.99),
-            "stream_requests_per_s": count / stream_s, "lanes": 2}
+            "stream_requests_per_s": count / stream_s, "lanes": 4}
 
 
 def main() -> int:

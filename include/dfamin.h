@@ -299,10 +299,10 @@ typedef struct dfa_server dfa_server;
 
 typedef struct dfa_server_config {
     size_t hbm_budget;           /* device bytes for admitted requests (0 = half the free memory) */
-    uint32_t lanes;              /* concurrent workers / streams (1..16, default 2) */
+    uint32_t lanes;              /* concurrent workers / streams (1..16, default 4) */
     uint32_t max_group;          /* requests per batched refinement (default 512) */
     uint32_t batch_max_states;   /* larger requests run alone (default 2^18) */
-    uint32_t batch_round_budget; /* rounds of a batched refinement (>= 3, default 64) */
+    uint32_t batch_round_budget; /* rounds of a batched refinement (>= 3, default 12) */
     int32_t tc_mode;             /* closure for requests run alone (default DFA_TC_AUTO) */
     uint32_t reserved[9];
 } dfa_server_config;
@@ -339,7 +339,10 @@ typedef struct dfa_server_stats {
 void dfa_server_config_default(dfa_server_config *cfg);
 /* NULL on failure (see dfa_last_error).  Uses the current HIP device. */
 dfa_server *dfa_server_create(const dfa_server_config *cfg);
-/* Copies the request's arrays; DFA_ENOMEM if it can never fit the budget. */
+/* Copies the request's arrays into page-locked host memory (pooled by the
+ * server; large arrays are copied by several threads), so the caller may free
+ * them on return; the lane that runs the request uploads them asynchronously.
+ * DFA_ENOMEM if the request can never fit the budget. */
 int dfa_server_submit(dfa_server *s, const dfa_request *req, uint64_t *ticket);
 /* DFA_EAGAIN while the request runs or waits. */
 int dfa_server_poll(dfa_server *s, uint64_t ticket, dfa_result *out);

@@ -25,7 +25,10 @@ Inclusion Checking":
 * ``equiv_hk``       -- Hopcroft-Karp with union-find (Section 4, Algorithm 6);
 * ``product_bfs``    -- the naive pair-set Hopcroft-Karp of Section 4, for
                         equivalence and for inclusion (changed acceptance test);
-* ``quotient``       -- the quotient DFA of a canonical partition (Section 2).
+* ``quotient``       -- the quotient DFA of a canonical partition (Section 2);
+* ``reachable``, ``minimise_reachable`` -- breadth-first reachability and the
+                        minimisation of the reachable part (Section 2 assumes
+                        every state reachable; this is the usual definition).
 
 Parity is pinned for every function (see tests/test_oracle_*.py): nothing here
 is "parity unpinned".
@@ -91,11 +94,15 @@ def _load():
         lib.orc_equiv_hk.argtypes = dfa_args + dfa_args + [ctypes.POINTER(ctypes.c_int)]
         lib.orc_product_bfs.argtypes = dfa_args + dfa_args + [
             ctypes.c_int, ctypes.POINTER(ctypes.c_int), _u64p]
+        lib.orc_reachable.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u32p, ctypes.c_uint32,
+                                      _u8p, _u32p]
+        lib.orc_minimise_reachable.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u32p, _u8p,
+                                               ctypes.c_uint32, _u32p, _u32p, _u32p]
         lib.orc_minimise_many.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
                                           ctypes.c_uint32, _u32p, _u8p, _u32p]
         for fn in ("orc_canonicalise", "orc_moore", "orc_naive_pr", "orc_hopcroft", "orc_table_fill",
                    "orc_pointer_jump", "orc_quotient", "orc_equiv_hk", "orc_product_bfs",
-                   "orc_minimise_many"):
+                   "orc_minimise_many", "orc_reachable", "orc_minimise_reachable"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -284,6 +291,33 @@ def minimise_many(deltas, accs, algo: str = "hopcroft") -> np.ndarray:
     _check(_load().orc_minimise_many(code, count, n, k, _p32(d), _p8(a), _p32(out)),
            "minimise_many")
     return out
+
+
+def reachable(delta, start: int = 0) -> np.ndarray:
+    """Boolean mask of the states reachable from ``start`` (breadth-first)."""
+    d = _as_delta(delta)
+    n, k = d.shape
+    out = np.empty(n, dtype=np.uint8)
+    cnt = ctypes.c_uint32()
+    _check(_load().orc_reachable(n, k, _p32(d), start, _p8(out), ctypes.byref(cnt)), "reachable")
+    return out.astype(bool)
+
+
+UNREACHABLE = 0xFFFFFFFF
+
+
+def minimise_reachable(delta, acc, start: int = 0):
+    """Minimisation of the part reachable from ``start``.  Returns (block,
+    num_blocks, num_reachable); block[q] = UNREACHABLE for unreachable q."""
+    d = _as_delta(delta)
+    a = _as_acc(acc)
+    n, k = d.shape
+    block = np.empty(n, dtype=np.uint32)
+    nb, nr = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(_load().orc_minimise_reachable(n, k, _p32(d), _p8(a), start, _p32(block),
+                                          ctypes.byref(nb), ctypes.byref(nr)),
+           "minimise_reachable")
+    return block, nb.value, nr.value
 
 
 def union(dA, accA, dB, accB) -> tuple[np.ndarray, np.ndarray]:

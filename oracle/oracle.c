@@ -36,6 +36,9 @@
  *                    Algorithm 5), sequential;
  *   orc_equiv_hk     Hopcroft-Karp equivalence with R+ kept by union-find
  *                    (Section 4, Algorithm 6);
+ *   orc_minimise_reachable  the minimal DFA in the usual sense: breadth-first
+ *                    reachability from the start, then Hopcroft on the
+ *                    reachable part (the paper prunes nothing, Section 2);
  *   orc_product_bfs  the "naive" Hopcroft-Karp variant of Section 4 (R kept as
  *                    a set of pairs, no closure) = reachability in the
  *                    synchronous product; inclusion uses the changed
@@ -832,6 +835,112 @@ int orc_product_bfs(uint32_t nA, uint32_t kA, const uint32_t *dA, const uint8_t 
 out:
     free(seen.slot);
     free(queue);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reachability and minimisation of the reachable part (Section 2: the       */
+/* paper assumes every state reachable and prunes nothing; the standard      */
+/* minimal DFA is the quotient of the reachable part).                        */
+/*                                                                          */
+/* orc_reachable: breadth-first search from `start`; reach[q] = 1 iff some  */
+/* word leads from start to q.                                              */
+/* orc_minimise_reachable: block[q] = smallest reachable state equivalent   */
+/* to q for reachable q, UINT32_MAX for the others; the relation is          */
+/* Hopcroft's on the sub-automaton of reachable states (its transitions stay */
+/* inside it), so it equals language equivalence restricted to them.        */
+/* ------------------------------------------------------------------------ */
+
+int orc_reachable(uint32_t n, uint32_t k, const uint32_t *delta, uint32_t start, uint8_t *reach,
+                  uint32_t *count)
+{
+    if (n == 0 || k == 0 || !delta || !reach || start >= n)
+        return ORC_EINVAL;
+    uint32_t *queue = malloc((size_t)n * sizeof *queue);
+    if (!queue)
+        return ORC_ENOMEM;
+    memset(reach, 0, n);
+    size_t head = 0, tail = 0;
+    reach[start] = 1;
+    queue[tail++] = start;
+    while (head < tail) {
+        const uint32_t q = queue[head++];
+        for (uint32_t a = 0; a < k; a++) {
+            const uint32_t t = delta[(size_t)q * k + a];
+            if (t >= n) {
+                free(queue);
+                return ORC_EINVAL;
+            }
+            if (!reach[t]) {
+                reach[t] = 1;
+                queue[tail++] = t;
+            }
+        }
+    }
+    free(queue);
+    if (count)
+        *count = (uint32_t)tail;
+    return ORC_OK;
+}
+
+int orc_minimise_reachable(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *acc,
+                           uint32_t start, uint32_t *block, uint32_t *num_blocks,
+                           uint32_t *num_reachable)
+{
+    int rc = check_dfa(n, k, delta, acc);
+    if (rc)
+        return rc;
+    uint8_t *reach = malloc(n);
+    uint32_t *dense = malloc((size_t)n * sizeof *dense);
+    uint32_t *orig = malloc((size_t)n * sizeof *orig);
+    if (!reach || !dense || !orig) {
+        rc = ORC_ENOMEM;
+        goto out;
+    }
+    uint32_t m = 0;
+    rc = orc_reachable(n, k, delta, start, reach, &m);
+    if (rc)
+        goto out;
+    /* the sub-automaton, states renumbered in increasing original order */
+    uint32_t next = 0;
+    for (uint32_t q = 0; q < n; q++)
+        if (reach[q]) {
+            dense[q] = next;
+            orig[next++] = q;
+        }
+    uint32_t *sd = malloc((size_t)m * k * sizeof *sd);
+    uint8_t *sa = malloc(m);
+    uint32_t *sb = malloc((size_t)m * sizeof *sb);
+    if (!sd || !sa || !sb) {
+        free(sd);
+        free(sa);
+        free(sb);
+        rc = ORC_ENOMEM;
+        goto out;
+    }
+    for (uint32_t i = 0; i < m; i++) {
+        const uint32_t q = orig[i];
+        for (uint32_t a = 0; a < k; a++)
+            sd[(size_t)i * k + a] = dense[delta[(size_t)q * k + a]];
+        sa[i] = acc[q] ? 1 : 0;
+    }
+    uint32_t nb = 0;
+    rc = orc_hopcroft(m, k, sd, sa, sb, &nb);
+    if (!rc) {
+        for (uint32_t q = 0; q < n; q++)
+            block[q] = reach[q] ? orig[sb[dense[q]]] : UINT32_MAX;
+        if (num_blocks)
+            *num_blocks = nb;
+        if (num_reachable)
+            *num_reachable = m;
+    }
+    free(sd);
+    free(sa);
+    free(sb);
+out:
+    free(reach);
+    free(dense);
+    free(orig);
     return rc;
 }
 

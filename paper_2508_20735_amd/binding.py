@@ -537,8 +537,8 @@ def equivalent_batch_device(a_list, b_list, *, loop: str = "graph", lds_stage=2,
 class Server:
     """dfa_server_*: continuous batching of minimise / equivalence requests."""
 
-    def __init__(self, hbm_budget: int = 0, lanes: int = 2, max_group: int = 512,
-                 batch_max_states: int = 1 << 18, batch_round_budget: int = 64,
+    def __init__(self, hbm_budget: int = 0, lanes: int = 4, max_group: int = 512,
+                 batch_max_states: int = 1 << 18, batch_round_budget: int = 12,
                  tc: str = "auto"):
         lib = load()
         cfg = ServerConfig()

@@ -324,6 +324,21 @@ struct RefineResult {
     uint64_t transitions = 0, bytes = 0;
 };
 
+// Whether plain rounds have stalled, after at least 8 rounds: over the last
+// four rounds no round added more than 1/4096 of the states still to be
+// separated (large inputs), or, after 32 rounds, no more than 1/64 of them
+// (small ones, where the closure is cheap and the remaining rounds would
+// each split a block or two).
+bool splitting_stalled(const RoundCtl &ctl, size_t N) {
+    if (ctl.round < 8) return false;
+    const uint64_t left = N - ctl.prev_count;
+    uint64_t recent_gain = 0;
+    for (uint32_t i = 1; i <= 4 && i <= ctl.round; ++i)
+        recent_gain = std::max<uint64_t>(recent_gain, ctl.gain_hist[(ctl.round - i) % kActiveHist]);
+    return (left >= 4096 && recent_gain * 4096 < left) ||
+           (ctl.round >= 32 && recent_gain * 64 < left);
+}
+
 // Builds the closure columns (all levels) from level 0 in c.cols, and the
 // signature column list.  Returns DFA_ENOMEM if the table does not fit.
 int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, uint32_t &levels) {
@@ -543,16 +558,10 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         last_round = res.ctl.round;
         last_active_sum = res.ctl.active_sum;
         if (res.ctl.done) break;
-        // closure on demand: over the last four rounds no round added more
-        // than 1/4096 of the states still to be separated (the chain-like
-        // regime where plain rounds each split only a few blocks)
-        const uint64_t left = N - res.ctl.prev_count;
-        uint64_t recent_gain = 0;
-        for (uint32_t i = 1; i <= 4 && i <= res.ctl.round; ++i)
-            recent_gain = std::max<uint64_t>(
-                recent_gain, res.ctl.gain_hist[(res.ctl.round - i) % kActiveHist]);
-        if (o.tc_mode == DFA_TC_AUTO && !seg && !res.tc_used && !tc_failed && res.ctl.round >= 8 &&
-            left >= 4096 && recent_gain * 4096 < left) {
+        // closure on demand: splitting has stalled (the chain-like regime
+        // where plain rounds each split only a few blocks)
+        if (o.tc_mode == DFA_TC_AUTO && !seg && !res.tc_used && !tc_failed &&
+            splitting_stalled(res.ctl, N)) {
             std::vector<uint32_t> tcmap;
             uint32_t levels = 0;
             int rc = build_closure(c, N, k, tcmap, levels);
@@ -663,13 +672,8 @@ int refine_leader(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t c
         last_active_sum = res.ctl.active_sum;
         if (res.ctl.done) break;
         // closure on demand, by the rule of the signature rounds
-        const uint64_t left = N - res.ctl.prev_count;
-        uint64_t recent_gain = 0;
-        for (uint32_t i = 1; i <= 4 && i <= res.ctl.round; ++i)
-            recent_gain = std::max<uint64_t>(
-                recent_gain, res.ctl.gain_hist[(res.ctl.round - i) % kActiveHist]);
-        if (o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed && res.ctl.round >= 8 &&
-            left >= 4096 && recent_gain * 4096 < left) {
+        if (o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed &&
+            splitting_stalled(res.ctl, N)) {
             std::vector<uint32_t> tcmap;
             uint32_t levels = 0;
             int rc = build_closure(c, N, k, tcmap, levels);
@@ -1311,7 +1315,8 @@ void release_ctx(Ctx &c) {
                       &c.presence_packed, &c.lab8, &c.stage_delta, &c.stage_acc, &c.stage_block,
                       &c.stage_qdelta, &c.stage_qacc, &c.stage_delta_b, &c.stage_acc_b,
                       &c.visited, &c.visited2, &c.front0, &c.front1, &c.parts, &c.tile_part,
-                      &c.seg_words, &c.batch_in, &c.batch_out};
+                      &c.seg_words, &c.batch_in, &c.batch_out, &c.new_leader, &c.moved,
+                      &c.chg, &c.single, &c.touched};
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     for (Buffer *b : bufs) {
         if (b->p) (void)hipFree(b->p);
@@ -1338,13 +1343,75 @@ void release_ctx(Ctx &c) {
 
 using Clock = std::chrono::steady_clock;
 
+// Page-locked host buffers for submitted inputs, reused across requests (one
+// free list per power-of-two size class); freed with the server.
+struct PinnedPool {
+    std::mutex mu;
+    std::map<size_t, std::vector<void *>> free_lists;
+    static size_t size_class(size_t bytes) {
+        size_t c = size_t(1) << 16;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    void *get(size_t bytes, size_t &cls) {
+        cls = size_class(bytes);
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = free_lists.find(cls);
+            if (it != free_lists.end() && !it->second.empty()) {
+                void *p = it->second.back();
+                it->second.pop_back();
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(void *p, size_t cls) {
+        std::lock_guard<std::mutex> g(mu);
+        free_lists[cls].push_back(p);
+    }
+    ~PinnedPool() {
+        for (auto &kv : free_lists)
+            for (void *p : kv.second) (void)hipHostFree(p);
+    }
+};
+
+// memcpy split over a few threads for large inputs (one thread reaches about
+// a quarter of the host's copy bandwidth).
+void parallel_copy(void *dst, const void *src, size_t bytes) {
+    constexpr size_t kSplitBytes = size_t(8) << 20;
+    if (bytes < kSplitBytes) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({8, hw / 2, bytes / (kSplitBytes / 4)});
+    const size_t chunk = ((bytes + nt - 1) / nt + 63) & ~size_t(63);
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < nt; ++i) {
+        const size_t off = i * chunk;
+        if (off >= bytes) break;
+        th.emplace_back([=] {
+            std::memcpy(static_cast<char *>(dst) + off, static_cast<const char *>(src) + off,
+                        std::min(chunk, bytes - off));
+        });
+    }
+    std::memcpy(dst, src, std::min(chunk, bytes));
+    for (auto &t : th) t.join();
+}
+
 struct ServedRequest {
     uint64_t ticket = 0;
     int kind = DFA_REQ_MINIMISE;
-    dfa_view a{}, b{};
-    std::vector<uint32_t> da, db;
-    std::vector<uint8_t> aa, ab;
-    size_t footprint = 0;
+    dfa_view a{}, b{};        // the inputs: host copies, then device copies while running
+    void *host_in = nullptr;  // page-locked copy made at submission
+    size_t host_cls = 0;
+    void *dev_in = nullptr;   // stream-ordered device allocation while running
+    size_t in_bytes = 0;
+    size_t off_acc_a = 0, off_delta_b = 0, off_acc_b = 0;
+    size_t footprint = 0;     // device bytes while it runs, inputs included
     size_t states = 0;
     Clock::time_point t_submit, t_start, t_done;
     bool done = false;
@@ -1359,6 +1426,7 @@ struct Server {
     int device = 0;
     dfa_server_config cfg{};
     dfa_tuning tune{};
+    PinnedPool pinned;             // host copies of submitted inputs
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<ServedRequest *> pending;
@@ -1397,7 +1465,8 @@ void finish(Server &s, ServedRequest *r, const std::lock_guard<std::mutex> &) {
     s.latencies.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
 }
 
-// Runs one request alone on a lane (closure on demand).
+// Runs one request alone on a lane (closure on demand); its inputs are
+// already on the device.
 void run_solo(Server &s, Ctx &c, ServedRequest *r) {
     dfa_options o;
     dfa_options_default(&o);
@@ -1405,14 +1474,22 @@ void run_solo(Server &s, Ctx &c, ServedRequest *r) {
     o.loop_mode = DFA_LOOP_CHUNK;
     dfa_stats st{};
     if (r->kind == DFA_REQ_MINIMISE) {
-        r->blocks.resize(r->a.n);
-        r->status = minimise_host(c, r->a.n, r->a.k, r->a.delta, r->a.accepting, r->blocks.data(),
-                                  nullptr, o, &st);
+        const size_t n = r->a.n;
+        r->blocks.resize(n);
+        r->status = c.stage_block.ensure(n * sizeof(uint32_t), "output copy");
+        if (r->status == DFA_OK)
+            r->status = minimise_impl(c, r->a.n, r->a.k, r->a.delta, r->a.accepting,
+                                      c.stage_block.as<uint32_t>(), nullptr, o, &st);
+        if (r->status == DFA_OK &&
+            (hipMemcpyAsync(r->blocks.data(), c.stage_block.p, n * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+             hipStreamSynchronize(c.stream) != hipSuccess))
+            r->status = fail(DFA_EDEVICE, "copy of the result failed");
         r->num_blocks = st.num_blocks;
         r->rounds = st.rounds;
     } else {
         int v = 0;
-        r->status = equivalent_host(c, &r->a, &r->b, &v, o, &st);
+        r->status = equivalent_impl(c, r->a, r->b, &v, o, &st);
         r->verdict = v;
         r->rounds = st.rounds;
     }
@@ -1433,15 +1510,11 @@ void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
     std::vector<bool> redo(count, false);
     int rc;
     if (grp[0]->kind == DFA_REQ_MINIMISE) {
-        std::vector<dfa_view> views(count);
-        for (uint32_t i = 0; i < count; ++i) views[i] = grp[i]->a;
-        std::vector<dfa_view> dev;
-        double h2d = 0;
-        const dfa_view *lists[1] = {views.data()};
-        rc = stage_views(c, count, lists, 1, dev, h2d);
+        std::vector<dfa_view> dev(count);
+        for (uint32_t i = 0; i < count; ++i) dev[i] = grp[i]->a;
         uint64_t total = 0;
         for (auto *r : grp) total += r->a.n;
-        if (rc == DFA_OK) rc = c.batch_out.ensure(total * sizeof(uint32_t), "batched outputs");
+        rc = c.batch_out.ensure(total * sizeof(uint32_t), "batched outputs");
         if (rc == DFA_OK)
             rc = minimise_batch_impl(c, count, dev.data(), c.batch_out.as<uint32_t>(), nullptr,
                                      nb.data(), rounds.data(), o, &bs);
@@ -1477,14 +1550,9 @@ void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
             va[i] = grp[i]->a;
             vb[i] = grp[i]->b;
         }
-        std::vector<dfa_view> dev;
-        double h2d = 0;
-        const dfa_view *lists[2] = {va.data(), vb.data()};
-        rc = stage_views(c, count, lists, 2, dev, h2d);
         std::vector<int32_t> verdicts(count);
-        if (rc == DFA_OK)
-            rc = equivalent_batch_impl(c, count, dev.data(), dev.data() + count, verdicts.data(),
-                                       o, &bs, rounds.data());
+        rc = equivalent_batch_impl(c, count, va.data(), vb.data(), verdicts.data(), o, &bs,
+                                   rounds.data());
         if (rc == DFA_OK || rc == DFA_ELIMIT) {
             for (uint32_t i = 0; i < count; ++i) {
                 redo[i] = rc == DFA_ELIMIT && rounds[i] > bs.rounds;
@@ -1516,13 +1584,14 @@ void lane_main(Server *sp, size_t lane) {
         if (init_ctx(c) == DFA_OK) c.tune = s.tune;
     }
     for (;;) {
-        std::vector<ServedRequest *> grp;
+        std::vector<ServedRequest *> grp, all;
         size_t fp = 0;
         {
             std::unique_lock<std::mutex> lk(s.mu);
             s.cv_work.wait(lk, [&] {
                 return s.stopping ||
-                       (!s.pending.empty() && s.in_use + s.pending.front()->footprint <= s.cfg.hbm_budget);
+                       (!s.pending.empty() &&
+                        s.in_use + s.pending.front()->footprint <= s.cfg.hbm_budget);
             });
             if (s.stopping) return;
             ServedRequest *head = s.pending.front();
@@ -1534,10 +1603,11 @@ void lane_main(Server *sp, size_t lane) {
                 for (auto it = s.pending.begin();
                      it != s.pending.end() && grp.size() < s.cfg.max_group;) {
                     ServedRequest *r = *it;
+                    const size_t extra = r->footprint;
                     if (r->kind == head->kind && r->states <= s.cfg.batch_max_states &&
-                        s.in_use + fp + r->footprint <= s.cfg.hbm_budget) {
+                        s.in_use + fp + extra <= s.cfg.hbm_budget) {
                         grp.push_back(r);
-                        fp += r->footprint;
+                        fp += extra;
                         it = s.pending.erase(it);
                     } else {
                         ++it;
@@ -1552,16 +1622,50 @@ void lane_main(Server *sp, size_t lane) {
         {
             std::lock_guard<std::mutex> g(c.mu);
             g_last_error.clear();
-            if (grp.size() == 1 && grp[0]->states > s.cfg.batch_max_states) {
-                run_solo(s, c, grp[0]);
-            } else {
-                run_group(s, c, grp);
+            // inputs to the device on the lane's stream (asynchronous copies
+            // from page-locked memory); a request whose copy cannot start
+            // fails alone
+            std::vector<ServedRequest *> ready;
+            for (auto *r : grp) {
+                uint8_t *dev = nullptr;
+                if (hipMallocAsync(reinterpret_cast<void **>(&dev), r->in_bytes, c.stream) !=
+                    hipSuccess) {
+                    r->status = fail(DFA_ENOMEM, "device allocation of %zu input bytes failed",
+                                     r->in_bytes);
+                    continue;
+                }
+                r->dev_in = dev;
+                if (hipMemcpyAsync(dev, r->host_in, r->in_bytes, hipMemcpyHostToDevice,
+                                   c.stream) != hipSuccess) {
+                    r->status = fail(DFA_EDEVICE, "copy of the request's inputs failed");
+                    continue;
+                }
+                r->a.delta = reinterpret_cast<const uint32_t *>(dev);
+                r->a.accepting = dev + r->off_acc_a;
+                if (r->kind == DFA_REQ_EQUIVALENT) {
+                    r->b.delta = reinterpret_cast<const uint32_t *>(dev + r->off_delta_b);
+                    r->b.accepting = dev + r->off_acc_b;
+                }
+                ready.push_back(r);
             }
+            all = grp;
+            grp.swap(ready);
+            if (grp.size() == 1 && grp[0]->states > s.cfg.batch_max_states)
+                run_solo(s, c, grp[0]);
+            else if (!grp.empty())
+                run_group(s, c, grp);
+        }
+        (void)hipStreamSynchronize(c.stream);  // the input copies have completed
+        for (auto *r : all) {
+            if (r->dev_in) (void)hipFreeAsync(r->dev_in, c.stream);
+            r->dev_in = nullptr;
+            if (r->host_in) s.pinned.put(r->host_in, r->host_cls);
+            r->host_in = nullptr;
         }
         {
             std::lock_guard<std::mutex> lk(s.mu);
             s.in_use -= fp;
-            for (auto *r : grp) {
+            for (auto *r : all) {
                 if (!r->batched) s.solo++;
                 finish(s, r, lk);
             }
@@ -1887,10 +1991,10 @@ void dfa_server_config_default(dfa_server_config *cfg) {
     if (!cfg) return;
     std::memset(cfg, 0, sizeof *cfg);
     cfg->hbm_budget = 0;
-    cfg->lanes = 2;
+    cfg->lanes = 4;
     cfg->max_group = 512;
     cfg->batch_max_states = 1u << 18;
-    cfg->batch_round_budget = 64;
+    cfg->batch_round_budget = 12;
     cfg->tc_mode = DFA_TC_AUTO;
 }
 
@@ -1925,6 +2029,14 @@ dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
         if (init_ctx(*dc) != DFA_OK) return nullptr;
         s->tune = dc->tune;
     }
+    {
+        // keep freed request memory in the device's pool for the next requests
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     s->t_created = Clock::now();
     for (uint32_t i = 0; i < cfg.lanes; ++i) s->lanes.push_back(std::make_unique<Ctx>());
     Server *raw = s.get();
@@ -1945,29 +2057,40 @@ int dfa_server_submit(dfa_server *handle, const dfa_request *req, uint64_t *tick
     }
     auto r = std::make_unique<ServedRequest>();
     r->kind = req->kind;
-    const size_t na = static_cast<size_t>(req->a.n) * req->a.k;
-    r->da.assign(req->a.delta, req->a.delta + na);
-    r->aa.assign(req->a.accepting, req->a.accepting + req->a.n);
-    r->a = req->a;
-    r->a.delta = r->da.data();
-    r->a.accepting = r->aa.data();
-    r->states = req->a.n;
-    if (req->kind == DFA_REQ_EQUIVALENT) {
-        const size_t nb = static_cast<size_t>(req->b.n) * req->b.k;
-        r->db.assign(req->b.delta, req->b.delta + nb);
-        r->ab.assign(req->b.accepting, req->b.accepting + req->b.n);
-        r->b = req->b;
-        r->b.delta = r->db.data();
-        r->b.accepting = r->ab.data();
-        r->states += req->b.n;
-    }
+    const bool two = req->kind == DFA_REQ_EQUIVALENT;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t da = static_cast<size_t>(req->a.n) * req->a.k * sizeof(uint32_t);
+    const size_t db = two ? static_cast<size_t>(req->b.n) * req->b.k * sizeof(uint32_t) : 0;
+    r->in_bytes = al(da) + al(req->a.n) + (two ? al(db) + al(req->b.n) : 0);
+    r->states = req->a.n + (two ? req->b.n : 0);
     r->footprint = request_footprint(r->states, req->a.k, s->cfg.tc_mode != DFA_TC_OFF);
-    std::lock_guard<std::mutex> lk(s->mu);
     if (r->footprint > s->cfg.hbm_budget) {
+        std::lock_guard<std::mutex> lk(s->mu);
         s->rejected++;
         return fail(DFA_ENOMEM, "request needs ~%zu bytes of device memory, budget is %zu",
                     r->footprint, s->cfg.hbm_budget);
     }
+    // the inputs are copied now (page-locked, so the lane's upload is an
+    // asynchronous DMA), so the caller may free them on return
+    r->off_acc_a = al(da);
+    r->off_delta_b = r->off_acc_a + al(req->a.n);
+    r->off_acc_b = r->off_delta_b + al(db);
+    uint8_t *host = static_cast<uint8_t *>(s->pinned.get(r->in_bytes, r->host_cls));
+    if (!host) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->rejected++;
+        return fail(DFA_ENOMEM, "page-locked host allocation of %zu bytes failed", r->in_bytes);
+    }
+    r->host_in = host;
+    parallel_copy(host, req->a.delta, da);
+    std::memcpy(host + r->off_acc_a, req->a.accepting, req->a.n);
+    r->a = req->a;
+    if (two) {
+        parallel_copy(host + r->off_delta_b, req->b.delta, db);
+        std::memcpy(host + r->off_acc_b, req->b.accepting, req->b.n);
+        r->b = req->b;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
     r->ticket = s->next_ticket++;
     r->t_submit = Clock::now();
     *ticket = r->ticket;
@@ -2065,6 +2188,13 @@ void dfa_server_destroy(dfa_server *handle) {
     for (auto &t : s->workers) t.join();
     (void)hipSetDevice(s->device);
     for (auto &c : s->lanes) release_ctx(*c);
+    // host copies of cancelled requests go back to the pool, which the
+    // server frees
+    for (auto &kv : s->requests)
+        if (kv.second->host_in) {
+            s->pinned.put(kv.second->host_in, kv.second->host_cls);
+            kv.second->host_in = nullptr;
+        }
     delete s;
 }
 

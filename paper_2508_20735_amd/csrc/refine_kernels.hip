@@ -248,23 +248,47 @@ __device__ __forceinline__ uint32_t acc_bit(const unsigned long long *accbits, u
 // label of q's new block; no table is needed.  Distinct patterns are counted
 // by the workgroups that set a bit first in a presence bitmap (deduplicated
 // in LDS per workgroup, then OR-ed into HBM).
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
     __shared__ uint32_t pres[(1u << kPatternMaxBits) / 32];
     if (p.ctl->done) return;
-    const uint32_t bits = p.k_eff + 1;
+    const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
+    const uint32_t bits = keff + 1;
     const uint32_t words = bits >= 5 ? (1u << bits) / 32 : 1u;
+    // up to 64 patterns: each thread keeps the patterns it saw in a register
+    const bool in_reg = bits <= 6;
     for (uint32_t i = threadIdx.x; i < words; i += kBlock) pres[i] = 0;
     __syncthreads();
     uint32_t *__restrict__ out = p.blockB;
+    unsigned long long seen_reg = 0;
     for (size_t q = global_tid(); q < p.N; q += grid_stride()) {
         uint32_t label = acc_bit(p.accbits, static_cast<uint32_t>(q));
-        for (uint32_t j = 0; j < p.k_eff; ++j) {
-            const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
-            label |= acc_bit(p.accbits, t) << (j + 1);
+        if constexpr (KC > 0) {
+            // all column entries first, then all acceptance bits
+            uint32_t t[KC];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) label |= acc_bit(p.accbits, t[j]) << (j + 1);
+        } else {
+            for (uint32_t j = 0; j < keff; ++j) {
+                const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+                label |= acc_bit(p.accbits, t) << (j + 1);
+            }
         }
         out[q] = label;
         if (p.lab8) p.lab8[q] = static_cast<uint8_t>(label);
-        atomicOr(pres + (label >> 5), 1u << (label & 31));
+        if (in_reg)
+            seen_reg |= 1ull << label;
+        else
+            atomicOr(pres + (label >> 5), 1u << (label & 31));
+    }
+    if (in_reg) {
+        seen_reg = wave_or64(seen_reg);
+        if (lane_id() == 0 && seen_reg) {
+            atomicOr(pres + 0, static_cast<uint32_t>(seen_reg));
+            if (words > 1) atomicOr(pres + 1, static_cast<uint32_t>(seen_reg >> 32));
+        }
     }
     __syncthreads();
     uint32_t fresh = 0;
@@ -288,12 +312,14 @@ __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
 // one bitmap access per tile, not one per state.
 constexpr uint32_t kLdsSlots = 2 * kBlock;
 
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
     __shared__ uint32_t lset[kLdsSlots];
     if (p.ctl->done) return;
     const uint32_t r = p.ctl->round;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
-    const uint32_t bits = p.k_eff + 1;
+    const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
+    const uint32_t bits = keff + 1;
     const uint32_t tx = threadIdx.x;
     uint32_t fresh = 0;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
@@ -305,9 +331,20 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
         uint32_t key = 0;
         if (q < p.N) {
             key = p.lab8[q];
-            for (uint32_t j = 0; j < p.k_eff; ++j) {
-                const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
-                key |= static_cast<uint32_t>(p.lab8[t]) << (bits * (j + 1));
+            if constexpr (KC > 0) {
+                // all column entries first, then all byte labels
+                uint32_t t[KC];
+#pragma unroll
+                for (int j = 0; j < KC; ++j)
+                    t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+#pragma unroll
+                for (int j = 0; j < KC; ++j)
+                    key |= static_cast<uint32_t>(p.lab8[t[j]]) << (bits * (j + 1));
+            } else {
+                for (uint32_t j = 0; j < keff; ++j) {
+                    const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+                    key |= static_cast<uint32_t>(p.lab8[t]) << (bits * (j + 1));
+                }
             }
             Y[q] = key;
             // keys are < 2^kPackedMaxBits, so ~0u marks an empty LDS slot
@@ -345,6 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
 // their block is now a singleton, and marks the blocks with a member whose
 // successor changed id in the last round.  It also clears the touched bitmap
 // of the next round.
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
     if (p.ctl->done) return;
     const uint32_t r = p.ctl->round;
@@ -358,6 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
     if (r <= p.ctl->all_active_until || !incremental_round(*p.ctl, p.N, r)) return;
     unsigned long long *__restrict__ T = p.touched + (r & 1u) * words;
     const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
+    const unsigned long long *__restrict__ chg = p.chg;
+    const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
         const size_t q = base + threadIdx.x;
@@ -366,19 +406,88 @@ __global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
         const size_t wd = first >> 6;
         const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
         const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
-        bool s = (sw >> lane_id()) & 1ull;
-        const uint32_t x = valid ? X[q] : 0u;
+        bool s = !valid || ((sw >> lane_id()) & 1ull);
         // a block formed last round with one member stays a singleton
-        if (valid && !s && ((aw >> lane_id()) & 1ull)) s = p.multi[x] != r;
+        const bool was_active = !s && ((aw >> lane_id()) & 1ull);
+        uint32_t x = 0;
+        if (was_active) {
+            x = X[q];
+            s = p.multi[x] != r;
+        }
         const unsigned long long nsw = __ballot(s);
         if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
-        if (!valid || s) continue;
+        if (s) continue;
+        // all column entries first, then all change bits: two dependent
+        // steps per state instead of two per letter
         bool dirty = false;
-        for (uint32_t j = 0; j < p.k_eff && !dirty; ++j) {
-            const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
-            dirty = (p.chg[t >> 6] >> (t & 63)) & 1ull;
+        if constexpr (KC > 0) {
+            uint32_t t[KC];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) dirty |= ((chg[t[j] >> 6] >> (t[j] & 63)) & 1ull) != 0;
+        } else {
+            for (uint32_t j0 = 0; j0 < keff && !dirty; j0 += 8) {
+                const uint32_t m = keff - j0 < 8 ? keff - j0 : 8;
+                uint32_t t[8];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j)
+                    if (j < m) t[j] = p.cols[static_cast<size_t>(p.colmap[j0 + j]) * p.N + q];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j)
+                    if (j < m) dirty |= ((chg[t[j] >> 6] >> (t[j] & 63)) & 1ull) != 0;
+            }
         }
-        if (dirty) atomicOr(T + (x >> 6), 1ull << (x & 63));
+        if (!dirty) continue;
+        if (!was_active) x = X[q];
+        atomicOr(T + (x >> 6), 1ull << (x & 63));
+    }
+}
+
+// Whether state q is refined this round (selective rounds), with the
+// bookkeeping of the selection: in full rounds the states refined last round
+// learn whether their block is now a singleton (the marking kernel does this
+// in incremental rounds), and the wave's mask of refined states is stored.
+// Every lane of the wave must call it (ballots).
+__device__ __forceinline__ bool select_state(const SigParams &p, size_t q, uint32_t w0, uint32_t r,
+                                             bool inc, const unsigned long long *T) {
+    const bool valid = q < p.N;
+    const size_t first = q - lane_id();
+    const size_t wd = first >> 6;
+    const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
+    bool s = !valid || ((sw >> lane_id()) & 1ull);
+    if (!inc) {
+        const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
+        if (!s && ((aw >> lane_id()) & 1ull)) s = p.multi[w0] != r;
+        const unsigned long long nsw = __ballot(s);
+        if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
+    }
+    const bool act = !s && (!inc || ((T[w0 >> 6] >> (w0 & 63)) & 1ull));
+    const unsigned long long am = __ballot(act);
+    if (lane_id() == 0 && first < p.N) p.active[wd] = am;
+    return act;
+}
+
+// Writes the key row and hash of a refined state; a state that holds its
+// block's id (selective rounds) claims its key's slot right away.
+__device__ __forceinline__ void emit_key(const SigParams &p, uint32_t *__restrict__ Y, size_t q,
+                                         uint32_t w0, const uint32_t *w, uint32_t keff, size_t W,
+                                         bool claim_holder, uint32_t epoch, uint32_t &claims) {
+    uint32_t *__restrict__ row = p.sig + q * W;
+    row[0] = w0;
+    uint64_t h = mix_step(kHashSeed, w0);
+    for (uint32_t j = 0; j < keff; ++j) {
+        row[1 + j] = w[j];
+        h = mix_step(h, w[j]);
+    }
+    h = mix_final(h);
+    p.hash[q] = h;
+    if (claim_holder && w0 == q) {
+        // the state that holds its block's id claims its key before the
+        // others group, so a block that does not split keeps its id
+        claim_slot(p.table, p.table_cap - 1, epoch, h, static_cast<uint32_t>(q));
+        Y[q] = w0;
+        ++claims;
     }
 }
 
@@ -388,7 +497,8 @@ __global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
 // and are copied to the output buffer.  A refined state that holds its
 // block's id claims a table slot for its key here, before any other state
 // looks its key up.
-// KC > 0: k_eff known at compile time (fully unrolled gathers);
+// KC > 0: k_eff known at compile time (fully unrolled gathers, two states per
+// thread);
 // KC == 0: runtime k_eff, gathers issued in batches of 8.
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
@@ -399,101 +509,73 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
     const bool all = r <= p.ctl->all_active_until;
     const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
     const size_t W = keff + 1;
-
-    if constexpr (KC > 0) {
-        if (all) {
-            // every state is refined: two states per thread, all independent
-            // loads issued before their values are used
-            for (size_t base = static_cast<size_t>(blockIdx.x) * (2 * kBlock); base < p.N;
-                 base += static_cast<size_t>(gridDim.x) * (2 * kBlock)) {
-                const size_t q[2] = {base + threadIdx.x, base + kBlock + threadIdx.x};
-                bool v[2];
-                uint32_t w0[2], t[2][KC], w[2][KC];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    v[i] = q[i] < p.N;
-                    const size_t first = q[i] - lane_id();
-                    const unsigned long long am = __ballot(v[i]);
-                    if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
-                }
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    w0[i] = v[i] ? X[q[i]] : 0u;
-#pragma unroll
-                    for (int j = 0; j < KC; ++j)
-                        t[i][j] = v[i] ? p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q[i]] : 0u;
-                }
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < KC; ++j) w[i][j] = v[i] ? X[t[i][j]] : 0u;
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    if (!v[i]) continue;
-                    uint32_t *__restrict__ row = p.sig + q[i] * W;
-                    row[0] = w0[i];
-                    uint64_t h = mix_step(kHashSeed, w0[i]);
-#pragma unroll
-                    for (int j = 0; j < KC; ++j) {
-                        row[1 + j] = w[i][j];
-                        h = mix_step(h, w[i][j]);
-                    }
-                    p.hash[q[i]] = mix_final(h);
-                }
-            }
-            return;
-        }
-    }
-
     const bool inc = !all && incremental_round(*p.ctl, p.N, r);
     const size_t words = (p.N + 63) / 64;
     const unsigned long long *__restrict__ T = p.touched + (r & 1u) * words;
     const uint32_t epoch = r % kEpochs + 1;
     uint32_t leaders = 0, claims = 0;
-    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
-         base += static_cast<size_t>(gridDim.x) * kBlock) {
-        const size_t q = base + threadIdx.x;
-        const bool valid = q < p.N;
-        const size_t first = base + (threadIdx.x & ~63u);
-        const size_t wd = first >> 6;
-        const uint32_t w0 = valid ? X[q] : 0u;
-        bool act = valid;
-        if (!all) {
-            const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
-            bool s = (sw >> lane_id()) & 1ull;
-            if (!inc) {
-                // states refined last round learn whether their block is now
-                // a singleton (the marking kernel does this in incremental
-                // rounds)
-                const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
-                if (valid && !s && ((aw >> lane_id()) & 1ull)) s = p.multi[w0] != r;
-                const unsigned long long nsw = __ballot(s);
-                if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
+
+    if constexpr (KC > 0) {
+        // two states per thread, all independent loads of both issued before
+        // their values are used
+        for (size_t base = static_cast<size_t>(blockIdx.x) * (2 * kBlock); base < p.N;
+             base += static_cast<size_t>(gridDim.x) * (2 * kBlock)) {
+            const size_t q[2] = {base + threadIdx.x, base + kBlock + threadIdx.x};
+            bool act[2];
+            uint32_t w0[2], t[2][KC], w[2][KC];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) w0[i] = q[i] < p.N ? X[q[i]] : 0u;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                if (all) {
+                    act[i] = q[i] < p.N;
+                    const size_t first = q[i] - lane_id();
+                    const unsigned long long am = __ballot(act[i]);
+                    if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
+                } else {
+                    act[i] = select_state(p, q[i], w0[i], r, inc, T);
+                    if (q[i] < p.N && !act[i]) {
+                        Y[q[i]] = w0[i];
+                        leaders += w0[i] == q[i] ? 1u : 0u;
+                    }
+                }
             }
-            act = valid && !s && (!inc || ((T[w0 >> 6] >> (w0 & 63)) & 1ull));
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < KC; ++j)
+                    t[i][j] = act[i] ? p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q[i]] : 0u;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < KC; ++j) w[i][j] = act[i] ? X[t[i][j]] : 0u;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                if (act[i]) emit_key(p, Y, q[i], w0[i], w[i], KC, W, !all, epoch, claims);
         }
-        const unsigned long long am = __ballot(act);
-        if (lane_id() == 0 && first < p.N) p.active[wd] = am;
-        if (valid && !act) {
-            Y[q] = w0;
-            leaders += w0 == q ? 1u : 0u;
-        }
-        if (!act) continue;
-        uint32_t *__restrict__ row = p.sig + q * W;
-        row[0] = w0;
-        uint64_t h = mix_step(kHashSeed, w0);
-        if constexpr (KC > 0) {
-            uint32_t t[KC], w[KC];
-#pragma unroll
-            for (int j = 0; j < KC; ++j) t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
-#pragma unroll
-            for (int j = 0; j < KC; ++j) w[j] = X[t[j]];
-#pragma unroll
-            for (int j = 0; j < KC; ++j) {
-                row[1 + j] = w[j];
-                h = mix_step(h, w[j]);
+    } else {
+        for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
+             base += static_cast<size_t>(gridDim.x) * kBlock) {
+            const size_t q = base + threadIdx.x;
+            const bool valid = q < p.N;
+            const uint32_t w0 = valid ? X[q] : 0u;
+            bool act = valid;
+            if (all) {
+                const size_t first = q - lane_id();
+                const unsigned long long am = __ballot(act);
+                if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
+            } else {
+                act = select_state(p, q, w0, r, inc, T);
+                if (valid && !act) {
+                    Y[q] = w0;
+                    leaders += w0 == q ? 1u : 0u;
+                }
             }
-        } else {
+            if (!act) continue;
+            uint32_t *__restrict__ row = p.sig + q * W;
+            row[0] = w0;
+            uint64_t h = mix_step(kHashSeed, w0);
+            // runtime k_eff: gathers issued in batches of 8
             for (uint32_t j0 = 0; j0 < keff; j0 += 8) {
                 const uint32_t m = keff - j0 < 8 ? keff - j0 : 8;
                 uint32_t t[8], w[8];
@@ -510,15 +592,13 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
                         h = mix_step(h, w[j]);
                     }
             }
-        }
-        h = mix_final(h);
-        p.hash[q] = h;
-        if (!all && w0 == q) {
-            // the state that holds its block's id claims its key before the
-            // others group, so a block that does not split keeps its id
-            claim_slot(p.table, p.table_cap - 1, epoch, h, static_cast<uint32_t>(q));
-            Y[q] = w0;
-            ++claims;
+            h = mix_final(h);
+            p.hash[q] = h;
+            if (!all && w0 == q) {
+                claim_slot(p.table, p.table_cap - 1, epoch, h, static_cast<uint32_t>(q));
+                Y[q] = w0;
+                ++claims;
+            }
         }
     }
     wg_add_spread(p.counters, 0, leaders + claims);
@@ -1129,13 +1209,28 @@ void launch_round_end(const RoundArgs &a, hipStream_t s) {
 }
 
 void launch_pattern_kernel(const RoundArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_pattern_round, dim3(round_grid(a, a.pattern_grid_cap)), dim3(kBlock), 0,
-                       s, sig_params(a));
+    const SigParams sp = sig_params(a);
+    const dim3 grid(round_grid(a, a.pattern_grid_cap)), block(kBlock);
+    switch (a.k_eff) {
+        case 1: hipLaunchKernelGGL(k_pattern_round<1>, grid, block, 0, s, sp); break;
+        case 2: hipLaunchKernelGGL(k_pattern_round<2>, grid, block, 0, s, sp); break;
+        case 3: hipLaunchKernelGGL(k_pattern_round<3>, grid, block, 0, s, sp); break;
+        case 4: hipLaunchKernelGGL(k_pattern_round<4>, grid, block, 0, s, sp); break;
+        case 8: hipLaunchKernelGGL(k_pattern_round<8>, grid, block, 0, s, sp); break;
+        default: hipLaunchKernelGGL(k_pattern_round<0>, grid, block, 0, s, sp); break;
+    }
 }
 
 void launch_packed_kernel(const RoundArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_packed_round, dim3(round_grid(a, a.pattern_grid_cap)), dim3(kBlock), 0, s,
-                       sig_params(a));
+    const SigParams sp = sig_params(a);
+    const dim3 grid(round_grid(a, a.pattern_grid_cap)), block(kBlock);
+    switch (a.k_eff) {
+        case 1: hipLaunchKernelGGL(k_packed_round<1>, grid, block, 0, s, sp); break;
+        case 2: hipLaunchKernelGGL(k_packed_round<2>, grid, block, 0, s, sp); break;
+        case 3: hipLaunchKernelGGL(k_packed_round<3>, grid, block, 0, s, sp); break;
+        case 4: hipLaunchKernelGGL(k_packed_round<4>, grid, block, 0, s, sp); break;
+        default: hipLaunchKernelGGL(k_packed_round<0>, grid, block, 0, s, sp); break;
+    }
 }
 
 void launch_pattern_round(const RoundArgs &a, hipStream_t s) {
@@ -1176,8 +1271,17 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
 }
 
 void launch_mark(const RoundArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_mark, dim3(round_grid(a, a.round_grid_cap)), dim3(kBlock), 0, s,
-                       sig_params(a));
+    const SigParams sp = sig_params(a);
+    const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
+    switch (a.k_eff) {
+        case 1: hipLaunchKernelGGL(k_mark<1>, grid, block, 0, s, sp); break;
+        case 2: hipLaunchKernelGGL(k_mark<2>, grid, block, 0, s, sp); break;
+        case 3: hipLaunchKernelGGL(k_mark<3>, grid, block, 0, s, sp); break;
+        case 4: hipLaunchKernelGGL(k_mark<4>, grid, block, 0, s, sp); break;
+        case 8: hipLaunchKernelGGL(k_mark<8>, grid, block, 0, s, sp); break;
+        case 16: hipLaunchKernelGGL(k_mark<16>, grid, block, 0, s, sp); break;
+        default: hipLaunchKernelGGL(k_mark<0>, grid, block, 0, s, sp); break;
+    }
 }
 
 void launch_ctl_full(RoundCtl *ctl, hipStream_t s) {
