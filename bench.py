@@ -62,6 +62,8 @@ def parse_args():
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served request stream")
     ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the comparison of grouping / refinement variants")
     return ap.parse_args()
 
 
@@ -159,6 +161,46 @@ def batch_leg(B, W, torch, np, count: int) -> dict:
             "speedup": tp / tb,
             "batched_transitions_per_s": work_b / tb,
             "plain_transitions_per_s": work_p / tp}
+
+
+def variants_leg(B, W, torch, np, dev, A_d, A_a, n) -> dict:
+    """The same GPU on the same inputs with the other refinement options:
+    sort-based grouping (sortPR's grouping) vs the hash table on the 2^22
+    minimisation; leader rounds (naivePR) vs signature rounds on the
+    bit-splitter B_20 of Table 2; reachability pruning on the 2^22 workload.
+    Median device time of 3 runs after one warm-up."""
+
+    def med(fn, runs=3):
+        fn()
+        ts = []
+        st = None
+        for _ in range(runs):
+            st = fn()
+            ts.append(st["device_ms"])
+        return float(np.median(ts)), st
+
+    block = torch.empty(n, dtype=torch.int32, device=dev)
+    out = {}
+    for alg in ("signature", "sort"):
+        ms, st = med(lambda: B.minimise_device(A_d, A_a, block, tc="off", loop="graph",
+                                               algorithm=alg).stats)
+        out[f"minimise_2e22_{alg}_ms"] = ms
+        out[f"minimise_2e22_{alg}_rounds"] = st["rounds"]
+    ms, st = med(lambda: B.minimise_device(A_d, A_a, block, tc="off", loop="graph",
+                                           prune=True).stats)
+    out["minimise_2e22_pruned_ms"] = ms
+    out["minimise_2e22_reachable"] = st["reachable"]
+    bs = W.bitsplitter(20)
+    bd = torch.from_numpy(bs.delta.view(np.int32)).to(dev)
+    ba = torch.from_numpy(bs.accepting).to(dev)
+    bb = torch.empty(bs.n, dtype=torch.int32, device=dev)
+    for alg in ("signature", "leader"):
+        ms, st = med(lambda: B.minimise_device(bd, ba, bb, tc="off", loop="graph",
+                                               algorithm=alg).stats)
+        out[f"b20_{alg}_ms"] = ms
+        out[f"b20_{alg}_rounds"] = st["rounds"]
+    out["b20_transitions"] = bs.n * bs.k
+    return out
 
 
 def serve_leg(B, W, count: int) -> dict:
@@ -345,6 +387,8 @@ def main() -> int:
         out["batched"] = batch_leg(B, W, torch, np, args.batch_count)
     if not args.no_serve:
         out["served"] = serve_leg(B, W, args.serve_requests)
+    if not args.no_variants:
+        out["variants"] = variants_leg(B, W, torch, np, dev, A_d, A_a, d.n)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, perm)
     print(json.dumps(out), flush=True)

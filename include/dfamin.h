@@ -70,6 +70,10 @@ extern "C" {
 /* ---- refinement algorithm ---- */
 #define DFA_ALGO_SIGNATURE 0 /* signature rounds with hashing: every block splits into
                                 all its classes at once (Section 3.3, Algorithm 4) */
+#define DFA_ALGO_SORT 2      /* signature rounds grouped by a stable radix sort of the
+                                signature hashes instead of the hash table (the grouping of
+                                sortPR, Section 3.3, Algorithm 4); same partitions and rounds
+                                as DFA_ALGO_SIGNATURE.  Single-DFA calls only. */
 #define DFA_ALGO_LEADER 1    /* leader rounds, naivePR (Section 3.2, Algorithm 2): the
                                 states that differ from their block's leader leave it
                                 together; with DFA_TC_ON this is transPR (Algorithm 5
@@ -95,8 +99,16 @@ typedef struct dfa_options {
                                  block per eight refined states (default) */
     int32_t algorithm;    /* DFA_ALGO_*, default DFA_ALGO_SIGNATURE; the batched calls
                              and the server accept only DFA_ALGO_SIGNATURE */
-    int32_t reserved[3];
+    int32_t prune;        /* dfa_minimise only: 0 = partition all n states (default, the
+                             paper's convention, Section 2); 1 = only the states reachable
+                             from `start` (breadth-first search first): block_out[q] =
+                             DFA_UNREACHABLE for the others, ids are the smallest
+                             reachable state of each block, and the quotient is the usual
+                             minimal DFA.  The batched calls and the server accept only 0 */
+    int32_t reserved[2];
 } dfa_options;
+
+#define DFA_UNREACHABLE 0xFFFFFFFFu /* block_out value of a pruned state */
 
 typedef struct dfa_stats {
     uint32_t rounds;          /* refinement rounds executed (signature or leader rounds);
@@ -107,7 +119,7 @@ typedef struct dfa_stats {
     uint32_t tc_used;         /* 1 if the closure letters were built */
     uint32_t tc_levels;       /* floor(log2 n) when tc_used */
     uint32_t plain_rounds;    /* rounds run on the input letters before switching to the closure */
-    uint32_t reserved0;
+    uint32_t reachable;       /* states partitioned: n, or the reachable ones with prune */
     double h2d_ms;            /* host-pointer calls: copy of the inputs */
     double device_ms;         /* device work of the call (HIP events) */
     double d2h_ms;            /* host-pointer calls: copy of the results */
@@ -154,7 +166,11 @@ typedef struct dfa_tuning {
                                 round-0 labels when (k_eff + 1)^2 <= 25 */
     uint32_t cached_probe;   /* 1: probe the grouping table with cached loads first */
     uint32_t chunk;          /* rounds per chunk when options.chunk is 0 (1..4096) */
-    uint32_t reserved[11];
+    uint32_t hash_bits;      /* 0 = full 64-bit key hashes (default); 1..63 keep only the
+                                low bits, so that distinct keys share hashes: slower, still
+                                exact (keys are always compared in full); for testing the
+                                collision paths of both groupings */
+    uint32_t reserved[10];
 } dfa_tuning;
 
 void dfa_tuning_default(dfa_tuning *t);

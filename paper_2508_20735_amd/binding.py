@@ -31,8 +31,10 @@ REQ_EQUIVALENT = 1
 
 TC = {"off": 0, "on": 1, "auto": 2}
 LOOP = {"host": 0, "chunk": 1, "graph": 2}
+# block id of a state removed by reachability pruning
+UNREACHABLE = 0xFFFFFFFF
 # signature rounds (sortPR semantics, hashed) or leader rounds (naivePR)
-ALGO = {"signature": 0, "leader": 1}
+ALGO = {"signature": 0, "leader": 1, "sort": 2}
 
 
 class DfaError(RuntimeError):
@@ -45,14 +47,15 @@ class Options(ctypes.Structure):
     _fields_ = [("tc_mode", ctypes.c_int32), ("loop_mode", ctypes.c_int32),
                 ("start", ctypes.c_uint32), ("max_rounds", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("lds_stage", ctypes.c_int32),
-                ("algorithm", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("algorithm", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_uint32), ("changing_rounds", ctypes.c_uint32),
                 ("num_blocks", ctypes.c_uint32), ("k_eff", ctypes.c_uint32),
                 ("tc_used", ctypes.c_uint32), ("tc_levels", ctypes.c_uint32),
-                ("plain_rounds", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("plain_rounds", ctypes.c_uint32), ("reachable", ctypes.c_uint32),
                 ("h2d_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("d2h_ms", ctypes.c_double), ("transitions_refined", ctypes.c_uint64),
                 ("algorithmic_bytes", ctypes.c_uint64)]
@@ -64,7 +67,8 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("round_grid_cap", ctypes.c_uint32), ("label_grid_cap", ctypes.c_uint32),
                 ("label_rounds", ctypes.c_uint32), ("cached_probe", ctypes.c_uint32),
-                ("chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 11)]
+                ("chunk", ctypes.c_uint32), ("hash_bits", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 10)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -228,7 +232,8 @@ def _check(rc: int, allow=()) -> int:
 
 
 def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: int = 0,
-            chunk: int = 0, lds_stage=2, algorithm: str = "signature") -> Options:
+            chunk: int = 0, lds_stage=2, algorithm: str = "signature",
+            prune: bool = False) -> Options:
     o = Options()
     load().dfa_options_default(ctypes.byref(o))
     o.tc_mode = TC[tc]
@@ -239,6 +244,7 @@ def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: i
     # True/False select always/never; 2 (the default) lets each round decide
     o.lds_stage = int(lds_stage) if not isinstance(lds_stage, bool) else (1 if lds_stage else 0)
     o.algorithm = ALGO[algorithm]
+    o.prune = 1 if prune else 0
     return o
 
 
@@ -311,12 +317,14 @@ class MinimiseResult:
 
 def minimise(delta, accepting, *, tc: str = "auto", loop: str = "graph", start: int = 0,
              max_rounds: int = 0, chunk: int = 0, lds_stage=2,
-             quotient: bool = False, algorithm: str = "signature") -> MinimiseResult:
-    """dfa_minimise on host arrays."""
+             quotient: bool = False, algorithm: str = "signature",
+             prune: bool = False) -> MinimiseResult:
+    """dfa_minimise on host arrays.  With ``prune``, only the states reachable
+    from ``start`` are partitioned (the others get UNREACHABLE)."""
     d, a = _host_arrays(delta, accepting)
     n, k = d.shape
     block = np.empty(n, dtype=np.uint32)
-    o = options(tc, loop, start, max_rounds, chunk, lds_stage, algorithm)
+    o = options(tc, loop, start, max_rounds, chunk, lds_stage, algorithm, prune)
     st = Stats()
     q = None
     if quotient:
@@ -352,7 +360,7 @@ def _check_device_tensor(t, dtype_name: str, numel: int, what: str):
 def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop: str = "graph",
                     start: int = 0, max_rounds: int = 0, chunk: int = 0, lds_stage=2,
                     quotient: bool = False, stream=None,
-                    algorithm: str = "signature") -> MinimiseResult:
+                    algorithm: str = "signature", prune: bool = False) -> MinimiseResult:
     """dfa_minimise_device on torch GPU tensors: delta int32/uint32 [n, k]
     (row-major), accepting uint8 [n]; block_out int32 [n] (allocated if None)."""
     import torch
@@ -364,7 +372,7 @@ def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop:
     if block_out is None:
         block_out = torch.empty(n, dtype=torch.int32, device=delta.device)
     _check_device_tensor(block_out, str(block_out.dtype), n, "block_out")
-    o = options(tc, loop, start, max_rounds, chunk, lds_stage, algorithm)
+    o = options(tc, loop, start, max_rounds, chunk, lds_stage, algorithm, prune)
     st = Stats()
     q = None
     if quotient:

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libdfamin.so")
-SOURCES = ["api.hip", "refine_kernels.hip", "leader_kernels.hip", "product_kernels.hip"]
+SOURCES = ["api.hip", "refine_kernels.hip", "leader_kernels.hip", "reach_kernels.hip",
+           "sort_kernels.hip", "product_kernels.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

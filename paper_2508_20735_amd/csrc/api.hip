@@ -107,6 +107,11 @@ struct Ctx {
     Buffer visited, visited2, front0, front1;
     Buffer new_leader, moved;
     Buffer chg, single, touched;
+    Buffer reach_visited, reach_qa, reach_qb, reach_flags, reach_dense, reach_orig, sub_delta,
+        sub_acc, sub_block;
+    Buffer sort_keys0, sort_keys1, sort_vals0, sort_vals1, sort_hist, sort_partials,
+        sort_runhead, sort_m;
+    hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr;  // pruned minimisation, whole call
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     size_t pinned_batch_cap = 0;
@@ -151,6 +156,8 @@ int init_ctx(Ctx &c) {
     HIP_TRY(hipEventCreate(&c.ev_start));
     HIP_TRY(hipEventCreate(&c.ev_stop));
     HIP_TRY(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreate(&c.ev_p0));
+    HIP_TRY(hipEventCreate(&c.ev_p1));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c.pinned), kPinnedWords * sizeof(uint32_t),
                           hipHostMallocDefault));
     dfa_tuning_default(&c.tune);
@@ -201,7 +208,8 @@ int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
 // ---- kernel timing ----
 
 enum class Kern {
-    Mark, Signature, Insert, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove, LeaderEnd
+    Mark, Signature, Insert, SortGroup, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove,
+    LeaderEnd
 };
 
 int prof_event(Ctx &c, size_t &idx) {
@@ -237,6 +245,7 @@ const char *kern_name(Kern kind) {
         case Kern::Mark: return "k_mark";
         case Kern::Signature: return "k_signature";
         case Kern::Insert: return "k_insert";
+        case Kern::SortGroup: return "sort_group";
         case Kern::RoundEnd: return "k_round_end";
         case Kern::Pattern: return "k_pattern_round";
         case Kern::Packed: return "k_packed_round";
@@ -259,6 +268,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
             case Kern::Mark: launch_mark(a, c.stream); break;
             case Kern::Signature: launch_signature(a, c.stream); break;
             case Kern::Insert: launch_insert(a, c.stream); break;
+            case Kern::SortGroup: launch_sort_group(a, c.stream); break;
             case Kern::RoundEnd: launch_round_end(a, c.stream); break;
             case Kern::Pattern: launch_pattern_kernel(a, c.stream); break;
             case Kern::Packed: launch_packed_kernel(a, c.stream); break;
@@ -283,7 +293,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
 int launch_full_round(Ctx &c, const RoundArgs &a, uint32_t round) {
     DFA_TRY(launch_kern(c, Kern::Mark, a, round));
     DFA_TRY(launch_kern(c, Kern::Signature, a, round));
-    DFA_TRY(launch_kern(c, Kern::Insert, a, round));
+    DFA_TRY(launch_kern(c, a.grouping ? Kern::SortGroup : Kern::Insert, a, round));
     if (a.seg.nseg) launch_seg_round(a, c.stream);
     return launch_kern(c, Kern::RoundEnd, a, round);
 }
@@ -322,6 +332,7 @@ struct RefineResult {
     uint32_t tc_used = 0, tc_levels = 0, plain_rounds = 0;
     const uint32_t *final_block = nullptr;
     uint64_t transitions = 0, bytes = 0;
+    uint32_t N = 0;  // states refined
 };
 
 // Whether plain rounds have stalled, after at least 8 rounds: over the last
@@ -429,7 +440,7 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t f
 // whose initial labels are in c.blockA (flags already written by the ingest
 // and init kernels).
 RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff, uint64_t cap,
-                          int lds_stage, bool packed, const SegArgs *seg) {
+                          int lds_stage, bool packed, const SegArgs *seg, uint32_t grouping) {
     RoundArgs ra;
     std::memset(&ra, 0, sizeof ra);
     if (seg) ra.seg = *seg;
@@ -458,6 +469,18 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
     ra.chg = c.chg.as<unsigned long long>();
     ra.single = c.single.as<unsigned long long>();
     ra.touched = c.touched.as<unsigned long long>();
+    ra.grouping = grouping;
+    ra.hash_bits = c.tune.hash_bits;
+    if (grouping) {
+        ra.sort.keys[0] = c.sort_keys0.as<unsigned long long>();
+        ra.sort.keys[1] = c.sort_keys1.as<unsigned long long>();
+        ra.sort.vals[0] = c.sort_vals0.as<uint32_t>();
+        ra.sort.vals[1] = c.sort_vals1.as<uint32_t>();
+        ra.sort.hist = c.sort_hist.as<uint32_t>();
+        ra.sort.partials = c.sort_partials.as<uint32_t>();
+        ra.sort.runhead = c.sort_runhead.as<uint32_t>();
+        ra.sort.m = c.sort_m.as<uint32_t>();
+    }
     return ra;
 }
 
@@ -468,6 +491,7 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
 // which keeps the partition and turns the labels into state ids.
 int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq, uint32_t eq_a,
            uint32_t eq_b, bool state_ids, RefineResult &res, const SegArgs *seg = nullptr) {
+    res.N = static_cast<uint32_t>(N);
     // target check, classes, identity letters (one readback)
     DFA_TRY(read_back(c, c.flags.p, (kFlagNonid + k) * sizeof(uint32_t)));
     if (c.pinned[kFlagErr]) return fail(DFA_EINVAL, "a transition target is >= n");
@@ -499,6 +523,18 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     DFA_TRY(c.touched.ensure(2 * words64 * sizeof(unsigned long long), "touched-block bits"));
     HIP_TRY(hipMemsetAsync(c.single.p, 0, words64 * sizeof(unsigned long long), c.stream));
     HIP_TRY(hipMemsetAsync(c.touched.p, 0, 2 * words64 * sizeof(unsigned long long), c.stream));
+    const uint32_t grouping = (o.algorithm == DFA_ALGO_SORT && !seg) ? 1u : 0u;
+    if (grouping) {
+        const SortPlan pl = sort_plan(N);
+        DFA_TRY(c.sort_keys0.ensure(N * sizeof(unsigned long long), "sort keys"));
+        DFA_TRY(c.sort_keys1.ensure(N * sizeof(unsigned long long), "sort keys"));
+        DFA_TRY(c.sort_vals0.ensure(N * sizeof(uint32_t), "sort values"));
+        DFA_TRY(c.sort_vals1.ensure(N * sizeof(uint32_t), "sort values"));
+        DFA_TRY(c.sort_hist.ensure(pl.hist_words * sizeof(uint32_t), "digit counts"));
+        DFA_TRY(c.sort_partials.ensure(pl.partial_words * sizeof(uint32_t), "scan partials"));
+        DFA_TRY(c.sort_runhead.ensure(N * sizeof(uint32_t), "run heads"));
+        DFA_TRY(c.sort_m.ensure(sizeof(uint32_t), "sort count"));
+    }
     // label rounds need at least three rounds of budget (ids become state
     // ids in the round after them)
     // (segmented refinements keep their segment labels: no label rounds)
@@ -529,7 +565,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     res.bytes = 0;
     bool first = true;
     for (;;) {
-        const RoundArgs ra = make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second, seg);
+        const RoundArgs ra = make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second, seg, grouping);
         if (first) {
             // rounds 0 (and 1) run on their own: label rounds when the
             // signatures are short enough
@@ -587,7 +623,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     if (state_ids && res.ctl.stable && res.ctl.round <= res.label_rounds) {
         launch_ctl_resume(ctl, c.stream);
         DFA_TRY(launch_full_round(c, make_round_args(c, cols, N, k_eff, cap, o.lds_stage,
-                                                     packed_second, seg),
+                                                     packed_second, seg, grouping),
                                   res.ctl.round));
         HIP_TRY(hipGetLastError());
         DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
@@ -608,6 +644,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
 // result is in c.blockA.
 int refine_leader(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq,
                   uint32_t eq_a, uint32_t eq_b, RefineResult &res) {
+    res.N = static_cast<uint32_t>(N);
     DFA_TRY(read_back(c, c.flags.p, (kFlagNonid + k) * sizeof(uint32_t)));
     if (c.pinned[kFlagErr]) return fail(DFA_EINVAL, "a transition target is >= n");
     std::vector<uint32_t> colmap;
@@ -714,6 +751,7 @@ void fill_stats(dfa_stats *st, const RefineResult &r) {
     st->plain_rounds = r.tc_used ? r.plain_rounds : r.ctl.round;
     st->transitions_refined = r.transitions;
     st->algorithmic_bytes = r.bytes;
+    st->reachable = r.N;
 }
 
 int check_options(const dfa_options &o) {
@@ -721,8 +759,10 @@ int check_options(const dfa_options &o) {
     if (o.loop_mode < DFA_LOOP_HOST || o.loop_mode > DFA_LOOP_GRAPH)
         return fail(DFA_EINVAL, "bad loop_mode");
     if (o.lds_stage < 0 || o.lds_stage > 2) return fail(DFA_EINVAL, "bad lds_stage");
-    if (o.algorithm != DFA_ALGO_SIGNATURE && o.algorithm != DFA_ALGO_LEADER)
+    if (o.algorithm != DFA_ALGO_SIGNATURE && o.algorithm != DFA_ALGO_LEADER &&
+        o.algorithm != DFA_ALGO_SORT)
         return fail(DFA_EINVAL, "bad algorithm");
+    if (o.prune != 0 && o.prune != 1) return fail(DFA_EINVAL, "bad prune");
     return DFA_OK;
 }
 
@@ -730,6 +770,7 @@ int check_batch_options(const dfa_options &o) {
     DFA_TRY(check_options(o));
     if (o.algorithm != DFA_ALGO_SIGNATURE)
         return fail(DFA_EINVAL, "batched calls run signature rounds only");
+    if (o.prune) return fail(DFA_EINVAL, "batched calls partition every state (prune = 0)");
     return DFA_OK;
 }
 
@@ -754,8 +795,12 @@ int prepare_refinement(Ctx &c, size_t N, uint32_t k) {
     return DFA_OK;
 }
 
+int minimise_pruned(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *acc,
+                    uint32_t *block_out, dfa_quotient *q, const dfa_options &o, dfa_stats *st);
+
 int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *acc,
                   uint32_t *block_out, dfa_quotient *q, const dfa_options &o, dfa_stats *st) {
+    if (o.prune) return minimise_pruned(c, n, k, delta, acc, block_out, q, o, st);
     DFA_TRY(prepare_refinement(c, n, k));
     const size_t id_range = n;  // refine() returns state ids
     DFA_TRY(c.canon.ensure(id_range * sizeof(uint32_t), "canonical ids"));
@@ -812,6 +857,86 @@ int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const u
         st->device_ms = ms;
     }
     return DFA_OK;
+}
+
+// Minimisation of the part reachable from o.start: breadth-first search,
+// dense renumbering of the reachable states (in increasing order), the
+// sub-automaton, its minimisation, and the ids mapped back (smallest
+// reachable member of each block; DFA_UNREACHABLE elsewhere).
+int minimise_pruned(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *acc,
+                    uint32_t *block_out, dfa_quotient *q, const dfa_options &o, dfa_stats *st) {
+    if (o.start >= n) return fail(DFA_EINVAL, "start (%u) >= n (%u)", o.start, n);
+    const size_t words64 = (static_cast<size_t>(n) + 63) / 64;
+    const size_t ntiles = (static_cast<size_t>(n) + kScanTile - 1) / kScanTile;
+    DFA_TRY(c.flags.ensure(4 * sizeof(uint32_t), "flags"));
+    DFA_TRY(c.scalars.ensure(16 * sizeof(uint32_t), "scalars"));
+    DFA_TRY(c.reach_visited.ensure(words64 * sizeof(unsigned long long), "visited bits"));
+    DFA_TRY(c.reach_qa.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "search queue"));
+    DFA_TRY(c.reach_qb.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "search queue"));
+    DFA_TRY(c.reach_flags.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "reachable flags"));
+    DFA_TRY(c.reach_dense.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "reachable numbering"));
+    DFA_TRY(c.reach_orig.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "reachable states"));
+    DFA_TRY(c.partials.ensure((ntiles + 1) * sizeof(uint32_t), "scan partials"));
+    HIP_TRY(hipEventRecord(c.ev_p0, c.stream));
+    uint32_t *err = c.flags.as<uint32_t>();
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(uint32_t), c.stream));
+    launch_check_targets(delta, static_cast<uint64_t>(n) * k, n, err, c.stream);
+    HIP_TRY(hipGetLastError());
+    DFA_TRY(read_back(c, err, sizeof(uint32_t)));
+    if (c.pinned[0]) return fail(DFA_EINVAL, "a transition target is >= n");
+
+    uint32_t *sizes = c.scalars.as<uint32_t>();
+    ReachArgs ra{delta, n, k, c.reach_visited.as<unsigned long long>(), c.reach_qa.as<uint32_t>(),
+                 c.reach_qb.as<uint32_t>(), sizes};
+    HIP_TRY(hipMemsetAsync(ra.visited, 0, words64 * sizeof(unsigned long long), c.stream));
+    launch_bfs_init(ra, o.start, c.stream);
+    const uint64_t cap = bfs_narrow_cap();
+    for (;;) {
+        HIP_TRY(hipGetLastError());
+        DFA_TRY(read_back(c, sizes, sizeof(uint32_t)));
+        const uint32_t frontier = c.pinned[0];
+        if (frontier == 0) break;
+        if (static_cast<uint64_t>(frontier) * k <= cap) {
+            launch_bfs_narrow(ra, c.stream);
+        } else {
+            launch_bfs_wide(ra, frontier, c.stream);
+            std::swap(ra.qa, ra.qb);
+        }
+    }
+    // dense numbering of the reachable states; m = their count
+    launch_reach_flags(ra.visited, n, c.reach_flags.as<uint32_t>(), c.stream);
+    launch_dense_leaders(c.reach_flags.as<uint32_t>(), n, c.partials.as<uint32_t>(),
+                         c.reach_dense.as<uint32_t>(), c.reach_orig.as<uint32_t>(), sizes + 2,
+                         c.stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(sizes + 3, c.reach_dense.as<uint32_t>() + o.start, sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, c.stream));
+    DFA_TRY(read_back(c, sizes + 2, 2 * sizeof(uint32_t)));
+    const uint32_t m = c.pinned[0], sub_start = c.pinned[1];
+    DFA_TRY(c.sub_delta.ensure(static_cast<size_t>(m) * k * sizeof(uint32_t), "sub-automaton"));
+    DFA_TRY(c.sub_acc.ensure(m, "sub-automaton"));
+    DFA_TRY(c.sub_block.ensure(static_cast<size_t>(m) * sizeof(uint32_t), "sub-automaton ids"));
+    launch_sub_dfa(delta, acc, k, c.reach_orig.as<uint32_t>(), c.reach_dense.as<uint32_t>(),
+                   sizes + 2, m, c.sub_delta.as<uint32_t>(), c.sub_acc.as<uint8_t>(), c.stream);
+    HIP_TRY(hipGetLastError());
+    dfa_options o2 = o;
+    o2.prune = 0;
+    o2.start = sub_start;
+    int rc = minimise_impl(c, m, k, c.sub_delta.as<uint32_t>(), c.sub_acc.as<uint8_t>(),
+                           c.sub_block.as<uint32_t>(), q, o2, st);
+    if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
+    launch_reach_expand(ra.visited, n, c.reach_dense.as<uint32_t>(), c.reach_orig.as<uint32_t>(),
+                        c.sub_block.as<uint32_t>(), block_out, c.stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(c.ev_p1, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    if (st) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c.ev_p0, c.ev_p1));
+        st->device_ms = ms;
+        st->reachable = m;
+    }
+    return rc;
 }
 
 int equivalent_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict,
@@ -1316,7 +1441,11 @@ void release_ctx(Ctx &c) {
                       &c.stage_qdelta, &c.stage_qacc, &c.stage_delta_b, &c.stage_acc_b,
                       &c.visited, &c.visited2, &c.front0, &c.front1, &c.parts, &c.tile_part,
                       &c.seg_words, &c.batch_in, &c.batch_out, &c.new_leader, &c.moved,
-                      &c.chg, &c.single, &c.touched};
+                      &c.chg, &c.single, &c.touched, &c.reach_visited, &c.reach_qa,
+                      &c.reach_qb, &c.reach_flags, &c.reach_dense, &c.reach_orig, &c.sub_delta,
+                      &c.sub_acc, &c.sub_block, &c.sort_keys0, &c.sort_keys1, &c.sort_vals0,
+                      &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,
+                      &c.sort_m};
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     for (Buffer *b : bufs) {
         if (b->p) (void)hipFree(b->p);
@@ -1330,6 +1459,9 @@ void release_ctx(Ctx &c) {
     if (c.ev_start) (void)hipEventDestroy(c.ev_start);
     if (c.ev_stop) (void)hipEventDestroy(c.ev_stop);
     if (c.ev_in) (void)hipEventDestroy(c.ev_in);
+    if (c.ev_p0) (void)hipEventDestroy(c.ev_p0);
+    if (c.ev_p1) (void)hipEventDestroy(c.ev_p1);
+    c.ev_p0 = c.ev_p1 = nullptr;
     if (c.pinned) (void)hipHostFree(c.pinned);
     if (c.pinned_batch) (void)hipHostFree(c.pinned_batch);
     if (c.stream) (void)hipStreamDestroy(c.stream);
@@ -1752,7 +1884,7 @@ int dfa_get_tuning(dfa_tuning *t) {
 int dfa_set_tuning(const dfa_tuning *t) {
     if (!t) return fail(DFA_EINVAL, "tuning is NULL");
     if (t->label_rounds > 2 || t->cached_probe > 1 || t->chunk == 0 || t->chunk > 4096 ||
-        t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24))
+        t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24) || t->hash_bits > 63)
         return fail(DFA_EINVAL, "tuning value out of range");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
@@ -1822,6 +1954,7 @@ int dfa_equivalent_device(const dfa_view *a, const dfa_view *b, int *verdict,
     dfa_options o = resolve(opt);
     DFA_TRY(check_pair(a, b, verdict));
     DFA_TRY(check_options(o));
+    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
     std::lock_guard<std::mutex> lock(c->mu);
@@ -1837,6 +1970,7 @@ int dfa_equivalent(const dfa_view *a, const dfa_view *b, int *verdict, const dfa
     dfa_options o = resolve(opt);
     DFA_TRY(check_pair(a, b, verdict));
     DFA_TRY(check_options(o));
+    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
     std::lock_guard<std::mutex> lock(c->mu);
@@ -1851,6 +1985,7 @@ int dfa_included_device(const dfa_view *a, const dfa_view *b, int *verdict,
     dfa_options o = resolve(opt);
     DFA_TRY(check_pair(a, b, verdict));
     DFA_TRY(check_options(o));
+    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
     std::lock_guard<std::mutex> lock(c->mu);
@@ -1865,6 +2000,7 @@ int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *p
     dfa_options o = resolve(opt);
     DFA_TRY(check_pair(a, b, verdict));
     DFA_TRY(check_options(o));
+    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
     std::lock_guard<std::mutex> lock(c->mu);

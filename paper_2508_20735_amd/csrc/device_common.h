@@ -67,5 +67,20 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
     return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+
+__device__ __forceinline__ bool rows_equal(const uint32_t *__restrict__ sig, size_t W, size_t a,
+                                           size_t b) {
+    const uint32_t *ra = sig + a * W;
+    const uint32_t *rb = sig + b * W;
+    for (size_t i = 0; i < W; ++i)
+        if (ra[i] != rb[i]) return false;
+    return true;
+}
+
+// Marks block `id` as having two or more members after round r.
+__device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_t tag) {
+    if (multi[id] != tag) multi[id] = tag;
+}
+
 }  // namespace
 }  // namespace dfamin

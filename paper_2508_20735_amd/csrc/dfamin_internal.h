@@ -135,6 +135,21 @@ void launch_part_output(const SegArgs &g, size_t N, const uint32_t *canon, uint3
 void launch_pair_verdicts(const SegArgs &g, const uint32_t *block, int32_t *verdicts,
                           hipStream_t s);
 
+// Buffers of the sort-based grouping (sort_kernels.hip); N = states.
+struct SortBuffers {
+    unsigned long long *keys[2];  // N hashes, ping-pong
+    uint32_t *vals[2];            // N states, ping-pong
+    uint32_t *hist;               // 256 * sort_tiles digit counts
+    uint32_t *partials;           // scan partials (partial_words)
+    uint32_t *runhead;            // N: run head position of each sorted element
+    uint32_t *m;                  // refined states this round (device)
+};
+struct SortPlan {
+    uint32_t sort_tiles, compact_tiles, hist_blocks, run_blocks;
+    uint64_t hist_words, partial_words;
+};
+SortPlan sort_plan(size_t N);
+
 // One signature round: signatures + hashes (and the periodic table clear),
 // then grouping through the table, then the round-end bookkeeping.
 struct RoundArgs {
@@ -163,8 +178,14 @@ struct RoundArgs {
     unsigned long long *chg;      // N/64 words
     unsigned long long *single;   // N/64 words, zero before the first round
     unsigned long long *touched;  // 2 * (N/64) words, zero before the first round
+    uint32_t grouping;          // 0: hash table; 1: sort (radix sort of the key hashes)
+    uint32_t hash_bits;         // 0: full hashes; else only the low bits (collision tests)
+    SortBuffers sort;           // grouping == 1
     SegArgs seg;                // nseg == 0: a single automaton
 };
+// Grouping of the round by sorting (grouping == 1), in place of the table
+// kernels.
+void launch_sort_group(const RoundArgs &a, hipStream_t s);
 // One round: marking of the blocks to refine, signatures, grouping, the
 // round end.
 void launch_round(const RoundArgs &a, hipStream_t s);
@@ -218,6 +239,36 @@ void launch_leader_round(const LeaderArgs &a, hipStream_t s);
 void launch_leader_elect(const LeaderArgs &a, hipStream_t s);
 void launch_leader_move(const LeaderArgs &a, hipStream_t s);
 void launch_leader_end(const LeaderArgs &a, hipStream_t s);
+
+// ---- reachability and the reachable sub-automaton (reach_kernels.hip) ----
+struct ReachArgs {
+    const uint32_t *delta;           // row-major n x k, targets < n (checked first)
+    uint32_t n, k;
+    unsigned long long *visited;     // n/64 words, zero before the search
+    uint32_t *qa, *qb;               // frontier queues, n entries each
+    uint32_t *sizes;                 // [0] entries in qa, [1] entries in qb
+};
+// *err = 1 if a target is >= n.
+void launch_check_targets(const uint32_t *delta, uint64_t total, uint32_t n, uint32_t *err,
+                          hipStream_t s);
+void launch_bfs_init(const ReachArgs &a, uint32_t start, hipStream_t s);
+// Expands levels in one workgroup while sizes[0] * k <= bfs_narrow_cap().
+void launch_bfs_narrow(const ReachArgs &a, hipStream_t s);
+// One level over qa (frontier entries) into qb, then sizes[0] = sizes[1];
+// the caller swaps qa and qb.
+void launch_bfs_wide(const ReachArgs &a, uint32_t frontier, hipStream_t s);
+uint32_t bfs_narrow_cap();
+// flags[q] = q if visited, all ones otherwise.
+void launch_reach_flags(const unsigned long long *visited, size_t n, uint32_t *flags,
+                        hipStream_t s);
+// sub_delta[i][a] = dense[delta[orig[i]][a]], sub_acc[i] = acc[orig[i]], i < *m_dev.
+void launch_sub_dfa(const uint32_t *delta, const uint8_t *acc, uint32_t k, const uint32_t *orig,
+                    const uint32_t *dense, const uint32_t *m_dev, uint32_t m_host,
+                    uint32_t *sub_delta, uint8_t *sub_acc, hipStream_t s);
+// block_out[q] = orig[sub_block[dense[q]]] if visited, all ones otherwise.
+void launch_reach_expand(const unsigned long long *visited, size_t n, const uint32_t *dense,
+                         const uint32_t *orig, const uint32_t *sub_block, uint32_t *block_out,
+                         hipStream_t s);
 
 // Pointer jumping, level i >= 1, all k letters:
 // cols[(i*k+a)*N + q] = cols[((i-1)*k+a)*N + cols[((i-1)*k+a)*N + q]];

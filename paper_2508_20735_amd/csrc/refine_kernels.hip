@@ -127,15 +127,6 @@ __global__ void k_ctl_full(RoundCtl *ctl) {
 
 // ---------------------------------------------------------------- round kernels
 
-__device__ __forceinline__ bool rows_equal(const uint32_t *__restrict__ sig, size_t W, size_t a,
-                                           size_t b) {
-    const uint32_t *ra = sig + a * W;
-    const uint32_t *rb = sig + b * W;
-    for (size_t i = 0; i < W; ++i)
-        if (ra[i] != rb[i]) return false;
-    return true;
-}
-
 __device__ __forceinline__ unsigned long long load_entry(const unsigned long long *p, bool cached) {
     return cached ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)
                   : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -177,11 +168,6 @@ __device__ __forceinline__ uint32_t find_or_claim(unsigned long long *table, uin
         s = (s + 1) & mask;
         e = load_entry(table + s, cached);
     }
-}
-
-// Marks block `id` as having two or more members after round r.
-__device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_t tag) {
-    if (multi[id] != tag) multi[id] = tag;
 }
 
 // Claims an empty slot for `self` without comparing keys: used when no
@@ -237,7 +223,13 @@ struct SigParams {
     unsigned long long *chg;
     unsigned long long *single;
     unsigned long long *touched;
+    uint32_t grouping;  // 1: sort grouping (no claims in the signature kernel)
+    uint32_t hash_bits;  // 0: full key hashes; else only the low bits
 };
+
+__device__ __forceinline__ uint64_t limit_hash(uint64_t h, uint32_t bits) {
+    return bits ? (h & ((1ull << bits) - 1ull)) : h;
+}
 
 __device__ __forceinline__ uint32_t acc_bit(const unsigned long long *accbits, uint32_t t) {
     return static_cast<uint32_t>(accbits[t >> 6] >> (t & 63)) & 1u;
@@ -480,7 +472,7 @@ __device__ __forceinline__ void emit_key(const SigParams &p, uint32_t *__restric
         row[1 + j] = w[j];
         h = mix_step(h, w[j]);
     }
-    h = mix_final(h);
+    h = limit_hash(mix_final(h), p.hash_bits);
     p.hash[q] = h;
     if (claim_holder && w0 == q) {
         // the state that holds its block's id claims its key before the
@@ -551,7 +543,9 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
                 for (int j = 0; j < KC; ++j) w[i][j] = act[i] ? X[t[i][j]] : 0u;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                if (act[i]) emit_key(p, Y, q[i], w0[i], w[i], KC, W, !all, epoch, claims);
+                if (act[i])
+                    emit_key(p, Y, q[i], w0[i], w[i], KC, W, !all && p.grouping == 0, epoch,
+                             claims);
         }
     } else {
         for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
@@ -592,9 +586,9 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
                         h = mix_step(h, w[j]);
                     }
             }
-            h = mix_final(h);
+            h = limit_hash(mix_final(h), p.hash_bits);
             p.hash[q] = h;
-            if (!all && w0 == q) {
+            if (!all && p.grouping == 0 && w0 == q) {
                 claim_slot(p.table, p.table_cap - 1, epoch, h, static_cast<uint32_t>(q));
                 Y[q] = w0;
                 ++claims;
@@ -1139,7 +1133,7 @@ SigParams sig_params(const RoundArgs &a) {
                      a.blockB,   a.sig,        a.hash,     a.table,    a.table_cap,
                      a.multi,    a.active,     a.accbits,  a.presence, a.presence_packed,
                      a.lab8,     a.counters,   a.ctl,      a.cached_probe, a.chg,
-                     a.single,   a.touched};
+                     a.single,   a.touched,    a.grouping, a.hash_bits};
 }
 
 unsigned round_grid(const RoundArgs &a, unsigned cap) {
@@ -1291,7 +1285,10 @@ void launch_ctl_full(RoundCtl *ctl, hipStream_t s) {
 void launch_round(const RoundArgs &a, hipStream_t s) {
     launch_mark(a, s);
     launch_signature(a, s);
-    launch_insert(a, s);
+    if (a.grouping)
+        launch_sort_group(a, s);
+    else
+        launch_insert(a, s);
     if (a.seg.nseg) launch_seg_round(a, s);
     launch_round_end(a, s);
 }

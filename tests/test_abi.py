@@ -92,3 +92,21 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.dfa_included(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v), None, None,
                             None) == B.DFA_EINVAL
     assert b"start" in lib.dfa_last_error()
+    # option values out of range, and options a call does not support
+    vb = B.View(4, 2, 0, d.ctypes.data, a.ctypes.data)
+    o.tc_mode = B.TC["off"]
+    o.prune = 1
+    assert lib.dfa_equivalent(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
+                              ctypes.byref(o), None) == B.DFA_EINVAL
+    assert b"prune" in lib.dfa_last_error()
+    o.prune = 2
+    assert lib.dfa_minimise(4, 2, d.ctypes.data, a.ctypes.data, out.ctypes.data, None,
+                            ctypes.byref(o), None) == B.DFA_EINVAL
+    o.prune = 0
+    o.algorithm = 5
+    assert lib.dfa_minimise(4, 2, d.ctypes.data, a.ctypes.data, out.ctypes.data, None,
+                            ctypes.byref(o), None) == B.DFA_EINVAL
+    o.algorithm = B.ALGO["leader"]
+    nb = np.zeros(1, dtype=np.uint32)
+    assert lib.dfa_minimise_batch(1, ctypes.byref(va), out.ctypes.data, None, nb.ctypes.data,
+                                  None, ctypes.byref(o), None) == B.DFA_EINVAL
