@@ -77,6 +77,18 @@ __device__ __forceinline__ bool rows_equal(const uint32_t *__restrict__ sig, siz
     return true;
 }
 
+// The columns a kernel reads, resolved once per thread: the column list
+// does not change during a launch, and holding the pointers in registers
+// keeps the compiler from reloading the list after every store.
+template <int KC>
+struct ColPtrs {
+    const uint32_t *c[KC > 0 ? KC : 1];
+    __device__ __forceinline__ ColPtrs(const uint32_t *cols, const uint32_t *colmap, size_t N) {
+#pragma unroll
+        for (int j = 0; j < KC; ++j) c[j] = cols + static_cast<size_t>(colmap[j]) * N;
+    }
+};
+
 // Marks block `id` as having two or more members after round r.
 __device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_t tag) {
     if (multi[id] != tag) multi[id] = tag;

@@ -253,13 +253,14 @@ __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
     __syncthreads();
     uint32_t *__restrict__ out = p.blockB;
     unsigned long long seen_reg = 0;
+    const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
     for (size_t q = global_tid(); q < p.N; q += grid_stride()) {
         uint32_t label = acc_bit(p.accbits, static_cast<uint32_t>(q));
         if constexpr (KC > 0) {
             // all column entries first, then all acceptance bits
             uint32_t t[KC];
 #pragma unroll
-            for (int j = 0; j < KC; ++j) t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+            for (int j = 0; j < KC; ++j) t[j] = colp.c[j][q];
 #pragma unroll
             for (int j = 0; j < KC; ++j) label |= acc_bit(p.accbits, t[j]) << (j + 1);
         } else {
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
     const uint32_t bits = keff + 1;
     const uint32_t tx = threadIdx.x;
     uint32_t fresh = 0;
+    const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
         for (uint32_t i = tx; i < kLdsSlots; i += kBlock) lset[i] = ~0u;
@@ -327,8 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
                 // all column entries first, then all byte labels
                 uint32_t t[KC];
 #pragma unroll
-                for (int j = 0; j < KC; ++j)
-                    t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+                for (int j = 0; j < KC; ++j) t[j] = colp.c[j][q];
 #pragma unroll
                 for (int j = 0; j < KC; ++j)
                     key |= static_cast<uint32_t>(p.lab8[t[j]]) << (bits * (j + 1));
@@ -390,49 +391,83 @@ __global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
     const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
     const unsigned long long *__restrict__ chg = p.chg;
     const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
-    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
-         base += static_cast<size_t>(gridDim.x) * kBlock) {
-        const size_t q = base + threadIdx.x;
-        const bool valid = q < p.N;
-        const size_t first = base + (threadIdx.x & ~63u);
-        const size_t wd = first >> 6;
-        const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
-        const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
-        bool s = !valid || ((sw >> lane_id()) & 1ull);
-        // a block formed last round with one member stays a singleton
-        const bool was_active = !s && ((aw >> lane_id()) & 1ull);
-        uint32_t x = 0;
-        if (was_active) {
-            x = X[q];
-            s = p.multi[x] != r;
+    const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
+    // S states per thread; each kind of load is issued for all of them before
+    // any of its values is used (the kernel is bound by load latency)
+    constexpr int S = 4;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * (S * kBlock); base < p.N;
+         base += static_cast<size_t>(gridDim.x) * (S * kBlock)) {
+        size_t q[S];
+        unsigned long long sw[S], aw[S];
+        bool s[S], was_active[S];
+        uint32_t x[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            q[i] = base + i * kBlock + threadIdx.x;
+            const size_t first = q[i] - lane_id();
+            sw[i] = first < p.N ? p.single[first >> 6] : ~0ull;
+            aw[i] = first < p.N ? p.active[first >> 6] : 0ull;
         }
-        const unsigned long long nsw = __ballot(s);
-        if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
-        if (s) continue;
-        // all column entries first, then all change bits: two dependent
-        // steps per state instead of two per letter
-        bool dirty = false;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            s[i] = q[i] >= p.N || ((sw[i] >> lane_id()) & 1ull);
+            // a block formed last round with one member stays a singleton
+            was_active[i] = !s[i] && ((aw[i] >> lane_id()) & 1ull);
+            x[i] = was_active[i] ? X[q[i]] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (was_active[i]) s[i] = p.multi[x[i]] != r;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const unsigned long long nsw = __ballot(s[i]);
+            const size_t first = q[i] - lane_id();
+            if (lane_id() == 0 && first < p.N && nsw != sw[i]) p.single[first >> 6] = nsw;
+        }
+        bool dirty[S];
         if constexpr (KC > 0) {
-            uint32_t t[KC];
+            // unconditional, straight-line loads (a state that needs none
+            // reads state 0's): conditional loads sit in branches, across
+            // which the compiler waits for every load in flight
+            uint32_t t[S][KC];
+            unsigned long long bits[S][KC];
 #pragma unroll
-            for (int j = 0; j < KC; ++j) t[j] = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+            for (int i = 0; i < S; ++i)
 #pragma unroll
-            for (int j = 0; j < KC; ++j) dirty |= ((chg[t[j] >> 6] >> (t[j] & 63)) & 1ull) != 0;
+                for (int j = 0; j < KC; ++j) t[i][j] = colp.c[j][s[i] ? 0 : q[i]];
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+#pragma unroll
+                for (int j = 0; j < KC; ++j) bits[i][j] = chg[t[i][j] >> 6];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                bool any = false;
+#pragma unroll
+                for (int j = 0; j < KC; ++j) any |= ((bits[i][j] >> (t[i][j] & 63)) & 1ull) != 0;
+                dirty[i] = !s[i] && any;
+            }
         } else {
-            for (uint32_t j0 = 0; j0 < keff && !dirty; j0 += 8) {
-                const uint32_t m = keff - j0 < 8 ? keff - j0 : 8;
-                uint32_t t[8];
 #pragma unroll
-                for (uint32_t j = 0; j < 8; ++j)
-                    if (j < m) t[j] = p.cols[static_cast<size_t>(p.colmap[j0 + j]) * p.N + q];
+            for (int i = 0; i < S; ++i) {
+                dirty[i] = false;
+                for (uint32_t j0 = 0; j0 < keff && !s[i] && !dirty[i]; j0 += 8) {
+                    const uint32_t m = keff - j0 < 8 ? keff - j0 : 8;
+                    uint32_t t[8];
 #pragma unroll
-                for (uint32_t j = 0; j < 8; ++j)
-                    if (j < m) dirty |= ((chg[t[j] >> 6] >> (t[j] & 63)) & 1ull) != 0;
+                    for (uint32_t j = 0; j < 8; ++j)
+                        if (j < m) t[j] = p.cols[static_cast<size_t>(p.colmap[j0 + j]) * p.N + q[i]];
+#pragma unroll
+                    for (uint32_t j = 0; j < 8; ++j)
+                        if (j < m) dirty[i] |= ((chg[t[j] >> 6] >> (t[j] & 63)) & 1ull) != 0;
+                }
             }
         }
-        if (!dirty) continue;
-        if (!was_active) x = X[q];
-        atomicOr(T + (x >> 6), 1ull << (x & 63));
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (!dirty[i]) continue;
+            const uint32_t xi = was_active[i] ? x[i] : X[q[i]];
+            atomicOr(T + (xi >> 6), 1ull << (xi & 63));
+        }
     }
 }
 
@@ -508,6 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
     uint32_t leaders = 0, claims = 0;
 
     if constexpr (KC > 0) {
+        const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
         // two states per thread, all independent loads of both issued before
         // their values are used
         for (size_t base = static_cast<size_t>(blockIdx.x) * (2 * kBlock); base < p.N;
@@ -532,15 +568,42 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
                     }
                 }
             }
+            // waves where most lanes are refined load unconditionally (the
+            // others reread the wave's first refined state, lines the wave
+            // fetches anyway); sparse waves load per lane
+            const unsigned long long am[2] = {__ballot(act[0]), __ballot(act[1])};
+            const uint32_t nact = static_cast<uint32_t>(__popcll(am[0])) +
+                                  static_cast<uint32_t>(__popcll(am[1]));
+            if (nact >= 64) {
+                // a slot with no refined lane borrows the other slot's (which
+                // then has all 64)
+                size_t qs[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i) {
+                    const int src = am[i] ? i : (i ^ 1);
+                    const size_t borrow =
+                        q[src] - lane_id() +
+                        static_cast<size_t>(__ffsll(static_cast<unsigned long long>(am[src])) - 1);
+                    qs[i] = act[i] ? q[i] : borrow;
+                }
 #pragma unroll
-                for (int j = 0; j < KC; ++j)
-                    t[i][j] = act[i] ? p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q[i]] : 0u;
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < KC; ++j) t[i][j] = colp.c[j][qs[i]];
 #pragma unroll
-                for (int j = 0; j < KC; ++j) w[i][j] = act[i] ? X[t[i][j]] : 0u;
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) w[i][j] = X[t[i][j]];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) t[i][j] = act[i] ? colp.c[j][q[i]] : 0u;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) w[i][j] = act[i] ? X[t[i][j]] : 0u;
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
                 if (act[i])
