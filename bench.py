@@ -19,7 +19,6 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,16 +31,13 @@ METRIC = "transitions refined/sec (n·|Σ|·rounds/s) and achieved HBM GB/s; bat
 UNIT = "transitions/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2508_20735_amd", "csrc", f)
-                  for f in ("refine_kernels.hip", "dfamin_internal.h")]
 
 
 def kernel_source_digest() -> str:
-    h = hashlib.sha1()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    """Digest of the round-kernel sources the counter summary was taken with
+    (the same files the summary tool hashes)."""
+    from paper_2508_20735_amd.profiling import kernel_source_digest as digest
+    return digest(ROOT)
 
 
 def parse_args():

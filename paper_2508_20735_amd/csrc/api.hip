@@ -111,6 +111,7 @@ struct Ctx {
         sub_acc, sub_block;
     Buffer sort_keys0, sort_keys1, sort_vals0, sort_vals1, sort_hist, sort_partials,
         sort_runhead, sort_m;
+    Buffer serve_in;  // server lanes: device copies of the running requests' inputs
     hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr;  // pruned minimisation, whole call
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
@@ -1445,7 +1446,7 @@ void release_ctx(Ctx &c) {
                       &c.reach_qb, &c.reach_flags, &c.reach_dense, &c.reach_orig, &c.sub_delta,
                       &c.sub_acc, &c.sub_block, &c.sort_keys0, &c.sort_keys1, &c.sort_vals0,
                       &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,
-                      &c.sort_m};
+                      &c.sort_m, &c.serve_in};
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     for (Buffer *b : bufs) {
         if (b->p) (void)hipFree(b->p);
@@ -1540,7 +1541,6 @@ struct ServedRequest {
     dfa_view a{}, b{};        // the inputs: host copies, then device copies while running
     void *host_in = nullptr;  // page-locked copy made at submission
     size_t host_cls = 0;
-    void *dev_in = nullptr;   // stream-ordered device allocation while running
     size_t in_bytes = 0;
     size_t off_acc_a = 0, off_delta_b = 0, off_acc_b = 0;
     size_t footprint = 0;     // device bytes while it runs, inputs included
@@ -1551,7 +1551,8 @@ struct ServedRequest {
     int verdict = 0;
     uint32_t num_blocks = 0, rounds = 0;
     bool batched = false;
-    std::vector<uint32_t> blocks;
+    uint32_t *blocks = nullptr;  // minimisation result, page-locked (server pool)
+    size_t blocks_cls = 0;
 };
 
 struct Server {
@@ -1607,13 +1608,17 @@ void run_solo(Server &s, Ctx &c, ServedRequest *r) {
     dfa_stats st{};
     if (r->kind == DFA_REQ_MINIMISE) {
         const size_t n = r->a.n;
-        r->blocks.resize(n);
         r->status = c.stage_block.ensure(n * sizeof(uint32_t), "output copy");
         if (r->status == DFA_OK)
             r->status = minimise_impl(c, r->a.n, r->a.k, r->a.delta, r->a.accepting,
                                       c.stage_block.as<uint32_t>(), nullptr, o, &st);
+        if (r->status == DFA_OK) {
+            r->blocks = static_cast<uint32_t *>(s.pinned.get(n * sizeof(uint32_t), r->blocks_cls));
+            if (!r->blocks)
+                r->status = fail(DFA_ENOMEM, "page-locked result buffer of %zu bytes", n * 4);
+        }
         if (r->status == DFA_OK &&
-            (hipMemcpyAsync(r->blocks.data(), c.stage_block.p, n * sizeof(uint32_t),
+            (hipMemcpyAsync(r->blocks, c.stage_block.p, n * sizeof(uint32_t),
                             hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
              hipStreamSynchronize(c.stream) != hipSuccess))
             r->status = fail(DFA_EDEVICE, "copy of the result failed");
@@ -1663,7 +1668,15 @@ void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
                     // a DFA that changed in every round may not be stable yet
                     redo[i] = rc == DFA_ELIMIT && rounds[i] > bs.rounds;
                     if (!redo[i]) {
-                        r->blocks.assign(src + pos, src + pos + r->a.n);
+                        r->blocks = static_cast<uint32_t *>(
+                            s.pinned.get(static_cast<size_t>(r->a.n) * sizeof(uint32_t),
+                                         r->blocks_cls));
+                        if (!r->blocks) {
+                            r->status = fail(DFA_ENOMEM, "page-locked result buffer");
+                            pos += r->a.n;
+                            continue;
+                        }
+                        std::memcpy(r->blocks, src + pos, r->a.n * sizeof(uint32_t));
                         r->num_blocks = nb[i];
                         r->rounds = rounds[i];
                         r->status = DFA_OK;
@@ -1755,30 +1768,30 @@ void lane_main(Server *sp, size_t lane) {
             std::lock_guard<std::mutex> g(c.mu);
             g_last_error.clear();
             // inputs to the device on the lane's stream (asynchronous copies
-            // from page-locked memory); a request whose copy cannot start
-            // fails alone
+            // from page-locked memory into the lane's own grow-only buffer)
             std::vector<ServedRequest *> ready;
-            for (auto *r : grp) {
-                uint8_t *dev = nullptr;
-                if (hipMallocAsync(reinterpret_cast<void **>(&dev), r->in_bytes, c.stream) !=
-                    hipSuccess) {
-                    r->status = fail(DFA_ENOMEM, "device allocation of %zu input bytes failed",
-                                     r->in_bytes);
-                    continue;
+            size_t in_total = 0;
+            for (auto *r : grp) in_total += r->in_bytes;
+            if (c.serve_in.ensure(in_total, "request inputs") != DFA_OK) {
+                for (auto *r : grp) r->status = DFA_ENOMEM;
+            } else {
+                uint8_t *dev = c.serve_in.as<uint8_t>();
+                for (auto *r : grp) {
+                    if (hipMemcpyAsync(dev, r->host_in, r->in_bytes, hipMemcpyHostToDevice,
+                                       c.stream) != hipSuccess) {
+                        r->status = fail(DFA_EDEVICE, "copy of the request's inputs failed");
+                        dev += r->in_bytes;
+                        continue;
+                    }
+                    r->a.delta = reinterpret_cast<const uint32_t *>(dev);
+                    r->a.accepting = dev + r->off_acc_a;
+                    if (r->kind == DFA_REQ_EQUIVALENT) {
+                        r->b.delta = reinterpret_cast<const uint32_t *>(dev + r->off_delta_b);
+                        r->b.accepting = dev + r->off_acc_b;
+                    }
+                    dev += r->in_bytes;
+                    ready.push_back(r);
                 }
-                r->dev_in = dev;
-                if (hipMemcpyAsync(dev, r->host_in, r->in_bytes, hipMemcpyHostToDevice,
-                                   c.stream) != hipSuccess) {
-                    r->status = fail(DFA_EDEVICE, "copy of the request's inputs failed");
-                    continue;
-                }
-                r->a.delta = reinterpret_cast<const uint32_t *>(dev);
-                r->a.accepting = dev + r->off_acc_a;
-                if (r->kind == DFA_REQ_EQUIVALENT) {
-                    r->b.delta = reinterpret_cast<const uint32_t *>(dev + r->off_delta_b);
-                    r->b.accepting = dev + r->off_acc_b;
-                }
-                ready.push_back(r);
             }
             all = grp;
             grp.swap(ready);
@@ -1789,8 +1802,6 @@ void lane_main(Server *sp, size_t lane) {
         }
         (void)hipStreamSynchronize(c.stream);  // the input copies have completed
         for (auto *r : all) {
-            if (r->dev_in) (void)hipFreeAsync(r->dev_in, c.stream);
-            r->dev_in = nullptr;
             if (r->host_in) s.pinned.put(r->host_in, r->host_cls);
             r->host_in = nullptr;
         }
@@ -1813,7 +1824,7 @@ void fill_result(const ServedRequest &r, dfa_result *out) {
     out->verdict = r.verdict;
     out->num_blocks = r.num_blocks;
     out->rounds = r.rounds;
-    out->blocks = r.kind == DFA_REQ_MINIMISE && r.status == DFA_OK ? r.blocks.data() : nullptr;
+    out->blocks = r.kind == DFA_REQ_MINIMISE && r.status == DFA_OK ? r.blocks : nullptr;
     out->n = r.a.n;
     out->batched = r.batched ? 1 : 0;
     out->queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
@@ -2165,14 +2176,6 @@ dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
         if (init_ctx(*dc) != DFA_OK) return nullptr;
         s->tune = dc->tune;
     }
-    {
-        // keep freed request memory in the device's pool for the next requests
-        hipMemPool_t pool = nullptr;
-        if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) {
-            uint64_t keep = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        }
-    }
     s->t_created = Clock::now();
     for (uint32_t i = 0; i < cfg.lanes; ++i) s->lanes.push_back(std::make_unique<Ctx>());
     Server *raw = s.get();
@@ -2270,6 +2273,7 @@ int dfa_result_release(dfa_server *handle, uint64_t ticket) {
     if (it == s->requests.end() || !it->second->done)
         return fail(DFA_EINVAL, "ticket %llu is unknown or not finished",
                     static_cast<unsigned long long>(ticket));
+    if (it->second->blocks) s->pinned.put(it->second->blocks, it->second->blocks_cls);
     s->requests.erase(it);
     return DFA_OK;
 }
@@ -2324,13 +2328,14 @@ void dfa_server_destroy(dfa_server *handle) {
     for (auto &t : s->workers) t.join();
     (void)hipSetDevice(s->device);
     for (auto &c : s->lanes) release_ctx(*c);
-    // host copies of cancelled requests go back to the pool, which the
-    // server frees
-    for (auto &kv : s->requests)
-        if (kv.second->host_in) {
-            s->pinned.put(kv.second->host_in, kv.second->host_cls);
-            kv.second->host_in = nullptr;
-        }
+    // host copies of cancelled requests and unreleased results go back to
+    // the pool, which the server frees
+    for (auto &kv : s->requests) {
+        if (kv.second->host_in) s->pinned.put(kv.second->host_in, kv.second->host_cls);
+        if (kv.second->blocks) s->pinned.put(kv.second->blocks, kv.second->blocks_cls);
+        kv.second->host_in = nullptr;
+        kv.second->blocks = nullptr;
+    }
     delete s;
 }
 

@@ -24,8 +24,8 @@ import re
 import sys
 from collections import defaultdict
 
-ROUND_KERNELS = ("k_signature", "k_insert", "k_insert_lds", "k_round_end", "k_pattern_round",
-                 "k_packed_round")
+ROUND_KERNELS = ("k_mark", "k_signature", "k_insert", "k_insert_lds", "k_round_end",
+                 "k_pattern_round", "k_packed_round")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -76,7 +76,7 @@ def per_dispatch(run_dir: str, counter: str) -> dict:
 
 def kernel_source_digest(root: str) -> str:
     h = hashlib.sha1()
-    for f in ("refine_kernels.hip", "dfamin_internal.h"):
+    for f in ("refine_kernels.hip", "dfamin_internal.h", "device_common.h"):
         with open(os.path.join(root, "paper_2508_20735_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
