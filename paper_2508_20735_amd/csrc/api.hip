@@ -113,6 +113,10 @@ struct Ctx {
         sort_runhead, sort_m;
     Buffer serve_in;  // server lanes: device copies of the running requests' inputs
     hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr;  // pruned minimisation, whole call
+    // waits on the stream sleep instead of spinning (server lanes, so that
+    // waiting lanes leave the host cores to submissions)
+    bool blocking_sync = false;
+    hipEvent_t ev_sync = nullptr;
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     size_t pinned_batch_cap = 0;
@@ -159,11 +163,21 @@ int init_ctx(Ctx &c) {
     HIP_TRY(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreate(&c.ev_p0));
     HIP_TRY(hipEventCreate(&c.ev_p1));
+    HIP_TRY(hipEventCreateWithFlags(&c.ev_sync, hipEventBlockingSync | hipEventDisableTiming));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c.pinned), kPinnedWords * sizeof(uint32_t),
                           hipHostMallocDefault));
     dfa_tuning_default(&c.tune);
     c.inited = true;
     return DFA_OK;
+}
+
+// Waits for the context's stream: spinning (the default, lowest latency) or
+// sleeping on a blocking-sync event (server lanes).
+hipError_t stream_sync(Ctx &c) {
+    if (!c.blocking_sync || !c.ev_sync) return hipStreamSynchronize(c.stream);
+    hipError_t e = hipEventRecord(c.ev_sync, c.stream);
+    if (e != hipSuccess) return e;
+    return hipEventSynchronize(c.ev_sync);
 }
 
 dfa_options resolve(const dfa_options *o) {
@@ -192,17 +206,17 @@ uint64_t next_pow2(uint64_t x) {
 int read_back(Ctx &c, const void *dev, size_t bytes) {
     if (bytes > kPinnedWords * sizeof(uint32_t)) return fail(DFA_EINVAL, "readback too large");
     HIP_TRY(hipMemcpyAsync(c.pinned, dev, bytes, hipMemcpyDeviceToHost, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     return DFA_OK;
 }
 
 int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
     if (bytes > kPinnedWords * sizeof(uint32_t)) return fail(DFA_EINVAL, "upload too large");
     // the pinned buffer may still be read by an earlier async copy
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     std::memcpy(c.pinned, host, bytes);
     HIP_TRY(hipMemcpyAsync(dev, c.pinned, bytes, hipMemcpyHostToDevice, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     return DFA_OK;
 }
 
@@ -844,7 +858,7 @@ int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const u
         q->num_blocks = c.pinned[0];
         q->start = c.pinned[1];
     } else {
-        HIP_TRY(hipStreamSynchronize(c.stream));
+        HIP_TRY(stream_sync(c));
     }
     if (r.ctl.limit) {
         fill_stats(st, r);
@@ -930,7 +944,7 @@ int minimise_pruned(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const
                         c.sub_block.as<uint32_t>(), block_out, c.stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c.ev_p1, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     if (st) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, c.ev_p0, c.ev_p1));
@@ -961,7 +975,7 @@ int equivalent_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict,
     RefineResult r;
     DFA_TRY(refine_any(c, N, k, o, 1, a.start, a.n + b.start, false, r));
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     fill_stats(st, r);
     if (st) {
         float ms = 0.f;
@@ -1040,7 +1054,7 @@ int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, ui
         std::swap(cur, nxt);
     }
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     *verdict = v;
     if (visited) *visited = count;
     if (st) {
@@ -1100,7 +1114,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 int ensure_pinned_batch(Ctx &c, size_t bytes) {
     if (c.pinned_batch && bytes <= c.pinned_batch_cap) return DFA_OK;
     if (c.pinned_batch) {
-        HIP_TRY(hipStreamSynchronize(c.stream));
+        HIP_TRY(stream_sync(c));
         (void)hipHostFree(c.pinned_batch);
         c.pinned_batch = nullptr;
         c.pinned_batch_cap = 0;
@@ -1172,7 +1186,7 @@ int refine_segments(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, uint3
                            hipMemcpyDeviceToHost, c.stream));
     HIP_TRY(hipMemcpyAsync(seg_changing.data(), g.seg_changing, nseg * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     return DFA_OK;
 }
 
@@ -1218,7 +1232,7 @@ int stage_views(Ctx &c, uint32_t count, const dfa_view *const *lists, int nlists
             dev_views.push_back(d);
         }
     HIP_TRY(hipMemcpyAsync(dev, c.pinned_batch, off, hipMemcpyHostToDevice, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     h2d_ms = ms_since(t0);
     return DFA_OK;
 }
@@ -1272,7 +1286,7 @@ int minimise_batch_impl(Ctx &c, uint32_t count, const dfa_view *views, uint32_t 
     launch_part_output(g, N, canon_ids, out_dev, c.stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     uint64_t transitions = 0;
     for (uint32_t i = 0; i < count; ++i) {
         if (num_blocks) num_blocks[i] = blocks[i];
@@ -1325,7 +1339,7 @@ int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_v
     HIP_TRY(hipMemcpyAsync(verdicts, c.batch_out.p, count * sizeof(int32_t), hipMemcpyDeviceToHost,
                            c.stream));
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     if (rounds_out)
         for (uint32_t i = 0; i < count; ++i) rounds_out[i] = changing[i] + 1;
     if (st) {
@@ -1361,7 +1375,7 @@ int minimise_host(Ctx &c_, uint32_t n, uint32_t k, const uint32_t *delta, const 
     HIP_TRY(hipMemcpyAsync(c->stage_delta.p, delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(hipMemcpyAsync(c->stage_acc.p, accepting, n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(stream_sync(*c));
     const double h2d = ms_since(t0);
     dfa_quotient dq{};
     if (q_out) {
@@ -1383,7 +1397,7 @@ int minimise_host(Ctx &c_, uint32_t n, uint32_t k, const uint32_t *delta, const 
         q_out->num_blocks = dq.num_blocks;
         q_out->start = dq.start;
     }
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(stream_sync(*c));
     if (stats) {
         stats->h2d_ms = h2d;
         stats->d2h_ms = ms_since(t0);
@@ -1413,7 +1427,7 @@ int equivalent_host(Ctx &c, const dfa_view *a, const dfa_view *b, int *verdict,
     dfa_view da, db;
     DFA_TRY(stage_view(c.stage_delta, c.stage_acc, a, da, c.stream));
     DFA_TRY(stage_view(c.stage_delta_b, c.stage_acc_b, b, db, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    HIP_TRY(stream_sync(c));
     const double h2d = ms_since(t0);
     int rc = equivalent_impl(c, da, db, verdict, o, stats);
     if (stats) stats->h2d_ms = h2d;
@@ -1460,6 +1474,8 @@ void release_ctx(Ctx &c) {
     if (c.ev_start) (void)hipEventDestroy(c.ev_start);
     if (c.ev_stop) (void)hipEventDestroy(c.ev_stop);
     if (c.ev_in) (void)hipEventDestroy(c.ev_in);
+    if (c.ev_sync) (void)hipEventDestroy(c.ev_sync);
+    c.ev_sync = nullptr;
     if (c.ev_p0) (void)hipEventDestroy(c.ev_p0);
     if (c.ev_p1) (void)hipEventDestroy(c.ev_p1);
     c.ev_p0 = c.ev_p1 = nullptr;
@@ -1620,7 +1636,7 @@ void run_solo(Server &s, Ctx &c, ServedRequest *r) {
         if (r->status == DFA_OK &&
             (hipMemcpyAsync(r->blocks, c.stage_block.p, n * sizeof(uint32_t),
                             hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
-             hipStreamSynchronize(c.stream) != hipSuccess))
+             stream_sync(c) != hipSuccess))
             r->status = fail(DFA_EDEVICE, "copy of the result failed");
         r->num_blocks = st.num_blocks;
         r->rounds = st.rounds;
@@ -1660,7 +1676,7 @@ void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
             if (rc2 == DFA_OK && hipMemcpyAsync(c.pinned_batch, c.batch_out.p,
                                                 total * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                                 c.stream) == hipSuccess &&
-                hipStreamSynchronize(c.stream) == hipSuccess) {
+                stream_sync(c) == hipSuccess) {
                 const uint32_t *src = reinterpret_cast<const uint32_t *>(c.pinned_batch);
                 uint64_t pos = 0;
                 for (uint32_t i = 0; i < count; ++i) {
@@ -1727,6 +1743,7 @@ void lane_main(Server *sp, size_t lane) {
     {
         std::lock_guard<std::mutex> g(c.mu);
         if (init_ctx(c) == DFA_OK) c.tune = s.tune;
+        c.blocking_sync = true;
     }
     for (;;) {
         std::vector<ServedRequest *> grp, all;
@@ -1800,7 +1817,7 @@ void lane_main(Server *sp, size_t lane) {
             else if (!grp.empty())
                 run_group(s, c, grp);
         }
-        (void)hipStreamSynchronize(c.stream);  // the input copies have completed
+        (void)stream_sync(c);  // the input copies have completed
         for (auto *r : all) {
             if (r->host_in) s.pinned.put(r->host_in, r->host_cls);
             r->host_in = nullptr;
@@ -2020,7 +2037,7 @@ int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *p
     dfa_view da, db;
     DFA_TRY(stage_view(c->stage_delta, c->stage_acc, a, da, c->stream));
     DFA_TRY(stage_view(c->stage_delta_b, c->stage_acc_b, b, db, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(stream_sync(*c));
     const double h2d = ms_since(t0);
     int rc = included_impl(*c, da, db, verdict, pairs_visited, stats);
     if (stats) stats->h2d_ms = h2d;
@@ -2074,7 +2091,7 @@ int dfa_minimise_batch(uint32_t count, const dfa_view *dfas, uint32_t *blocks_co
     DFA_TRY(ensure_pinned_batch(*c, total * sizeof(uint32_t)));
     HIP_TRY(hipMemcpyAsync(c->pinned_batch, c->batch_out.p, total * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(stream_sync(*c));
     uint64_t pos = 0;
     const uint32_t *src = reinterpret_cast<const uint32_t *>(c->pinned_batch);
     for (uint32_t i = 0; i < count; ++i) {

@@ -2,30 +2,34 @@
 //
 // One refinement round (the signature rounds of Section 3.3, Algorithm 4,
 // with grouping by hashing instead of sorting):
-//   k_signature  every state q writes its signature
+//   k_mark       bookkeeping of the states to refine: a block with one member
+//                never splits again (singleton bits); once a round changed
+//                few ids, only blocks with a member whose successor changed
+//                id can split, and those blocks are marked ("touched").
+//   k_signature  every refined state q writes its signature
 //                  ( block[q], block[col_0[q]], ..., block[col_{k_eff-1}[q]] )
 //                into a row of `sig` and a 64-bit hash of it.  Column reads are
 //                coalesced (symbol-major layout); the block ids are gathers.
-//   k_insert     groups equal signatures in a lock-free open-addressing table
-//                in HBM.  The hash only picks the slot and a 24-bit tag; keys
-//                are always compared in full, so grouping is exact.  The first
-//                state to claim a slot becomes the representative, and its
-//                index is the new block id of every state with that signature.
-//                The LDS variant first groups the 256 states of a workgroup in
-//                an LDS table, so only one state per distinct signature and
+//                The other states keep their id.
+//   k_insert     groups equal signatures.  A member whose key equals the key
+//                of the state that holds its block's id keeps that id (a
+//                direct compare, no table).  The others go through a
+//                lock-free open-addressing table in HBM: the hash only picks
+//                the slot and a 24-bit tag, keys are always compared in full,
+//                so grouping is exact; the first state to claim a slot
+//                becomes the id of every state with that signature.  The LDS
+//                variant first groups the 256 states of a workgroup in an LDS
+//                table, so only one state per distinct signature and
 //                workgroup touches the HBM table.
-//   k_round_end  one workgroup: the block count of the round is the number
-//                of claimed slots plus the singleton states that were not
-//                refined; an unchanged count means the partition is stable
-//                (the block id leads the signature, so each round refines the
-//                previous one).
-// A block with a single state never splits again: states whose block was a
-// singleton after the previous round skip the signature and grouping work
-// (their id is final).  Round 0 groups by the bit pattern of acceptance of q
-// and its successors when that pattern is short enough, without a table.
-// Block ids during the rounds are representatives chosen by the hardware's
-// atomic order; the final partition is renumbered canonically (smallest state
-// of each block) once, by k_canon_min / k_canon_apply.
+//   k_round_end  one workgroup: the block count of the round (the states
+//                that hold their block's id); an unchanged count means the
+//                partition is stable (the block id leads the signature, so
+//                each round refines the previous one).
+// Rounds 0 and 1 can group by exact labels without a table (acceptance bit
+// patterns, then packed pattern labels).  Block ids during the rounds are
+// member states chosen by the hardware's atomic order; the final partition
+// is renumbered canonically (smallest state of each block) once, by
+// k_canon_min / k_canon_apply.
 #include "device_common.h"
 
 namespace dfamin {
@@ -167,27 +171,6 @@ __device__ __forceinline__ uint32_t find_or_claim(unsigned long long *table, uin
         }
         s = (s + 1) & mask;
         e = load_entry(table + s, cached);
-    }
-}
-
-// Claims an empty slot for `self` without comparing keys: used when no
-// entry of the current epoch can hold an equal key (the states claiming this
-// way all have different block ids, which lead their keys).
-__device__ __forceinline__ void claim_slot(unsigned long long *table, uint64_t mask,
-                                           uint32_t epoch, uint64_t h, uint32_t self) {
-    const uint32_t tag = (epoch << 24) | static_cast<uint32_t>(h >> 40);
-    const unsigned long long want = (static_cast<unsigned long long>(tag) << 32) | self;
-    uint64_t s = h & mask;
-    unsigned long long e = load_entry(table + s, false);
-    for (;;) {
-        if (static_cast<uint32_t>(e >> 56) != epoch) {
-            const unsigned long long prev = atomicCAS(table + s, e, want);
-            if (prev == e) return;
-            e = prev;
-            continue;
-        }
-        s = (s + 1) & mask;
-        e = load_entry(table + s, false);
     }
 }
 
@@ -496,10 +479,10 @@ __device__ __forceinline__ bool select_state(const SigParams &p, size_t q, uint3
 }
 
 // Writes the key row and hash of a refined state; a state that holds its
-// block's id (selective rounds) claims its key's slot right away.
+// block's id (selective rounds) keeps it and counts as its block.
 __device__ __forceinline__ void emit_key(const SigParams &p, uint32_t *__restrict__ Y, size_t q,
                                          uint32_t w0, const uint32_t *w, uint32_t keff, size_t W,
-                                         bool claim_holder, uint32_t epoch, uint32_t &claims) {
+                                         bool holder_keeps, uint32_t &claims) {
     uint32_t *__restrict__ row = p.sig + q * W;
     row[0] = w0;
     uint64_t h = mix_step(kHashSeed, w0);
@@ -509,10 +492,10 @@ __device__ __forceinline__ void emit_key(const SigParams &p, uint32_t *__restric
     }
     h = limit_hash(mix_final(h), p.hash_bits);
     p.hash[q] = h;
-    if (claim_holder && w0 == q) {
-        // the state that holds its block's id claims its key before the
-        // others group, so a block that does not split keeps its id
-        claim_slot(p.table, p.table_cap - 1, epoch, h, static_cast<uint32_t>(q));
+    if (holder_keeps && w0 == q) {
+        // the state that holds its block's id keeps it: the members with
+        // its key join it without the table (grouping kernels), so a block
+        // that does not split keeps its id
         Y[q] = w0;
         ++claims;
     }
@@ -522,8 +505,7 @@ __device__ __forceinline__ void emit_key(const SigParams &p, uint32_t *__restric
 // round refines everything (the first rounds), or if its block is not a
 // singleton and, in incremental rounds, is touched; the others keep their id
 // and are copied to the output buffer.  A refined state that holds its
-// block's id claims a table slot for its key here, before any other state
-// looks its key up.
+// block's id keeps it (its block survives with that id).
 // KC > 0: k_eff known at compile time (fully unrolled gathers, two states per
 // thread);
 // KC == 0: runtime k_eff, gathers issued in batches of 8.
@@ -539,7 +521,6 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
     const bool inc = !all && incremental_round(*p.ctl, p.N, r);
     const size_t words = (p.N + 63) / 64;
     const unsigned long long *__restrict__ T = p.touched + (r & 1u) * words;
-    const uint32_t epoch = r % kEpochs + 1;
     uint32_t leaders = 0, claims = 0;
 
     if constexpr (KC > 0) {
@@ -607,8 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
                 if (act[i])
-                    emit_key(p, Y, q[i], w0[i], w[i], KC, W, !all && p.grouping == 0, epoch,
-                             claims);
+                    emit_key(p, Y, q[i], w0[i], w[i], KC, W, !all && p.grouping == 0, claims);
         }
     } else {
         for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
@@ -652,7 +632,6 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
             h = limit_hash(mix_final(h), p.hash_bits);
             p.hash[q] = h;
             if (!all && p.grouping == 0 && w0 == q) {
-                claim_slot(p.table, p.table_cap - 1, epoch, h, static_cast<uint32_t>(q));
                 Y[q] = w0;
                 ++claims;
             }
@@ -713,8 +692,12 @@ __global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
         bool ch = false;
         if (act) {
             const uint32_t x = X[q];
-            // a state holding its block's id claimed in the signature kernel
-            if (all || x != q) {
+            // the state holding its block's id kept it in the signature
+            // kernel; a member with the same key joins it directly
+            if (!all && x != q && rows_equal(p.sig, p.W, q, x)) {
+                Y[q] = x;
+                mark_multi(p.multi, x, r + 1);
+            } else if (all || x != q) {
                 bool claimed = false;
                 const uint32_t id = find_or_claim(p.table, p.mask, epoch, p.hash[q],
                                                   static_cast<uint32_t>(q), p.sig, p.W,
@@ -768,9 +751,15 @@ __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
             continue;
         }
         const uint32_t x = act ? X[q] : 0u;
-        // a state holding its block's id claimed in the signature kernel;
-        // the others group in LDS first
-        const bool grp = act && (all || x != q);
+        // the state holding its block's id kept it in the signature kernel;
+        // a member with the same key joins it directly, the others group in
+        // LDS first
+        const bool joins = act && !all && x != q && rows_equal(p.sig, p.W, q, x);
+        if (joins) {
+            Y[q] = x;
+            mark_multi(p.multi, x, r + 1);
+        }
+        const bool grp = act && !joins && (all || x != q);
         for (uint32_t i = tx; i < kLdsSlots; i += kBlock) ltab[i] = kEmptyPair;
         lsize[tx] = 0;
         __syncthreads();
