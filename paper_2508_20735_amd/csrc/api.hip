@@ -887,7 +887,7 @@ int minimise_pruned(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const
     DFA_TRY(c.scalars.ensure(16 * sizeof(uint32_t), "scalars"));
     DFA_TRY(c.reach_visited.ensure(words64 * sizeof(unsigned long long), "visited bits"));
     DFA_TRY(c.reach_qa.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "search queue"));
-    DFA_TRY(c.reach_qb.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "search queue"));
+    DFA_TRY(c.reach_qb.ensure(static_cast<size_t>(n), "search marks"));
     DFA_TRY(c.reach_flags.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "reachable flags"));
     DFA_TRY(c.reach_dense.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "reachable numbering"));
     DFA_TRY(c.reach_orig.ensure(static_cast<size_t>(n) * sizeof(uint32_t), "reachable states"));
@@ -901,25 +901,43 @@ int minimise_pruned(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const
     if (c.pinned[0]) return fail(DFA_EINVAL, "a transition target is >= n");
 
     uint32_t *sizes = c.scalars.as<uint32_t>();
-    ReachArgs ra{delta, n, k, c.reach_visited.as<unsigned long long>(), c.reach_qa.as<uint32_t>(),
-                 c.reach_qb.as<uint32_t>(), sizes};
+    ReachArgs ra{delta, n, k, c.reach_visited.as<unsigned long long>(), c.reach_qb.as<uint8_t>(),
+                 c.reach_qa.as<uint32_t>(), sizes};
     HIP_TRY(hipMemsetAsync(ra.visited, 0, words64 * sizeof(unsigned long long), c.stream));
+    HIP_TRY(hipMemsetAsync(ra.mark, 0, n, c.stream));
     launch_bfs_init(ra, o.start, c.stream);
+    // small frontiers: a queue expanded in one workgroup; large ones: dense
+    // levels over the marks (frontier mark f, alternating 2 / 3)
     const uint64_t cap = bfs_narrow_cap();
+    bool dense = false;
+    uint8_t f = 2;
     for (;;) {
         HIP_TRY(hipGetLastError());
-        DFA_TRY(read_back(c, sizes, sizeof(uint32_t)));
-        const uint32_t frontier = c.pinned[0];
-        if (frontier == 0) break;
-        if (static_cast<uint64_t>(frontier) * k <= cap) {
-            launch_bfs_narrow(ra, c.stream);
-        } else {
-            launch_bfs_wide(ra, frontier, c.stream);
-            std::swap(ra.qa, ra.qb);
+        if (!dense) {
+            DFA_TRY(read_back(c, sizes, sizeof(uint32_t)));
+            const uint32_t frontier = c.pinned[0];
+            if (frontier == 0) break;
+            if (static_cast<uint64_t>(frontier) * k <= cap) {
+                launch_bfs_narrow(ra, c.stream);
+                continue;
+            }
+            launch_bfs_list_to_marks(ra, frontier, f, c.stream);
+            dense = true;
+        }
+        const uint8_t nf = f == 2 ? 3 : 2;
+        launch_bfs_dense(ra, f, nf, c.stream);
+        HIP_TRY(hipGetLastError());
+        DFA_TRY(read_back(c, sizes + 1, sizeof(uint32_t)));
+        const uint32_t stored = c.pinned[0];  // >= the new states; 0 iff none
+        if (stored == 0) break;
+        f = nf;
+        if (static_cast<uint64_t>(stored) * k <= cap) {
+            launch_bfs_marks_to_list(ra, f, c.stream);
+            dense = false;
         }
     }
     // dense numbering of the reachable states; m = their count
-    launch_reach_flags(ra.visited, n, c.reach_flags.as<uint32_t>(), c.stream);
+    launch_reach_flags(ra.mark, n, c.reach_flags.as<uint32_t>(), c.stream);
     launch_dense_leaders(c.reach_flags.as<uint32_t>(), n, c.partials.as<uint32_t>(),
                          c.reach_dense.as<uint32_t>(), c.reach_orig.as<uint32_t>(), sizes + 2,
                          c.stream);
@@ -940,7 +958,7 @@ int minimise_pruned(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const
     int rc = minimise_impl(c, m, k, c.sub_delta.as<uint32_t>(), c.sub_acc.as<uint8_t>(),
                            c.sub_block.as<uint32_t>(), q, o2, st);
     if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
-    launch_reach_expand(ra.visited, n, c.reach_dense.as<uint32_t>(), c.reach_orig.as<uint32_t>(),
+    launch_reach_expand(ra.mark, n, c.reach_dense.as<uint32_t>(), c.reach_orig.as<uint32_t>(),
                         c.sub_block.as<uint32_t>(), block_out, c.stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(c.ev_p1, c.stream));

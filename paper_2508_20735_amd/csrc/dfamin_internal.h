@@ -245,8 +245,9 @@ struct ReachArgs {
     const uint32_t *delta;           // row-major n x k, targets < n (checked first)
     uint32_t n, k;
     unsigned long long *visited;     // n/64 words, zero before the search
-    uint32_t *qa, *qb;               // frontier queues, n entries each
-    uint32_t *sizes;                 // [0] entries in qa, [1] entries in qb
+    uint8_t *mark;                   // n: 0 unvisited, 1 settled, 2 / 3 dense frontier
+    uint32_t *qa;                    // frontier queue, n entries
+    uint32_t *sizes;                 // [0] entries in qa, [1] marks stored by a dense level
 };
 // *err = 1 if a target is >= n.
 void launch_check_targets(const uint32_t *delta, uint64_t total, uint32_t n, uint32_t *err,
@@ -254,19 +255,22 @@ void launch_check_targets(const uint32_t *delta, uint64_t total, uint32_t n, uin
 void launch_bfs_init(const ReachArgs &a, uint32_t start, hipStream_t s);
 // Expands levels in one workgroup while sizes[0] * k <= bfs_narrow_cap().
 void launch_bfs_narrow(const ReachArgs &a, hipStream_t s);
-// One level over qa (frontier entries) into qb, then sizes[0] = sizes[1];
-// the caller swaps qa and qb.
-void launch_bfs_wide(const ReachArgs &a, uint32_t frontier, hipStream_t s);
 uint32_t bfs_narrow_cap();
-// flags[q] = q if visited, all ones otherwise.
-void launch_reach_flags(const unsigned long long *visited, size_t n, uint32_t *flags,
-                        hipStream_t s);
+// The count listed states of qa become the frontier mark f.
+void launch_bfs_list_to_marks(const ReachArgs &a, uint32_t count, uint8_t f, hipStream_t s);
+// One dense level: frontier f expands into nf; sizes[1] = marks stored
+// (0 iff no new state).
+void launch_bfs_dense(const ReachArgs &a, uint8_t f, uint8_t nf, hipStream_t s);
+// The states marked f settle and are listed in qa; sizes[0] = their number.
+void launch_bfs_marks_to_list(const ReachArgs &a, uint8_t f, hipStream_t s);
+// flags[q] = q if marked (reached), all ones otherwise.
+void launch_reach_flags(const uint8_t *mark, size_t n, uint32_t *flags, hipStream_t s);
 // sub_delta[i][a] = dense[delta[orig[i]][a]], sub_acc[i] = acc[orig[i]], i < *m_dev.
 void launch_sub_dfa(const uint32_t *delta, const uint8_t *acc, uint32_t k, const uint32_t *orig,
                     const uint32_t *dense, const uint32_t *m_dev, uint32_t m_host,
                     uint32_t *sub_delta, uint8_t *sub_acc, hipStream_t s);
-// block_out[q] = orig[sub_block[dense[q]]] if visited, all ones otherwise.
-void launch_reach_expand(const unsigned long long *visited, size_t n, const uint32_t *dense,
+// block_out[q] = orig[sub_block[dense[q]]] if marked, all ones otherwise.
+void launch_reach_expand(const uint8_t *mark, size_t n, const uint32_t *dense,
                          const uint32_t *orig, const uint32_t *sub_block, uint32_t *block_out,
                          hipStream_t s);
 

@@ -3,12 +3,16 @@
 // reachable part (the usual minimal DFA; the paper itself prunes nothing,
 // Section 2).
 //
-// The search keeps a visited bitmap (one bit per state) and two frontier
-// queues.  A frontier of at most kNarrowCap / k states is expanded inside one
-// workgroup, level after level, with both queues in LDS (long thin searches,
-// such as chains, then cost no launch per level); a larger frontier is
-// expanded by a grid-wide launch per level, appending with one atomic per
-// wave.  Every state enters a queue once, so both loops end.
+// The search keeps a mark byte per state (0 unvisited, 1 settled, 2 / 3 in
+// the frontier of an even / odd level) and a frontier queue.  A frontier of
+// at most kNarrowCap / k states is expanded inside one workgroup, level after
+// level, with both queues in LDS (long thin searches, such as chains, then
+// cost no launch per level; a visited bitmap with atomics dedupes within the
+// workgroup).  A larger frontier is expanded by dense levels: every state is
+// scanned, the frontier ones expand, and unvisited targets get the next
+// level's mark by plain stores (several writers store the same value), so
+// wide levels use no atomics on the visited set.  Every state is marked once,
+// so both loops end.
 #include "device_common.h"
 
 namespace dfamin {
@@ -37,6 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_check_targets(const uint32_t *__rest
 __global__ void k_bfs_init(ReachArgs a, uint32_t start) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     a.visited[start >> 6] |= 1ull << (start & 63);
+    a.mark[start] = 1;
     a.qa[0] = start;
     a.sizes[0] = 1;
     a.sizes[1] = 0;
@@ -66,8 +71,12 @@ __global__ __launch_bounds__(kNarrowThreads) void k_bfs_narrow(ReachArgs a) {
         for (uint32_t i = tx; i < work; i += kNarrowThreads) {
             const uint32_t q = buf[cur][i / k];
             const uint32_t t = a.delta[static_cast<size_t>(q) * k + (i % k)];
-            // at most one entry per (state, letter) pair: pos < s * k <= kNarrowCap
-            if (visit(a.visited, t)) buf[nxt][atomicAdd(&sz[nxt], 1u)] = t;
+            // at most one entry per (state, letter) pair: pos < s * k <= kNarrowCap;
+            // states settled by dense levels carry a mark, not a bit
+            if (a.mark[t] == 0 && visit(a.visited, t)) {
+                a.mark[t] = 1;
+                buf[nxt][atomicAdd(&sz[nxt], 1u)] = t;
+            }
         }
         __syncthreads();
         cur = nxt;
@@ -77,46 +86,80 @@ __global__ __launch_bounds__(kNarrowThreads) void k_bfs_narrow(ReachArgs a) {
     if (tx == 0) a.sizes[0] = s;
 }
 
-// One level over a large frontier: qa (sizes[0] entries) -> qb (sizes[1]).
-__global__ __launch_bounds__(kBlock) void k_bfs_wide(ReachArgs a) {
-    const uint64_t work = static_cast<uint64_t>(a.sizes[0]) * a.k;
-    const uint32_t lane = lane_id();
-    for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kBlock; base < work;
-         base += static_cast<uint64_t>(gridDim.x) * kBlock) {
-        const uint64_t i = base + threadIdx.x;
-        bool fresh = false;
-        uint32_t t = 0;
-        if (i < work) {
-            const uint32_t q = a.qa[i / a.k];
-            t = a.delta[static_cast<size_t>(q) * a.k + (i % a.k)];
-            fresh = visit(a.visited, t);
+// Queue -> marks: the listed states become the frontier of a dense level.
+__global__ __launch_bounds__(kBlock) void k_bfs_list_to_marks(ReachArgs a, uint8_t f) {
+    const uint32_t s = a.sizes[0];
+    for (size_t i = global_tid(); i < s; i += grid_stride()) a.mark[a.qa[i]] = f;
+}
+
+// One dense level: states marked f expand (unvisited targets get nf) and
+// settle.  sizes[1] += number of marks stored (an upper bound of the new
+// states: two lanes may store the same target; zero iff none was stored).
+__global__ __launch_bounds__(kBlock) void k_bfs_dense(ReachArgs a, uint8_t f, uint8_t nf) {
+    uint32_t stored = 0;
+    for (size_t q = global_tid(); q < a.n; q += grid_stride()) {
+        if (a.mark[q] != f) continue;
+        const uint32_t *row = a.delta + q * a.k;
+        // letters in groups of 8: the row entries, then their marks, are
+        // loaded together before any store
+        for (uint32_t j0 = 0; j0 < a.k; j0 += 8) {
+            const uint32_t m = a.k - j0 < 8 ? a.k - j0 : 8;
+            uint32_t t[8];
+            uint8_t mk[8];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) t[j] = j < m ? row[j0 + j] : static_cast<uint32_t>(q);
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) mk[j] = a.mark[t[j]];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j)
+                if (j < m && mk[j] == 0) {
+                    a.mark[t[j]] = nf;
+                    ++stored;
+                }
         }
-        const unsigned long long m = __ballot(fresh);
+        a.mark[q] = 1;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) stored += __shfl_xor(stored, d, 64);
+    if (lane_id() == 0 && stored) atomicAdd(a.sizes + 1, stored);
+}
+
+// Marks -> queue: the states marked f settle and are listed in qa (one
+// append atomic per wave); sizes[0] = their number.
+__global__ __launch_bounds__(kBlock) void k_bfs_marks_to_list(ReachArgs a, uint8_t f) {
+    const uint32_t lane = lane_id();
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < a.n;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        const size_t q = base + threadIdx.x;
+        const bool hit = q < a.n && a.mark[q] == f;
+        const unsigned long long m = __ballot(hit);
         if (m == 0) continue;
         const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
         uint32_t pos = 0;
-        if (static_cast<int>(lane) == leader) pos = atomicAdd(a.sizes + 1, static_cast<uint32_t>(__popcll(m)));
+        if (static_cast<int>(lane) == leader)
+            pos = atomicAdd(a.sizes, static_cast<uint32_t>(__popcll(m)));
         pos = __shfl(pos, leader, 64);
-        if (fresh) {
+        if (hit) {
             const unsigned long long below = lane ? (m & ((1ull << lane) - 1ull)) : 0ull;
-            a.qb[pos + static_cast<uint32_t>(__popcll(below))] = t;
+            a.qa[pos + static_cast<uint32_t>(__popcll(below))] = static_cast<uint32_t>(q);
+            a.mark[q] = 1;
         }
     }
 }
 
-__global__ void k_bfs_next(uint32_t *sizes) {
+__global__ void k_bfs_set(uint32_t *sizes, uint32_t i0, uint32_t v0, uint32_t i1, uint32_t v1) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        sizes[0] = sizes[1];
-        sizes[1] = 0;
+        sizes[i0] = v0;
+        sizes[i1] = v1;
     }
 }
 
 // flags[q] = q for reachable q, all ones otherwise (the input of the dense
 // numbering, which numbers the states with flags[q] == q).
-__global__ __launch_bounds__(kBlock) void k_reach_flags(const unsigned long long *visited, size_t n,
+__global__ __launch_bounds__(kBlock) void k_reach_flags(const uint8_t *mark, size_t n,
                                                         uint32_t *flags) {
     for (size_t q = global_tid(); q < n; q += grid_stride())
-        flags[q] = ((visited[q >> 6] >> (q & 63)) & 1ull) ? static_cast<uint32_t>(q) : ~0u;
+        flags[q] = mark[q] ? static_cast<uint32_t>(q) : ~0u;
 }
 
 // Sub-automaton: row i is the reachable state orig[i], targets renumbered.
@@ -140,15 +183,13 @@ __global__ __launch_bounds__(kBlock) void k_sub_dfa(const uint32_t *__restrict__
 // block_out[q] = orig[sub_block[dense[q]]] for reachable q, kUnreachable
 // otherwise (sub_block is canonical, and dense keeps the original order, so
 // the result is the smallest reachable state of the block).
-__global__ __launch_bounds__(kBlock) void k_reach_expand(const unsigned long long *visited,
-                                                         size_t n, const uint32_t *dense,
+__global__ __launch_bounds__(kBlock) void k_reach_expand(const uint8_t *mark, size_t n,
+                                                         const uint32_t *dense,
                                                          const uint32_t *orig,
                                                          const uint32_t *sub_block,
                                                          uint32_t *block_out) {
-    for (size_t q = global_tid(); q < n; q += grid_stride()) {
-        const bool r = (visited[q >> 6] >> (q & 63)) & 1ull;
-        block_out[q] = r ? orig[sub_block[dense[q]]] : 0xFFFFFFFFu;
-    }
+    for (size_t q = global_tid(); q < n; q += grid_stride())
+        block_out[q] = mark[q] ? orig[sub_block[dense[q]]] : 0xFFFFFFFFu;
 }
 
 unsigned grid_of(uint64_t work, unsigned cap = 8192) {
@@ -174,17 +215,24 @@ void launch_bfs_narrow(const ReachArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_bfs_narrow, dim3(1), dim3(kNarrowThreads), 0, s, a);
 }
 
-void launch_bfs_wide(const ReachArgs &a, uint32_t frontier, hipStream_t s) {
-    hipLaunchKernelGGL(k_bfs_wide, dim3(grid_of(static_cast<uint64_t>(frontier) * a.k)),
-                       dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_bfs_next, dim3(1), dim3(64), 0, s, a.sizes);
+void launch_bfs_list_to_marks(const ReachArgs &a, uint32_t count, uint8_t f, hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_list_to_marks, dim3(grid_of(count)), dim3(kBlock), 0, s, a, f);
+}
+
+void launch_bfs_dense(const ReachArgs &a, uint8_t f, uint8_t nf, hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_set, dim3(1), dim3(64), 0, s, a.sizes, 1u, 0u, 1u, 0u);
+    hipLaunchKernelGGL(k_bfs_dense, dim3(grid_of(a.n)), dim3(kBlock), 0, s, a, f, nf);
+}
+
+void launch_bfs_marks_to_list(const ReachArgs &a, uint8_t f, hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_set, dim3(1), dim3(64), 0, s, a.sizes, 0u, 0u, 0u, 0u);
+    hipLaunchKernelGGL(k_bfs_marks_to_list, dim3(grid_of(a.n)), dim3(kBlock), 0, s, a, f);
 }
 
 uint32_t bfs_narrow_cap() { return kNarrowCap; }
 
-void launch_reach_flags(const unsigned long long *visited, size_t n, uint32_t *flags,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_reach_flags, dim3(grid_of(n)), dim3(kBlock), 0, s, visited, n, flags);
+void launch_reach_flags(const uint8_t *mark, size_t n, uint32_t *flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_reach_flags, dim3(grid_of(n)), dim3(kBlock), 0, s, mark, n, flags);
 }
 
 void launch_sub_dfa(const uint32_t *delta, const uint8_t *acc, uint32_t k, const uint32_t *orig,
@@ -194,10 +242,10 @@ void launch_sub_dfa(const uint32_t *delta, const uint8_t *acc, uint32_t k, const
                        0, s, delta, acc, k, orig, dense, m_dev, sub_delta, sub_acc);
 }
 
-void launch_reach_expand(const unsigned long long *visited, size_t n, const uint32_t *dense,
+void launch_reach_expand(const uint8_t *mark, size_t n, const uint32_t *dense,
                          const uint32_t *orig, const uint32_t *sub_block, uint32_t *block_out,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_reach_expand, dim3(grid_of(n)), dim3(kBlock), 0, s, visited, n, dense,
+    hipLaunchKernelGGL(k_reach_expand, dim3(grid_of(n)), dim3(kBlock), 0, s, mark, n, dense,
                        orig, sub_block, block_out);
 }
 
