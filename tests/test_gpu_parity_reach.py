@@ -103,3 +103,13 @@ def test_pruned_device_api_and_errors():
     with pytest.raises(B.DfaError) as e:
         B.minimise(bad, d.accepting, prune=True)
     assert e.value.status == B.DFA_EINVAL
+
+
+@pytest.mark.parametrize("algorithm", ["leader", "sort"])
+def test_pruned_with_other_algorithms(algorithm):
+    """Pruning composes with the other refinement algorithms: the same ids."""
+    d = W.random_dfa(20000, 3, 0.3, 61)
+    res = B.minimise(d.delta, d.accepting, tc="off", prune=True, start=3, algorithm=algorithm)
+    block, nb, nr = oracle.minimise_reachable(d.delta, d.accepting, 3)
+    np.testing.assert_array_equal(res.block, block)
+    assert res.stats["num_blocks"] == nb and res.stats["reachable"] == nr

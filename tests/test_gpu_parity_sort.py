@@ -103,3 +103,17 @@ def test_forced_hash_collisions(restore_tuning, algorithm, bits):
         block, nb, rounds, changing = oracle.moore(d.delta, d.accepting)
         np.testing.assert_array_equal(res.block, block)
         assert (res.stats["rounds"], res.stats["changing_rounds"]) == (rounds, changing)
+
+
+def test_sort_transpr_and_leader_equivalence_agree():
+    """Equivalence verdicts agree across the three algorithms and the closure
+    modes on the paper's families."""
+    cases = [(W.fibonacci(11), W.permuted_copy(W.fibonacci(11), 2)[0]),
+             (W.bitsplitter(9), W.mutate_one(W.bitsplitter(9), 4)[0]),
+             (W.random_dfa(5000, 4, 0.2, 70), W.mutate_one(W.random_dfa(5000, 4, 0.2, 70), 71)[0])]
+    for a, b in cases:
+        expect = oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
+        for alg in ("signature", "sort", "leader"):
+            for tc in ("off", "on"):
+                got, _ = B.equivalent(a, b, tc=tc, algorithm=alg)
+                assert got == expect, (alg, tc)
