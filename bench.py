@@ -60,6 +60,8 @@ def parse_args():
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the comparison of grouping / refinement variants")
+    ap.add_argument("--no-table2", action="store_true",
+                    help="skip the runs on the paper's Table 2 families")
     return ap.parse_args()
 
 
@@ -196,6 +198,51 @@ def variants_leg(B, W, torch, np, dev, A_d, A_a, n) -> dict:
         out[f"b20_{alg}_ms"] = ms
         out[f"b20_{alg}_rounds"] = st["rounds"]
     out["b20_transitions"] = bs.n * bs.k
+    return out
+
+
+# Table 2 of the paper (TITAN RTX, times include the host-to-device copy):
+# context for the runs below, not a target.
+PAPER_TABLE2_MS = {
+    "Fib20": {"naivePR": 308.8, "sortPR": 3909.2, "transPR": 1.7},
+    "B20": {"naivePR": 19.3, "sortPR": 520.2, "transPR": 139.8},
+    "B22": {"naivePR": 82.6, "sortPR": 2538.5, "transPR": 728.7},
+}
+
+
+def table2_leg(B, W, torch, np, dev) -> dict:
+    """The paper's Table 2 families on this GPU: leader rounds (naivePR),
+    signature rounds grouped by hashing and by sorting (sortPR's semantics),
+    transPR (closure + naivePR) and the closure on demand.  Device time with
+    the input resident, median of 3 runs after one warm-up."""
+    runs = {
+        "Fib20": (lambda: W.fibonacci(21),
+                  [("naivePR", "leader", "off"), ("signature", "signature", "off"),
+                   ("transPR", "leader", "on"), ("signature_tc_auto", "signature", "auto")]),
+        "B20": (lambda: W.bitsplitter(20),
+                [("naivePR", "leader", "off"), ("signature", "signature", "off"),
+                 ("sort", "sort", "off"), ("transPR", "leader", "on")]),
+        "B22": (lambda: W.bitsplitter(22),
+                [("naivePR", "leader", "off"), ("signature", "signature", "off"),
+                 ("sort", "sort", "off")]),
+    }
+    out = {}
+    for name, (make, variants) in runs.items():
+        d = make()
+        delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
+        acc = torch.from_numpy(d.accepting).to(dev)
+        blk = torch.empty(d.n, dtype=torch.int32, device=dev)
+        row = {"n": d.n, "k": d.k, "paper_ms": PAPER_TABLE2_MS[name]}
+        for label, alg, tc in variants:
+            def once():
+                return B.minimise_device(delta, acc, blk, tc=tc, loop="graph",
+                                         algorithm=alg).stats
+            once()
+            sts = [once() for _ in range(3)]
+            row[label] = {"ms": float(np.median([st["device_ms"] for st in sts])),
+                          "rounds": sts[-1]["rounds"], "num_blocks": sts[-1]["num_blocks"]}
+        out[name] = row
+        del delta, acc, blk
     return out
 
 
@@ -385,6 +432,8 @@ def main() -> int:
         out["served"] = serve_leg(B, W, args.serve_requests)
     if not args.no_variants:
         out["variants"] = variants_leg(B, W, torch, np, dev, A_d, A_a, d.n)
+    if not args.no_table2:
+        out["table2"] = table2_leg(B, W, torch, np, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, perm)
     print(json.dumps(out), flush=True)

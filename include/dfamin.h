@@ -86,13 +86,23 @@ extern "C" {
                             on the device once the partition is stable; the host
                             checks once per chunk */
 #define DFA_LOOP_GRAPH 2 /* like CHUNK, each chunk replayed from a captured hipGraph */
+#define DFA_LOOP_PERSISTENT 3 /* each chunk is one cooperative launch that loops over
+                                 the rounds on the device, its phases separated by grid
+                                 barriers, and stops as soon as the partition is stable
+                                 (the while-loop of Algorithms 2 and 4, Section 3, kept
+                                 on the device).  Single-DFA
+                                 calls with DFA_ALGO_SIGNATURE or DFA_ALGO_LEADER;
+                                 DFA_EINVAL with DFA_ALGO_SORT and in batched calls */
 
 typedef struct dfa_options {
     int32_t tc_mode;      /* DFA_TC_*, default DFA_TC_AUTO */
     int32_t loop_mode;    /* DFA_LOOP_*, default DFA_LOOP_GRAPH */
     uint32_t start;       /* start state used for the quotient's start (default 0) */
     uint32_t max_rounds;  /* 0 = until stable */
-    uint32_t chunk;       /* rounds per chunk in CHUNK/GRAPH mode (0 = library default) */
+    uint32_t chunk;       /* rounds per chunk in CHUNK/GRAPH mode; 0 = automatic: the
+                             tuned start length (dfa_tuning.chunk), doubled after each
+                             chunk that did not finish, up to 256 rounds (32 while
+                             TC AUTO may still switch the closure on) */
     int32_t lds_stage;    /* 1 = pre-group keys in LDS before the global table,
                              0 = insert every key into the global table,
                              2 = LDS only in rounds after one that formed at most one
@@ -165,7 +175,7 @@ typedef struct dfa_tuning {
                                 k_eff + 1 <= 16; 2: round 1 then groups by the packed
                                 round-0 labels when (k_eff + 1)^2 <= 25 */
     uint32_t cached_probe;   /* 1: probe the grouping table with cached loads first */
-    uint32_t chunk;          /* rounds per chunk when options.chunk is 0 (1..4096) */
+    uint32_t chunk;          /* first chunk's rounds when options.chunk is 0 (1..4096) */
     uint32_t hash_bits;      /* 0 = full 64-bit key hashes (default); 1..63 keep only the
                                 low bits, so that distinct keys share hashes: slower, still
                                 exact (keys are always compared in full); for testing the

@@ -30,7 +30,7 @@ REQ_MINIMISE = 0
 REQ_EQUIVALENT = 1
 
 TC = {"off": 0, "on": 1, "auto": 2}
-LOOP = {"host": 0, "chunk": 1, "graph": 2}
+LOOP = {"host": 0, "chunk": 1, "graph": 2, "persistent": 3}
 # block id of a state removed by reachability pruning
 UNREACHABLE = 0xFFFFFFFF
 # signature rounds (sortPR semantics, hashed) or leader rounds (naivePR)

@@ -120,8 +120,12 @@ struct Ctx {
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     size_t pinned_batch_cap = 0;
-    hipGraphExec_t graph = nullptr;
-    GraphKey graph_key{};
+    // captured chunks, one per chunk length in use (automatic chunks grow
+    // 4, 8, ..., 256 within one call), replaced round-robin
+    static constexpr int kGraphSlots = 8;
+    hipGraphExec_t graphs[kGraphSlots] = {};
+    GraphKey graph_keys[kGraphSlots] = {};
+    int graph_victim = 0;
     // kernel timing (dfa_profile_enable): event pairs around the round
     // kernels, folded into per-kernel totals after every readback
     bool profiling = false;
@@ -365,6 +369,17 @@ bool splitting_stalled(const RoundCtl &ctl, size_t N) {
            (ctl.round >= 32 && recent_gain * 64 < left);
 }
 
+// Rounds in the next chunk when the caller leaves the length to the library:
+// the tuned start length, doubled after every chunk that did not finish, up
+// to 256 rounds (32 while the closure may still be switched on, so that a
+// stall is seen soon after it starts).  Short refinements keep few no-op
+// rounds; long ones need few host round trips.
+uint32_t grown_chunk(uint32_t chunk, bool tc_pending, bool profiling) {
+    uint32_t cap = tc_pending ? 32u : 256u;
+    if (profiling) cap = std::min(cap, kActiveHist);
+    return std::max(chunk, std::min(chunk * 2, cap));
+}
+
 // Builds the closure columns (all levels) from level 0 in c.cols, and the
 // signature column list.  Returns DFA_ENOMEM if the table does not fit.
 int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, uint32_t &levels) {
@@ -407,6 +422,13 @@ int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
 // refinement, from a captured graph in GRAPH mode.
 int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t first_round,
               const LeaderArgs *la = nullptr) {
+    if (mode == DFA_LOOP_PERSISTENT && !c.profiling) {
+        const hipError_t e = la ? launch_leader_persistent(*la, rounds, c.stream)
+                                : launch_rounds_persistent(ra, rounds, c.stream);
+        if (e != hipSuccess)
+            return fail(DFA_EDEVICE, "persistent round loop: %s", hipGetErrorString(e));
+        return DFA_OK;
+    }
     if (mode == DFA_LOOP_GRAPH && !c.profiling) {
         GraphKey key;
         std::memset(&key, 0, sizeof key);
@@ -416,10 +438,15 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t f
             std::memcpy(&key.args, &ra, sizeof ra);
         key.chunk = rounds;
         key.leader = la ? 1u : 0u;
-        if (!c.graph || !(c.graph_key == key)) {
-            if (c.graph) {
-                (void)hipGraphExecDestroy(c.graph);
-                c.graph = nullptr;
+        int slot = -1;
+        for (int i = 0; i < Ctx::kGraphSlots; ++i)
+            if (c.graphs[i] && c.graph_keys[i] == key) slot = i;
+        if (slot < 0) {
+            slot = c.graph_victim;
+            c.graph_victim = (c.graph_victim + 1) % Ctx::kGraphSlots;
+            if (c.graphs[slot]) {
+                (void)hipGraphExecDestroy(c.graphs[slot]);
+                c.graphs[slot] = nullptr;
             }
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
@@ -430,15 +457,15 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t f
                     launch_round(ra, c.stream);
             }
             HIP_TRY(hipStreamEndCapture(c.stream, &g));
-            hipError_t e = hipGraphInstantiate(&c.graph, g, nullptr, nullptr, 0);
+            hipError_t e = hipGraphInstantiate(&c.graphs[slot], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) {
-                c.graph = nullptr;
+                c.graphs[slot] = nullptr;
                 return fail(DFA_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
             }
-            c.graph_key = key;
+            c.graph_keys[slot] = key;
         }
-        HIP_TRY(hipGraphLaunch(c.graph, c.stream));
+        HIP_TRY(hipGraphLaunch(c.graphs[slot], c.stream));
     } else {
         for (uint32_t i = 0; i < rounds; ++i) {
             if (la)
@@ -632,6 +659,9 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             res.tc_levels = levels;
             res.plain_rounds = res.ctl.round;
         }
+        if (!o.chunk)
+            chunk = grown_chunk(chunk, o.tc_mode == DFA_TC_AUTO && !seg && !res.tc_used && !tc_failed,
+                                c.profiling);
     }
     res.k_eff = k_eff;
     uint32_t rounds_run = res.ctl.round;
@@ -742,6 +772,9 @@ int refine_leader(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t c
             res.tc_levels = levels;
             res.plain_rounds = res.ctl.round;
         }
+        if (!o.chunk)
+            chunk = grown_chunk(chunk, o.tc_mode == DFA_TC_AUTO && !res.tc_used && !tc_failed,
+                                c.profiling);
     }
     res.k_eff = k_eff;
     res.final_block = c.blockA.as<uint32_t>();
@@ -771,13 +804,15 @@ void fill_stats(dfa_stats *st, const RefineResult &r) {
 
 int check_options(const dfa_options &o) {
     if (o.tc_mode < DFA_TC_OFF || o.tc_mode > DFA_TC_AUTO) return fail(DFA_EINVAL, "bad tc_mode");
-    if (o.loop_mode < DFA_LOOP_HOST || o.loop_mode > DFA_LOOP_GRAPH)
+    if (o.loop_mode < DFA_LOOP_HOST || o.loop_mode > DFA_LOOP_PERSISTENT)
         return fail(DFA_EINVAL, "bad loop_mode");
     if (o.lds_stage < 0 || o.lds_stage > 2) return fail(DFA_EINVAL, "bad lds_stage");
     if (o.algorithm != DFA_ALGO_SIGNATURE && o.algorithm != DFA_ALGO_LEADER &&
         o.algorithm != DFA_ALGO_SORT)
         return fail(DFA_EINVAL, "bad algorithm");
     if (o.prune != 0 && o.prune != 1) return fail(DFA_EINVAL, "bad prune");
+    if (o.loop_mode == DFA_LOOP_PERSISTENT && o.algorithm == DFA_ALGO_SORT)
+        return fail(DFA_EINVAL, "the persistent loop groups with the hash table (not with sort)");
     return DFA_OK;
 }
 
@@ -786,6 +821,8 @@ int check_batch_options(const dfa_options &o) {
     if (o.algorithm != DFA_ALGO_SIGNATURE)
         return fail(DFA_EINVAL, "batched calls run signature rounds only");
     if (o.prune) return fail(DFA_EINVAL, "batched calls partition every state (prune = 0)");
+    if (o.loop_mode == DFA_LOOP_PERSISTENT)
+        return fail(DFA_EINVAL, "batched calls run host, chunk or graph loops");
     return DFA_OK;
 }
 
@@ -1485,8 +1522,10 @@ void release_ctx(Ctx &c) {
         b->p = nullptr;
         b->cap = 0;
     }
-    if (c.graph) (void)hipGraphExecDestroy(c.graph);
-    c.graph = nullptr;
+    for (hipGraphExec_t &g : c.graphs) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     for (hipEvent_t e : c.evpool) (void)hipEventDestroy(e);
     c.evpool.clear();
     if (c.ev_start) (void)hipEventDestroy(c.ev_start);

@@ -189,6 +189,11 @@ void launch_sort_group(const RoundArgs &a, hipStream_t s);
 // One round: marking of the blocks to refine, signatures, grouping, the
 // round end.
 void launch_round(const RoundArgs &a, hipStream_t s);
+// Up to `rounds` rounds (table grouping, one DFA) in one cooperative launch
+// of at most as many workgroups as fit on the device together; stops early
+// once the partition is stable.  hipErrorInvalidValue for segmented or
+// sort-grouped rounds.
+hipError_t launch_rounds_persistent(const RoundArgs &a, uint32_t rounds, hipStream_t s);
 // The marking kernel alone (also clears the table every kEpochs rounds).
 void launch_mark(const RoundArgs &a, hipStream_t s);
 // The next round refines every state of a multi-state block (used after the
@@ -236,6 +241,9 @@ void launch_leader_init(const unsigned long long *accbits, size_t N, uint32_t *l
                         uint32_t *block, hipStream_t s);
 // One round (elect, move, end); the three launches separately for timing.
 void launch_leader_round(const LeaderArgs &a, hipStream_t s);
+// Up to `rounds` leader rounds in one cooperative launch (co-resident grid);
+// stops early once no state moves.
+hipError_t launch_leader_persistent(const LeaderArgs &a, uint32_t rounds, hipStream_t s);
 void launch_leader_elect(const LeaderArgs &a, hipStream_t s);
 void launch_leader_move(const LeaderArgs &a, hipStream_t s);
 void launch_leader_end(const LeaderArgs &a, hipStream_t s);

@@ -27,6 +27,8 @@
 //                   equivalence split; the round budget).
 // A leader never differs from itself, so states with block[q] == q (among
 // them every singleton block) cost one coalesced read per round.
+#include <hip/hip_cooperative_groups.h>
+
 #include "device_common.h"
 
 namespace dfamin {
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_leader_blocks(const unsigned long lo
         block[q] = ((accbits[q >> 6] >> (q & 63)) & 1ull) ? lf : lr;
 }
 
-__global__ __launch_bounds__(kBlock) void k_leader_elect(LeaderArgs a) {
+__device__ __forceinline__ void leader_elect_body(const LeaderArgs &a) {
     __shared__ uint32_t ckey[kElectSlots];
     __shared__ uint32_t cmin[kElectSlots];
     if (a.ctl->done) return;
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_leader_elect(LeaderArgs a) {
     wg_add_spread(a.counters, 2, processed);
 }
 
-__global__ __launch_bounds__(kBlock) void k_leader_move(LeaderArgs a) {
+__device__ __forceinline__ void leader_move_body(const LeaderArgs &a) {
     if (a.ctl->done) return;
     const size_t N = a.N;
     uint32_t fresh = 0, moved = 0;
@@ -170,8 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_leader_move(LeaderArgs a) {
     wg_add_spread(a.counters, 1, moved);
 }
 
-__global__ __launch_bounds__(kBlock) void k_leader_end(RoundCtl *ctl, const uint32_t *block,
-                                                       uint32_t *counters) {
+__device__ __forceinline__ void leader_end_body(RoundCtl *ctl, const uint32_t *block,
+                                                uint32_t *counters) {
     __shared__ uint32_t red[3][kBlock / 64];
     if (ctl->done) return;
     uint32_t v[3] = {0, 0, 0};
@@ -217,7 +219,48 @@ __global__ __launch_bounds__(kBlock) void k_leader_end(RoundCtl *ctl, const uint
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_leader_elect(LeaderArgs a) { leader_elect_body(a); }
+
+__global__ __launch_bounds__(kBlock) void k_leader_move(LeaderArgs a) { leader_move_body(a); }
+
+__global__ __launch_bounds__(kBlock) void k_leader_end(RoundCtl *ctl, const uint32_t *block,
+                                                       uint32_t *counters) {
+    leader_end_body(ctl, block, counters);
+}
+
+// Persistent loop of leader rounds: the three phases of a round separated by
+// grid barriers inside one cooperative launch (the stop flag is read right
+// after a barrier and written only by the last phase, so every workgroup
+// takes the same barriers).
+__global__ __launch_bounds__(kBlock) void k_leader_persistent(LeaderArgs a, uint32_t rounds) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (uint32_t i = 0; i < rounds; ++i) {
+        if (__hip_atomic_load(&a.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        leader_elect_body(a);
+        grid.sync();
+        leader_move_body(a);
+        grid.sync();
+        if (blockIdx.x == 0) leader_end_body(a.ctl, a.block, a.counters);
+        grid.sync();
+    }
+}
+
 }  // namespace
+
+hipError_t launch_leader_persistent(const LeaderArgs &a, uint32_t rounds, hipStream_t s) {
+    const void *kernel = reinterpret_cast<const void *>(&k_leader_persistent);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
+    if (e != hipSuccess) return e;
+    if (cus <= 0 || per_cu <= 0) return hipErrorInvalidConfiguration;
+    const unsigned grid =
+        std::min(leader_grid(a.N), static_cast<unsigned>(cus) * static_cast<unsigned>(per_cu));
+    LeaderArgs args_a = a;
+    void *args[] = {&args_a, &rounds};
+    return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
+}
 
 void launch_leader_init(const unsigned long long *accbits, size_t N, uint32_t *lead,
                         uint32_t *block, hipStream_t s) {

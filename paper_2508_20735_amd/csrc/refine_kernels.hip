@@ -30,6 +30,8 @@
 // member states chosen by the hardware's atomic order; the final partition
 // is renumbered canonically (smallest state of each block) once, by
 // k_canon_min / k_canon_apply.
+#include <hip/hip_cooperative_groups.h>
+
 #include "device_common.h"
 
 namespace dfamin {
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
 // successor changed id in the last round.  It also clears the touched bitmap
 // of the next round.
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
+__device__ __forceinline__ void mark_body(const SigParams &p) {
     if (p.ctl->done) return;
     const uint32_t r = p.ctl->round;
     // the table is cleared every kEpochs rounds (its entries carry the epoch)
@@ -510,7 +512,7 @@ __device__ __forceinline__ void emit_key(const SigParams &p, uint32_t *__restric
 // thread);
 // KC == 0: runtime k_eff, gathers issued in batches of 8.
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
+__device__ __forceinline__ void signature_body(const SigParams &p) {
     if (p.ctl->done) return;
     const uint32_t r = p.ctl->round;
     const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
@@ -673,7 +675,7 @@ __device__ __forceinline__ bool stage_in_lds(const InsParams &p) {
 // Counter words: [0] blocks after the round, [1] states not refined,
 // [2] states whose id changed, [3] blocks formed by claims.  The signature
 // kernel adds the unrefined block holders and its own claims.
-__global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
+__device__ __forceinline__ void insert_body(const InsParams &p) {
     if (p.ctl->done || stage_in_lds(p)) return;
     const uint32_t r = p.ctl->round;
     const uint32_t epoch = r % kEpochs + 1;
@@ -725,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_insert(InsParams p) {
 // first state of each local group goes to the HBM table; the others copy its
 // result through LDS.
 
-__global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
+__device__ __forceinline__ void insert_lds_body(const InsParams &p) {
     __shared__ unsigned long long ltab[kLdsSlots];
     __shared__ uint32_t gid[kBlock];
     __shared__ uint32_t lsize[kBlock];
@@ -820,9 +822,9 @@ __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) {
 
 // One workgroup: the round's block count (spread counters), the stop tests,
 // and the counter reset.
-__global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint32_t *blockA,
-                                                       const uint32_t *blockB, uint32_t *counters,
-                                                       uint32_t N) {
+__device__ __forceinline__ void round_end_body(RoundCtl *ctl, const uint32_t *blockA,
+                                               const uint32_t *blockB, uint32_t *counters,
+                                               uint32_t N) {
     constexpr int kWords = 4;  // blocks, idle states, changed ids, claims
     __shared__ uint32_t red[kWords][kBlock / 64];
     if (ctl->done) return;
@@ -868,6 +870,54 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint3
     if (!ctl->done && ctl->max_rounds && r + 1 >= ctl->max_rounds) {
         ctl->limit = 1;
         ctl->done = 1;
+    }
+}
+
+// The round kernels: one launch per phase (host, chunk and graph loops).
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_mark(SigParams p) {
+    mark_body<KC>(p);
+}
+
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
+    signature_body<KC>(p);
+}
+
+__global__ __launch_bounds__(kBlock) void k_insert(InsParams p) { insert_body(p); }
+
+__global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) { insert_lds_body(p); }
+
+__global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint32_t *blockA,
+                                                       const uint32_t *blockB, uint32_t *counters,
+                                                       uint32_t N) {
+    round_end_body(ctl, blockA, blockB, counters, N);
+}
+
+// Persistent loop: up to `rounds` rounds inside one cooperative launch, the
+// phases of a round separated by grid barriers instead of kernel boundaries
+// (the barrier's release and acquire make each phase's writes visible to
+// every workgroup, on every XCD, before the next phase reads them).  Every
+// workgroup takes the same barriers: the stop flag is read right after a
+// barrier and written only by the round's last phase, between two barriers.
+// The grid must fit on the device at once (the cooperative launch refuses
+// more workgroups than can be resident together).
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_rounds_persistent(SigParams sp, InsParams ip,
+                                                               RoundCtl *ctl, uint32_t rounds) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (uint32_t i = 0; i < rounds; ++i) {
+        if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        mark_body<KC>(sp);
+        grid.sync();
+        signature_body<KC>(sp);
+        grid.sync();
+        insert_lds_body(ip);
+        insert_body(ip);
+        grid.sync();
+        if (blockIdx.x == 0)
+            round_end_body(ctl, ip.blockA, ip.blockB, ip.counters, static_cast<uint32_t>(ip.N));
+        grid.sync();
     }
 }
 
@@ -1192,6 +1242,24 @@ unsigned round_grid(const RoundArgs &a, unsigned cap) {
     return grid_for(a.N, cap ? cap : (1u << 30));
 }
 
+InsParams ins_params(const RoundArgs &a) {
+    return InsParams{a.sig,    a.hash,   a.N,     a.k_eff + 1, a.table,    a.table_cap - 1,
+                     a.blockA, a.blockB, a.multi, a.active,    a.counters, a.ctl,
+                     a.cached_probe, a.lds_stage, a.chg};
+}
+
+// Workgroups of `kernel` that fit on the current device at once.
+hipError_t coresident_grid(const void *kernel, unsigned &grid) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
+    if (e != hipSuccess) return e;
+    if (cus <= 0 || per_cu <= 0) return hipErrorInvalidConfiguration;
+    grid = static_cast<unsigned>(cus) * static_cast<unsigned>(per_cu);
+    return hipSuccess;
+}
+
 }  // namespace
 
 void launch_ingest(const uint32_t *delta, uint32_t n, uint32_t k, uint32_t *cols, size_t N,
@@ -1307,9 +1375,7 @@ void launch_signature(const RoundArgs &a, hipStream_t s) {
 
 void launch_insert(const RoundArgs &a, hipStream_t s) {
     const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
-    const InsParams ip{a.sig,    a.hash,   a.N,     a.k_eff + 1, a.table,    a.table_cap - 1,
-                       a.blockA, a.blockB, a.multi, a.active,    a.counters, a.ctl,
-                       a.cached_probe, a.lds_stage, a.chg};
+    const InsParams ip = ins_params(a);
     // the two grouping variants; exactly one of them works in a given round
     // (lds_stage 2 decides on the device from the previous round)
     if (a.lds_stage != 0) hipLaunchKernelGGL(k_insert_lds, grid, block, 0, s, ip);
@@ -1343,6 +1409,28 @@ void launch_round(const RoundArgs &a, hipStream_t s) {
         launch_insert(a, s);
     if (a.seg.nseg) launch_seg_round(a, s);
     launch_round_end(a, s);
+}
+
+hipError_t launch_rounds_persistent(const RoundArgs &a, uint32_t rounds, hipStream_t s) {
+    if (a.seg.nseg || a.grouping) return hipErrorInvalidValue;
+    const void *kernel;
+    switch (a.k_eff) {
+        case 1: kernel = reinterpret_cast<const void *>(&k_rounds_persistent<1>); break;
+        case 2: kernel = reinterpret_cast<const void *>(&k_rounds_persistent<2>); break;
+        case 3: kernel = reinterpret_cast<const void *>(&k_rounds_persistent<3>); break;
+        case 4: kernel = reinterpret_cast<const void *>(&k_rounds_persistent<4>); break;
+        case 8: kernel = reinterpret_cast<const void *>(&k_rounds_persistent<8>); break;
+        default: kernel = reinterpret_cast<const void *>(&k_rounds_persistent<0>); break;
+    }
+    unsigned fit = 0;
+    hipError_t e = coresident_grid(kernel, fit);
+    if (e != hipSuccess) return e;
+    const unsigned grid = std::min(round_grid(a, a.round_grid_cap), fit);
+    SigParams sp = sig_params(a);
+    InsParams ip = ins_params(a);
+    RoundCtl *ctl = a.ctl;
+    void *args[] = {&sp, &ip, &ctl, &rounds};
+    return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t *diff,

@@ -118,16 +118,15 @@ def bitsplitter(n: int) -> DFA:
     if n < 2:
         raise ValueError("bit-splitters need n >= 2 (B_1 has no letters)")
     N = 1 << n
-    s = np.arange(N, dtype=np.int64)
-    cols = []
+    s = np.arange(N, dtype=np.uint32)
+    delta = np.empty((N, n - 1), dtype=np.uint32)
     for j in range(1, n):
-        b = (s >> j) & 1
-        lead = (s >> (j - 1)) & 1
-        high = (s >> (j + 1)) << (j + 1)
-        moved = high | ((1 - b) << j)
-        cols.append(np.where(lead == 1, moved, s))
-    delta = np.stack(cols, axis=1).astype(np.uint32)
-    acc = ((s >> (n - 1)) & 1).astype(np.uint8)
+        # moved = high bits kept, bit j inverted, bits below j cleared
+        moved = (s >> np.uint32(j + 1)) << np.uint32(j + 1)
+        moved |= (~(s >> np.uint32(j)) & np.uint32(1)) << np.uint32(j)
+        lead = (s >> np.uint32(j - 1)) & np.uint32(1)
+        delta[:, j - 1] = np.where(lead == 1, moved, s)
+    acc = ((s >> np.uint32(n - 1)) & np.uint32(1)).astype(np.uint8)
     return DFA(delta, acc, 0)
 
 
