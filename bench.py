@@ -213,12 +213,14 @@ PAPER_TABLE2_MS = {
 def table2_leg(B, W, torch, np, dev) -> dict:
     """The paper's Table 2 families on this GPU: leader rounds (naivePR),
     signature rounds grouped by hashing and by sorting (sortPR's semantics),
-    transPR (closure + naivePR) and the closure on demand.  Device time with
-    the input resident, median of 3 runs after one warm-up."""
+    transPR (closure + naivePR), signature rounds over the closure letters,
+    and the closure on demand.  Device time with the input resident, median
+    of 3 runs after one warm-up."""
     runs = {
         "Fib20": (lambda: W.fibonacci(21),
                   [("naivePR", "leader", "off"), ("signature", "signature", "off"),
-                   ("transPR", "leader", "on"), ("signature_tc_auto", "signature", "auto")]),
+                   ("transPR", "leader", "on"), ("signature_tc_on", "signature", "on"),
+                   ("signature_tc_auto", "signature", "auto")]),
         "B20": (lambda: W.bitsplitter(20),
                 [("naivePR", "leader", "off"), ("signature", "signature", "off"),
                  ("sort", "sort", "off"), ("transPR", "leader", "on")]),

@@ -38,6 +38,7 @@ constexpr int kSpread = 64;        // per-round counters, one per 128-byte line
 constexpr int kSpreadStride = 32;  // uint32 words between two counters
 constexpr uint32_t kPatternMaxBits = 16;  // first round by bit patterns if k_eff + 1 <= 16
 constexpr uint32_t kPackedMaxBits = 25;   // round 1 by packed labels if (k_eff + 1)^2 <= 25
+constexpr uint32_t kPersistentGroupsPerCu = 1;  // workgroups per CU in the persistent loops
 constexpr uint32_t kActiveHist = 64;      // rounds of refined-state counts kept in RoundCtl
 
 // Round-loop state kept on the device so that rounds can be enqueued (or

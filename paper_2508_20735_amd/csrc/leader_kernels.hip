@@ -255,8 +255,11 @@ hipError_t launch_leader_persistent(const LeaderArgs &a, uint32_t rounds, hipStr
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
     if (e != hipSuccess) return e;
     if (cus <= 0 || per_cu <= 0) return hipErrorInvalidConfiguration;
-    const unsigned grid =
-        std::min(leader_grid(a.N), static_cast<unsigned>(cus) * static_cast<unsigned>(per_cu));
+    // at most one workgroup per CU: a grid barrier's cost grows with the
+    // workgroups that arrive at it
+    const unsigned fit = static_cast<unsigned>(cus) *
+                         std::min(static_cast<unsigned>(per_cu), kPersistentGroupsPerCu);
+    const unsigned grid = std::min(leader_grid(a.N), fit);
     LeaderArgs args_a = a;
     void *args[] = {&args_a, &rounds};
     return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);

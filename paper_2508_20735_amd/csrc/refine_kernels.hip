@@ -1248,7 +1248,7 @@ InsParams ins_params(const RoundArgs &a) {
                      a.cached_probe, a.lds_stage, a.chg};
 }
 
-// Workgroups of `kernel` that fit on the current device at once.
+// Workgroups of the persistent loop: no more than fit on the device at once.
 hipError_t coresident_grid(const void *kernel, unsigned &grid) {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1256,7 +1256,9 @@ hipError_t coresident_grid(const void *kernel, unsigned &grid) {
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
     if (e != hipSuccess) return e;
     if (cus <= 0 || per_cu <= 0) return hipErrorInvalidConfiguration;
-    grid = static_cast<unsigned>(cus) * static_cast<unsigned>(per_cu);
+    // at most one workgroup per CU: a grid barrier's cost grows with the
+    // workgroups that arrive at it
+    grid = static_cast<unsigned>(cus) * std::min(static_cast<unsigned>(per_cu), kPersistentGroupsPerCu);
     return hipSuccess;
 }
 
