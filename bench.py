@@ -62,6 +62,8 @@ def parse_args():
                     help="skip the comparison of grouping / refinement variants")
     ap.add_argument("--no-table2", action="store_true",
                     help="skip the runs on the paper's Table 2 families")
+    ap.add_argument("--no-products", action="store_true",
+                    help="skip the product explorations (Tables 4 and 5 families)")
     return ap.parse_args()
 
 
@@ -245,6 +247,52 @@ def table2_leg(B, W, torch, np, dev) -> dict:
                           "rounds": sts[-1]["rounds"], "num_blocks": sts[-1]["num_blocks"]}
         out[name] = row
         del delta, acc, blk
+    return out
+
+
+# Tables 4 and 5 of the paper: exploration time (ms) of the product on an
+# RTX 3090 and a Titan RTX (initialisation excluded): context only.
+PAPER_PRODUCT_MS = {
+    "memory20_incl": (117, 173), "memory22_incl": (309, 420), "memory24_incl": (1269, 1481),
+    "Bext20_self": (130, 302), "C30_self": (239, 271), "C32_self": (556, 553),
+}
+
+
+def product_leg(B, W, torch, np, dev) -> dict:
+    """Product exploration (Section 4): inclusion of forgetful memory_n in
+    perfect memory_n (Table 5) and equivalence of B'_n and C_n with
+    themselves by product exploration (Table 4).  Device time with the inputs
+    resident, median of 3 runs after one warm-up; pairs = reached pairs."""
+    def t(x):
+        x = np.ascontiguousarray(x)
+        return torch.from_numpy(x.view(np.int32) if x.dtype == np.uint32 else x).to(dev)
+
+    runs = [("memory20_incl", lambda: (W.memory(20, True), W.memory(20, False)), "incl"),
+            ("memory22_incl", lambda: (W.memory(22, True), W.memory(22, False)), "incl"),
+            ("memory24_incl", lambda: (W.memory(24, True), W.memory(24, False)), "incl"),
+            ("Bext20_self", lambda: (W.extended_bitsplitter(20),) * 2, "equiv"),
+            ("C30_self", lambda: (W.cycle(30),) * 2, "equiv"),
+            ("C32_self", lambda: (W.cycle(32),) * 2, "equiv")]
+    out = {}
+    for name, make, kind in runs:
+        a, b = make()
+        args = (t(a.delta), t(a.accepting), a.start, t(b.delta), t(b.accepting), b.start)
+
+        def once():
+            if kind == "incl":
+                ok, pairs, st = B.included_device(*args)
+            else:
+                ok, st = B.equivalent_device(*args, method="product")
+                pairs = st["reachable"]
+            return ok, pairs, st
+        once()
+        res = [once() for _ in range(3)]
+        ms = float(np.median([r[2]["device_ms"] for r in res]))
+        ok, pairs, st = res[-1]
+        out[name] = {"verdict": ok, "pairs": pairs, "levels": st["rounds"], "ms": ms,
+                     "pairs_per_s": pairs / (ms * 1e-3),
+                     "paper_exploration_ms_rtx3090_titanrtx": PAPER_PRODUCT_MS[name]}
+        del args
     return out
 
 
@@ -436,6 +484,8 @@ def main() -> int:
         out["variants"] = variants_leg(B, W, torch, np, dev, A_d, A_a, d.n)
     if not args.no_table2:
         out["table2"] = table2_leg(B, W, torch, np, dev)
+    if not args.no_products:
+        out["products"] = product_leg(B, W, torch, np, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, perm)
     print(json.dumps(out), flush=True)

@@ -115,8 +115,18 @@ typedef struct dfa_options {
                              DFA_UNREACHABLE for the others, ids are the smallest
                              reachable state of each block, and the quotient is the usual
                              minimal DFA.  The batched calls and the server accept only 0 */
-    int32_t reserved[2];
+    int32_t equiv_method; /* dfa_equivalent only: DFA_EQ_UNION (default) refines the
+                             disjoint union; DFA_EQ_PRODUCT explores the synchronous
+                             product breadth-first from (start_a, start_b) and stops at
+                             the first pair with exactly one accepting side (Section 4's
+                             Hopcroft-Karp over the plain set of reached pairs; the
+                             refinement options are then ignored).  The batched calls
+                             and the server accept only DFA_EQ_UNION */
+    int32_t reserved;
 } dfa_options;
+
+#define DFA_EQ_UNION 0
+#define DFA_EQ_PRODUCT 1
 
 #define DFA_UNREACHABLE 0xFFFFFFFFu /* block_out value of a pruned state */
 
@@ -129,7 +139,10 @@ typedef struct dfa_stats {
     uint32_t tc_used;         /* 1 if the closure letters were built */
     uint32_t tc_levels;       /* floor(log2 n) when tc_used */
     uint32_t plain_rounds;    /* rounds run on the input letters before switching to the closure */
-    uint32_t reachable;       /* states partitioned: n, or the reachable ones with prune */
+    uint32_t reachable;       /* states partitioned: n, or the reachable ones with prune;
+                                 product exploration (dfa_included, DFA_EQ_PRODUCT): the
+                                 pairs visited, saturating at 2^32 - 1, with `rounds` =
+                                 the breadth-first levels expanded */
     double h2d_ms;            /* host-pointer calls: copy of the inputs */
     double device_ms;         /* device work of the call (HIP events) */
     double d2h_ms;            /* host-pointer calls: copy of the results */

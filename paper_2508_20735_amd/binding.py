@@ -35,6 +35,8 @@ LOOP = {"host": 0, "chunk": 1, "graph": 2, "persistent": 3}
 UNREACHABLE = 0xFFFFFFFF
 # signature rounds (sortPR semantics, hashed) or leader rounds (naivePR)
 ALGO = {"signature": 0, "leader": 1, "sort": 2}
+# equivalence by refining the disjoint union, or by exploring the product
+EQ = {"union": 0, "product": 1}
 
 
 class DfaError(RuntimeError):
@@ -48,7 +50,7 @@ class Options(ctypes.Structure):
                 ("start", ctypes.c_uint32), ("max_rounds", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("lds_stage", ctypes.c_int32),
                 ("algorithm", ctypes.c_int32), ("prune", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("equiv_method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -233,7 +235,7 @@ def _check(rc: int, allow=()) -> int:
 
 def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: int = 0,
             chunk: int = 0, lds_stage=2, algorithm: str = "signature",
-            prune: bool = False) -> Options:
+            prune: bool = False, method: str = "union") -> Options:
     o = Options()
     load().dfa_options_default(ctypes.byref(o))
     o.tc_mode = TC[tc]
@@ -245,6 +247,7 @@ def options(tc: str = "auto", loop: str = "graph", start: int = 0, max_rounds: i
     o.lds_stage = int(lds_stage) if not isinstance(lds_stage, bool) else (1 if lds_stage else 0)
     o.algorithm = ALGO[algorithm]
     o.prune = 1 if prune else 0
+    o.equiv_method = EQ[method]
     return o
 
 
@@ -405,11 +408,14 @@ def _view_device(delta, accepting, start) -> View:
 
 
 def equivalent(A, B, *, tc: str = "auto", loop: str = "graph", max_rounds: int = 0,
-               chunk: int = 0, lds_stage=2, algorithm: str = "signature") -> tuple[bool, dict]:
-    """dfa_equivalent on two host DFAs (objects with delta, accepting, start)."""
+               chunk: int = 0, lds_stage=2, algorithm: str = "signature",
+               method: str = "union") -> tuple[bool, dict]:
+    """dfa_equivalent on two host DFAs (objects with delta, accepting, start).
+    method "union" refines the disjoint union; "product" explores the product
+    (stats: rounds = levels, reachable = pairs visited)."""
     va, keep_a = _view_host(A)
     vb, keep_b = _view_host(B)
-    o = options(tc, loop, 0, max_rounds, chunk, lds_stage, algorithm)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage, algorithm, method=method)
     v = ctypes.c_int()
     st = Stats()
     _check(load().dfa_equivalent(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
@@ -419,10 +425,11 @@ def equivalent(A, B, *, tc: str = "auto", loop: str = "graph", max_rounds: int =
 
 def equivalent_device(dA, accA, sA, dB, accB, sB, *, tc: str = "auto", loop: str = "graph",
                       max_rounds: int = 0, chunk: int = 0, lds_stage=2,
-                      stream=None, algorithm: str = "signature") -> tuple[bool, dict]:
+                      stream=None, algorithm: str = "signature",
+                      method: str = "union") -> tuple[bool, dict]:
     va = _view_device(dA, accA, sA)
     vb = _view_device(dB, accB, sB)
-    o = options(tc, loop, 0, max_rounds, chunk, lds_stage, algorithm)
+    o = options(tc, loop, 0, max_rounds, chunk, lds_stage, algorithm, method=method)
     v = ctypes.c_int()
     st = Stats()
     _check(load().dfa_equivalent_device(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),

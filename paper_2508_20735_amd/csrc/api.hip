@@ -811,6 +811,8 @@ int check_options(const dfa_options &o) {
         o.algorithm != DFA_ALGO_SORT)
         return fail(DFA_EINVAL, "bad algorithm");
     if (o.prune != 0 && o.prune != 1) return fail(DFA_EINVAL, "bad prune");
+    if (o.equiv_method != DFA_EQ_UNION && o.equiv_method != DFA_EQ_PRODUCT)
+        return fail(DFA_EINVAL, "bad equiv_method");
     if (o.loop_mode == DFA_LOOP_PERSISTENT && o.algorithm == DFA_ALGO_SORT)
         return fail(DFA_EINVAL, "the persistent loop groups with the hash table (not with sort)");
     return DFA_OK;
@@ -823,6 +825,8 @@ int check_batch_options(const dfa_options &o) {
     if (o.prune) return fail(DFA_EINVAL, "batched calls partition every state (prune = 0)");
     if (o.loop_mode == DFA_LOOP_PERSISTENT)
         return fail(DFA_EINVAL, "batched calls run host, chunk or graph loops");
+    if (o.equiv_method != DFA_EQ_UNION)
+        return fail(DFA_EINVAL, "batched equivalence refines unions (equiv_method = DFA_EQ_UNION)");
     return DFA_OK;
 }
 
@@ -1009,8 +1013,12 @@ int minimise_pruned(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const
     return rc;
 }
 
+int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, uint64_t *visited,
+                  dfa_stats *st, int mode);
+
 int equivalent_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict,
                     const dfa_options &o, dfa_stats *st) {
+    if (o.equiv_method == DFA_EQ_PRODUCT) return included_impl(c, a, b, verdict, nullptr, st, 1);
     const size_t N = static_cast<size_t>(a.n) + b.n;
     if (N >= 0xFFFFFFFFull) return fail(DFA_EINVAL, "nA + nB must be < 2^32 - 1");
     const uint32_t k = a.k;
@@ -1048,8 +1056,11 @@ int equivalent_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict,
     return DFA_OK;
 }
 
+// Breadth-first exploration of the synchronous product from (start_a,
+// start_b), one level per launch.  mode 0: inclusion (refuted by p accepting,
+// q rejecting); mode 1: equivalence (refuted by exactly one accepting side).
 int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, uint64_t *visited,
-                  dfa_stats *st) {
+                  dfa_stats *st, int mode = 0) {
     const uint32_t k = a.k;
     // reuse the flag buffer for the target checks (no refinement here)
     DFA_TRY(c.flags.ensure((kFlagNonid + k) * sizeof(uint32_t), "flags"));
@@ -1077,8 +1088,10 @@ int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, ui
     uint32_t *sc = c.scalars.as<uint32_t>();
     Buffer *cur = &c.front0, *nxt = &c.front1;
     uint64_t count = 1, fsize = 1;
+    uint32_t levels = 0;
     int v = 1;
     while (fsize > 0) {
+        ++levels;
         const uint64_t need = fsize * k;
         if (need >= 0xFFFFFFFFull) return fail(DFA_ENOMEM, "frontier too large");
         DFA_TRY(nxt->ensure(need * sizeof(unsigned long long), "frontier"));
@@ -1092,7 +1105,7 @@ int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, ui
             cap = ncap;
         }
         HIP_TRY(hipMemsetAsync(sc, 0, 3 * sizeof(uint32_t), c.stream));
-        ProductArgs pa{a.delta, b.delta, a.accepting, b.accepting, k, 0,
+        ProductArgs pa{a.delta, b.delta, a.accepting, b.accepting, k, mode,
                        cur->as<unsigned long long>(), static_cast<uint32_t>(fsize),
                        nxt->as<unsigned long long>(), static_cast<uint32_t>(need), sc,
                        c.visited.as<unsigned long long>(), cap, sc + 1, sc + 2};
@@ -1117,6 +1130,8 @@ int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, ui
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
         st->device_ms = ms;
+        st->rounds = levels;
+        st->reachable = static_cast<uint32_t>(std::min<uint64_t>(count, 0xFFFFFFFFull));
     }
     return DFA_OK;
 }

@@ -41,6 +41,8 @@ def test_default_options(lib):
     lib.dfa_options_default(ctypes.byref(o))
     assert o.tc_mode == B.TC["auto"] and o.loop_mode == B.LOOP["graph"]
     assert o.start == 0 and o.max_rounds == 0 and o.lds_stage == 2
+    assert o.algorithm == B.ALGO["signature"] and o.prune == 0
+    assert o.equiv_method == B.EQ["union"]
 
 
 def test_struct_sizes_match_header():
@@ -123,3 +125,14 @@ def test_bad_arguments_rejected_on_host(lib):
     o.loop_mode = 4
     assert lib.dfa_minimise(4, 2, d.ctypes.data, a.ctypes.data, out.ctypes.data, None,
                             ctypes.byref(o), None) == B.DFA_EINVAL
+    # equivalence by product exploration: single pairs only
+    o.loop_mode = B.LOOP["graph"]
+    o.equiv_method = 7
+    assert lib.dfa_equivalent(ctypes.byref(va), ctypes.byref(vb), ctypes.byref(v),
+                              ctypes.byref(o), None) == B.DFA_EINVAL
+    assert b"equiv_method" in lib.dfa_last_error()
+    o.equiv_method = B.EQ["product"]
+    verdicts = np.zeros(1, dtype=np.int32)
+    assert lib.dfa_equivalent_batch(1, ctypes.byref(va), ctypes.byref(vb), verdicts.ctypes.data,
+                                    ctypes.byref(o), None) == B.DFA_EINVAL
+    assert b"DFA_EQ_UNION" in lib.dfa_last_error()

@@ -239,6 +239,73 @@ def test_equivalence_families():
     assert not B.equivalent(F, P)[0]
 
 
+# ------------------------------------------- equivalence by product exploration
+
+def test_product_equivalence_tiny_random_pairs():
+    """method="product": the breadth-first pair exploration of Section 4 with
+    the equivalence test (exactly one accepting side).  Verdicts match the
+    oracle's exploration; when equivalent, so does the number of pairs."""
+    rng = np.random.default_rng(17)
+    seen = {True: 0, False: 0}
+    for _ in range(300):
+        nA, nB, k = int(rng.integers(1, 6)), int(rng.integers(1, 6)), int(rng.integers(1, 3))
+        A = W.DFA(rng.integers(0, nA, (nA, k)).astype(np.uint32),
+                  rng.integers(0, 2, nA).astype(np.uint8), int(rng.integers(0, nA)))
+        Bd = W.DFA(rng.integers(0, nB, (nB, k)).astype(np.uint32),
+                   rng.integers(0, 2, nB).astype(np.uint8), int(rng.integers(0, nB)))
+        ref, ref_pairs = oracle.product_bfs(A.delta, A.accepting, A.start, Bd.delta,
+                                            Bd.accepting, Bd.start, "equivalence")
+        got, st = B.equivalent(A, Bd, method="product")
+        assert got == ref
+        assert got == oracle.equiv_hk(A.delta, A.accepting, A.start, Bd.delta, Bd.accepting,
+                                      Bd.start)
+        if ref:
+            assert st["reachable"] == ref_pairs
+        seen[ref] += 1
+    assert seen[True] > 10 and seen[False] > 10
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_product_equivalence_permuted_and_mutated(seed):
+    d = W.random_dfa(20000 + 1111 * seed, 2 + seed, 0.2, seed)
+    perm, _ = W.permuted_copy(d, seed + 10)
+    mut, _ = W.mutate_one(d, seed + 20)
+    got, st = B.equivalent(d, perm, method="product")
+    ok, pairs = oracle.product_bfs(d.delta, d.accepting, d.start, perm.delta, perm.accepting,
+                                   perm.start, "equivalence")
+    assert got and ok and st["reachable"] == pairs and st["rounds"] >= 1
+    expect = oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting, mut.start)
+    assert B.equivalent(d, mut, method="product")[0] == expect
+    assert B.equivalent(d, mut, method="union")[0] == expect
+
+
+def test_product_equivalence_families():
+    """Table 4: a DFA against itself explores 2^(n+1) pairs for B'_n and
+    fib(n) pairs for C_n; memory_n forgetful and perfect differ."""
+    d = W.extended_bitsplitter(10)
+    ok, st = B.equivalent(d, d, method="product")
+    assert ok and st["reachable"] == 2 ** 11
+    c = W.cycle(20)
+    ok, st = B.equivalent(c, c, method="product")
+    assert ok and st["reachable"] == W.fib_numbers(20)
+    F, P = W.memory(9, True), W.memory(9, False)
+    assert not B.equivalent(F, P, method="product")[0]
+    assert not B.equivalent(P, F, method="product")[0]
+
+
+def test_product_equivalence_device_api():
+    import torch
+    d = W.random_dfa(30000, 3, 0.3, 41)
+    perm, _ = W.permuted_copy(d, 42)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x).view(
+        np.int32 if x.dtype == np.uint32 else np.uint8)).to(dev)
+    got, st = B.equivalent_device(t(d.delta), t(d.accepting), d.start, t(perm.delta),
+                                  t(perm.accepting), perm.start, method="product")
+    # the reached pairs are (q, pi(q)) for the states q reachable from the start
+    assert got and st["reachable"] == int(np.count_nonzero(oracle.reachable(d.delta, d.start)))
+
+
 # ---------------------------------------------------------------- inclusion
 
 @pytest.mark.parametrize("n", [3, 5, 9, 12])
