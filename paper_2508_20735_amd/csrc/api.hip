@@ -1082,7 +1082,9 @@ int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, ui
     launch_visited_clear(c.visited.as<unsigned long long>(), cap, c.stream);
     const unsigned long long start = (static_cast<unsigned long long>(a.start) << 32) | b.start;
     launch_visited_insert_start(c.visited.as<unsigned long long>(), cap, start, c.stream);
-    DFA_TRY(c.front0.ensure(sizeof(unsigned long long), "frontier"));
+    // both frontier buffers hold at least a narrow launch's frontier
+    DFA_TRY(c.front0.ensure(kProductNarrowCap * sizeof(unsigned long long), "frontier"));
+    DFA_TRY(c.front1.ensure(kProductNarrowCap * sizeof(unsigned long long), "frontier"));
     DFA_TRY(upload(c, c.front0.p, &start, sizeof start));
     DFA_TRY(c.scalars.ensure(16 * sizeof(uint32_t), "scalars"));
     uint32_t *sc = c.scalars.as<uint32_t>();
@@ -1090,7 +1092,38 @@ int included_impl(Ctx &c, const dfa_view &a, const dfa_view &b, int *verdict, ui
     uint64_t count = 1, fsize = 1;
     uint32_t levels = 0;
     int v = 1;
+    // levels per narrow launch: bounds the pairs one launch may add
+    constexpr uint32_t kNarrowLevels = 256;
     while (fsize > 0) {
+        if (fsize * k <= kProductNarrowCap) {
+            // thin frontier: levels expanded inside one workgroup, the set
+            // sized first for every pair the launch may add (at half load)
+            const uint64_t most = count + static_cast<uint64_t>(kNarrowLevels) * kProductNarrowCap;
+            if (most * 2 > cap) {
+                const uint64_t ncap = next_pow2(most * 2);
+                DFA_TRY(c.visited2.ensure(ncap * sizeof(unsigned long long), "visited set"));
+                launch_visited_clear(c.visited2.as<unsigned long long>(), ncap, c.stream);
+                launch_rehash(c.visited.as<unsigned long long>(), cap,
+                              c.visited2.as<unsigned long long>(), ncap, c.stream);
+                std::swap(c.visited, c.visited2);
+                cap = ncap;
+            }
+            HIP_TRY(hipMemsetAsync(sc + 4, 0, 4 * sizeof(uint32_t), c.stream));
+            ProductArgs pa{a.delta, b.delta, a.accepting, b.accepting, k, mode,
+                           cur->as<unsigned long long>(), static_cast<uint32_t>(fsize), nullptr, 0,
+                           nullptr, c.visited.as<unsigned long long>(), cap, nullptr, nullptr};
+            launch_product_narrow(pa, kNarrowLevels, sc + 4, c.stream);
+            HIP_TRY(hipGetLastError());
+            DFA_TRY(read_back(c, sc + 4, 4 * sizeof(uint32_t)));
+            fsize = c.pinned[0];
+            count += c.pinned[1];
+            levels += c.pinned[2];
+            if (c.pinned[3]) {
+                v = 0;
+                break;
+            }
+            continue;
+        }
         ++levels;
         const uint64_t need = fsize * k;
         if (need >= 0xFFFFFFFFull) return fail(DFA_ENOMEM, "frontier too large");

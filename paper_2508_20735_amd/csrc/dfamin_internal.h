@@ -330,6 +330,15 @@ struct ProductArgs {
     uint32_t *overflow;        // set to 1 when `next` overflows
 };
 void launch_product_level(const ProductArgs &a, hipStream_t s);
+// Narrow exploration inside one workgroup (LDS queues of kProductNarrowCap
+// pairs): requires frontier_size * k <= kProductNarrowCap and room in the
+// visited set for max_levels * kProductNarrowCap more pairs at half load;
+// out[0..3] = (frontier size, pairs added, levels, refuted); out[3] must be
+// zero on entry.  The frontier stays in a.frontier.
+constexpr uint32_t kProductNarrowThreads = 1024;
+constexpr uint32_t kProductNarrowCap = 8192;
+void launch_product_narrow(const ProductArgs &a, uint32_t max_levels, uint32_t *out,
+                           hipStream_t s);
 void launch_visited_clear(unsigned long long *visited, uint64_t cap, hipStream_t s);
 void launch_visited_insert_start(unsigned long long *visited, uint64_t cap,
                                  unsigned long long key, hipStream_t s);

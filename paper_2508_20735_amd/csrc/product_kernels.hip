@@ -70,6 +70,70 @@ __global__ __launch_bounds__(kBlock) void k_product_level(ProductArgs a) {
     }
 }
 
+// One workgroup expands levels while the frontier times k fits an LDS queue
+// (long, thin explorations such as C_n's products, where a launch and a host
+// round trip per level would dominate).  Pairs are inserted into the same
+// HBM set as by k_product_level; new pairs go to the other LDS queue.  Stops
+// when the frontier is empty, a refuting pair is expanded, the next
+// frontier could overflow the queue, or after max_levels levels; the
+// remaining frontier is written back to `frontier`, and out[] receives
+// (frontier size, pairs added, levels expanded, refuted).
+__global__ __launch_bounds__(kProductNarrowThreads) void k_product_narrow(ProductArgs a,
+                                                                          uint32_t max_levels,
+                                                                          uint32_t *out) {
+    __shared__ unsigned long long buf[2][kProductNarrowCap];
+    __shared__ uint32_t next_size, refuted;
+    const uint32_t tx = threadIdx.x;
+    const uint64_t mask = a.visited_cap - 1;
+    unsigned long long *frontier = const_cast<unsigned long long *>(a.frontier);
+    uint32_t s = a.frontier_size;
+    if (static_cast<uint64_t>(s) * a.k > kProductNarrowCap) return;  // the host checked; stay safe
+    for (uint32_t i = tx; i < s; i += kProductNarrowThreads) buf[0][i] = frontier[i];
+    if (tx == 0) refuted = 0;
+    uint32_t cur = 0, levels = 0, added = 0;
+    for (;;) {
+        if (s == 0 || levels == max_levels || static_cast<uint64_t>(s) * a.k > kProductNarrowCap) break;
+        if (tx == 0) next_size = 0;
+        __syncthreads();
+        for (uint32_t i = tx; i < s; i += kProductNarrowThreads) {
+            const unsigned long long key = buf[cur][i];
+            const uint32_t p = static_cast<uint32_t>(key >> 32), q = static_cast<uint32_t>(key);
+            const bool fa = a.accA[p] != 0, fb = a.accB[q] != 0;
+            const bool bad = a.mode == 0 ? (fa && !fb) : (fa != fb);
+            if (bad) {
+                refuted = 1;
+                continue;
+            }
+            for (uint32_t c = 0; c < a.k; ++c) {
+                const unsigned long long nk =
+                    (static_cast<unsigned long long>(a.dA[static_cast<size_t>(p) * a.k + c]) << 32) |
+                    a.dB[static_cast<size_t>(q) * a.k + c];
+                // at most s * k fresh pairs <= kProductNarrowCap
+                if (set_insert(a.visited, mask, nk)) buf[cur ^ 1u][atomicAdd(&next_size, 1u)] = nk;
+            }
+        }
+        __syncthreads();
+        ++levels;
+        const uint32_t n = next_size;
+        const bool stop = refuted != 0;
+        __syncthreads();  // every thread has read next_size before it is reset
+        if (stop) {
+            s = 0;
+            if (tx == 0) out[3] = 1;
+            break;
+        }
+        added += n;
+        s = n;
+        cur ^= 1u;
+    }
+    for (uint32_t i = tx; i < s; i += kProductNarrowThreads) frontier[i] = buf[cur][i];
+    if (tx == 0) {
+        out[0] = s;
+        out[1] = added;
+        out[2] = levels;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_visited_clear(unsigned long long *tab, uint64_t cap) {
     for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < cap;
          i += static_cast<size_t>(gridDim.x) * blockDim.x)
@@ -101,6 +165,12 @@ unsigned grid_for(size_t work) {
 
 void launch_product_level(const ProductArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_product_level, dim3(grid_for(a.frontier_size)), dim3(kBlock), 0, s, a);
+}
+
+void launch_product_narrow(const ProductArgs &a, uint32_t max_levels, uint32_t *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_product_narrow, dim3(1), dim3(kProductNarrowThreads), 0, s, a, max_levels,
+                       out);
 }
 
 void launch_visited_clear(unsigned long long *visited, uint64_t cap, hipStream_t s) {

@@ -293,6 +293,47 @@ def test_product_equivalence_families():
     assert not B.equivalent(P, F, method="product")[0]
 
 
+def _bfs_dist(delta, start):
+    """Breadth-first distance of every state from start (-1: unreachable),
+    by a plain level-by-level search."""
+    dist = np.full(delta.shape[0], -1, dtype=np.int64)
+    dist[start] = 0
+    front, depth = np.array([start]), 0
+    while front.size:
+        nxt = np.unique(delta[front].ravel())
+        nxt = nxt[dist[nxt] < 0]
+        depth += 1
+        dist[nxt] = depth
+        front = nxt
+    return dist
+
+
+def test_product_deep_thin_search():
+    """C_25 against itself: 121,393 pairs over more levels than one
+    workgroup-local launch expands (256), a few hundred pairs per level.  The
+    levels expanded are the search depth + 1 (the last level adds nothing)."""
+    c = W.cycle(25)
+    dist = _bfs_dist(c.delta, c.start)
+    depth = int(dist.max())
+    assert depth > 256
+    ok, st = B.equivalent(c, c, method="product")
+    assert ok and st["reachable"] == W.fib_numbers(25) and st["rounds"] == depth + 1
+    ok, pairs, st = B.included(c, c)
+    assert ok and pairs == W.fib_numbers(25) and st["rounds"] == depth + 1
+    # a refuting pair deep in the search: accept, in the copy, one more state
+    # among the farthest from the start
+    other = W.DFA(c.delta, c.accepting.copy(), c.start)
+    far = int(np.flatnonzero((dist == depth) & (c.accepting == 0))[0])
+    other.accepting[far] = 1
+    expect = oracle.equiv_hk(c.delta, c.accepting, c.start, other.delta, other.accepting,
+                             other.start)
+    assert B.equivalent(c, other, method="product")[0] == expect
+    assert B.included(c, other)[0] == oracle.included(c.delta, c.accepting, c.start,
+                                                       other.delta, other.accepting, other.start)
+    assert B.included(other, c)[0] == oracle.included(other.delta, other.accepting, other.start,
+                                                       c.delta, c.accepting, c.start)
+
+
 def test_product_equivalence_device_api():
     import torch
     d = W.random_dfa(30000, 3, 0.3, 41)
@@ -308,7 +349,7 @@ def test_product_equivalence_device_api():
 
 # ---------------------------------------------------------------- inclusion
 
-@pytest.mark.parametrize("n", [3, 5, 9, 12])
+@pytest.mark.parametrize("n", [3, 5, 9, 12, 16])
 def test_inclusion_memory_table5(n):
     """Table 5: forgetful memory_n is included in perfect memory_n, and the
     explored product has (2n+1) 2^(n-2) states; the converse fails."""
