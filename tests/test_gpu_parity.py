@@ -580,6 +580,66 @@ def test_batch_workload_small_slice():
         assert v == oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
 
 
+def _certify(d, block):
+    """The ids are canonical (each the smallest member of its block) and the
+    partition is stable and refines acceptance, so every block lies inside one
+    equivalence class (Section 2); with the oracle's block count it is the
+    coarsest one."""
+    q = np.arange(d.n)
+    assert (block <= q).all() and (block[block] == block).all()
+    assert (d.accepting == d.accepting[block]).all()
+    assert (block[d.delta] == block[d.delta[block]]).all()
+
+
+def test_batch_workload_full_size():
+    """The 4,096-DFA batch workload at full size, in the launch configuration
+    the benchmark times (one batched call per kind): every DFA's partition is
+    certified stable with canonical ids, 256 seeded samples are compared with
+    the oracle state by state (rounds included), and all 2,048 equivalence
+    verdicts with the oracle's."""
+    items = W.batch_workload(count=4096, paired_from=2048)
+    dfas = [it.dfa for it in items]
+    blocks, nb, rounds, _ = B.minimise_batch(dfas)
+    for d, blk, c in zip(dfas, blocks, nb):
+        _certify(d, blk)
+        assert c == np.count_nonzero(blk == np.arange(d.n))
+    for i in np.random.default_rng(404).choice(len(dfas), 256, replace=False):
+        d = dfas[i]
+        ref, rnb, rrounds, _ = oracle.moore(d.delta, d.accepting)
+        np.testing.assert_array_equal(blocks[i], ref)
+        assert (nb[i], rounds[i]) == (rnb, rrounds)
+    pairs = [(it.dfa, it.pair) for it in items if it.pair is not None]
+    verdicts, _ = B.equivalent_batch(pairs)
+    expect = [oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
+              for a, b in pairs]
+    assert list(verdicts) == expect
+    assert 0 < sum(expect) < len(expect)
+
+
+def test_server_serving_workload_full_size():
+    """The first 16 requests of the serving workload at full size (n up to
+    2.3M, chain DFAs included), through a server with the default
+    configuration as the benchmark runs it: every result equals the oracle's."""
+    reqs = W.serving_workload(96, rate=1.0)[:16]
+    with B.Server() as srv:
+        tickets = [srv.submit_minimise(r.dfa) if r.kind == "minimise" else
+                   srv.submit_equivalent(r.dfa, r.other) for r in reqs]
+        results = [srv.wait(t) for t in tickets]
+    kinds = set()
+    for r, got in zip(reqs, results):
+        assert got["status"] == 0
+        if r.kind == "minimise":
+            hb, hnb = oracle.hopcroft(r.dfa.delta, r.dfa.accepting)
+            np.testing.assert_array_equal(got["blocks"], hb)
+            assert got["num_blocks"] == hnb
+        else:
+            assert got["verdict"] == oracle.equiv_hk(r.dfa.delta, r.dfa.accepting, r.dfa.start,
+                                                     r.other.delta, r.other.accepting,
+                                                     r.other.start)
+        kinds.add(r.kind)
+    assert kinds == {"minimise", "equivalent"}
+
+
 # ---------------------------------------------------------------- serving
 
 def _serving_mix(seed, count):
