@@ -219,6 +219,12 @@ typedef struct dfa_kernel_time {
 
 int dfa_profile_enable(int on);
 int dfa_profile_read(dfa_kernel_time *out, int cap, int *count);
+/* Restricts the timing to the round kernel of that name (as reported in
+ * dfa_kernel_time.name, e.g. "k_signature"): the other kernels run without
+ * events, so the timed region is barely disturbed.  NULL or "" times every
+ * round kernel again.  Kept across dfa_profile_enable calls.  DFA_EINVAL for
+ * a name of 32 characters or more. */
+int dfa_profile_only(const char *name);
 
 /*
  * Minimise one DFA (Section 2 problem statement; Section 3.3, Algorithm 4

@@ -139,8 +139,8 @@ EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
                   "dfa_equivalent", "dfa_equivalent_device", "dfa_included",
                   "dfa_included_device", "dfa_last_error", "dfa_device_info",
                   "dfa_tuning_default", "dfa_get_tuning", "dfa_set_tuning",
-                  "dfa_profile_enable", "dfa_profile_read", "dfa_minimise_batch",
-                  "dfa_minimise_batch_device", "dfa_equivalent_batch",
+                  "dfa_profile_enable", "dfa_profile_read", "dfa_profile_only",
+                  "dfa_minimise_batch", "dfa_minimise_batch_device", "dfa_equivalent_batch",
                   "dfa_equivalent_batch_device", "dfa_server_config_default",
                   "dfa_server_create", "dfa_server_submit", "dfa_server_poll",
                   "dfa_server_wait", "dfa_result_release", "dfa_server_get_stats",
@@ -214,6 +214,7 @@ def load(build_if_missing: bool = True):
         lib.dfa_server_destroy.restype = None
         lib.dfa_profile_enable.argtypes = [i32]
         lib.dfa_profile_read.argtypes = [P(KernelTime), i32, P(i32)]
+        lib.dfa_profile_only.argtypes = [ctypes.c_char_p]
         for fn in ("dfa_minimise", "dfa_minimise_device", "dfa_equivalent",
                    "dfa_equivalent_device", "dfa_included", "dfa_included_device",
                    "dfa_device_info", "dfa_get_tuning", "dfa_set_tuning",
@@ -278,6 +279,11 @@ def set_tuning(**values) -> dict:
 def profile_enable(on: bool = True) -> None:
     """Start (and clear) or stop per-kernel event timing in the library."""
     _check(load().dfa_profile_enable(1 if on else 0))
+
+
+def profile_only(name: str | None) -> None:
+    """Time only the round kernel `name` (e.g. "k_signature"); None: all."""
+    _check(load().dfa_profile_only(name.encode() if name else None))
 
 
 def profile_read() -> dict:

@@ -129,6 +129,7 @@ struct Ctx {
     // kernel timing (dfa_profile_enable): event pairs around the round
     // kernels, folded into per-kernel totals after every readback
     bool profiling = false;
+    std::string prof_only;  // time only this kernel ("" = every round kernel)
     struct KernelTime {
         uint64_t launches = 0;
         double ms = 0;
@@ -278,7 +279,8 @@ const char *kern_name(Kern kind) {
 template <class Args>
 int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
     size_t e0 = 0, e1 = 0;
-    if (c.profiling) {
+    const bool timed = c.profiling && (c.prof_only.empty() || c.prof_only == kern_name(kind));
+    if (timed) {
         DFA_TRY(prof_event(c, e0));
         HIP_TRY(hipEventRecord(c.evpool[e0], c.stream));
     }
@@ -301,7 +303,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
             default: return fail(DFA_EDEVICE, "internal: round kernel with leader arguments");
         }
     }
-    if (c.profiling) {
+    if (timed) {
         DFA_TRY(prof_event(c, e1));
         HIP_TRY(hipEventRecord(c.evpool[e1], c.stream));
         c.pending.push_back({kern_name(kind), e0, e1, round, kern_bytes(kind, a.k_eff)});
@@ -1970,6 +1972,16 @@ int dfa_profile_enable(int on) {
     c->ktimes.clear();
     c->pending.clear();
     c->ev_used = 0;
+    return DFA_OK;
+}
+
+int dfa_profile_only(const char *name) {
+    if (name && std::strlen(name) >= sizeof(dfa_kernel_time{}.name))
+        return fail(DFA_EINVAL, "kernel name too long");
+    Ctx *c = nullptr;
+    DFA_TRY(get_ctx(c));
+    std::lock_guard<std::mutex> lock(c->mu);
+    c->prof_only = name ? name : "";
     return DFA_OK;
 }
 

@@ -136,3 +136,8 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.dfa_equivalent_batch(1, ctypes.byref(va), ctypes.byref(vb), verdicts.ctypes.data,
                                     ctypes.byref(o), None) == B.DFA_EINVAL
     assert b"DFA_EQ_UNION" in lib.dfa_last_error()
+
+
+def test_profile_only_rejects_long_names(lib):
+    assert lib.dfa_profile_only(b"k" * 40) == B.DFA_EINVAL
+    assert b"too long" in lib.dfa_last_error()

@@ -640,6 +640,31 @@ def test_server_serving_workload_full_size():
     assert kinds == {"minimise", "equivalent"}
 
 
+def test_kernel_timing_all_and_one():
+    """Per-kernel event timing: every round kernel, or only the one named
+    (the others then run without events); results are unchanged."""
+    d = W.random_dfa(50000, 4, 0.1, 77)
+    ref = _ref(d)
+    try:
+        B.profile_only(None)
+        B.profile_enable(True)
+        res = B.minimise(d.delta, d.accepting, tc="off", loop="chunk")
+        every = B.profile_read()
+        assert {"k_signature", "k_insert", "k_mark", "k_round_end"} <= set(every)
+        B.profile_only("k_signature")
+        B.profile_enable(True)
+        res2 = B.minimise(d.delta, d.accepting, tc="off", loop="chunk")
+        one = B.profile_read()
+        assert set(one) == {"k_signature"}
+        assert one["k_signature"]["launches"] == every["k_signature"]["launches"]
+        assert one["k_signature"]["algorithmic_bytes"] == every["k_signature"]["algorithmic_bytes"]
+    finally:
+        B.profile_enable(False)
+        B.profile_only(None)
+    np.testing.assert_array_equal(res.block, ref[0])
+    np.testing.assert_array_equal(res2.block, ref[0])
+
+
 # ---------------------------------------------------------------- serving
 
 def _serving_mix(seed, count):
