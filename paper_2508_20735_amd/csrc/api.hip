@@ -106,7 +106,7 @@ struct Ctx {
         stage_acc_b;
     Buffer visited, visited2, front0, front1;
     Buffer new_leader, moved;
-    Buffer chg, single, touched;
+    Buffer chg, single, touched, chg_sum;
     Buffer reach_visited, reach_qa, reach_qb, reach_flags, reach_dense, reach_orig, sub_delta,
         sub_acc, sub_block;
     Buffer sort_keys0, sort_keys1, sort_vals0, sort_vals1, sort_hist, sort_partials,
@@ -511,6 +511,7 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
     ra.pattern_grid_cap = c.tune.label_grid_cap;
     ra.cached_probe = c.tune.cached_probe;
     ra.chg = c.chg.as<unsigned long long>();
+    ra.chg_sum = c.chg_sum.as<unsigned long long>();
     ra.single = c.single.as<unsigned long long>();
     ra.touched = c.touched.as<unsigned long long>();
     ra.grouping = grouping;
@@ -567,6 +568,9 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     DFA_TRY(c.touched.ensure(2 * words64 * sizeof(unsigned long long), "touched-block bits"));
     HIP_TRY(hipMemsetAsync(c.single.p, 0, words64 * sizeof(unsigned long long), c.stream));
     HIP_TRY(hipMemsetAsync(c.touched.p, 0, 2 * words64 * sizeof(unsigned long long), c.stream));
+    const size_t sum_words = (N + 4095) / 4096;
+    DFA_TRY(c.chg_sum.ensure(2 * sum_words * sizeof(unsigned long long), "changed-wave summary"));
+    HIP_TRY(hipMemsetAsync(c.chg_sum.p, 0, 2 * sum_words * sizeof(unsigned long long), c.stream));
     const uint32_t grouping = (o.algorithm == DFA_ALGO_SORT && !seg) ? 1u : 0u;
     if (grouping) {
         const SortPlan pl = sort_plan(N);
@@ -1561,7 +1565,7 @@ void release_ctx(Ctx &c) {
                       &c.stage_qdelta, &c.stage_qacc, &c.stage_delta_b, &c.stage_acc_b,
                       &c.visited, &c.visited2, &c.front0, &c.front1, &c.parts, &c.tile_part,
                       &c.seg_words, &c.batch_in, &c.batch_out, &c.new_leader, &c.moved,
-                      &c.chg, &c.single, &c.touched, &c.reach_visited, &c.reach_qa,
+                      &c.chg, &c.single, &c.touched, &c.chg_sum, &c.reach_visited, &c.reach_qa,
                       &c.reach_qb, &c.reach_flags, &c.reach_dense, &c.reach_orig, &c.sub_delta,
                       &c.sub_acc, &c.sub_block, &c.sort_keys0, &c.sort_keys1, &c.sort_vals0,
                       &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,

@@ -208,6 +208,7 @@ struct SigParams {
     unsigned long long *chg;
     unsigned long long *single;
     unsigned long long *touched;
+    unsigned long long *chg_sum;
     uint32_t grouping;  // 1: sort grouping (no claims in the signature kernel)
     uint32_t hash_bits;  // 0: full key hashes; else only the low bits
 };
@@ -371,10 +372,29 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
     const size_t words = (p.N + 63) / 64;
     unsigned long long *__restrict__ Tn = p.touched + ((r + 1) & 1u) * words;
     for (size_t i = global_tid(); i < words; i += grid_stride()) Tn[i] = 0ull;
+    // this round's changed-wave summary starts empty (the grouping kernels
+    // fill it)
+    const size_t sum_words = (p.N + 4095) >> 12;
+    unsigned long long *__restrict__ Sn = p.chg_sum + (r & 1u) * sum_words;
+    for (size_t i = global_tid(); i < sum_words; i += grid_stride()) Sn[i] = 0ull;
     if (r <= p.ctl->all_active_until || !incremental_round(*p.ctl, p.N, r)) return;
     unsigned long long *__restrict__ T = p.touched + (r & 1u) * words;
     const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
     const unsigned long long *__restrict__ chg = p.chg;
+    // last round's summary in LDS: a successor's changed-id word is read
+    // only when its wave changed an id (the few waves of an incremental
+    // round), instead of one random gather per transition
+    __shared__ unsigned long long lsum[kSumLdsWords];
+    const bool filter = sum_words <= kSumLdsWords;
+    if (filter) {
+        const unsigned long long *__restrict__ Sp = p.chg_sum + ((r - 1) & 1u) * sum_words;
+        for (size_t i = threadIdx.x; i < sum_words; i += kBlock) lsum[i] = Sp[i];
+        __syncthreads();
+    }
+    auto changed = [&](uint32_t t) -> bool {
+        if (filter && !((lsum[t >> 12] >> ((t >> 6) & 63)) & 1ull)) return false;
+        return ((chg[t >> 6] >> (t & 63)) & 1ull) != 0;
+    };
     const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
     const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
     // S states per thread; each kind of load is issued for all of them before
@@ -415,20 +435,15 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
             // reads state 0's): conditional loads sit in branches, across
             // which the compiler waits for every load in flight
             uint32_t t[S][KC];
-            unsigned long long bits[S][KC];
 #pragma unroll
             for (int i = 0; i < S; ++i)
 #pragma unroll
                 for (int j = 0; j < KC; ++j) t[i][j] = colp.c[j][s[i] ? 0 : q[i]];
 #pragma unroll
-            for (int i = 0; i < S; ++i)
-#pragma unroll
-                for (int j = 0; j < KC; ++j) bits[i][j] = chg[t[i][j] >> 6];
-#pragma unroll
             for (int i = 0; i < S; ++i) {
                 bool any = false;
 #pragma unroll
-                for (int j = 0; j < KC; ++j) any |= ((bits[i][j] >> (t[i][j] & 63)) & 1ull) != 0;
+                for (int j = 0; j < KC; ++j) any |= changed(t[i][j]);
                 dirty[i] = !s[i] && any;
             }
         } else {
@@ -443,7 +458,7 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
                         if (j < m) t[j] = p.cols[static_cast<size_t>(p.colmap[j0 + j]) * p.N + q[i]];
 #pragma unroll
                     for (uint32_t j = 0; j < 8; ++j)
-                        if (j < m) dirty[i] |= ((chg[t[j] >> 6] >> (t[j] & 63)) & 1ull) != 0;
+                        if (j < m) dirty[i] |= changed(t[j]);
                 }
             }
         }
@@ -660,7 +675,18 @@ struct InsParams {
     uint32_t cached_probe;
     int lds_stage;
     unsigned long long *chg;
+    unsigned long long *chg_sum;
 };
+
+// Stores a wave's changed-id mask and, if it is not empty, sets the wave's
+// bit in the round's summary (lane 0 only).
+__device__ __forceinline__ void store_changed(unsigned long long *chg, unsigned long long *chg_sum,
+                                              size_t N, uint32_t r, size_t first,
+                                              unsigned long long cm) {
+    if (lane_id() != 0 || first >= N) return;
+    chg[first >> 6] = cm;
+    if (cm) atomicOr(chg_sum + (r & 1u) * ((N + 4095) >> 12) + (first >> 12), 1ull << ((first >> 6) & 63));
+}
 
 // Whether this round stages keys in LDS (uniform across the grid).
 __device__ __forceinline__ bool stage_in_lds(const InsParams &p) {
@@ -713,7 +739,7 @@ __device__ __forceinline__ void insert_body(const InsParams &p) {
             }
         }
         const unsigned long long cm = __ballot(ch);
-        if (lane_id() == 0 && first < p.N) p.chg[first >> 6] = cm;
+        store_changed(p.chg, p.chg_sum, p.N, r, first, cm);
         changed += ch ? 1u : 0u;
     }
     wg_add_spread(p.counters, 0, blocks);
@@ -810,7 +836,7 @@ __device__ __forceinline__ void insert_lds_body(const InsParams &p) {
             ch = id != x;
         }
         const unsigned long long cm = __ballot(ch);
-        if (lane_id() == 0 && first < p.N) p.chg[first >> 6] = cm;
+        store_changed(p.chg, p.chg_sum, p.N, r, first, cm);
         changed += ch ? 1u : 0u;
         __syncthreads();
     }
@@ -1235,7 +1261,7 @@ SigParams sig_params(const RoundArgs &a) {
                      a.blockB,   a.sig,        a.hash,     a.table,    a.table_cap,
                      a.multi,    a.active,     a.accbits,  a.presence, a.presence_packed,
                      a.lab8,     a.counters,   a.ctl,      a.cached_probe, a.chg,
-                     a.single,   a.touched,    a.grouping, a.hash_bits};
+                     a.single,   a.touched,    a.chg_sum,  a.grouping, a.hash_bits};
 }
 
 unsigned round_grid(const RoundArgs &a, unsigned cap) {
@@ -1245,7 +1271,7 @@ unsigned round_grid(const RoundArgs &a, unsigned cap) {
 InsParams ins_params(const RoundArgs &a) {
     return InsParams{a.sig,    a.hash,   a.N,     a.k_eff + 1, a.table,    a.table_cap - 1,
                      a.blockA, a.blockB, a.multi, a.active,    a.counters, a.ctl,
-                     a.cached_probe, a.lds_stage, a.chg};
+                     a.cached_probe, a.lds_stage, a.chg, a.chg_sum};
 }
 
 // Workgroups of the persistent loop: no more than fit on the device at once.

@@ -295,8 +295,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_assign(AssignArgs a) {
 // State order: changed-id bits and the counts the table kernels keep.
 __global__ __launch_bounds__(kBlock) void k_sort_finish(const unsigned long long *active, size_t N,
                                                        uint32_t *blockA, uint32_t *blockB,
-                                                       unsigned long long *chg, uint32_t *counters,
-                                                       const RoundCtl *ctl) {
+                                                       unsigned long long *chg,
+                                                       unsigned long long *chg_sum,
+                                                       uint32_t *counters, const RoundCtl *ctl) {
     if (ctl->done) return;
     const uint32_t r = ctl->round;
     const uint32_t *__restrict__ X = (r & 1u) ? blockB : blockA;
@@ -312,7 +313,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_finish(const unsigned long long
         idle += (valid && !act) ? 1u : 0u;
         const bool ch = act && Y[q] != X[q];
         const unsigned long long cm = __ballot(ch);
-        if (lane_id() == 0 && first < N) chg[first >> 6] = cm;
+        if (lane_id() == 0 && first < N) {
+            chg[first >> 6] = cm;
+            // the wave's bit in the round's changed-wave summary
+            if (cm)
+                atomicOr(chg_sum + (r & 1u) * ((N + 4095) >> 12) + (first >> 12),
+                         1ull << ((first >> 6) & 63));
+        }
         changed += ch ? 1u : 0u;
     }
     wg_add_spread(counters, 1, idle);
@@ -383,7 +390,7 @@ void launch_sort_group(const RoundArgs &a, hipStream_t s) {
                         a.blockA,  a.blockB,  a.multi,    a.counters, a.ctl};
     hipLaunchKernelGGL(k_sort_assign, dim3(grid_n(a.N)), dim3(kBlock), 0, s, aa);
     hipLaunchKernelGGL(k_sort_finish, dim3(grid_n(a.N)), dim3(kBlock), 0, s, a.active, a.N,
-                       a.blockA, a.blockB, a.chg, a.counters, a.ctl);
+                       a.blockA, a.blockB, a.chg, a.chg_sum, a.counters, a.ctl);
 }
 
 }  // namespace dfamin
