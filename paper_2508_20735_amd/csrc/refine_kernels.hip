@@ -420,9 +420,12 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
             was_active[i] = !s[i] && ((aw[i] >> lane_id()) & 1ull);
             x[i] = was_active[i] ? X[q[i]] : 0u;
         }
+        // a block id is one of the block's states, so a state whose id is
+        // another state's index shares its block; a state holding its own
+        // index learns from its own mark (a coalesced read)
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (was_active[i]) s[i] = p.multi[x[i]] != r;
+            if (was_active[i]) s[i] = x[i] == q[i] && p.multi[q[i]] != r;
 #pragma unroll
         for (int i = 0; i < S; ++i) {
             const unsigned long long nsw = __ballot(s[i]);
@@ -485,7 +488,8 @@ __device__ __forceinline__ bool select_state(const SigParams &p, size_t q, uint3
     bool s = !valid || ((sw >> lane_id()) & 1ull);
     if (!inc) {
         const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
-        if (!s && ((aw >> lane_id()) & 1ull)) s = p.multi[w0] != r;
+        // (a state whose id is another state's index shares its block)
+        if (!s && ((aw >> lane_id()) & 1ull)) s = w0 == q && p.multi[q] != r;
         const unsigned long long nsw = __ballot(s);
         if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
     }
