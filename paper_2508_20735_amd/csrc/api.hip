@@ -107,6 +107,9 @@ struct Ctx {
     Buffer visited, visited2, front0, front1;
     Buffer new_leader, moved;
     Buffer chg, single, touched, chg_sum;
+    // the column list last uploaded, and the buffer it went to
+    std::vector<uint32_t> colmap_on_device;
+    const void *colmap_on_device_at = nullptr;
     Buffer reach_visited, reach_qa, reach_qb, reach_flags, reach_dense, reach_orig, sub_delta,
         sub_acc, sub_block;
     Buffer sort_keys0, sort_keys1, sort_vals0, sort_vals1, sort_hist, sort_partials,
@@ -415,9 +418,21 @@ int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, u
 
 int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
     DFA_TRY(c.colmap.ensure(std::max<size_t>(colmap.size(), 1) * sizeof(uint32_t), "colmap"));
-    if (!colmap.empty())
-        DFA_TRY(upload(c, c.colmap.p, colmap.data(), colmap.size() * sizeof(uint32_t)));
+    // the list usually repeats from call to call: upload (a synchronous
+    // copy) only when the device does not hold it already
+    if (colmap.empty() || (c.colmap.p == c.colmap_on_device_at && colmap == c.colmap_on_device))
+        return DFA_OK;
+    DFA_TRY(upload(c, c.colmap.p, colmap.data(), colmap.size() * sizeof(uint32_t)));
+    c.colmap_on_device = colmap;
+    c.colmap_on_device_at = c.colmap.p;
     return DFA_OK;
+}
+
+// Adds the first `bytes` of b (rounded up to 8) to a zeroing list.
+void zero_add(ZeroList &z, Buffer &b, size_t bytes) {
+    z.p[z.count] = b.as<unsigned long long>();
+    z.words[z.count] = (bytes + 7) / 8;
+    ++z.count;
 }
 
 // Enqueues `rounds` rounds of signature (ra) or leader (la != nullptr)
@@ -537,6 +552,31 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
 int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq, uint32_t eq_a,
            uint32_t eq_b, bool state_ids, RefineResult &res, const SegArgs *seg = nullptr) {
     res.N = static_cast<uint32_t>(N);
+    // state that starts empty, cleared in one launch queued before the
+    // readback below, so that the device clears while the host waits
+    const uint64_t cap = next_pow2(std::max<uint64_t>(2 * N, 1024));
+    const size_t words64 = (N + 63) / 64;
+    const size_t sum_words = (N + 4095) / 4096;
+    DFA_TRY(c.table.ensure(cap * sizeof(unsigned long long), "hash table"));
+    DFA_TRY(c.chg.ensure(words64 * sizeof(unsigned long long), "changed-id bits"));
+    DFA_TRY(c.single.ensure(words64 * sizeof(unsigned long long), "singleton bits"));
+    DFA_TRY(c.touched.ensure(2 * words64 * sizeof(unsigned long long), "touched-block bits"));
+    DFA_TRY(c.chg_sum.ensure(2 * sum_words * sizeof(unsigned long long), "changed-wave summary"));
+    // label rounds: the packed-label bitmap too when k letters could use it
+    // (identity letters, known after the readback, only make k_eff smaller)
+    const bool packed_possible = !seg && (k + 1) * (k + 1) <= kPackedMaxBits;
+    if (packed_possible)
+        DFA_TRY(c.presence_packed.ensure((size_t(1) << kPackedMaxBits) / 8, "label bitmap"));
+    {
+        ZeroList z{};
+        zero_add(z, c.table, cap * sizeof(unsigned long long));
+        zero_add(z, c.single, words64 * sizeof(unsigned long long));
+        zero_add(z, c.touched, 2 * words64 * sizeof(unsigned long long));
+        zero_add(z, c.chg_sum, 2 * sum_words * sizeof(unsigned long long));
+        if (packed_possible) zero_add(z, c.presence_packed, (size_t(1) << kPackedMaxBits) / 8);
+        launch_zero(z, c.stream);
+        HIP_TRY(hipGetLastError());
+    }
     // target check, classes, identity letters (one readback)
     DFA_TRY(read_back(c, c.flags.p, (kFlagNonid + k) * sizeof(uint32_t)));
     if (c.pinned[kFlagErr]) return fail(DFA_EINVAL, "a transition target is >= n");
@@ -544,9 +584,6 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     for (uint32_t a = 0; a < k; ++a)
         if (c.pinned[kFlagNonid + a]) colmap.push_back(a);
 
-    const uint64_t cap = next_pow2(std::max<uint64_t>(2 * N, 1024));
-    DFA_TRY(c.table.ensure(cap * sizeof(unsigned long long), "hash table"));
-    HIP_TRY(hipMemsetAsync(c.table.p, 0, cap * sizeof(unsigned long long), c.stream));
     DFA_TRY(c.ctl.ensure(sizeof(RoundCtl), "round state"));
     RoundCtl *ctl = c.ctl.as<RoundCtl>();
 
@@ -562,15 +599,6 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     uint32_t k_eff = static_cast<uint32_t>(colmap.size());
     DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
     DFA_TRY(c.hash.ensure(N * sizeof(uint64_t), "hashes"));
-    const size_t words64 = (N + 63) / 64;
-    DFA_TRY(c.chg.ensure(words64 * sizeof(unsigned long long), "changed-id bits"));
-    DFA_TRY(c.single.ensure(words64 * sizeof(unsigned long long), "singleton bits"));
-    DFA_TRY(c.touched.ensure(2 * words64 * sizeof(unsigned long long), "touched-block bits"));
-    HIP_TRY(hipMemsetAsync(c.single.p, 0, words64 * sizeof(unsigned long long), c.stream));
-    HIP_TRY(hipMemsetAsync(c.touched.p, 0, 2 * words64 * sizeof(unsigned long long), c.stream));
-    const size_t sum_words = (N + 4095) / 4096;
-    DFA_TRY(c.chg_sum.ensure(2 * sum_words * sizeof(unsigned long long), "changed-wave summary"));
-    HIP_TRY(hipMemsetAsync(c.chg_sum.p, 0, 2 * sum_words * sizeof(unsigned long long), c.stream));
     const uint32_t grouping = (o.algorithm == DFA_ALGO_SORT && !seg) ? 1u : 0u;
     if (grouping) {
         const SortPlan pl = sort_plan(N);
@@ -595,9 +623,11 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             : 0u;
     if (packed_second) {
         DFA_TRY(c.lab8.ensure(N, "byte labels"));
-        DFA_TRY(c.presence_packed.ensure((size_t(1) << kPackedMaxBits) / 8, "label bitmap"));
-        HIP_TRY(hipMemsetAsync(c.presence_packed.p, 0, (size_t(1) << kPackedMaxBits) / 8,
-                               c.stream));
+        if (!packed_possible) {  // not cleared above
+            DFA_TRY(c.presence_packed.ensure((size_t(1) << kPackedMaxBits) / 8, "label bitmap"));
+            HIP_TRY(hipMemsetAsync(c.presence_packed.p, 0, (size_t(1) << kPackedMaxBits) / 8,
+                                   c.stream));
+        }
     }
     res.label_rounds = pattern_first + packed_second;
     launch_ctl_reset(ctl, c.flags.as<uint32_t>() + kFlagClass, o.max_rounds, check_eq, eq_a, eq_b,
@@ -841,19 +871,23 @@ int prepare_refinement(Ctx &c, size_t N, uint32_t k) {
     const size_t ncols = static_cast<size_t>(L + 1) * k;
     const size_t words64 = (N + 63) / 64;
     DFA_TRY(c.cols.ensure(static_cast<size_t>(k) * N * sizeof(uint32_t), "columns"));
-    DFA_TRY(c.flags.ensure((kFlagNonid + 2 * ncols) * sizeof(uint32_t), "flags"));
+    DFA_TRY(c.flags.ensure((kFlagNonid + 2 * ncols + 2) * sizeof(uint32_t), "flags"));
     DFA_TRY(c.blockA.ensure(N * sizeof(uint32_t), "blocks"));
     DFA_TRY(c.blockB.ensure(N * sizeof(uint32_t), "blocks"));
-    DFA_TRY(c.multi.ensure(N * sizeof(uint32_t), "block marks"));
+    DFA_TRY(c.multi.ensure((N + 1) * sizeof(uint32_t), "block marks"));
     DFA_TRY(c.active.ensure(words64 * sizeof(unsigned long long), "active masks"));
     DFA_TRY(c.accbits.ensure(words64 * sizeof(unsigned long long), "acceptance bits"));
-    DFA_TRY(c.counters.ensure(kSpread * kSpreadStride * sizeof(uint32_t), "counters"));
+    DFA_TRY(c.counters.ensure(kSpread * kSpreadStride * sizeof(uint32_t) + 8, "counters"));
     DFA_TRY(c.presence.ensure((1u << kPatternMaxBits) / 8, "pattern bitmap"));
-    HIP_TRY(hipMemsetAsync(c.flags.p, 0, (kFlagNonid + k) * sizeof(uint32_t), c.stream));
-    HIP_TRY(hipMemsetAsync(c.multi.p, 0, N * sizeof(uint32_t), c.stream));
-    HIP_TRY(hipMemsetAsync(c.accbits.p, 0, words64 * sizeof(unsigned long long), c.stream));
-    HIP_TRY(hipMemsetAsync(c.counters.p, 0, kSpread * kSpreadStride * sizeof(uint32_t), c.stream));
-    HIP_TRY(hipMemsetAsync(c.presence.p, 0, (1u << kPatternMaxBits) / 8, c.stream));
+    // every clear in one launch (separate memsets cost host time each)
+    ZeroList z{};
+    zero_add(z, c.flags, (kFlagNonid + k) * sizeof(uint32_t));
+    zero_add(z, c.multi, N * sizeof(uint32_t));
+    zero_add(z, c.accbits, words64 * sizeof(unsigned long long));
+    zero_add(z, c.counters, kSpread * kSpreadStride * sizeof(uint32_t));
+    zero_add(z, c.presence, (1u << kPatternMaxBits) / 8);
+    launch_zero(z, c.stream);
+    HIP_TRY(hipGetLastError());
     return DFA_OK;
 }
 

@@ -296,6 +296,15 @@ void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t 
 
 // Canonical renumbering: out[q] = min{ q' : ids[q'] == ids[q] } for ids <
 // id_range; scratch_min holds id_range words.
+// Zeroes up to kZeroRegions byte regions (8-byte aligned, sizes multiples of
+// 8) in one launch.
+constexpr int kZeroRegions = 8;
+struct ZeroList {
+    unsigned long long *p[kZeroRegions];
+    size_t words[kZeroRegions];  // 8-byte words
+    int count;
+};
+void launch_zero(const ZeroList &z, hipStream_t s);
 void launch_canonicalise(const uint32_t *ids, size_t N, size_t id_range, uint32_t *scratch_min,
                          uint32_t *out, hipStream_t s);
 

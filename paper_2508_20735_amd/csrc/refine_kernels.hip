@@ -1104,6 +1104,13 @@ __global__ __launch_bounds__(kBlock) void k_jump(uint32_t *__restrict__ cols, si
 
 // ---------------------------------------------------------------- canonical ids
 
+__global__ __launch_bounds__(kBlock) void k_zero(ZeroList z) {
+    for (int r = 0; r < z.count; ++r) {
+        unsigned long long *__restrict__ p = z.p[r];
+        for (size_t i = global_tid(); i < z.words[r]; i += grid_stride()) p[i] = 0ull;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
     for (size_t i = global_tid(); i < n; i += grid_stride()) p[i] = v;
 }
@@ -1469,6 +1476,13 @@ void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t 
                  uint32_t *nonid, hipStream_t s) {
     dim3 grid(grid_for(N, kDefaultGridCap), k);
     hipLaunchKernelGGL(k_jump, grid, dim3(kBlock), 0, s, cols, N, k, level, diff, nonid);
+}
+
+void launch_zero(const ZeroList &z, hipStream_t s) {
+    size_t most = 0;
+    for (int r = 0; r < z.count; ++r) most = std::max(most, z.words[r]);
+    if (most == 0) return;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(most, kDefaultGridCap)), dim3(kBlock), 0, s, z);
 }
 
 void launch_canonicalise(const uint32_t *ids, size_t N, size_t id_range, uint32_t *scratch_min,
