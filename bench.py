@@ -298,6 +298,32 @@ def product_leg(B, W, torch, np, dev) -> dict:
     return out
 
 
+def gather_reference(torch, dev, sizes) -> dict:
+    """Random-gather rate of the device as a plain framework gather reaches
+    it (torch indexing: 4 * size random int32 gathers from a size-element
+    array, int64 indices), median of 10 timed repetitions: the ceiling of a
+    kernel whose successor-id gathers hit random lines."""
+    out = {}
+    for size in sizes:
+        x = torch.randint(0, size, (size,), dtype=torch.int32, device=dev)
+        idx = torch.randint(0, size, (4 * size,), dtype=torch.int64, device=dev)
+        for _ in range(3):
+            x[idx]
+        times = []
+        for _ in range(10):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            x[idx]
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = sorted(times)[len(times) // 2]
+        out[str(size)] = 4 * size / (ms * 1e-3)
+        del x, idx
+    return out
+
+
 def serve_leg(B, W, count: int) -> dict:
     """Served requests: n log-uniform in [1,000, 4,194,304], k in {2,4,8,16},
     80% minimise / 20% equivalence, 10% chain DFAs, host arrays.  First a
@@ -486,6 +512,25 @@ def main() -> int:
             "avg_launch_us": avg_s * 1e6, "launches": kd["launches"],
             "algorithmic_bytes_per_launch": bytes_per_launch,
         }
+        if dom == "k_signature":
+            # the kernel gathers k block ids per refined state: its rate of
+            # random gathers against the device's, measured the same way on
+            # the union's size (most launches refine the 2n-state unions)
+            k_eff = d.k
+            gathers = kd["algorithmic_bytes"] / (8 * k_eff + 8) * k_eff
+            ref = gather_reference(torch, dev, [d.n, 2 * d.n])
+            achieved_g = gathers / (kd["total_ms"] / 1e3)
+            out["gather_roofline"] = {
+                "kernel": dom, "achieved": achieved_g / 1e9, "peak": ref[str(2 * d.n)] / 1e9,
+                "unit": "G gathers/s", "frac": achieved_g / ref[str(2 * d.n)],
+                "reference": ("torch index gather: 4 * size random int32 gathers from a "
+                              "size-element array (size = 2n), median of 10"),
+                "reference_by_size": {s_: v / 1e9 for s_, v in ref.items()},
+                "note": ("achieved = the timed region's gathers over all k_signature launches, "
+                         "incremental rounds included (their fixed per-state work has no "
+                         "gathers); full-round launches in the kernel trace run at the "
+                         "reference rate"),
+            }
         out["kernels_profiled_steps"] = args.profile_steps
         out["kernels"] = {
             k: {"launches": v["launches"], "avg_us": v["total_ms"] / v["launches"] * 1e3,
