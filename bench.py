@@ -165,12 +165,13 @@ def batch_leg(B, W, torch, np, count: int) -> dict:
             "plain_transitions_per_s": work_p / tp}
 
 
-def variants_leg(B, W, torch, np, dev, A_d, A_a, n) -> dict:
+def variants_leg(B, W, torch, np, dev, A_d, A_a, n, pairs) -> dict:
     """The same GPU on the same inputs with the other refinement options:
     sort-based grouping (sortPR's grouping) vs the hash table on the 2^22
     minimisation; leader rounds (naivePR) vs signature rounds on the
-    bit-splitter B_20 of Table 2; reachability pruning on the 2^22 workload.
-    Median device time of 3 runs after one warm-up."""
+    bit-splitter B_20 of Table 2; reachability pruning on the 2^22 workload;
+    the step's two equivalences decided by product exploration instead of
+    refining the union.  Median device time of 3 runs after one warm-up."""
 
     def med(fn, runs=3):
         fn()
@@ -202,6 +203,12 @@ def variants_leg(B, W, torch, np, dev, A_d, A_a, n) -> dict:
         out[f"b20_{alg}_ms"] = ms
         out[f"b20_{alg}_rounds"] = st["rounds"]
     out["b20_transitions"] = bs.n * bs.k
+    for name, (start, P_d, P_a, p_start) in pairs.items():
+        for method in ("union", "product"):
+            ms, st = med(lambda: B.equivalent_device(A_d, A_a, start, P_d, P_a, p_start,
+                                                     method=method)[1])
+            out[f"equiv_2e22_{name}_{method}_ms"] = ms
+        out[f"equiv_2e22_{name}_product_pairs"] = st["reachable"]
     return out
 
 
@@ -543,7 +550,9 @@ def main() -> int:
     if not args.no_serve:
         out["served"] = serve_leg(B, W, args.serve_requests)
     if not args.no_variants:
-        out["variants"] = variants_leg(B, W, torch, np, dev, A_d, A_a, d.n)
+        out["variants"] = variants_leg(B, W, torch, np, dev, A_d, A_a, d.n,
+                                       {"permuted": (d.start, P_d, P_a, perm.start),
+                                        "mutated": (d.start, M_d, M_a, mut.start)})
     if not args.no_table2:
         out["table2"] = table2_leg(B, W, torch, np, dev)
     if not args.no_products:
