@@ -427,7 +427,7 @@ def large():
 def test_config_large_minimise(large):
     """n = 2^22, k = 4, p = 0.1: every state compared with the oracle."""
     d, ref = large
-    for loop in ("graph", "host"):
+    for loop in ("graph", "host", "chunk"):
         res = check_minimise(d, tc="auto", loop=loop, ref=ref)
         assert res.stats["tc_used"] == 0
         assert res.stats["changing_rounds"] == ref[3]
@@ -443,6 +443,42 @@ def test_config_large_equivalence(large):
     assert got == expected
     # twins (q and its copy) separate in a few rounds: no closure is built
     assert st["tc_used"] == 0
+
+
+def test_config_large_bench_step_configuration(large):
+    """The benchmark's step as it is timed: device tensors, chunked rounds
+    with only the signature kernel carrying events.  Minimisation ids,
+    quotient and both verdicts equal the oracle's."""
+    import torch
+    d, ref = large
+    perm, _ = W.permuted_copy(d, W.CFG_LARGE_PERM_SEED)
+    mut, _ = W.mutate_one(d, W.CFG_LARGE_MUT_SEED)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x).view(
+        np.int32 if x.dtype == np.uint32 else np.uint8)).to(dev)
+    A_d, A_a = t(d.delta), t(d.accepting)
+    try:
+        B.profile_only("k_signature")
+        B.profile_enable(True)
+        res = B.minimise_device(A_d, A_a, quotient=True, loop="chunk")
+        e1, _ = B.equivalent_device(A_d, A_a, d.start, t(perm.delta), t(perm.accepting),
+                                    perm.start, loop="chunk")
+        e2, _ = B.equivalent_device(A_d, A_a, d.start, t(mut.delta), t(mut.accepting),
+                                    mut.start, loop="chunk")
+        timed = B.profile_read()
+    finally:
+        B.profile_enable(False)
+        B.profile_only(None)
+    np.testing.assert_array_equal(res.block.cpu().numpy().view(np.uint32), ref[0])
+    qn, qd, qa, qs = oracle.quotient(d.delta, d.accepting, ref[0], d.start)
+    gn, gd, ga, gs = res.quotient
+    assert gn == qn and gs == qs
+    np.testing.assert_array_equal(gd.cpu().numpy().view(np.uint32), qd)
+    np.testing.assert_array_equal(ga.cpu().numpy(), qa)
+    assert e1 is True
+    assert e2 == oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting,
+                                 mut.start)
+    assert set(timed) == {"k_signature"}
 
 
 def test_config_chain_closure():
