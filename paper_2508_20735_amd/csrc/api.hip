@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -50,9 +51,15 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 // Grow-only device allocation.
+// Every device allocation gets a new number, so that cached facts about a
+// buffer's contents never outlive the allocation (a new one may reuse the
+// address).
+std::atomic<uint64_t> g_allocation_number{0};
+
 struct Buffer {
     void *p = nullptr;
     size_t cap = 0;
+    uint64_t allocation = 0;  // number of the current allocation (0: none)
     int ensure(size_t bytes, const char *what) {
         if (p && bytes <= cap) return DFA_OK;
         if (p) {
@@ -70,6 +77,7 @@ struct Buffer {
                         hipGetErrorString(e));
         }
         cap = want;
+        allocation = ++g_allocation_number;
         return DFA_OK;
     }
     template <class T>
@@ -107,9 +115,9 @@ struct Ctx {
     Buffer visited, visited2, front0, front1;
     Buffer new_leader, moved;
     Buffer chg, single, touched, chg_sum;
-    // the column list last uploaded, and the buffer it went to
+    // the column list last uploaded, and the allocation it went to
     std::vector<uint32_t> colmap_on_device;
-    const void *colmap_on_device_at = nullptr;
+    uint64_t colmap_on_device_in = 0;
     Buffer reach_visited, reach_qa, reach_qb, reach_flags, reach_dense, reach_orig, sub_delta,
         sub_acc, sub_block;
     Buffer sort_keys0, sort_keys1, sort_vals0, sort_vals1, sort_hist, sort_partials,
@@ -420,11 +428,12 @@ int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
     DFA_TRY(c.colmap.ensure(std::max<size_t>(colmap.size(), 1) * sizeof(uint32_t), "colmap"));
     // the list usually repeats from call to call: upload (a synchronous
     // copy) only when the device does not hold it already
-    if (colmap.empty() || (c.colmap.p == c.colmap_on_device_at && colmap == c.colmap_on_device))
+    if (colmap.empty() ||
+        (c.colmap.allocation == c.colmap_on_device_in && colmap == c.colmap_on_device))
         return DFA_OK;
     DFA_TRY(upload(c, c.colmap.p, colmap.data(), colmap.size() * sizeof(uint32_t)));
     c.colmap_on_device = colmap;
-    c.colmap_on_device_at = c.colmap.p;
+    c.colmap_on_device_in = c.colmap.allocation;
     return DFA_OK;
 }
 
@@ -1609,6 +1618,7 @@ void release_ctx(Ctx &c) {
         if (b->p) (void)hipFree(b->p);
         b->p = nullptr;
         b->cap = 0;
+        b->allocation = 0;
     }
     for (hipGraphExec_t &g : c.graphs) {
         if (g) (void)hipGraphExecDestroy(g);

@@ -199,6 +199,21 @@ def test_cycle_and_extended_bitsplitter(i):
         check_minimise(d, tc="auto")
 
 
+def test_column_lists_across_calls():
+    """Consecutive calls whose signatures use different column lists (all
+    letters, a dropped identity letter, the closure levels, then all letters
+    again): the device's list is replaced whenever it differs."""
+    d = W.random_dfa(30000, 3, 0.3, 88)
+    ident = W.DFA(d.delta.copy(), d.accepting.copy(), 0)
+    ident.delta[:, 1] = np.arange(d.n, dtype=np.uint32)
+    for case, tc in ((d, "off"), (ident, "off"), (d, "off"), (d, "on"), (ident, "on"),
+                     (d, "off"), (ident, "off")):
+        res = B.minimise(case.delta, case.accepting, tc=tc)
+        hb, hnb = oracle.hopcroft(case.delta, case.accepting)
+        np.testing.assert_array_equal(res.block, hb)
+        assert res.stats["num_blocks"] == hnb
+
+
 # ---------------------------------------------------------------- equivalence
 
 def test_equivalence_tiny_random_pairs():
