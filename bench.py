@@ -252,8 +252,10 @@ def table2_leg(B, W, torch, np, dev) -> dict:
                                          algorithm=alg).stats
             once()
             sts = [once() for _ in range(3)]
-            row[label] = {"ms": float(np.median([st["device_ms"] for st in sts])),
-                          "rounds": sts[-1]["rounds"], "num_blocks": sts[-1]["num_blocks"]}
+            ms = float(np.median([st["device_ms"] for st in sts]))
+            row[label] = {"ms": ms, "rounds": sts[-1]["rounds"],
+                          "num_blocks": sts[-1]["num_blocks"],
+                          "algorithmic_GBps": sts[-1]["algorithmic_bytes"] / (ms * 1e-3) / 1e9}
         out[name] = row
         del delta, acc, blk
     return out
