@@ -565,7 +565,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     // readback below, so that the device clears while the host waits
     const uint64_t cap = next_pow2(std::max<uint64_t>(2 * N, 1024));
     const size_t words64 = (N + 63) / 64;
-    const size_t sum_words = (N + 4095) / 4096;
+    const size_t sum_words = summary_words(N);
     DFA_TRY(c.table.ensure(cap * sizeof(unsigned long long), "hash table"));
     DFA_TRY(c.chg.ensure(words64 * sizeof(unsigned long long), "changed-id bits"));
     DFA_TRY(c.single.ensure(words64 * sizeof(unsigned long long), "singleton bits"));

@@ -94,5 +94,26 @@ __device__ __forceinline__ void mark_multi(uint32_t *multi, uint32_t id, uint32_
     if (multi[id] != tag) multi[id] = tag;
 }
 
+// Sets the summary bits of the groups holding a changed state, from a wave's
+// changed-id mask (states first .. first + 63, first a multiple of 64).
+__device__ __forceinline__ void set_summary(unsigned long long *sum, size_t first,
+                                            unsigned long long cm) {
+    constexpr uint32_t G = 1u << kSumShift;  // states per bit
+    unsigned long long bits = 0;
+    if constexpr (G >= 64) {
+        bits = cm ? 1ull : 0ull;
+    } else {
+#pragma unroll
+        for (uint32_t g = 0; g < 64 / G; ++g)
+            if ((cm >> (g * G)) & ((1ull << G) - 1ull)) bits |= 1ull << g;
+    }
+    if (bits) atomicOr(sum + (first >> kSumWordShift), bits << ((first >> kSumShift) & 63));
+}
+
+// Whether state t's group is marked in a summary.
+__device__ __forceinline__ bool summary_bit(const unsigned long long *sum, uint32_t t) {
+    return ((sum[t >> kSumWordShift] >> ((t >> kSumShift) & 63)) & 1ull) != 0;
+}
+
 }  // namespace
 }  // namespace dfamin

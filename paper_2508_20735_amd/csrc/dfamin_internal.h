@@ -38,7 +38,18 @@ constexpr int kSpread = 64;        // per-round counters, one per 128-byte line
 constexpr int kSpreadStride = 32;  // uint32 words between two counters
 constexpr uint32_t kPatternMaxBits = 16;  // first round by bit patterns if k_eff + 1 <= 16
 constexpr uint32_t kPackedMaxBits = 25;   // round 1 by packed labels if (k_eff + 1)^2 <= 25
-constexpr uint32_t kSumLdsWords = 2048;  // changed-wave summary words held in LDS (N <= 2^23)
+// Changed-id summary: one bit per group of 2^kSumShift consecutive states,
+// set when a state of the group changed its id in the round; 64 groups per
+// word.  Incremental marking holds up to kSumLdsWords words in LDS.
+constexpr uint32_t kSumShift = 5;
+constexpr uint32_t kSumWordShift = kSumShift + 6;
+constexpr uint32_t kSumLdsWords = 4096;  // 32 KB: N <= 2^23 with 32-state groups
+// workgroups of the marking kernel: each loads the summary into LDS, so fewer
+// and longer-lived workgroups load less
+constexpr uint32_t kMarkGridCap = 1024;
+__host__ __device__ inline size_t summary_words(size_t N) {
+    return (N + (size_t(1) << kSumWordShift) - 1) >> kSumWordShift;
+}
 constexpr uint32_t kPersistentGroupsPerCu = 1;  // workgroups per CU in the persistent loops
 constexpr uint32_t kActiveHist = 64;      // rounds of refined-state counts kept in RoundCtl
 
@@ -180,8 +191,8 @@ struct RoundArgs {
     unsigned long long *chg;      // N/64 words
     unsigned long long *single;   // N/64 words, zero before the first round
     unsigned long long *touched;  // 2 * (N/64) words, zero before the first round
-    // 2 * ceil(N/4096) words: in the words of parity r & 1, bit w is set when a
-    // state of wave w (states 64w .. 64w+63) changed its id in round r
+    // 2 * summary_words(N) words: in the words of parity r & 1, bit g is set
+    // when a state of group g (2^kSumShift states) changed its id in round r
     unsigned long long *chg_sum;
     uint32_t grouping;          // 0: hash table; 1: sort (radix sort of the key hashes)
     uint32_t hash_bits;         // 0: full hashes; else only the low bits (collision tests)

@@ -374,7 +374,7 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
     for (size_t i = global_tid(); i < words; i += grid_stride()) Tn[i] = 0ull;
     // this round's changed-wave summary starts empty (the grouping kernels
     // fill it)
-    const size_t sum_words = (p.N + 4095) >> 12;
+    const size_t sum_words = summary_words(p.N);
     unsigned long long *__restrict__ Sn = p.chg_sum + (r & 1u) * sum_words;
     for (size_t i = global_tid(); i < sum_words; i += grid_stride()) Sn[i] = 0ull;
     if (r <= p.ctl->all_active_until || !incremental_round(*p.ctl, p.N, r)) return;
@@ -382,8 +382,8 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
     const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
     const unsigned long long *__restrict__ chg = p.chg;
     // last round's summary in LDS: a successor's changed-id word is read
-    // only when its wave changed an id (the few waves of an incremental
-    // round), instead of one random gather per transition
+    // only when its group of states changed an id (the few groups of an
+    // incremental round), instead of one random gather per transition
     __shared__ unsigned long long lsum[kSumLdsWords];
     const bool filter = sum_words <= kSumLdsWords;
     if (filter) {
@@ -392,7 +392,7 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
         __syncthreads();
     }
     auto changed = [&](uint32_t t) -> bool {
-        if (filter && !((lsum[t >> 12] >> ((t >> 6) & 63)) & 1ull)) return false;
+        if (filter && !summary_bit(lsum, t)) return false;
         return ((chg[t >> 6] >> (t & 63)) & 1ull) != 0;
     };
     const uint32_t keff = KC > 0 ? static_cast<uint32_t>(KC) : p.k_eff;
@@ -682,14 +682,14 @@ struct InsParams {
     unsigned long long *chg_sum;
 };
 
-// Stores a wave's changed-id mask and, if it is not empty, sets the wave's
-// bit in the round's summary (lane 0 only).
+// Stores a wave's changed-id mask and sets the summary bits of its groups
+// with a changed state (lane 0 only).
 __device__ __forceinline__ void store_changed(unsigned long long *chg, unsigned long long *chg_sum,
                                               size_t N, uint32_t r, size_t first,
                                               unsigned long long cm) {
     if (lane_id() != 0 || first >= N) return;
     chg[first >> 6] = cm;
-    if (cm) atomicOr(chg_sum + (r & 1u) * ((N + 4095) >> 12) + (first >> 12), 1ull << ((first >> 6) & 63));
+    set_summary(chg_sum + (r & 1u) * summary_words(N), first, cm);
 }
 
 // Whether this round stages keys in LDS (uniform across the grid).
@@ -1423,7 +1423,8 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
 
 void launch_mark(const RoundArgs &a, hipStream_t s) {
     const SigParams sp = sig_params(a);
-    const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
+    const unsigned cap = a.round_grid_cap ? std::min(a.round_grid_cap, kMarkGridCap) : kMarkGridCap;
+    const dim3 grid(round_grid(a, cap)), block(kBlock);
     switch (a.k_eff) {
         case 1: hipLaunchKernelGGL(k_mark<1>, grid, block, 0, s, sp); break;
         case 2: hipLaunchKernelGGL(k_mark<2>, grid, block, 0, s, sp); break;

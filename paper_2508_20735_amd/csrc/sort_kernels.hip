@@ -315,10 +315,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_finish(const unsigned long long
         const unsigned long long cm = __ballot(ch);
         if (lane_id() == 0 && first < N) {
             chg[first >> 6] = cm;
-            // the wave's bit in the round's changed-wave summary
-            if (cm)
-                atomicOr(chg_sum + (r & 1u) * ((N + 4095) >> 12) + (first >> 12),
-                         1ull << ((first >> 6) & 63));
+            // the round's changed-id summary
+            set_summary(chg_sum + (r & 1u) * summary_words(N), first, cm);
         }
         changed += ch ? 1u : 0u;
     }
