@@ -185,7 +185,7 @@ typedef struct dfa_tuning {
     uint32_t label_grid_cap; /* workgroups of the label rounds; 0 = one per 256 states */
     uint32_t label_rounds;   /* 0: every round uses the table; 1: round 0 groups by the bit
                                 pattern of acceptance of q and its successors when
-                                k_eff + 1 <= 16; 2: round 1 then groups by the packed
+                                k_eff + 1 <= 17; 2: round 1 then groups by the packed
                                 round-0 labels when (k_eff + 1)^2 <= 25 */
     uint32_t cached_probe;   /* 1: probe the grouping table with cached loads first */
     uint32_t chunk;          /* first chunk's rounds when options.chunk is 0 (1..4096) */

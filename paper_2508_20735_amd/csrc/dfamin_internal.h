@@ -36,7 +36,7 @@ constexpr int kBlock = 256;        // threads per workgroup
 constexpr uint32_t kEpochs = 255;  // table epochs before it is cleared
 constexpr int kSpread = 64;        // per-round counters, one per 128-byte line
 constexpr int kSpreadStride = 32;  // uint32 words between two counters
-constexpr uint32_t kPatternMaxBits = 16;  // first round by bit patterns if k_eff + 1 <= 16
+constexpr uint32_t kPatternMaxBits = 17;  // first round by bit patterns if k_eff + 1 <= 17
 constexpr uint32_t kPackedMaxBits = 25;   // round 1 by packed labels if (k_eff + 1)^2 <= 25
 // Changed-id summary: one bit per group of 2^kSumShift consecutive states,
 // set when a state of the group changed its id in the round; 64 groups per

@@ -1408,6 +1408,7 @@ void launch_signature(const RoundArgs &a, hipStream_t s) {
         case 6: hipLaunchKernelGGL(k_signature<6>, grid, block, 0, s, sp); break;
         case 7: hipLaunchKernelGGL(k_signature<7>, grid, block, 0, s, sp); break;
         case 8: hipLaunchKernelGGL(k_signature<8>, grid, block, 0, s, sp); break;
+        case 16: hipLaunchKernelGGL(k_signature<16>, grid, block, 0, s, sp); break;
         default: hipLaunchKernelGGL(k_signature<0>, grid, block, 0, s, sp); break;
     }
 }

@@ -52,6 +52,7 @@ def check_minimise(d, tc="off", loop="graph", lds=2, quotient=False, ref=None):
     (1, 1, 0.5, 1), (2, 1, 0.5, 2), (3, 2, 0.5, 3), (63, 2, 0.3, 4), (64, 3, 0.5, 5),
     (65, 2, 0.5, 6), (255, 4, 0.1, 7), (256, 2, 0.5, 8), (257, 5, 0.5, 9),
     (1000, 3, 0.2, 10), (4097, 8, 0.4, 11), (12345, 9, 0.3, 12), (5000, 17, 0.5, 13),
+    (20000, 16, 0.3, 21), (3000, 15, 0.4, 22),
 ])
 @pytest.mark.parametrize("loop", LOOPS)
 def test_random_small(n, k, p, seed, loop):

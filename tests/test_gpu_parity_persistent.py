@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 SIZES = [
     (1, 1, 0.5, 1), (2, 1, 0.5, 2), (3, 2, 0.5, 3), (63, 2, 0.3, 4), (64, 3, 0.5, 5),
     (257, 5, 0.5, 9), (4097, 8, 0.4, 11), (12345, 9, 0.3, 12), (5000, 17, 0.5, 13),
+    (20000, 16, 0.3, 21), (3000, 15, 0.4, 22),
     (70000, 4, 0.2, 15), (300000, 2, 0.5, 16),
 ]
 
