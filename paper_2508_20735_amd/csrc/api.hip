@@ -395,7 +395,8 @@ uint32_t grown_chunk(uint32_t chunk, bool tc_pending, bool profiling) {
 
 // Builds the closure columns (all levels) from level 0 in c.cols, and the
 // signature column list.  Returns DFA_ENOMEM if the table does not fit.
-int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, uint32_t &levels) {
+int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, uint32_t &levels,
+                  const unsigned long long *single = nullptr) {
     const uint32_t L = floor_log2(N);
     const size_t ncols = static_cast<size_t>(L + 1) * k;
     DFA_TRY(c.tc_cols.ensure(ncols * N * sizeof(uint32_t), "closure columns"));
@@ -409,6 +410,13 @@ int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, u
     HIP_TRY(hipMemsetAsync(diff, 0, ncols * sizeof(uint32_t), c.stream));
     for (uint32_t i = 1; i <= L; ++i)
         launch_jump(c.tc_cols.as<uint32_t>(), N, k, i, diff, nonid, c.stream);
+    if (single) {
+        // on demand, mid-refinement: only the states outside singleton
+        // blocks are refined from here on, so the columns are judged on them
+        HIP_TRY(hipMemsetAsync(nonid, 0, 2 * ncols * sizeof(uint32_t), c.stream));
+        launch_column_flags(c.tc_cols.as<uint32_t>(), N, k, static_cast<uint32_t>(ncols), single,
+                            diff, nonid, c.stream);
+    }
     HIP_TRY(hipGetLastError());
     DFA_TRY(read_back(c, nonid, 2 * ncols * sizeof(uint32_t)));
     const uint32_t *h_nonid = c.pinned, *h_diff = c.pinned + ncols;
@@ -687,7 +695,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             splitting_stalled(res.ctl, N)) {
             std::vector<uint32_t> tcmap;
             uint32_t levels = 0;
-            int rc = build_closure(c, N, k, tcmap, levels);
+            int rc = build_closure(c, N, k, tcmap, levels, c.single.as<unsigned long long>());
             if (rc == DFA_ENOMEM) {  // stay on the plain letters
                 tc_failed = true;
                 g_last_error.clear();

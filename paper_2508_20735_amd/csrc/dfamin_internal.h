@@ -302,6 +302,12 @@ void launch_reach_expand(const uint8_t *mark, size_t n, const uint32_t *dense,
 // cols[(i*k+a)*N + q] = cols[((i-1)*k+a)*N + cols[((i-1)*k+a)*N + q]];
 // diff[i*k+a] = 1 if the level differs from level i-1 somewhere,
 // nonid[i*k+a] = 1 if it is not the identity.
+// Identity / previous-level flags of ncols closure columns (k letters per
+// level) over the states whose bit in `single` is clear; diff and nonid must
+// be zero.
+void launch_column_flags(const uint32_t *cols, size_t N, uint32_t k, uint32_t ncols,
+                         const unsigned long long *single, uint32_t *diff, uint32_t *nonid,
+                         hipStream_t s);
 void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t *diff,
                  uint32_t *nonid, hipStream_t s);
 

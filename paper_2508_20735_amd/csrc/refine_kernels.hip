@@ -1102,6 +1102,29 @@ __global__ __launch_bounds__(kBlock) void k_jump(uint32_t *__restrict__ cols, si
     wave_set_flag(nonid + static_cast<size_t>(level) * k + a, moves);
 }
 
+// Flags of the closure columns over the states outside singleton blocks:
+// nonid[c] when column c moves such a state, diff[c] when it differs from
+// the previous level of its letter on such a state (level 0: unused).
+// Singletons never split, so a column that is the identity, or repeats its
+// previous level, on every other state only repeats a key component there.
+__global__ __launch_bounds__(kBlock) void k_col_flags(const uint32_t *__restrict__ cols, size_t N,
+                                                      uint32_t k,
+                                                      const unsigned long long *__restrict__ single,
+                                                      uint32_t *diff, uint32_t *nonid) {
+    const uint32_t c = blockIdx.y;
+    const uint32_t *__restrict__ col = cols + static_cast<size_t>(c) * N;
+    const uint32_t *__restrict__ prev = c >= k ? cols + static_cast<size_t>(c - k) * N : col;
+    bool d = false, moves = false;
+    for (size_t q = global_tid(); q < N; q += grid_stride()) {
+        if ((single[q >> 6] >> (q & 63)) & 1ull) continue;
+        const uint32_t t = col[q];
+        d |= t != prev[q];
+        moves |= t != q;
+    }
+    wave_set_flag(diff + c, d);
+    wave_set_flag(nonid + c, moves);
+}
+
 // ---------------------------------------------------------------- canonical ids
 
 __global__ __launch_bounds__(kBlock) void k_zero(ZeroList z) {
@@ -1472,6 +1495,13 @@ hipError_t launch_rounds_persistent(const RoundArgs &a, uint32_t rounds, hipStre
     RoundCtl *ctl = a.ctl;
     void *args[] = {&sp, &ip, &ctl, &rounds};
     return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+void launch_column_flags(const uint32_t *cols, size_t N, uint32_t k, uint32_t ncols,
+                         const unsigned long long *single, uint32_t *diff, uint32_t *nonid,
+                         hipStream_t s) {
+    dim3 grid(grid_for(N, kDefaultGridCap / 4), ncols);
+    hipLaunchKernelGGL(k_col_flags, grid, dim3(kBlock), 0, s, cols, N, k, single, diff, nonid);
 }
 
 void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t *diff,
