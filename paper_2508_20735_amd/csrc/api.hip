@@ -432,6 +432,26 @@ int build_closure(Ctx &c, size_t N, uint32_t k, std::vector<uint32_t> &colmap, u
     return DFA_OK;
 }
 
+// Judges the closure columns again on the states outside singleton blocks
+// (only those are refined from now on) and keeps, of `colmap`, the columns
+// that are not the identity there and differ from their letter's previous
+// level there; a dropped column only repeats a key component on those states.
+int rejudge_columns(Ctx &c, size_t N, uint32_t k, uint32_t levels,
+                    const std::vector<uint32_t> &colmap, std::vector<uint32_t> &kept) {
+    const size_t ncols = static_cast<size_t>(levels + 1) * k;
+    uint32_t *nonid = c.flags.as<uint32_t>() + kFlagNonid;
+    uint32_t *diff = nonid + ncols;
+    HIP_TRY(hipMemsetAsync(nonid, 0, 2 * ncols * sizeof(uint32_t), c.stream));
+    launch_column_flags(c.tc_cols.as<uint32_t>(), N, k, static_cast<uint32_t>(ncols),
+                        c.single.as<unsigned long long>(), diff, nonid, c.stream);
+    HIP_TRY(hipGetLastError());
+    DFA_TRY(read_back(c, nonid, 2 * ncols * sizeof(uint32_t)));
+    kept.clear();
+    for (uint32_t col : colmap)
+        if (c.pinned[col] && (col < k || c.pinned[ncols + col])) kept.push_back(col);
+    return DFA_OK;
+}
+
 int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
     DFA_TRY(c.colmap.ensure(std::max<size_t>(colmap.size(), 1) * sizeof(uint32_t), "colmap"));
     // the list usually repeats from call to call: upload (a synchronous
@@ -614,6 +634,9 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     }
     DFA_TRY(set_colmap(c, colmap));
     uint32_t k_eff = static_cast<uint32_t>(colmap.size());
+    // closure columns are judged once more when many states are singletons
+    // (AUTO judges them on the remaining states when it builds them)
+    bool rejudged = false;
     DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
     DFA_TRY(c.hash.ensure(N * sizeof(uint64_t), "hashes"));
     const uint32_t grouping = (o.algorithm == DFA_ALGO_SORT && !seg) ? 1u : 0u;
@@ -703,6 +726,8 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             }
             DFA_TRY(rc);
             DFA_TRY(set_colmap(c, tcmap));
+            colmap = tcmap;
+            rejudged = true;
             k_eff = static_cast<uint32_t>(tcmap.size());
             DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
             // new letters: the next round refines every multi-state block
@@ -711,6 +736,18 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             res.tc_used = 1;
             res.tc_levels = levels;
             res.plain_rounds = res.ctl.round;
+        }
+        // closure built before any state was a singleton (tc ON): once a
+        // quarter of the states are, its columns are judged on the others
+        if (res.tc_used && !rejudged && !seg && res.ctl.prev_count >= N / 4) {
+            rejudged = true;
+            std::vector<uint32_t> kept;
+            DFA_TRY(rejudge_columns(c, N, k, res.tc_levels, colmap, kept));
+            if (!kept.empty() && kept.size() < colmap.size()) {
+                colmap = kept;
+                DFA_TRY(set_colmap(c, colmap));
+                k_eff = static_cast<uint32_t>(colmap.size());
+            }
         }
         if (!o.chunk)
             chunk = grown_chunk(chunk, o.tc_mode == DFA_TC_AUTO && !seg && !res.tc_used && !tc_failed,
