@@ -466,10 +466,12 @@ int set_colmap(Ctx &c, const std::vector<uint32_t> &colmap) {
 }
 
 // Adds the first `bytes` of b (rounded up to 8) to a zeroing list.
-void zero_add(ZeroList &z, Buffer &b, size_t bytes) {
+int zero_add(ZeroList &z, Buffer &b, size_t bytes) {
+    if (z.count >= kZeroRegions) return fail(DFA_EDEVICE, "internal: zeroing list is full");
     z.p[z.count] = b.as<unsigned long long>();
     z.words[z.count] = (bytes + 7) / 8;
     ++z.count;
+    return DFA_OK;
 }
 
 // Enqueues `rounds` rounds of signature (ra) or leader (la != nullptr)
@@ -606,11 +608,12 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         DFA_TRY(c.presence_packed.ensure((size_t(1) << kPackedMaxBits) / 8, "label bitmap"));
     {
         ZeroList z{};
-        zero_add(z, c.table, cap * sizeof(unsigned long long));
-        zero_add(z, c.single, words64 * sizeof(unsigned long long));
-        zero_add(z, c.touched, 2 * words64 * sizeof(unsigned long long));
-        zero_add(z, c.chg_sum, 2 * sum_words * sizeof(unsigned long long));
-        if (packed_possible) zero_add(z, c.presence_packed, (size_t(1) << kPackedMaxBits) / 8);
+        DFA_TRY(zero_add(z, c.table, cap * sizeof(unsigned long long)));
+        DFA_TRY(zero_add(z, c.single, words64 * sizeof(unsigned long long)));
+        DFA_TRY(zero_add(z, c.touched, 2 * words64 * sizeof(unsigned long long)));
+        DFA_TRY(zero_add(z, c.chg_sum, 2 * sum_words * sizeof(unsigned long long)));
+        if (packed_possible)
+            DFA_TRY(zero_add(z, c.presence_packed, (size_t(1) << kPackedMaxBits) / 8));
         launch_zero(z, c.stream);
         HIP_TRY(hipGetLastError());
     }
@@ -935,11 +938,11 @@ int prepare_refinement(Ctx &c, size_t N, uint32_t k) {
     DFA_TRY(c.presence.ensure((1u << kPatternMaxBits) / 8, "pattern bitmap"));
     // every clear in one launch (separate memsets cost host time each)
     ZeroList z{};
-    zero_add(z, c.flags, (kFlagNonid + k) * sizeof(uint32_t));
-    zero_add(z, c.multi, N * sizeof(uint32_t));
-    zero_add(z, c.accbits, words64 * sizeof(unsigned long long));
-    zero_add(z, c.counters, kSpread * kSpreadStride * sizeof(uint32_t));
-    zero_add(z, c.presence, (1u << kPatternMaxBits) / 8);
+    DFA_TRY(zero_add(z, c.flags, (kFlagNonid + k) * sizeof(uint32_t)));
+    DFA_TRY(zero_add(z, c.multi, N * sizeof(uint32_t)));
+    DFA_TRY(zero_add(z, c.accbits, words64 * sizeof(unsigned long long)));
+    DFA_TRY(zero_add(z, c.counters, kSpread * kSpreadStride * sizeof(uint32_t)));
+    DFA_TRY(zero_add(z, c.presence, (1u << kPatternMaxBits) / 8));
     launch_zero(z, c.stream);
     HIP_TRY(hipGetLastError());
     return DFA_OK;
