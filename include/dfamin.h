@@ -101,7 +101,7 @@ typedef struct dfa_options {
     uint32_t max_rounds;  /* 0 = until stable */
     uint32_t chunk;       /* rounds per chunk in CHUNK/GRAPH mode; 0 = automatic: the
                              tuned start length (dfa_tuning.chunk), doubled after each
-                             chunk that did not finish, up to 256 rounds (32 while
+                             chunk that did not finish, up to 256 rounds (8 while
                              TC AUTO may still switch the closure on) */
     int32_t lds_stage;    /* 1 = pre-group keys in LDS before the global table,
                              0 = insert every key into the global table,

@@ -369,7 +369,7 @@ struct RefineResult {
 
 // Whether plain rounds have stalled, after at least 8 rounds: over the last
 // four rounds no round added more than 1/4096 of the states still to be
-// separated (large inputs), or, after 32 rounds, no more than 1/64 of them
+// separated (large inputs), or, after 16 rounds, no more than 1/64 of them
 // (small ones, where the closure is cheap and the remaining rounds would
 // each split a block or two).
 bool splitting_stalled(const RoundCtl &ctl, size_t N) {
@@ -379,16 +379,16 @@ bool splitting_stalled(const RoundCtl &ctl, size_t N) {
     for (uint32_t i = 1; i <= 4 && i <= ctl.round; ++i)
         recent_gain = std::max<uint64_t>(recent_gain, ctl.gain_hist[(ctl.round - i) % kActiveHist]);
     return (left >= 4096 && recent_gain * 4096 < left) ||
-           (ctl.round >= 32 && recent_gain * 64 < left);
+           (ctl.round >= 16 && recent_gain * 64 < left);
 }
 
 // Rounds in the next chunk when the caller leaves the length to the library:
 // the tuned start length, doubled after every chunk that did not finish, up
-// to 256 rounds (32 while the closure may still be switched on, so that a
+// to 256 rounds (8 while the closure may still be switched on, so that a
 // stall is seen soon after it starts).  Short refinements keep few no-op
 // rounds; long ones need few host round trips.
 uint32_t grown_chunk(uint32_t chunk, bool tc_pending, bool profiling) {
-    uint32_t cap = tc_pending ? 32u : 256u;
+    uint32_t cap = tc_pending ? 8u : 256u;
     if (profiling) cap = std::min(cap, kActiveHist);
     return std::max(chunk, std::min(chunk * 2, cap));
 }
@@ -637,9 +637,12 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     }
     DFA_TRY(set_colmap(c, colmap));
     uint32_t k_eff = static_cast<uint32_t>(colmap.size());
-    // closure columns are judged once more when many states are singletons
-    // (AUTO judges them on the remaining states when it builds them)
+    // closure columns are judged once more on the states outside singleton
+    // blocks: built first (tc ON), once a quarter of the states are
+    // singletons; built on demand, after the first chunk on the new columns
+    // (singleton marks lag a round behind the splits)
     bool rejudged = false;
+    uint32_t switched_at = 0;
     DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
     DFA_TRY(c.hash.ensure(N * sizeof(uint64_t), "hashes"));
     const uint32_t grouping = (o.algorithm == DFA_ALGO_SORT && !seg) ? 1u : 0u;
@@ -730,7 +733,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             DFA_TRY(rc);
             DFA_TRY(set_colmap(c, tcmap));
             colmap = tcmap;
-            rejudged = true;
+            switched_at = res.ctl.round;
             k_eff = static_cast<uint32_t>(tcmap.size());
             DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
             // new letters: the next round refines every multi-state block
@@ -740,9 +743,10 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
             res.tc_levels = levels;
             res.plain_rounds = res.ctl.round;
         }
-        // closure built before any state was a singleton (tc ON): once a
-        // quarter of the states are, its columns are judged on the others
-        if (res.tc_used && !rejudged && !seg && res.ctl.prev_count >= N / 4) {
+        // the closure's columns judged again on the states outside singleton
+        // blocks (see above)
+        if (res.tc_used && !rejudged && !seg &&
+            (switched_at ? res.ctl.round > switched_at : res.ctl.prev_count >= N / 4)) {
             rejudged = true;
             std::vector<uint32_t> kept;
             DFA_TRY(rejudge_columns(c, N, k, res.tc_levels, colmap, kept));
