@@ -1,0 +1,93 @@
+"""GPU parity of every option combination on tiny and degenerate DFAs (one
+state, all states accepting or rejecting, identity letters, a self-loop
+chain): algorithm x closure mode x loop mode x pruning, each against the
+oracle (Hopcroft's partition, or the reachable part's with pruning).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_20735_amd import binding as B
+from paper_2508_20735_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    rng = np.random.default_rng(2024)
+    out = []
+    for n, k in ((1, 1), (1, 3), (2, 1), (2, 3), (5, 2), (40, 3)):
+        delta = rng.integers(0, n, (n, k)).astype(np.uint32)
+        for acc_kind in ("random", "all", "none"):
+            acc = {"random": rng.integers(0, 2, n), "all": np.ones(n),
+                   "none": np.zeros(n)}[acc_kind].astype(np.uint8)
+            out.append((f"n{n}k{k}{acc_kind}", W.DFA(delta.copy(), acc, 0)))
+    # identity letters next to a moving one, and a chain
+    ident = np.tile(np.arange(7, dtype=np.uint32)[:, None], (1, 3))
+    ident[:, 1] = (np.arange(7) + 1) % 7
+    out.append(("ident", W.DFA(ident, np.array([1, 0, 0, 1, 0, 0, 0], dtype=np.uint8), 2)))
+    out.append(("chain", W.chain_with_tail(33, 17, 9)))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name,d", CASES, ids=[c[0] for c in CASES])
+def test_every_option_combination(name, d):
+    hb, hnb = oracle.hopcroft(d.delta, d.accepting)
+    rb, rnb, rn = oracle.minimise_reachable(d.delta, d.accepting, d.start)
+    for alg, tc, loop, prune in itertools.product(("signature", "sort", "leader"),
+                                                  ("off", "on", "auto"),
+                                                  ("host", "chunk", "graph", "persistent"),
+                                                  (False, True)):
+        if loop == "persistent" and alg == "sort":
+            continue  # rejected (EINVAL), checked in the ABI tests
+        res = B.minimise(d.delta, d.accepting, tc=tc, loop=loop, algorithm=alg, prune=prune,
+                         start=d.start, quotient=True)
+        want, wnb = (rb, rnb) if prune else (hb, hnb)
+        np.testing.assert_array_equal(res.block, want, err_msg=f"{alg} {tc} {loop} {prune}")
+        assert res.stats["num_blocks"] == wnb, (alg, tc, loop, prune)
+        gn, gd, ga, gs = res.quotient
+        assert gn == wnb
+        # the quotient is minimal and equivalent to the input from its start
+        assert oracle.hopcroft(gd, ga)[1] == gn
+        assert oracle.equiv_hk(d.delta, d.accepting, d.start, gd, ga, gs)
+
+
+def _pairs():
+    by_k = {}
+    for name, d in CASES:
+        by_k.setdefault(d.k, []).append((name, d))
+    out = []
+    for k, group in sorted(by_k.items()):
+        for (na, a), (nb, b) in itertools.product(group, group):
+            out.append((f"{na}-{nb}", a, b))
+    return out
+
+
+PAIRS = _pairs()
+
+
+@pytest.mark.parametrize("k", sorted({d.k for _, d in CASES}))
+def test_equivalence_and_inclusion_every_method(k):
+    """Equivalence (union refinement under each algorithm, closure and loop
+    mode, and the product search) and inclusion in both directions, on every
+    ordered pair of the cases above over the same alphabet."""
+    for name, a, b in (p for p in PAIRS if p[1].k == k):
+        want = oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
+        for alg, tc, loop in itertools.product(("signature", "sort", "leader"),
+                                               ("off", "auto"), ("host", "graph", "persistent")):
+            if loop == "persistent" and alg == "sort":
+                continue
+            got, _ = B.equivalent(a, b, tc=tc, loop=loop, algorithm=alg)
+            assert got == want, (name, alg, tc, loop)
+        got, st = B.equivalent(a, b, method="product")
+        assert got == want, (name, "product")
+        for x, y in ((a, b), (b, a)):
+            inc = oracle.included(x.delta, x.accepting, x.start, y.delta, y.accepting, y.start)
+            got, pairs, _ = B.included(x, y)
+            assert got == inc, (name, "included")
+            assert pairs >= 1
