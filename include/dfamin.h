@@ -34,6 +34,12 @@
  *   - Calls block until their results are ready.  Calls on one device are
  *     serialised inside the library (it keeps one grow-only device workspace
  *     per device).
+ *   - Calls may come from several host threads.  The graph loop builds its
+ *     round graphs node by node and captures no stream, so nothing another
+ *     thread does can disturb it.  During a call, the calling thread's
+ *     stream-capture interaction mode is relaxed, so the library's
+ *     allocations never invalidate a capture that another thread (of the
+ *     caller, or another library) has in progress.
  *   - The caller owns every buffer it passes; the library keeps no pointer
  *     after a call returns.
  *   - Host-pointer calls (dfa_minimise, dfa_equivalent, dfa_included) copy the
@@ -85,7 +91,7 @@ extern "C" {
 #define DFA_LOOP_CHUNK 1 /* rounds are enqueued in chunks; kernels turn into no-ops
                             on the device once the partition is stable; the host
                             checks once per chunk */
-#define DFA_LOOP_GRAPH 2 /* like CHUNK, each chunk replayed from a captured hipGraph */
+#define DFA_LOOP_GRAPH 2 /* like CHUNK, each chunk replayed from a hipGraph (built once per chunk shape) */
 #define DFA_LOOP_PERSISTENT 3 /* each chunk is one cooperative launch that loops over
                                  the rounds on the device, its phases separated by grid
                                  barriers, and stops as soon as the partition is stable

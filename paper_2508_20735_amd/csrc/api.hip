@@ -24,6 +24,12 @@
 #include "dfamin_internal.h"
 
 namespace dfamin {
+
+GraphRecorder *&graph_recorder() {
+    thread_local GraphRecorder *recorder = nullptr;
+    return recorder;
+}
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -88,7 +94,7 @@ struct Buffer {
 
 constexpr size_t kPinnedWords = 1u << 16;
 
-// A captured chunk is reused while the round arguments and the chunk length
+// A chunk graph is reused while the round arguments and the chunk length
 // are unchanged (RoundArgs / LeaderArgs values are built from zeroed storage,
 // so they can be compared bytewise).
 struct GraphKey {
@@ -97,6 +103,25 @@ struct GraphKey {
     uint32_t chunk;
     uint32_t leader;
     bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof *this) == 0; }
+};
+
+// Holds one device context's lock for the length of a library call, and for
+// that long lets the calling thread allocate, free and synchronise without
+// invalidating a graph capture that another thread (a server lane, another
+// caller) has in progress: the thread's capture interaction mode is relaxed,
+// and the caller's own mode comes back on return.
+struct RelaxedCapture {
+    hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+    RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&mode); }
+    ~RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&mode); }
+    RelaxedCapture(const RelaxedCapture &) = delete;
+    RelaxedCapture &operator=(const RelaxedCapture &) = delete;
+};
+
+struct CallScope {
+    RelaxedCapture relaxed;
+    std::lock_guard<std::mutex> lock;
+    explicit CallScope(std::mutex &m) : lock(m) {}
 };
 
 struct Ctx {
@@ -131,7 +156,7 @@ struct Ctx {
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     size_t pinned_batch_cap = 0;
-    // captured chunks, one per chunk length in use (automatic chunks grow
+    // chunk graphs, one per chunk length in use (automatic chunks grow
     // 4, 8, ..., 256 within one call), replaced round-robin
     static constexpr int kGraphSlots = 8;
     hipGraphExec_t graphs[kGraphSlots] = {};
@@ -474,8 +499,38 @@ int zero_add(ZeroList &z, Buffer &b, size_t bytes) {
     return DFA_OK;
 }
 
+// Builds `rounds` rounds into an executable graph, node by node (the launch
+// helpers append kernel nodes while a recorder is set on this thread), so no
+// stream is captured and no other thread's call can disturb the build.
+int build_round_graph(const RoundArgs &ra, const LeaderArgs *la, uint32_t rounds,
+                      hipGraphExec_t &out) {
+    out = nullptr;
+    GraphRecorder rec;
+    HIP_TRY(hipGraphCreate(&rec.graph, 0));
+    {
+        struct Recording {
+            explicit Recording(GraphRecorder *r) { graph_recorder() = r; }
+            ~Recording() { graph_recorder() = nullptr; }
+        } recording(&rec);
+        for (uint32_t i = 0; i < rounds && rec.error == hipSuccess; ++i) {
+            if (la)
+                launch_leader_round(*la, nullptr);
+            else
+                launch_round(ra, nullptr);
+        }
+    }
+    hipError_t e = rec.error;
+    if (e == hipSuccess) e = hipGraphInstantiate(&out, rec.graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(rec.graph);
+    if (e != hipSuccess) {
+        out = nullptr;
+        return fail(DFA_EDEVICE, "building the round graph: %s", hipGetErrorString(e));
+    }
+    return DFA_OK;
+}
+
 // Enqueues `rounds` rounds of signature (ra) or leader (la != nullptr)
-// refinement, from a captured graph in GRAPH mode.
+// refinement, from a graph in GRAPH mode.
 int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t first_round,
               const LeaderArgs *la = nullptr) {
     if (mode == DFA_LOOP_PERSISTENT && !c.profiling) {
@@ -504,21 +559,7 @@ int run_chunk(Ctx &c, const RoundArgs &ra, uint32_t rounds, int mode, uint32_t f
                 (void)hipGraphExecDestroy(c.graphs[slot]);
                 c.graphs[slot] = nullptr;
             }
-            hipGraph_t g = nullptr;
-            HIP_TRY(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
-            for (uint32_t i = 0; i < rounds; ++i) {
-                if (la)
-                    launch_leader_round(*la, c.stream);
-                else
-                    launch_round(ra, c.stream);
-            }
-            HIP_TRY(hipStreamEndCapture(c.stream, &g));
-            hipError_t e = hipGraphInstantiate(&c.graphs[slot], g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                c.graphs[slot] = nullptr;
-                return fail(DFA_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-            }
+            DFA_TRY(build_round_graph(ra, la, rounds, c.graphs[slot]));
             c.graph_keys[slot] = key;
         }
         HIP_TRY(hipGraphLaunch(c.graphs[slot], c.stream));
@@ -1944,6 +1985,8 @@ void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
 }
 
 void lane_main(Server *sp, size_t lane) {
+    // the lane allocates and synchronises while other threads may capture
+    RelaxedCapture relaxed;
     Server &s = *sp;
     (void)hipSetDevice(s.device);
     Ctx &c = *s.lanes[lane];
@@ -2066,7 +2109,7 @@ extern "C" {
 int dfa_profile_enable(int on) {
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     c->profiling = on != 0;
     c->ktimes.clear();
@@ -2080,7 +2123,7 @@ int dfa_profile_only(const char *name) {
         return fail(DFA_EINVAL, "kernel name too long");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     c->prof_only = name ? name : "";
     return DFA_OK;
 }
@@ -2089,7 +2132,7 @@ int dfa_profile_read(dfa_kernel_time *out, int cap, int *count) {
     if (!count || (cap > 0 && !out)) return fail(DFA_EINVAL, "NULL profile buffer");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     int i = 0;
     for (const auto &kv : c->ktimes) {
@@ -2120,7 +2163,7 @@ int dfa_get_tuning(dfa_tuning *t) {
     if (!t) return fail(DFA_EINVAL, "tuning is NULL");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     *t = c->tune;
     return DFA_OK;
@@ -2133,7 +2176,7 @@ int dfa_set_tuning(const dfa_tuning *t) {
         return fail(DFA_EINVAL, "tuning value out of range");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     c->tune = *t;
     return DFA_OK;
@@ -2173,7 +2216,7 @@ int dfa_minimise_device(uint32_t n, uint32_t k, const uint32_t *delta, const uin
     DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     DFA_TRY(join_stream(*c, stream));
     if (stats) std::memset(stats, 0, sizeof *stats);
@@ -2188,7 +2231,7 @@ int dfa_minimise(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *a
     DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     return minimise_host(*c, n, k, delta, accepting, block_out, q_out, o, stats);
 }
@@ -2202,7 +2245,7 @@ int dfa_equivalent_device(const dfa_view *a, const dfa_view *b, int *verdict,
     if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     DFA_TRY(join_stream(*c, stream));
     if (stats) std::memset(stats, 0, sizeof *stats);
@@ -2218,7 +2261,7 @@ int dfa_equivalent(const dfa_view *a, const dfa_view *b, int *verdict, const dfa
     if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     return equivalent_host(*c, a, b, verdict, o, stats);
 }
@@ -2233,7 +2276,7 @@ int dfa_included_device(const dfa_view *a, const dfa_view *b, int *verdict,
     if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     DFA_TRY(join_stream(*c, stream));
     return included_impl(*c, *a, *b, verdict, pairs_visited, stats);
@@ -2248,7 +2291,7 @@ int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *p
     if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     auto t0 = std::chrono::steady_clock::now();
     dfa_view da, db;
@@ -2273,7 +2316,7 @@ int dfa_minimise_batch_device(uint32_t count, const dfa_view *dfas, uint32_t *bl
     if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     DFA_TRY(join_stream(*c, stream));
     if (stats) std::memset(stats, 0, sizeof *stats);
@@ -2291,7 +2334,7 @@ int dfa_minimise_batch(uint32_t count, const dfa_view *dfas, uint32_t *blocks_co
     if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     if (stats) std::memset(stats, 0, sizeof *stats);
     std::vector<dfa_view> dev;
@@ -2336,7 +2379,7 @@ int dfa_equivalent_batch_device(uint32_t count, const dfa_view *a, const dfa_vie
         if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     DFA_TRY(join_stream(*c, stream));
     if (stats) std::memset(stats, 0, sizeof *stats);
@@ -2355,7 +2398,7 @@ int dfa_equivalent_batch(uint32_t count, const dfa_view *a, const dfa_view *b, i
         if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
     Ctx *c = nullptr;
     DFA_TRY(get_ctx(c));
-    std::lock_guard<std::mutex> lock(c->mu);
+    CallScope lock(c->mu);
     DFA_TRY(init_ctx(*c));
     if (stats) std::memset(stats, 0, sizeof *stats);
     std::vector<dfa_view> dev;
@@ -2380,6 +2423,7 @@ void dfa_server_config_default(dfa_server_config *cfg) {
 }
 
 dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
+    RelaxedCapture relaxed;
     g_last_error.clear();
     dfa_server_config cfg;
     dfa_server_config_default(&cfg);
@@ -2406,7 +2450,7 @@ dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
     {
         Ctx *dc = nullptr;
         if (get_ctx(dc) != DFA_OK) return nullptr;
-        std::lock_guard<std::mutex> lock(dc->mu);
+        CallScope lock(dc->mu);
         if (init_ctx(*dc) != DFA_OK) return nullptr;
         s->tune = dc->tune;
     }
@@ -2418,6 +2462,7 @@ dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
 }
 
 int dfa_server_submit(dfa_server *handle, const dfa_request *req, uint64_t *ticket) {
+    RelaxedCapture relaxed;  // page-locked staging may be allocated here
     g_last_error.clear();
     Server *s = reinterpret_cast<Server *>(handle);
     if (!s || !req || !ticket) return fail(DFA_EINVAL, "NULL server, request or ticket");
@@ -2500,6 +2545,7 @@ int dfa_server_wait(dfa_server *handle, uint64_t ticket, dfa_result *out) {
 }
 
 int dfa_result_release(dfa_server *handle, uint64_t ticket) {
+    RelaxedCapture relaxed;
     Server *s = reinterpret_cast<Server *>(handle);
     if (!s) return fail(DFA_EINVAL, "NULL server");
     std::lock_guard<std::mutex> lk(s->mu);
@@ -2544,6 +2590,7 @@ int dfa_server_get_stats(dfa_server *handle, dfa_server_stats *out) {
 }
 
 void dfa_server_destroy(dfa_server *handle) {
+    RelaxedCapture relaxed;
     Server *s = reinterpret_cast<Server *>(handle);
     if (!s) return;
     {

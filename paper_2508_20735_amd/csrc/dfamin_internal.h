@@ -30,6 +30,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "launch.h"
+
 namespace dfamin {
 
 constexpr int kBlock = 256;        // threads per workgroup

@@ -268,21 +268,21 @@ hipError_t launch_leader_persistent(const LeaderArgs &a, uint32_t rounds, hipStr
 void launch_leader_init(const unsigned long long *accbits, size_t N, uint32_t *lead,
                         uint32_t *block, hipStream_t s) {
     const unsigned g = leader_grid(N);
-    hipLaunchKernelGGL(k_class_leaders, dim3(leader_grid((N + 63) / 64)), dim3(kBlock), 0, s,
+    launch_kernel(k_class_leaders, dim3(leader_grid((N + 63) / 64)), dim3(kBlock), 0, s,
                        accbits, N, lead);
-    hipLaunchKernelGGL(k_leader_blocks, dim3(g), dim3(kBlock), 0, s, accbits, N, lead, block);
+    launch_kernel(k_leader_blocks, dim3(g), dim3(kBlock), 0, s, accbits, N, lead, block);
 }
 
 void launch_leader_elect(const LeaderArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_leader_elect, dim3(leader_grid(a.N)), dim3(kBlock), 0, s, a);
+    launch_kernel(k_leader_elect, dim3(leader_grid(a.N)), dim3(kBlock), 0, s, a);
 }
 
 void launch_leader_move(const LeaderArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_leader_move, dim3(leader_grid(a.N)), dim3(kBlock), 0, s, a);
+    launch_kernel(k_leader_move, dim3(leader_grid(a.N)), dim3(kBlock), 0, s, a);
 }
 
 void launch_leader_end(const LeaderArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_leader_end, dim3(1), dim3(kBlock), 0, s, a.ctl, a.block, a.counters);
+    launch_kernel(k_leader_end, dim3(1), dim3(kBlock), 0, s, a.ctl, a.block, a.counters);
 }
 
 void launch_leader_round(const LeaderArgs &a, hipStream_t s) {

@@ -164,27 +164,27 @@ unsigned grid_for(size_t work) {
 }  // namespace
 
 void launch_product_level(const ProductArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_product_level, dim3(grid_for(a.frontier_size)), dim3(kBlock), 0, s, a);
+    launch_kernel(k_product_level, dim3(grid_for(a.frontier_size)), dim3(kBlock), 0, s, a);
 }
 
 void launch_product_narrow(const ProductArgs &a, uint32_t max_levels, uint32_t *out,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_product_narrow, dim3(1), dim3(kProductNarrowThreads), 0, s, a, max_levels,
+    launch_kernel(k_product_narrow, dim3(1), dim3(kProductNarrowThreads), 0, s, a, max_levels,
                        out);
 }
 
 void launch_visited_clear(unsigned long long *visited, uint64_t cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_visited_clear, dim3(grid_for(cap)), dim3(kBlock), 0, s, visited, cap);
+    launch_kernel(k_visited_clear, dim3(grid_for(cap)), dim3(kBlock), 0, s, visited, cap);
 }
 
 void launch_visited_insert_start(unsigned long long *visited, uint64_t cap,
                                  unsigned long long key, hipStream_t s) {
-    hipLaunchKernelGGL(k_visited_insert_start, dim3(1), dim3(64), 0, s, visited, cap, key);
+    launch_kernel(k_visited_insert_start, dim3(1), dim3(64), 0, s, visited, cap, key);
 }
 
 void launch_rehash(const unsigned long long *old_tab, uint64_t old_cap,
                    unsigned long long *new_tab, uint64_t new_cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_rehash, dim3(grid_for(old_cap)), dim3(kBlock), 0, s, old_tab, old_cap,
+    launch_kernel(k_rehash, dim3(grid_for(old_cap)), dim3(kBlock), 0, s, old_tab, old_cap,
                        new_tab, new_cap);
 }
 

@@ -203,49 +203,49 @@ unsigned grid_of(uint64_t work, unsigned cap = 8192) {
 
 void launch_check_targets(const uint32_t *delta, uint64_t total, uint32_t n, uint32_t *err,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_check_targets, dim3(grid_of(total)), dim3(kBlock), 0, s, delta, total, n,
+    launch_kernel(k_check_targets, dim3(grid_of(total)), dim3(kBlock), 0, s, delta, total, n,
                        err);
 }
 
 void launch_bfs_init(const ReachArgs &a, uint32_t start, hipStream_t s) {
-    hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, s, a, start);
+    launch_kernel(k_bfs_init, dim3(1), dim3(64), 0, s, a, start);
 }
 
 void launch_bfs_narrow(const ReachArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_bfs_narrow, dim3(1), dim3(kNarrowThreads), 0, s, a);
+    launch_kernel(k_bfs_narrow, dim3(1), dim3(kNarrowThreads), 0, s, a);
 }
 
 void launch_bfs_list_to_marks(const ReachArgs &a, uint32_t count, uint8_t f, hipStream_t s) {
-    hipLaunchKernelGGL(k_bfs_list_to_marks, dim3(grid_of(count)), dim3(kBlock), 0, s, a, f);
+    launch_kernel(k_bfs_list_to_marks, dim3(grid_of(count)), dim3(kBlock), 0, s, a, f);
 }
 
 void launch_bfs_dense(const ReachArgs &a, uint8_t f, uint8_t nf, hipStream_t s) {
-    hipLaunchKernelGGL(k_bfs_set, dim3(1), dim3(64), 0, s, a.sizes, 1u, 0u, 1u, 0u);
-    hipLaunchKernelGGL(k_bfs_dense, dim3(grid_of(a.n)), dim3(kBlock), 0, s, a, f, nf);
+    launch_kernel(k_bfs_set, dim3(1), dim3(64), 0, s, a.sizes, 1u, 0u, 1u, 0u);
+    launch_kernel(k_bfs_dense, dim3(grid_of(a.n)), dim3(kBlock), 0, s, a, f, nf);
 }
 
 void launch_bfs_marks_to_list(const ReachArgs &a, uint8_t f, hipStream_t s) {
-    hipLaunchKernelGGL(k_bfs_set, dim3(1), dim3(64), 0, s, a.sizes, 0u, 0u, 0u, 0u);
-    hipLaunchKernelGGL(k_bfs_marks_to_list, dim3(grid_of(a.n)), dim3(kBlock), 0, s, a, f);
+    launch_kernel(k_bfs_set, dim3(1), dim3(64), 0, s, a.sizes, 0u, 0u, 0u, 0u);
+    launch_kernel(k_bfs_marks_to_list, dim3(grid_of(a.n)), dim3(kBlock), 0, s, a, f);
 }
 
 uint32_t bfs_narrow_cap() { return kNarrowCap; }
 
 void launch_reach_flags(const uint8_t *mark, size_t n, uint32_t *flags, hipStream_t s) {
-    hipLaunchKernelGGL(k_reach_flags, dim3(grid_of(n)), dim3(kBlock), 0, s, mark, n, flags);
+    launch_kernel(k_reach_flags, dim3(grid_of(n)), dim3(kBlock), 0, s, mark, n, flags);
 }
 
 void launch_sub_dfa(const uint32_t *delta, const uint8_t *acc, uint32_t k, const uint32_t *orig,
                     const uint32_t *dense, const uint32_t *m_dev, uint32_t m_host,
                     uint32_t *sub_delta, uint8_t *sub_acc, hipStream_t s) {
-    hipLaunchKernelGGL(k_sub_dfa, dim3(grid_of(static_cast<uint64_t>(m_host) * k)), dim3(kBlock),
+    launch_kernel(k_sub_dfa, dim3(grid_of(static_cast<uint64_t>(m_host) * k)), dim3(kBlock),
                        0, s, delta, acc, k, orig, dense, m_dev, sub_delta, sub_acc);
 }
 
 void launch_reach_expand(const uint8_t *mark, size_t n, const uint32_t *dense,
                          const uint32_t *orig, const uint32_t *sub_block, uint32_t *block_out,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_reach_expand, dim3(grid_of(n)), dim3(kBlock), 0, s, mark, n, dense,
+    launch_kernel(k_reach_expand, dim3(grid_of(n)), dim3(kBlock), 0, s, mark, n, dense,
                        orig, sub_block, block_out);
 }
 

@@ -1327,60 +1327,60 @@ hipError_t coresident_grid(const void *kernel, unsigned &grid) {
 void launch_ingest(const uint32_t *delta, uint32_t n, uint32_t k, uint32_t *cols, size_t N,
                    uint32_t offset, uint32_t target_offset, uint32_t *err, uint32_t *nonid,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_ingest, dim3(grid_for(n)), dim3(kBlock), 0, s, delta, n, k, cols, N,
+    launch_kernel(k_ingest, dim3(grid_for(n)), dim3(kBlock), 0, s, delta, n, k, cols, N,
                        offset, target_offset, err, nonid);
 }
 
 void launch_init_blocks(const uint8_t *acc, uint32_t n, uint32_t offset, uint32_t *block,
                         unsigned long long *accbits, uint32_t *class_flags, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_blocks, dim3(grid_for(n, kDefaultGridCap)), dim3(kBlock), 0, s, acc,
+    launch_kernel(k_init_blocks, dim3(grid_for(n, kDefaultGridCap)), dim3(kBlock), 0, s, acc,
                        n, offset, block, accbits, class_flags);
 }
 
 void launch_ctl_reset(RoundCtl *ctl, const uint32_t *class_flags, uint32_t max_rounds,
                       uint32_t check_eq, uint32_t eq_a, uint32_t eq_b, uint32_t pattern_first,
                       uint32_t packed_second, const uint32_t *init_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, class_flags, max_rounds,
+    launch_kernel(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, class_flags, max_rounds,
                        check_eq, eq_a, eq_b, pattern_first, packed_second, init_count);
 }
 
 void launch_ingest_parts(const SegArgs &g, size_t N, uint32_t k, uint32_t *cols, uint32_t *err,
                          uint32_t *nonid, hipStream_t s) {
-    hipLaunchKernelGGL(k_ingest_parts, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g,
+    launch_kernel(k_ingest_parts, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g,
                        N, k, cols, err, nonid);
 }
 
 void launch_init_parts(const SegArgs &g, size_t N, uint32_t *block, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_parts, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g, N,
+    launch_kernel(k_init_parts, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g, N,
                        block);
-    hipLaunchKernelGGL(k_seg_init, dim3(grid_for(g.nseg, kDefaultGridCap)), dim3(kBlock), 0, s, g);
+    launch_kernel(k_seg_init, dim3(grid_for(g.nseg, kDefaultGridCap)), dim3(kBlock), 0, s, g);
 }
 
 void launch_seg_round(const RoundArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_seg_count, dim3(grid_for(a.N, kDefaultGridCap)), dim3(kBlock), 0, s,
+    launch_kernel(k_seg_count, dim3(grid_for(a.N, kDefaultGridCap)), dim3(kBlock), 0, s,
                        a.seg, a.N, a.ctl, a.blockA, a.blockB);
-    hipLaunchKernelGGL(k_seg_end, dim3(grid_for(a.seg.nseg, kDefaultGridCap)), dim3(kBlock), 0, s,
+    launch_kernel(k_seg_end, dim3(grid_for(a.seg.nseg, kDefaultGridCap)), dim3(kBlock), 0, s,
                        a.seg, a.ctl);
 }
 
 void launch_part_output(const SegArgs &g, size_t N, const uint32_t *canon, uint32_t *out,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_part_output, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g, N,
+    launch_kernel(k_part_output, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g, N,
                        canon, out);
 }
 
 void launch_pair_verdicts(const SegArgs &g, const uint32_t *block, int32_t *verdicts,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_pair_verdicts, dim3(grid_for(g.nseg, kDefaultGridCap)), dim3(kBlock), 0,
+    launch_kernel(k_pair_verdicts, dim3(grid_for(g.nseg, kDefaultGridCap)), dim3(kBlock), 0,
                        s, g, block, verdicts);
 }
 
 void launch_ctl_resume(RoundCtl *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, s, ctl);
+    launch_kernel(k_ctl_resume, dim3(1), dim3(64), 0, s, ctl);
 }
 
 void launch_round_end(const RoundArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(kBlock), 0, s, a.ctl, a.blockA, a.blockB,
+    launch_kernel(k_round_end, dim3(1), dim3(kBlock), 0, s, a.ctl, a.blockA, a.blockB,
                        a.counters, static_cast<uint32_t>(a.N));
 }
 
@@ -1388,12 +1388,12 @@ void launch_pattern_kernel(const RoundArgs &a, hipStream_t s) {
     const SigParams sp = sig_params(a);
     const dim3 grid(round_grid(a, a.pattern_grid_cap)), block(kBlock);
     switch (a.k_eff) {
-        case 1: hipLaunchKernelGGL(k_pattern_round<1>, grid, block, 0, s, sp); break;
-        case 2: hipLaunchKernelGGL(k_pattern_round<2>, grid, block, 0, s, sp); break;
-        case 3: hipLaunchKernelGGL(k_pattern_round<3>, grid, block, 0, s, sp); break;
-        case 4: hipLaunchKernelGGL(k_pattern_round<4>, grid, block, 0, s, sp); break;
-        case 8: hipLaunchKernelGGL(k_pattern_round<8>, grid, block, 0, s, sp); break;
-        default: hipLaunchKernelGGL(k_pattern_round<0>, grid, block, 0, s, sp); break;
+        case 1: launch_kernel(k_pattern_round<1>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_pattern_round<2>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_pattern_round<3>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_pattern_round<4>, grid, block, 0, s, sp); break;
+        case 8: launch_kernel(k_pattern_round<8>, grid, block, 0, s, sp); break;
+        default: launch_kernel(k_pattern_round<0>, grid, block, 0, s, sp); break;
     }
 }
 
@@ -1401,11 +1401,11 @@ void launch_packed_kernel(const RoundArgs &a, hipStream_t s) {
     const SigParams sp = sig_params(a);
     const dim3 grid(round_grid(a, a.pattern_grid_cap)), block(kBlock);
     switch (a.k_eff) {
-        case 1: hipLaunchKernelGGL(k_packed_round<1>, grid, block, 0, s, sp); break;
-        case 2: hipLaunchKernelGGL(k_packed_round<2>, grid, block, 0, s, sp); break;
-        case 3: hipLaunchKernelGGL(k_packed_round<3>, grid, block, 0, s, sp); break;
-        case 4: hipLaunchKernelGGL(k_packed_round<4>, grid, block, 0, s, sp); break;
-        default: hipLaunchKernelGGL(k_packed_round<0>, grid, block, 0, s, sp); break;
+        case 1: launch_kernel(k_packed_round<1>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_packed_round<2>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_packed_round<3>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_packed_round<4>, grid, block, 0, s, sp); break;
+        default: launch_kernel(k_packed_round<0>, grid, block, 0, s, sp); break;
     }
 }
 
@@ -1423,16 +1423,16 @@ void launch_signature(const RoundArgs &a, hipStream_t s) {
     const SigParams sp = sig_params(a);
     const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
     switch (a.k_eff) {
-        case 1: hipLaunchKernelGGL(k_signature<1>, grid, block, 0, s, sp); break;
-        case 2: hipLaunchKernelGGL(k_signature<2>, grid, block, 0, s, sp); break;
-        case 3: hipLaunchKernelGGL(k_signature<3>, grid, block, 0, s, sp); break;
-        case 4: hipLaunchKernelGGL(k_signature<4>, grid, block, 0, s, sp); break;
-        case 5: hipLaunchKernelGGL(k_signature<5>, grid, block, 0, s, sp); break;
-        case 6: hipLaunchKernelGGL(k_signature<6>, grid, block, 0, s, sp); break;
-        case 7: hipLaunchKernelGGL(k_signature<7>, grid, block, 0, s, sp); break;
-        case 8: hipLaunchKernelGGL(k_signature<8>, grid, block, 0, s, sp); break;
-        case 16: hipLaunchKernelGGL(k_signature<16>, grid, block, 0, s, sp); break;
-        default: hipLaunchKernelGGL(k_signature<0>, grid, block, 0, s, sp); break;
+        case 1: launch_kernel(k_signature<1>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_signature<2>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_signature<3>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_signature<4>, grid, block, 0, s, sp); break;
+        case 5: launch_kernel(k_signature<5>, grid, block, 0, s, sp); break;
+        case 6: launch_kernel(k_signature<6>, grid, block, 0, s, sp); break;
+        case 7: launch_kernel(k_signature<7>, grid, block, 0, s, sp); break;
+        case 8: launch_kernel(k_signature<8>, grid, block, 0, s, sp); break;
+        case 16: launch_kernel(k_signature<16>, grid, block, 0, s, sp); break;
+        default: launch_kernel(k_signature<0>, grid, block, 0, s, sp); break;
     }
 }
 
@@ -1441,8 +1441,8 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
     const InsParams ip = ins_params(a);
     // the two grouping variants; exactly one of them works in a given round
     // (lds_stage 2 decides on the device from the previous round)
-    if (a.lds_stage != 0) hipLaunchKernelGGL(k_insert_lds, grid, block, 0, s, ip);
-    if (a.lds_stage != 1) hipLaunchKernelGGL(k_insert, grid, block, 0, s, ip);
+    if (a.lds_stage != 0) launch_kernel(k_insert_lds, grid, block, 0, s, ip);
+    if (a.lds_stage != 1) launch_kernel(k_insert, grid, block, 0, s, ip);
 }
 
 void launch_mark(const RoundArgs &a, hipStream_t s) {
@@ -1450,18 +1450,18 @@ void launch_mark(const RoundArgs &a, hipStream_t s) {
     const unsigned cap = a.round_grid_cap ? std::min(a.round_grid_cap, kMarkGridCap) : kMarkGridCap;
     const dim3 grid(round_grid(a, cap)), block(kBlock);
     switch (a.k_eff) {
-        case 1: hipLaunchKernelGGL(k_mark<1>, grid, block, 0, s, sp); break;
-        case 2: hipLaunchKernelGGL(k_mark<2>, grid, block, 0, s, sp); break;
-        case 3: hipLaunchKernelGGL(k_mark<3>, grid, block, 0, s, sp); break;
-        case 4: hipLaunchKernelGGL(k_mark<4>, grid, block, 0, s, sp); break;
-        case 8: hipLaunchKernelGGL(k_mark<8>, grid, block, 0, s, sp); break;
-        case 16: hipLaunchKernelGGL(k_mark<16>, grid, block, 0, s, sp); break;
-        default: hipLaunchKernelGGL(k_mark<0>, grid, block, 0, s, sp); break;
+        case 1: launch_kernel(k_mark<1>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_mark<2>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_mark<3>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_mark<4>, grid, block, 0, s, sp); break;
+        case 8: launch_kernel(k_mark<8>, grid, block, 0, s, sp); break;
+        case 16: launch_kernel(k_mark<16>, grid, block, 0, s, sp); break;
+        default: launch_kernel(k_mark<0>, grid, block, 0, s, sp); break;
     }
 }
 
 void launch_ctl_full(RoundCtl *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_full, dim3(1), dim3(64), 0, s, ctl);
+    launch_kernel(k_ctl_full, dim3(1), dim3(64), 0, s, ctl);
 }
 
 void launch_round(const RoundArgs &a, hipStream_t s) {
@@ -1501,39 +1501,39 @@ void launch_column_flags(const uint32_t *cols, size_t N, uint32_t k, uint32_t nc
                          const unsigned long long *single, uint32_t *diff, uint32_t *nonid,
                          hipStream_t s) {
     dim3 grid(grid_for(N, kDefaultGridCap / 4), ncols);
-    hipLaunchKernelGGL(k_col_flags, grid, dim3(kBlock), 0, s, cols, N, k, single, diff, nonid);
+    launch_kernel(k_col_flags, grid, dim3(kBlock), 0, s, cols, N, k, single, diff, nonid);
 }
 
 void launch_jump(uint32_t *cols, size_t N, uint32_t k, uint32_t level, uint32_t *diff,
                  uint32_t *nonid, hipStream_t s) {
     dim3 grid(grid_for(N, kDefaultGridCap), k);
-    hipLaunchKernelGGL(k_jump, grid, dim3(kBlock), 0, s, cols, N, k, level, diff, nonid);
+    launch_kernel(k_jump, grid, dim3(kBlock), 0, s, cols, N, k, level, diff, nonid);
 }
 
 void launch_zero(const ZeroList &z, hipStream_t s) {
     size_t most = 0;
     for (int r = 0; r < z.count; ++r) most = std::max(most, z.words[r]);
     if (most == 0) return;
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(most, kDefaultGridCap)), dim3(kBlock), 0, s, z);
+    launch_kernel(k_zero, dim3(grid_for(most, kDefaultGridCap)), dim3(kBlock), 0, s, z);
 }
 
 void launch_canonicalise(const uint32_t *ids, size_t N, size_t id_range, uint32_t *scratch_min,
                          uint32_t *out, hipStream_t s) {
     const dim3 grid(grid_for(N)), block(kBlock);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(id_range, kDefaultGridCap)), block, 0, s,
+    launch_kernel(k_fill_u32, dim3(grid_for(id_range, kDefaultGridCap)), block, 0, s,
                        scratch_min, id_range, ~0u);
-    hipLaunchKernelGGL(k_canon_min, grid, block, 0, s, ids, N, scratch_min);
-    hipLaunchKernelGGL(k_canon_apply, grid, block, 0, s, ids, N, scratch_min, out);
+    launch_kernel(k_canon_min, grid, block, 0, s, ids, N, scratch_min);
+    launch_kernel(k_canon_apply, grid, block, 0, s, ids, N, scratch_min, out);
 }
 
 void launch_dense_leaders(const uint32_t *block, size_t N, uint32_t *partials, uint32_t *dense,
                           uint32_t *leader_of, uint32_t *num_blocks, hipStream_t s) {
     const uint32_t ntiles = static_cast<uint32_t>((N + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_leader_partials, dim3(ntiles), dim3(kScanThreads), 0, s, block, N,
+    launch_kernel(k_leader_partials, dim3(ntiles), dim3(kScanThreads), 0, s, block, N,
                        partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, ntiles,
+    launch_kernel(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, partials, ntiles,
                        num_blocks);
-    hipLaunchKernelGGL(k_leader_rank, dim3(ntiles), dim3(kScanThreads), 0, s, block, N, partials,
+    launch_kernel(k_leader_rank, dim3(ntiles), dim3(kScanThreads), 0, s, block, N, partials,
                        dense, leader_of);
 }
 
@@ -1541,9 +1541,9 @@ void launch_quotient(const uint32_t *delta, const uint8_t *acc, uint32_t k,
                      const uint32_t *block, const uint32_t *dense, const uint32_t *leader_of,
                      const uint32_t *num_blocks, uint32_t n, uint32_t start, uint32_t *dq,
                      uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_of_state, dim3(grid_for(n, kDefaultGridCap)), dim3(kBlock), 0, s,
+    launch_kernel(k_dense_of_state, dim3(grid_for(n, kDefaultGridCap)), dim3(kBlock), 0, s,
                        block, dense, static_cast<size_t>(n), dq);
-    hipLaunchKernelGGL(k_quotient, dim3(grid_for(static_cast<size_t>(n) * k, kDefaultGridCap)),
+    launch_kernel(k_quotient, dim3(grid_for(static_cast<size_t>(n) * k, kDefaultGridCap)),
                        dim3(kBlock), 0, s, delta, acc, k, dq, leader_of, num_blocks, start, qdelta,
                        qacc, qstart);
 }
@@ -1551,7 +1551,7 @@ void launch_quotient(const uint32_t *delta, const uint8_t *acc, uint32_t k,
 void launch_quotient_identity(const uint32_t *delta, const uint8_t *acc, uint32_t n, uint32_t k,
                               uint32_t start, uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_quotient_identity,
+    launch_kernel(k_quotient_identity,
                        dim3(grid_for(static_cast<size_t>(n) * k, kDefaultGridCap)), dim3(kBlock),
                        0, s, delta, acc, static_cast<size_t>(n), k, start, qdelta, qacc, qstart);
 }

@@ -15,7 +15,7 @@
 // stable scatter in which each tile walks its items stripe by stripe; within
 // a stripe a wave ranks its lanes by digit with eight ballots.  All launch
 // sizes depend on N only (the count m of refined states is read on the
-// device), so the round can be captured in a graph.
+// device), so the round can be replayed from a graph.
 #include <algorithm>
 
 #include "device_common.h"
@@ -353,41 +353,41 @@ void launch_sort_group(const RoundArgs &a, hipStream_t s) {
     const SortBuffers &b = a.sort;
     const SortPlan pl = sort_plan(a.N);
     // compaction of the refined states, in state order
-    hipLaunchKernelGGL(k_compact_count, dim3(pl.compact_tiles), dim3(64), 0, s, a.active, a.N,
+    launch_kernel(k_compact_count, dim3(pl.compact_tiles), dim3(64), 0, s, a.active, a.N,
                        b.partials);
-    hipLaunchKernelGGL(k_scan_partials_op<SumOp>, dim3(1), dim3(kSortThreads), 0, s, b.partials,
+    launch_kernel(k_scan_partials_op<SumOp>, dim3(1), dim3(kSortThreads), 0, s, b.partials,
                        pl.compact_tiles);
-    hipLaunchKernelGGL(k_compact_write, dim3(pl.compact_tiles), dim3(64), 0, s, a.active, a.N,
+    launch_kernel(k_compact_write, dim3(pl.compact_tiles), dim3(64), 0, s, a.active, a.N,
                        a.hash, b.partials, pl.compact_tiles, b.keys[0], b.vals[0], b.m);
     // stable radix sort by hash, 8 passes
     for (uint32_t pass = 0; pass < 64 / kRadixBits; ++pass) {
         const uint32_t in = pass & 1u, out = in ^ 1u;
         const uint32_t shift = pass * kRadixBits;
-        hipLaunchKernelGGL(k_radix_hist, dim3(pl.sort_tiles), dim3(kSortThreads), 0, s, b.keys[in],
+        launch_kernel(k_radix_hist, dim3(pl.sort_tiles), dim3(kSortThreads), 0, s, b.keys[in],
                            b.m, shift, b.hist, pl.sort_tiles);
-        hipLaunchKernelGGL(k_scan_reduce<SumOp>, dim3(pl.hist_blocks), dim3(kSortThreads), 0, s,
+        launch_kernel(k_scan_reduce<SumOp>, dim3(pl.hist_blocks), dim3(kSortThreads), 0, s,
                            b.hist, pl.hist_words, nullptr, b.partials);
-        hipLaunchKernelGGL(k_scan_partials_op<SumOp>, dim3(1), dim3(kSortThreads), 0, s,
+        launch_kernel(k_scan_partials_op<SumOp>, dim3(1), dim3(kSortThreads), 0, s,
                            b.partials, pl.hist_blocks);
-        hipLaunchKernelGGL((k_scan_apply<SumOp, false>), dim3(pl.hist_blocks), dim3(kSortThreads),
+        launch_kernel((k_scan_apply<SumOp, false>), dim3(pl.hist_blocks), dim3(kSortThreads),
                            0, s, b.hist, pl.hist_words, nullptr, b.partials);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(pl.sort_tiles), dim3(kSortThreads), 0, s,
+        launch_kernel(k_radix_scatter, dim3(pl.sort_tiles), dim3(kSortThreads), 0, s,
                            b.keys[in], b.vals[in], b.keys[out], b.vals[out], b.m, shift, b.hist,
                            pl.sort_tiles);
     }
     // runs of equal hashes: position of each element's run head
-    hipLaunchKernelGGL(k_run_heads, dim3(grid_n(a.N)), dim3(kBlock), 0, s, b.keys[0], b.m,
+    launch_kernel(k_run_heads, dim3(grid_n(a.N)), dim3(kBlock), 0, s, b.keys[0], b.m,
                        b.runhead);
-    hipLaunchKernelGGL(k_scan_reduce<MaxOp>, dim3(pl.run_blocks), dim3(kSortThreads), 0, s,
+    launch_kernel(k_scan_reduce<MaxOp>, dim3(pl.run_blocks), dim3(kSortThreads), 0, s,
                        b.runhead, 0, b.m, b.partials);
-    hipLaunchKernelGGL(k_scan_partials_op<MaxOp>, dim3(1), dim3(kSortThreads), 0, s, b.partials,
+    launch_kernel(k_scan_partials_op<MaxOp>, dim3(1), dim3(kSortThreads), 0, s, b.partials,
                        pl.run_blocks);
-    hipLaunchKernelGGL((k_scan_apply<MaxOp, true>), dim3(pl.run_blocks), dim3(kSortThreads), 0, s,
+    launch_kernel((k_scan_apply<MaxOp, true>), dim3(pl.run_blocks), dim3(kSortThreads), 0, s,
                        b.runhead, 0, b.m, b.partials);
     const AssignArgs aa{b.vals[0], b.runhead, b.m,        a.sig,      a.k_eff + 1,
                         a.blockA,  a.blockB,  a.multi,    a.counters, a.ctl};
-    hipLaunchKernelGGL(k_sort_assign, dim3(grid_n(a.N)), dim3(kBlock), 0, s, aa);
-    hipLaunchKernelGGL(k_sort_finish, dim3(grid_n(a.N)), dim3(kBlock), 0, s, a.active, a.N,
+    launch_kernel(k_sort_assign, dim3(grid_n(a.N)), dim3(kBlock), 0, s, aa);
+    launch_kernel(k_sort_finish, dim3(grid_n(a.N)), dim3(kBlock), 0, s, a.active, a.N,
                        a.blockA, a.blockB, a.chg, a.chg_sum, a.counters, a.ctl);
 }
 
