@@ -91,3 +91,42 @@ def test_equivalence_and_inclusion_every_method(k):
             got, pairs, _ = B.included(x, y)
             assert got == inc, (name, "included")
             assert pairs >= 1
+
+
+@pytest.mark.parametrize("k", [33, 64, 130])
+def test_large_alphabets(k):
+    """Alphabets above the specialised signature widths (the generic path)
+    and closures of more than 64 columns (k * (floor(log2 n) + 1) up to
+    1,560): every algorithm and closure mode gives Hopcroft's partition;
+    Moore's round count without the closure.  Some letters are the identity
+    and some repeat another letter, so column dropping has work to do."""
+    # 60 copies of a 50-state chain (letter a steps 0, 1 or 2 states towards
+    # the one accepting state), each transition going to a random copy of
+    # its target: blocks of 60 states, separated over about 25 rounds
+    rng = np.random.default_rng(k)
+    step = rng.integers(0, 3, k)
+    step[0], step[1], step[k - 1] = 1, 0, 1
+    i = np.arange(50)
+    chain = np.minimum(i[:, None] + step[None, :], 49)
+    q = np.arange(3000)
+    delta = (chain[q % 50] + 50 * rng.integers(0, 60, (3000, k))).astype(np.uint32)
+    delta[:, 1] = q
+    delta[:, k - 1] = delta[:, 0]
+    d = W.DFA(delta, (q % 50 == 49).astype(np.uint8), 0)
+    hb, hnb = oracle.hopcroft(d.delta, d.accepting)
+    mb, mnb, mrounds, mchanging = oracle.moore(d.delta, d.accepting)
+    for alg, tc in itertools.product(("signature", "sort", "leader"), ("off", "auto", "on")):
+        res = B.minimise(d.delta, d.accepting, tc=tc, algorithm=alg, quotient=True)
+        np.testing.assert_array_equal(res.block, hb, err_msg=f"{alg} {tc}")
+        assert res.stats["num_blocks"] == hnb
+        if tc == "off" and alg != "leader":
+            assert (res.stats["rounds"], res.stats["changing_rounds"]) == (mrounds, mchanging)
+        gn, gd, ga, gs = res.quotient
+        assert gn == hnb and oracle.hopcroft(gd, ga)[1] == gn
+    # a larger instance through the segmented batch path as well
+    big = W.random_dfa(100000, 40, 0.2, 800)
+    hb2, _ = oracle.hopcroft(big.delta, big.accepting)
+    np.testing.assert_array_equal(B.minimise(big.delta, big.accepting, tc="off").block, hb2)
+    blocks, _, _, _ = B.minimise_batch([d, big], tc="off")
+    np.testing.assert_array_equal(blocks[0], hb)
+    np.testing.assert_array_equal(blocks[1], hb2)
