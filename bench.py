@@ -64,6 +64,8 @@ def parse_args():
                     help="skip the comparison of grouping / refinement variants")
     ap.add_argument("--no-table2", action="store_true",
                     help="skip the runs on the paper's Table 2 families")
+    ap.add_argument("--no-host-path", action="store_true",
+                    help="skip the same step through the host-pointer calls (copies included)")
     ap.add_argument("--no-products", action="store_true",
                     help="skip the product explorations (Tables 4 and 5 families)")
     return ap.parse_args()
@@ -210,6 +212,37 @@ def variants_leg(B, W, torch, np, dev, A_d, A_a, n, pairs) -> dict:
             out[f"equiv_2e22_{name}_{method}_ms"] = ms
         out[f"equiv_2e22_{name}_product_pairs"] = st["reachable"]
     return out
+
+
+def host_path_leg(B, np, d, perm, mut, steps: int = 5) -> dict:
+    """The timed step through the host-pointer calls: the DFAs start in host
+    memory (pageable numpy arrays) and the block ids and quotient come back to
+    it, so the rate includes the PCIe copies each way.  Not the headline
+    value, which is measured with the inputs resident in HBM."""
+
+    def step():
+        r = B.minimise(d.delta, d.accepting, quotient=True)
+        _, s1 = B.equivalent(d, perm)
+        _, s2 = B.equivalent(d, mut)
+        stats = (r.stats, s1, s2)
+        return (sum(s["transitions_refined"] for s in stats),
+                sum(s["h2d_ms"] for s in stats), sum(s["d2h_ms"] for s in stats),
+                sum(s["device_ms"] for s in stats))
+
+    step()
+    work = h2d = d2h = device = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w, a, b, c = step()
+        work, h2d, d2h, device = work + w, h2d + a, d2h + b, device + c
+    wall = time.perf_counter() - t0
+    return {"steps": steps, "ms_per_step": wall / steps * 1e3,
+            "transitions_per_s": work / wall, "h2d_ms_per_step": h2d / steps,
+            "d2h_ms_per_step": d2h / steps, "device_ms_per_step": device / steps,
+            "bytes_in_per_step": int(3 * d.delta.nbytes + 3 * d.accepting.nbytes
+                                     + perm.delta.nbytes + mut.delta.nbytes
+                                     + perm.accepting.nbytes + mut.accepting.nbytes),
+            "bytes_out_per_step": int(4 * d.n + d.delta.nbytes + d.n)}
 
 
 # Table 2 of the paper (TITAN RTX, times include the host-to-device copy):
@@ -555,6 +588,8 @@ def main() -> int:
         out["variants"] = variants_leg(B, W, torch, np, dev, A_d, A_a, d.n,
                                        {"permuted": (d.start, P_d, P_a, perm.start),
                                         "mutated": (d.start, M_d, M_a, mut.start)})
+    if not args.no_host_path:
+        out["host_path"] = host_path_leg(B, np, d, perm, mut)
     if not args.no_table2:
         out["table2"] = table2_leg(B, W, torch, np, dev)
     if not args.no_products:

@@ -347,7 +347,7 @@ def minimise(delta, accepting, *, tc: str = "auto", loop: str = "graph", start: 
     res = MinimiseResult(block, st.as_dict())
     if q is not None:
         B = q.num_blocks
-        res.quotient = (B, qd[:B].copy(), qa[:B].copy(), q.start)
+        res.quotient = (B, qd[:B], qa[:B], q.start)
     return res
 
 

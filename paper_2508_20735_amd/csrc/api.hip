@@ -155,6 +155,9 @@ struct Ctx {
     hipEvent_t ev_sync = nullptr;
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
+    uint8_t *ring[2] = {nullptr, nullptr};  // page-locked chunks for large host copies
+    hipEvent_t ring_ev[2] = {nullptr, nullptr};
+    bool ring_recorded[2] = {false, false};  // ring_ev[i] has been recorded
     size_t pinned_batch_cap = 0;
     // chunk graphs, one per chunk length in use (automatic chunks grow
     // 4, 8, ..., 256 within one call), replaced round-robin
@@ -1603,6 +1606,108 @@ int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_v
 }
 
 // dfa_minimise on an initialised context (host pointers in and out).
+// memcpy split over a few threads for large inputs (one thread reaches about
+// a quarter of the host's copy bandwidth).
+void parallel_copy(void *dst, const void *src, size_t bytes) {
+    constexpr size_t kSplitBytes = size_t(8) << 20;
+    if (bytes < kSplitBytes) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({8, hw / 2, bytes / (kSplitBytes / 4)});
+    const size_t chunk = ((bytes + nt - 1) / nt + 63) & ~size_t(63);
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < nt; ++i) {
+        const size_t off = i * chunk;
+        if (off >= bytes) break;
+        th.emplace_back([=] {
+            std::memcpy(static_cast<char *>(dst) + off, static_cast<const char *>(src) + off,
+                        std::min(chunk, bytes - off));
+        });
+    }
+    std::memcpy(dst, src, std::min(chunk, bytes));
+    for (auto &t : th) t.join();
+}
+
+// Copies of large pageable host arrays go through two page-locked chunks:
+// host threads fill (or drain) one chunk while the DMA engine moves the
+// other, instead of the runtime's own single-threaded staging of pageable
+// memory.  Small arrays are copied directly.
+constexpr size_t kRingChunk = size_t(16) << 20;
+constexpr size_t kRingMinBytes = size_t(8) << 20;
+
+int ensure_ring(Ctx &c) {
+    for (int i = 0; i < 2; ++i) {
+        if (!c.ring[i] &&
+            hipHostMalloc(reinterpret_cast<void **>(&c.ring[i]), kRingChunk, hipHostMallocDefault) !=
+                hipSuccess) {
+            c.ring[i] = nullptr;
+            (void)hipGetLastError();
+            return fail(DFA_ENOMEM, "page-locked staging of %zu bytes failed", kRingChunk);
+        }
+        if (!c.ring_ev[i]) HIP_TRY(hipEventCreateWithFlags(&c.ring_ev[i], hipEventDisableTiming));
+    }
+    return DFA_OK;
+}
+
+// Host -> device on the context's stream; returns once the last chunk is
+// queued (the caller synchronises the stream).
+int copy_to_device(Ctx &c, void *dst, const void *src, size_t bytes) {
+    if (bytes < kRingMinBytes) {
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream));
+        return DFA_OK;
+    }
+    DFA_TRY(ensure_ring(c));
+    size_t i = 0;
+    for (size_t off = 0; off < bytes; off += kRingChunk, ++i) {
+        const size_t len = std::min(kRingChunk, bytes - off);
+        const int slot = static_cast<int>(i & 1);
+        // the chunk's previous DMA (of this call or an earlier one) must be
+        // done before it is refilled
+        if (c.ring_recorded[slot]) HIP_TRY(hipEventSynchronize(c.ring_ev[slot]));
+        parallel_copy(c.ring[slot], static_cast<const char *>(src) + off, len);
+        HIP_TRY(hipMemcpyAsync(static_cast<char *>(dst) + off, c.ring[slot], len,
+                               hipMemcpyHostToDevice, c.stream));
+        HIP_TRY(hipEventRecord(c.ring_ev[slot], c.stream));
+        c.ring_recorded[slot] = true;
+    }
+    return DFA_OK;
+}
+
+// Device -> host, after the work queued on the context's stream.  A large
+// array is in `dst` on return; a small one once the caller has synchronised
+// the stream.
+int copy_to_host(Ctx &c, void *dst, const void *src, size_t bytes) {
+    if (bytes < kRingMinBytes) {
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
+        return DFA_OK;
+    }
+    DFA_TRY(ensure_ring(c));
+    const size_t chunks = (bytes + kRingChunk - 1) / kRingChunk;
+    auto queue = [&](size_t i) -> int {
+        const size_t off = i * kRingChunk;
+        const int slot = static_cast<int>(i & 1);
+        HIP_TRY(hipMemcpyAsync(c.ring[slot], static_cast<const char *>(src) + off,
+                               std::min(kRingChunk, bytes - off), hipMemcpyDeviceToHost,
+                               c.stream));
+        HIP_TRY(hipEventRecord(c.ring_ev[slot], c.stream));
+        c.ring_recorded[slot] = true;
+        return DFA_OK;
+    };
+    DFA_TRY(queue(0));
+    if (chunks > 1) DFA_TRY(queue(1));
+    for (size_t i = 0; i < chunks; ++i) {
+        const int slot = static_cast<int>(i & 1);
+        const size_t off = i * kRingChunk;
+        HIP_TRY(hipEventSynchronize(c.ring_ev[slot]));
+        parallel_copy(static_cast<char *>(dst) + off, c.ring[slot],
+                      std::min(kRingChunk, bytes - off));
+        if (i + 2 < chunks) DFA_TRY(queue(i + 2));
+    }
+    return DFA_OK;
+}
+
 int minimise_host(Ctx &c_, uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *accepting,
                   uint32_t *block_out, dfa_quotient *q_out, const dfa_options &o,
                   dfa_stats *stats) {
@@ -1617,9 +1722,8 @@ int minimise_host(Ctx &c_, uint32_t n, uint32_t k, const uint32_t *delta, const 
         DFA_TRY(c->stage_qacc.ensure(n, "quotient copy"));
     }
     auto t0 = std::chrono::steady_clock::now();
-    HIP_TRY(hipMemcpyAsync(c->stage_delta.p, delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice,
-                           c->stream));
-    HIP_TRY(hipMemcpyAsync(c->stage_acc.p, accepting, n, hipMemcpyHostToDevice, c->stream));
+    DFA_TRY(copy_to_device(*c, c->stage_delta.p, delta, nk * sizeof(uint32_t)));
+    DFA_TRY(copy_to_device(*c, c->stage_acc.p, accepting, n));
     HIP_TRY(stream_sync(*c));
     const double h2d = ms_since(t0);
     dfa_quotient dq{};
@@ -1631,14 +1735,11 @@ int minimise_host(Ctx &c_, uint32_t n, uint32_t k, const uint32_t *delta, const 
                            c->stage_block.as<uint32_t>(), q_out ? &dq : nullptr, o, stats);
     if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
     t0 = std::chrono::steady_clock::now();
-    HIP_TRY(hipMemcpyAsync(block_out, c->stage_block.p, static_cast<size_t>(n) * sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, c->stream));
+    DFA_TRY(copy_to_host(*c, block_out, c->stage_block.p, static_cast<size_t>(n) * sizeof(uint32_t)));
     if (q_out) {
-        HIP_TRY(hipMemcpyAsync(q_out->delta, dq.delta,
-                               static_cast<size_t>(dq.num_blocks) * k * sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipMemcpyAsync(q_out->accepting, dq.accepting, dq.num_blocks,
-                               hipMemcpyDeviceToHost, c->stream));
+        DFA_TRY(copy_to_host(*c, q_out->delta, dq.delta,
+                             static_cast<size_t>(dq.num_blocks) * k * sizeof(uint32_t)));
+        DFA_TRY(copy_to_host(*c, q_out->accepting, dq.accepting, dq.num_blocks));
         q_out->num_blocks = dq.num_blocks;
         q_out->start = dq.start;
     }
@@ -1651,12 +1752,12 @@ int minimise_host(Ctx &c_, uint32_t n, uint32_t k, const uint32_t *delta, const 
 }
 
 
-int stage_view(Buffer &bd, Buffer &ba, const dfa_view *v, dfa_view &out, hipStream_t s) {
+int stage_view(Ctx &c, Buffer &bd, Buffer &ba, const dfa_view *v, dfa_view &out) {
     const size_t nk = static_cast<size_t>(v->n) * v->k;
     DFA_TRY(bd.ensure(nk * sizeof(uint32_t), "input copy"));
     DFA_TRY(ba.ensure(v->n, "input copy"));
-    HIP_TRY(hipMemcpyAsync(bd.p, v->delta, nk * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ba.p, v->accepting, v->n, hipMemcpyHostToDevice, s));
+    DFA_TRY(copy_to_device(c, bd.p, v->delta, nk * sizeof(uint32_t)));
+    DFA_TRY(copy_to_device(c, ba.p, v->accepting, v->n));
     out = *v;
     out.delta = bd.as<uint32_t>();
     out.accepting = ba.as<uint8_t>();
@@ -1670,8 +1771,8 @@ int equivalent_host(Ctx &c, const dfa_view *a, const dfa_view *b, int *verdict,
     if (stats) std::memset(stats, 0, sizeof *stats);
     auto t0 = std::chrono::steady_clock::now();
     dfa_view da, db;
-    DFA_TRY(stage_view(c.stage_delta, c.stage_acc, a, da, c.stream));
-    DFA_TRY(stage_view(c.stage_delta_b, c.stage_acc_b, b, db, c.stream));
+    DFA_TRY(stage_view(c, c.stage_delta, c.stage_acc, a, da));
+    DFA_TRY(stage_view(c, c.stage_delta_b, c.stage_acc_b, b, db));
     HIP_TRY(stream_sync(c));
     const double h2d = ms_since(t0);
     int rc = equivalent_impl(c, da, db, verdict, o, stats);
@@ -1729,6 +1830,13 @@ void release_ctx(Ctx &c) {
     c.ev_p0 = c.ev_p1 = nullptr;
     if (c.pinned) (void)hipHostFree(c.pinned);
     if (c.pinned_batch) (void)hipHostFree(c.pinned_batch);
+    for (int i = 0; i < 2; ++i) {
+        if (c.ring[i]) (void)hipHostFree(c.ring[i]);
+        if (c.ring_ev[i]) (void)hipEventDestroy(c.ring_ev[i]);
+        c.ring[i] = nullptr;
+        c.ring_ev[i] = nullptr;
+        c.ring_recorded[i] = false;
+    }
     if (c.stream) (void)hipStreamDestroy(c.stream);
     c.ev_start = c.ev_stop = c.ev_in = nullptr;
     c.pinned = nullptr;
@@ -1775,29 +1883,6 @@ struct PinnedPool {
     }
 };
 
-// memcpy split over a few threads for large inputs (one thread reaches about
-// a quarter of the host's copy bandwidth).
-void parallel_copy(void *dst, const void *src, size_t bytes) {
-    constexpr size_t kSplitBytes = size_t(8) << 20;
-    if (bytes < kSplitBytes) {
-        std::memcpy(dst, src, bytes);
-        return;
-    }
-    const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
-    const size_t nt = std::min<size_t>({8, hw / 2, bytes / (kSplitBytes / 4)});
-    const size_t chunk = ((bytes + nt - 1) / nt + 63) & ~size_t(63);
-    std::vector<std::thread> th;
-    for (size_t i = 1; i < nt; ++i) {
-        const size_t off = i * chunk;
-        if (off >= bytes) break;
-        th.emplace_back([=] {
-            std::memcpy(static_cast<char *>(dst) + off, static_cast<const char *>(src) + off,
-                        std::min(chunk, bytes - off));
-        });
-    }
-    std::memcpy(dst, src, std::min(chunk, bytes));
-    for (auto &t : th) t.join();
-}
 
 struct ServedRequest {
     uint64_t ticket = 0;
@@ -2295,8 +2380,8 @@ int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *p
     DFA_TRY(init_ctx(*c));
     auto t0 = std::chrono::steady_clock::now();
     dfa_view da, db;
-    DFA_TRY(stage_view(c->stage_delta, c->stage_acc, a, da, c->stream));
-    DFA_TRY(stage_view(c->stage_delta_b, c->stage_acc_b, b, db, c->stream));
+    DFA_TRY(stage_view(*c, c->stage_delta, c->stage_acc, a, da));
+    DFA_TRY(stage_view(*c, c->stage_delta_b, c->stage_acc_b, b, db));
     HIP_TRY(stream_sync(*c));
     const double h2d = ms_since(t0);
     int rc = included_impl(*c, da, db, verdict, pairs_visited, stats);

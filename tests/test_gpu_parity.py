@@ -813,3 +813,26 @@ def test_server_admission_and_errors():
         r = srv.wait(srv.submit_minimise(good))
         np.testing.assert_array_equal(r["blocks"], oracle.hopcroft(good.delta, good.accepting)[0])
         assert srv.stats()["rejected"] == 1
+
+
+@pytest.mark.parametrize("n,k", [(2 * 1024 * 1024 + 3, 5), (1 << 21, 4), ((1 << 21) - 1, 1)])
+def test_host_copies_through_staging_chunks(n, k):
+    """Host-pointer calls move large arrays through two page-locked 16 MiB
+    chunks.  Inputs of 2.5, exactly 2 and under one chunk(s), a block array and
+    quotient above the direct-copy threshold, and two back-to-back uploads
+    (the operands of an equivalence) reusing the chunks: every byte arrives."""
+    d = W.random_dfa(n, k, 0.3, 90 + k)
+    res = B.minimise(d.delta, d.accepting, tc="off", quotient=True)
+    hb, hnb = oracle.hopcroft(d.delta, d.accepting)
+    np.testing.assert_array_equal(res.block, hb)
+    qn, qd, qa, qs = oracle.quotient(d.delta, d.accepting, hb, d.start)
+    gn, gd, ga, gs = res.quotient
+    assert gn == qn == hnb and gs == qs
+    np.testing.assert_array_equal(gd, qd)
+    np.testing.assert_array_equal(ga, qa)
+    perm, _ = W.permuted_copy(d, 91 + k)
+    mut, _ = W.mutate_one(d, 92 + k)
+    assert B.equivalent(d, perm, tc="off")[0]
+    want = oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting, mut.start)
+    assert B.equivalent(d, mut, tc="off")[0] == want
+    assert B.included(d, perm)[0]
