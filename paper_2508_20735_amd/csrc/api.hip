@@ -1359,6 +1359,68 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 // ---- batches: many DFAs in one segmented refinement ----
 
+// memcpy split over a few threads for large inputs (one thread reaches about
+// a quarter of the host's copy bandwidth).
+void parallel_copy(void *dst, const void *src, size_t bytes) {
+    constexpr size_t kSplitBytes = size_t(8) << 20;
+    if (bytes < kSplitBytes) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({8, hw / 2, bytes / (kSplitBytes / 4)});
+    const size_t chunk = ((bytes + nt - 1) / nt + 63) & ~size_t(63);
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < nt; ++i) {
+        const size_t off = i * chunk;
+        if (off >= bytes) break;
+        th.emplace_back([=] {
+            std::memcpy(static_cast<char *>(dst) + off, static_cast<const char *>(src) + off,
+                        std::min(chunk, bytes - off));
+        });
+    }
+    std::memcpy(dst, src, std::min(chunk, bytes));
+    for (auto &t : th) t.join();
+}
+
+// Many small copies (the DFAs of a batch) on up to 8 threads, each taking a
+// run of consecutive copies of about equal total size.
+struct CopyJob {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+void parallel_copies(const std::vector<CopyJob> &jobs) {
+    size_t total = 0;
+    for (const CopyJob &j : jobs) total += j.bytes;
+    if (jobs.size() == 1) {
+        parallel_copy(jobs[0].dst, jobs[0].src, jobs[0].bytes);
+        return;
+    }
+    const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({8, hw / 2, total / (size_t(2) << 20) + 1});
+    auto run = [&jobs](size_t lo, size_t hi) {
+        for (size_t i = lo; i < hi; ++i) std::memcpy(jobs[i].dst, jobs[i].src, jobs[i].bytes);
+    };
+    if (nt <= 1) {
+        run(0, jobs.size());
+        return;
+    }
+    // cut the job list where the running total passes each 1/nt of the bytes
+    std::vector<size_t> cut{0};
+    size_t acc = 0;
+    for (size_t i = 0; i < jobs.size() && cut.size() < nt; ++i) {
+        acc += jobs[i].bytes;
+        if (acc * nt >= total * cut.size()) cut.push_back(i + 1);
+    }
+    cut.push_back(jobs.size());
+    std::vector<std::thread> th;
+    for (size_t t = 1; t + 1 < cut.size(); ++t) th.emplace_back(run, cut[t], cut[t + 1]);
+    run(cut[0], cut[1]);
+    for (auto &t : th) t.join();
+}
+
 int ensure_pinned_batch(Ctx &c, size_t bytes) {
     if (c.pinned_batch && bytes <= c.pinned_batch_cap) return DFA_OK;
     if (c.pinned_batch) {
@@ -1466,19 +1528,22 @@ int stage_views(Ctx &c, uint32_t count, const dfa_view *const *lists, int nlists
     size_t off = 0;
     dev_views.clear();
     uint8_t *dev = c.batch_in.as<uint8_t>();
+    std::vector<CopyJob> jobs;
+    jobs.reserve(2 * static_cast<size_t>(count) * nlists);
     for (int l = 0; l < nlists; ++l)
         for (uint32_t i = 0; i < count; ++i) {
             const dfa_view &v = lists[l][i];
             dfa_view d = v;
             const size_t db = static_cast<size_t>(v.n) * v.k * 4;
-            std::memcpy(c.pinned_batch + off, v.delta, db);
+            jobs.push_back({c.pinned_batch + off, v.delta, db});
             d.delta = reinterpret_cast<const uint32_t *>(dev + off);
             off += (db + 255) & ~size_t(255);
-            std::memcpy(c.pinned_batch + off, v.accepting, v.n);
+            jobs.push_back({c.pinned_batch + off, v.accepting, v.n});
             d.accepting = dev + off;
             off += (static_cast<size_t>(v.n) + 255) & ~size_t(255);
             dev_views.push_back(d);
         }
+    parallel_copies(jobs);
     HIP_TRY(hipMemcpyAsync(dev, c.pinned_batch, off, hipMemcpyHostToDevice, c.stream));
     HIP_TRY(stream_sync(c));
     h2d_ms = ms_since(t0);
@@ -1606,29 +1671,6 @@ int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_v
 }
 
 // dfa_minimise on an initialised context (host pointers in and out).
-// memcpy split over a few threads for large inputs (one thread reaches about
-// a quarter of the host's copy bandwidth).
-void parallel_copy(void *dst, const void *src, size_t bytes) {
-    constexpr size_t kSplitBytes = size_t(8) << 20;
-    if (bytes < kSplitBytes) {
-        std::memcpy(dst, src, bytes);
-        return;
-    }
-    const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
-    const size_t nt = std::min<size_t>({8, hw / 2, bytes / (kSplitBytes / 4)});
-    const size_t chunk = ((bytes + nt - 1) / nt + 63) & ~size_t(63);
-    std::vector<std::thread> th;
-    for (size_t i = 1; i < nt; ++i) {
-        const size_t off = i * chunk;
-        if (off >= bytes) break;
-        th.emplace_back([=] {
-            std::memcpy(static_cast<char *>(dst) + off, static_cast<const char *>(src) + off,
-                        std::min(chunk, bytes - off));
-        });
-    }
-    std::memcpy(dst, src, std::min(chunk, bytes));
-    for (auto &t : th) t.join();
-}
 
 // Copies of large pageable host arrays go through two page-locked chunks:
 // host threads fill (or drain) one chunk while the DMA engine moves the
@@ -2439,11 +2481,13 @@ int dfa_minimise_batch(uint32_t count, const dfa_view *dfas, uint32_t *blocks_co
     HIP_TRY(stream_sync(*c));
     uint64_t pos = 0;
     const uint32_t *src = reinterpret_cast<const uint32_t *>(c->pinned_batch);
+    std::vector<CopyJob> jobs(count);
     for (uint32_t i = 0; i < count; ++i) {
         const uint64_t dst = block_offsets ? block_offsets[i] : pos;
-        std::memcpy(blocks_concat + dst, src + pos, dfas[i].n * sizeof(uint32_t));
+        jobs[i] = {blocks_concat + dst, src + pos, dfas[i].n * sizeof(uint32_t)};
         pos += dfas[i].n;
     }
+    parallel_copies(jobs);
     if (stats) {
         stats->h2d_ms = h2d;
         stats->d2h_ms = ms_since(t0);
