@@ -14,6 +14,8 @@
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <exception>
 #include <thread>
 #include <type_traits>
 #include <unordered_map>
@@ -40,7 +42,11 @@ int fail(int code, const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    try {
+        g_last_error = buf;
+    } catch (...) {
+        // the status still tells the caller what failed
+    }
     return code;
 }
 
@@ -1361,6 +1367,24 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 // memcpy split over a few threads for large inputs (one thread reaches about
 // a quarter of the host's copy bandwidth).
+// Runs part(0) .. part(parts - 1): part 0 on the calling thread, the others
+// on threads of their own.  If a thread cannot be started, the calling
+// thread runs the parts left over, so no exception leaves with a joinable
+// thread.
+template <typename F>
+void parallel_for(size_t parts, const F &part) {
+    std::vector<std::thread> th;
+    size_t next = 1;  // first part not handed to a thread
+    try {
+        th.reserve(parts);
+        for (; next < parts; ++next) th.emplace_back(part, next);
+    } catch (const std::exception &) {
+    }
+    if (parts) part(0);
+    for (size_t i = next; i < parts; ++i) part(i);
+    for (auto &t : th) t.join();
+}
+
 void parallel_copy(void *dst, const void *src, size_t bytes) {
     constexpr size_t kSplitBytes = size_t(8) << 20;
     if (bytes < kSplitBytes) {
@@ -1370,17 +1394,13 @@ void parallel_copy(void *dst, const void *src, size_t bytes) {
     const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
     const size_t nt = std::min<size_t>({8, hw / 2, bytes / (kSplitBytes / 4)});
     const size_t chunk = ((bytes + nt - 1) / nt + 63) & ~size_t(63);
-    std::vector<std::thread> th;
-    for (size_t i = 1; i < nt; ++i) {
+    auto part = [=](size_t i) {
         const size_t off = i * chunk;
-        if (off >= bytes) break;
-        th.emplace_back([=] {
+        if (off < bytes)
             std::memcpy(static_cast<char *>(dst) + off, static_cast<const char *>(src) + off,
                         std::min(chunk, bytes - off));
-        });
-    }
-    std::memcpy(dst, src, std::min(chunk, bytes));
-    for (auto &t : th) t.join();
+    };
+    parallel_for(nt, part);
 }
 
 // Many small copies (the DFAs of a batch) on up to 8 threads, each taking a
@@ -1415,10 +1435,7 @@ void parallel_copies(const std::vector<CopyJob> &jobs) {
         if (acc * nt >= total * cut.size()) cut.push_back(i + 1);
     }
     cut.push_back(jobs.size());
-    std::vector<std::thread> th;
-    for (size_t t = 1; t + 1 < cut.size(); ++t) th.emplace_back(run, cut[t], cut[t + 1]);
-    run(cut[0], cut[1]);
-    for (auto &t : th) t.join();
+    parallel_for(cut.size() - 1, [&](size_t t) { run(cut[t], cut[t + 1]); });
 }
 
 int ensure_pinned_batch(Ctx &c, size_t bytes) {
@@ -2158,7 +2175,8 @@ void lane_main(Server *sp, size_t lane) {
             for (auto *r : grp) r->t_start = now;
             if (grp.size() > 1 || small) s.groups++;
         }
-        {
+        all = grp;
+        try {
             std::lock_guard<std::mutex> g(c.mu);
             g_last_error.clear();
             // inputs to the device on the lane's stream (asynchronous copies
@@ -2187,12 +2205,19 @@ void lane_main(Server *sp, size_t lane) {
                     ready.push_back(r);
                 }
             }
-            all = grp;
             grp.swap(ready);
             if (grp.size() == 1 && grp[0]->states > s.cfg.batch_max_states)
                 run_solo(s, c, grp[0]);
             else if (!grp.empty())
                 run_group(s, c, grp);
+        } catch (const std::exception &e) {
+            // a host allocation failed: the group's requests fail, the lane
+            // goes on with the next ones
+            const int code = dynamic_cast<const std::bad_alloc *>(&e) ? DFA_ENOMEM : DFA_EDEVICE;
+            for (auto *r : all) {
+                r->status = code;
+                r->batched = false;
+            }
         }
         (void)stream_sync(c);  // the input copies have completed
         for (auto *r : all) {
@@ -2226,6 +2251,21 @@ void fill_result(const ServedRequest &r, dfa_result *out) {
     out->latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
 }
 
+// Runs an entry point's body so that no C++ exception crosses the C ABI: a
+// failed host allocation becomes DFA_ENOMEM, anything else DFA_EDEVICE.
+template <typename F>
+int guarded(F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(DFA_ENOMEM, "host memory allocation failed");
+    } catch (const std::exception &e) {
+        return fail(DFA_EDEVICE, "host error: %s", e.what());
+    } catch (...) {
+        return fail(DFA_EDEVICE, "host error");
+    }
+}
+
 }  // namespace
 }  // namespace dfamin
 
@@ -2234,46 +2274,52 @@ using namespace dfamin;
 extern "C" {
 
 int dfa_profile_enable(int on) {
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    c->profiling = on != 0;
-    c->ktimes.clear();
-    c->pending.clear();
-    c->ev_used = 0;
-    return DFA_OK;
+    return guarded([&]() -> int {
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        c->profiling = on != 0;
+        c->ktimes.clear();
+        c->pending.clear();
+        c->ev_used = 0;
+        return DFA_OK;
+    });
 }
 
 int dfa_profile_only(const char *name) {
-    if (name && std::strlen(name) >= sizeof(dfa_kernel_time{}.name))
-        return fail(DFA_EINVAL, "kernel name too long");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    c->prof_only = name ? name : "";
-    return DFA_OK;
+    return guarded([&]() -> int {
+        if (name && std::strlen(name) >= sizeof(dfa_kernel_time{}.name))
+            return fail(DFA_EINVAL, "kernel name too long");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        c->prof_only = name ? name : "";
+        return DFA_OK;
+    });
 }
 
 int dfa_profile_read(dfa_kernel_time *out, int cap, int *count) {
-    if (!count || (cap > 0 && !out)) return fail(DFA_EINVAL, "NULL profile buffer");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    int i = 0;
-    for (const auto &kv : c->ktimes) {
-        if (i < cap) {
-            std::memset(&out[i], 0, sizeof out[i]);
-            std::snprintf(out[i].name, sizeof out[i].name, "%s", kv.first.c_str());
-            out[i].launches = kv.second.launches;
-            out[i].total_ms = kv.second.ms;
-            out[i].algorithmic_bytes = kv.second.bytes;
+    return guarded([&]() -> int {
+        if (!count || (cap > 0 && !out)) return fail(DFA_EINVAL, "NULL profile buffer");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        int i = 0;
+        for (const auto &kv : c->ktimes) {
+            if (i < cap) {
+                std::memset(&out[i], 0, sizeof out[i]);
+                std::snprintf(out[i].name, sizeof out[i].name, "%s", kv.first.c_str());
+                out[i].launches = kv.second.launches;
+                out[i].total_ms = kv.second.ms;
+                out[i].algorithmic_bytes = kv.second.bytes;
+            }
+            ++i;
         }
-        ++i;
-    }
-    *count = i;
-    return DFA_OK;
+        *count = i;
+        return DFA_OK;
+    });
 }
 
 void dfa_tuning_default(dfa_tuning *t) {
@@ -2287,26 +2333,30 @@ void dfa_tuning_default(dfa_tuning *t) {
 }
 
 int dfa_get_tuning(dfa_tuning *t) {
-    if (!t) return fail(DFA_EINVAL, "tuning is NULL");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    *t = c->tune;
-    return DFA_OK;
+    return guarded([&]() -> int {
+        if (!t) return fail(DFA_EINVAL, "tuning is NULL");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        *t = c->tune;
+        return DFA_OK;
+    });
 }
 
 int dfa_set_tuning(const dfa_tuning *t) {
-    if (!t) return fail(DFA_EINVAL, "tuning is NULL");
-    if (t->label_rounds > 2 || t->cached_probe > 1 || t->chunk == 0 || t->chunk > 4096 ||
-        t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24) || t->hash_bits > 63)
-        return fail(DFA_EINVAL, "tuning value out of range");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    c->tune = *t;
-    return DFA_OK;
+    return guarded([&]() -> int {
+        if (!t) return fail(DFA_EINVAL, "tuning is NULL");
+        if (t->label_rounds > 2 || t->cached_probe > 1 || t->chunk == 0 || t->chunk > 4096 ||
+            t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24) || t->hash_bits > 63)
+            return fail(DFA_EINVAL, "tuning value out of range");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        c->tune = *t;
+        return DFA_OK;
+    });
 }
 
 void dfa_options_default(dfa_options *opt) {
@@ -2323,112 +2373,126 @@ void dfa_options_default(dfa_options *opt) {
 const char *dfa_last_error(void) { return g_last_error.c_str(); }
 
 int dfa_device_info(char *name, size_t name_cap, int *compute_units, size_t *hbm_bytes) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    hipDeviceProp_t p;
-    HIP_TRY(hipGetDeviceProperties(&p, dev));
-    if (name && name_cap) {
-        std::snprintf(name, name_cap, "%s (%s)", p.name, p.gcnArchName);
-    }
-    if (compute_units) *compute_units = p.multiProcessorCount;
-    if (hbm_bytes) *hbm_bytes = p.totalGlobalMem;
-    return DFA_OK;
+    return guarded([&]() -> int {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        hipDeviceProp_t p;
+        HIP_TRY(hipGetDeviceProperties(&p, dev));
+        if (name && name_cap) {
+            std::snprintf(name, name_cap, "%s (%s)", p.name, p.gcnArchName);
+        }
+        if (compute_units) *compute_units = p.multiProcessorCount;
+        if (hbm_bytes) *hbm_bytes = p.totalGlobalMem;
+        return DFA_OK;
+    });
 }
 
 int dfa_minimise_device(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *accepting,
                         uint32_t *block_out, dfa_quotient *q_out, const dfa_options *opt,
                         dfa_stats *stats, void *stream) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    DFA_TRY(join_stream(*c, stream));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    return minimise_impl(*c, n, k, delta, accepting, block_out, q_out, o, stats);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        DFA_TRY(join_stream(*c, stream));
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return minimise_impl(*c, n, k, delta, accepting, block_out, q_out, o, stats);
+    });
 }
 
 int dfa_minimise(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_t *accepting,
                  uint32_t *block_out, dfa_quotient *q_out, const dfa_options *opt,
                  dfa_stats *stats) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    return minimise_host(*c, n, k, delta, accepting, block_out, q_out, o, stats);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        return minimise_host(*c, n, k, delta, accepting, block_out, q_out, o, stats);
+    });
 }
 
 int dfa_equivalent_device(const dfa_view *a, const dfa_view *b, int *verdict,
                           const dfa_options *opt, dfa_stats *stats, void *stream) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_pair(a, b, verdict));
-    DFA_TRY(check_options(o));
-    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    DFA_TRY(join_stream(*c, stream));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    return equivalent_impl(*c, *a, *b, verdict, o, stats);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_pair(a, b, verdict));
+        DFA_TRY(check_options(o));
+        if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        DFA_TRY(join_stream(*c, stream));
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return equivalent_impl(*c, *a, *b, verdict, o, stats);
+    });
 }
 
 int dfa_equivalent(const dfa_view *a, const dfa_view *b, int *verdict, const dfa_options *opt,
                    dfa_stats *stats) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_pair(a, b, verdict));
-    DFA_TRY(check_options(o));
-    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    return equivalent_host(*c, a, b, verdict, o, stats);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_pair(a, b, verdict));
+        DFA_TRY(check_options(o));
+        if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        return equivalent_host(*c, a, b, verdict, o, stats);
+    });
 }
 
 int dfa_included_device(const dfa_view *a, const dfa_view *b, int *verdict,
                         uint64_t *pairs_visited, const dfa_options *opt, dfa_stats *stats,
                         void *stream) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_pair(a, b, verdict));
-    DFA_TRY(check_options(o));
-    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    DFA_TRY(join_stream(*c, stream));
-    return included_impl(*c, *a, *b, verdict, pairs_visited, stats);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_pair(a, b, verdict));
+        DFA_TRY(check_options(o));
+        if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        DFA_TRY(join_stream(*c, stream));
+        return included_impl(*c, *a, *b, verdict, pairs_visited, stats);
+    });
 }
 
 int dfa_included(const dfa_view *a, const dfa_view *b, int *verdict, uint64_t *pairs_visited,
                  const dfa_options *opt, dfa_stats *stats) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_pair(a, b, verdict));
-    DFA_TRY(check_options(o));
-    if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    auto t0 = std::chrono::steady_clock::now();
-    dfa_view da, db;
-    DFA_TRY(stage_view(*c, c->stage_delta, c->stage_acc, a, da));
-    DFA_TRY(stage_view(*c, c->stage_delta_b, c->stage_acc_b, b, db));
-    HIP_TRY(stream_sync(*c));
-    const double h2d = ms_since(t0);
-    int rc = included_impl(*c, da, db, verdict, pairs_visited, stats);
-    if (stats) stats->h2d_ms = h2d;
-    return rc;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_pair(a, b, verdict));
+        DFA_TRY(check_options(o));
+        if (o.prune) return fail(DFA_EINVAL, "prune applies to dfa_minimise only");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        auto t0 = std::chrono::steady_clock::now();
+        dfa_view da, db;
+        DFA_TRY(stage_view(*c, c->stage_delta, c->stage_acc, a, da));
+        DFA_TRY(stage_view(*c, c->stage_delta_b, c->stage_acc_b, b, db));
+        HIP_TRY(stream_sync(*c));
+        const double h2d = ms_since(t0);
+        int rc = included_impl(*c, da, db, verdict, pairs_visited, stats);
+        if (stats) stats->h2d_ms = h2d;
+        return rc;
+    });
 }
 
 
@@ -2436,107 +2500,115 @@ int dfa_minimise_batch_device(uint32_t count, const dfa_view *dfas, uint32_t *bl
                               const uint64_t *block_offsets, uint32_t *num_blocks,
                               uint32_t *rounds, const dfa_options *opt, dfa_batch_stats *stats,
                               void *stream) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_views(count, dfas, "dfas"));
-    DFA_TRY(check_batch_options(o));
-    if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    DFA_TRY(join_stream(*c, stream));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    return minimise_batch_impl(*c, count, dfas, blocks_concat, block_offsets, num_blocks, rounds,
-                               o, stats);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_views(count, dfas, "dfas"));
+        DFA_TRY(check_batch_options(o));
+        if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        DFA_TRY(join_stream(*c, stream));
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return minimise_batch_impl(*c, count, dfas, blocks_concat, block_offsets, num_blocks, rounds,
+                                   o, stats);
+    });
 }
 
 int dfa_minimise_batch(uint32_t count, const dfa_view *dfas, uint32_t *blocks_concat,
                        const uint64_t *block_offsets, uint32_t *num_blocks, uint32_t *rounds,
                        const dfa_options *opt, dfa_batch_stats *stats) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_views(count, dfas, "dfas"));
-    DFA_TRY(check_batch_options(o));
-    if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    std::vector<dfa_view> dev;
-    double h2d = 0;
-    const dfa_view *lists[1] = {dfas};
-    DFA_TRY(stage_views(*c, count, lists, 1, dev, h2d));
-    uint64_t total = 0;
-    for (uint32_t i = 0; i < count; ++i) total += dfas[i].n;
-    DFA_TRY(c->batch_out.ensure(total * sizeof(uint32_t), "batched outputs"));
-    int rc = minimise_batch_impl(*c, count, dev.data(), c->batch_out.as<uint32_t>(), nullptr,
-                                 num_blocks, rounds, o, stats);
-    if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
-    auto t0 = std::chrono::steady_clock::now();
-    DFA_TRY(ensure_pinned_batch(*c, total * sizeof(uint32_t)));
-    HIP_TRY(hipMemcpyAsync(c->pinned_batch, c->batch_out.p, total * sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(stream_sync(*c));
-    uint64_t pos = 0;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(c->pinned_batch);
-    std::vector<CopyJob> jobs(count);
-    for (uint32_t i = 0; i < count; ++i) {
-        const uint64_t dst = block_offsets ? block_offsets[i] : pos;
-        jobs[i] = {blocks_concat + dst, src + pos, dfas[i].n * sizeof(uint32_t)};
-        pos += dfas[i].n;
-    }
-    parallel_copies(jobs);
-    if (stats) {
-        stats->h2d_ms = h2d;
-        stats->d2h_ms = ms_since(t0);
-    }
-    return rc;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_views(count, dfas, "dfas"));
+        DFA_TRY(check_batch_options(o));
+        if (!blocks_concat) return fail(DFA_EINVAL, "blocks_concat is NULL");
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        std::vector<dfa_view> dev;
+        double h2d = 0;
+        const dfa_view *lists[1] = {dfas};
+        DFA_TRY(stage_views(*c, count, lists, 1, dev, h2d));
+        uint64_t total = 0;
+        for (uint32_t i = 0; i < count; ++i) total += dfas[i].n;
+        DFA_TRY(c->batch_out.ensure(total * sizeof(uint32_t), "batched outputs"));
+        int rc = minimise_batch_impl(*c, count, dev.data(), c->batch_out.as<uint32_t>(), nullptr,
+                                     num_blocks, rounds, o, stats);
+        if (rc != DFA_OK && rc != DFA_ELIMIT) return rc;
+        auto t0 = std::chrono::steady_clock::now();
+        DFA_TRY(ensure_pinned_batch(*c, total * sizeof(uint32_t)));
+        HIP_TRY(hipMemcpyAsync(c->pinned_batch, c->batch_out.p, total * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(stream_sync(*c));
+        uint64_t pos = 0;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(c->pinned_batch);
+        std::vector<CopyJob> jobs(count);
+        for (uint32_t i = 0; i < count; ++i) {
+            const uint64_t dst = block_offsets ? block_offsets[i] : pos;
+            jobs[i] = {blocks_concat + dst, src + pos, dfas[i].n * sizeof(uint32_t)};
+            pos += dfas[i].n;
+        }
+        parallel_copies(jobs);
+        if (stats) {
+            stats->h2d_ms = h2d;
+            stats->d2h_ms = ms_since(t0);
+        }
+        return rc;
+    });
 }
 
 int dfa_equivalent_batch_device(uint32_t count, const dfa_view *a, const dfa_view *b,
                                 int32_t *verdicts, const dfa_options *opt,
                                 dfa_batch_stats *stats, void *stream) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_views(count, a, "a"));
-    DFA_TRY(check_views(count, b, "b"));
-    DFA_TRY(check_batch_options(o));
-    if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
-    for (uint32_t i = 0; i < count; ++i)
-        if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    DFA_TRY(join_stream(*c, stream));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    return equivalent_batch_impl(*c, count, a, b, verdicts, o, stats);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_views(count, a, "a"));
+        DFA_TRY(check_views(count, b, "b"));
+        DFA_TRY(check_batch_options(o));
+        if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
+        for (uint32_t i = 0; i < count; ++i)
+            if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        DFA_TRY(join_stream(*c, stream));
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return equivalent_batch_impl(*c, count, a, b, verdicts, o, stats);
+    });
 }
 
 int dfa_equivalent_batch(uint32_t count, const dfa_view *a, const dfa_view *b, int32_t *verdicts,
                          const dfa_options *opt, dfa_batch_stats *stats) {
-    g_last_error.clear();
-    dfa_options o = resolve(opt);
-    DFA_TRY(check_views(count, a, "a"));
-    DFA_TRY(check_views(count, b, "b"));
-    DFA_TRY(check_batch_options(o));
-    if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
-    for (uint32_t i = 0; i < count; ++i)
-        if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
-    Ctx *c = nullptr;
-    DFA_TRY(get_ctx(c));
-    CallScope lock(c->mu);
-    DFA_TRY(init_ctx(*c));
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    std::vector<dfa_view> dev;
-    double h2d = 0;
-    const dfa_view *lists[2] = {a, b};
-    DFA_TRY(stage_views(*c, count, lists, 2, dev, h2d));
-    int rc = equivalent_batch_impl(*c, count, dev.data(), dev.data() + count, verdicts, o, stats);
-    if (stats) stats->h2d_ms = h2d;
-    return rc;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_views(count, a, "a"));
+        DFA_TRY(check_views(count, b, "b"));
+        DFA_TRY(check_batch_options(o));
+        if (!verdicts) return fail(DFA_EINVAL, "verdicts is NULL");
+        for (uint32_t i = 0; i < count; ++i)
+            if (a[i].k != b[i].k) return fail(DFA_EINVAL, "pair %u: alphabet sizes differ", i);
+        Ctx *c = nullptr;
+        DFA_TRY(get_ctx(c));
+        CallScope lock(c->mu);
+        DFA_TRY(init_ctx(*c));
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        std::vector<dfa_view> dev;
+        double h2d = 0;
+        const dfa_view *lists[2] = {a, b};
+        DFA_TRY(stage_views(*c, count, lists, 2, dev, h2d));
+        int rc = equivalent_batch_impl(*c, count, dev.data(), dev.data() + count, verdicts, o, stats);
+        if (stats) stats->h2d_ms = h2d;
+        return rc;
+    });
 }
 
 
@@ -2552,201 +2624,233 @@ void dfa_server_config_default(dfa_server_config *cfg) {
 }
 
 dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
-    RelaxedCapture relaxed;
-    g_last_error.clear();
-    dfa_server_config cfg;
-    dfa_server_config_default(&cfg);
-    if (cfg_in) cfg = *cfg_in;
-    if (cfg.lanes == 0 || cfg.lanes > 16 || cfg.max_group == 0 || cfg.batch_round_budget < 3 ||
-        cfg.tc_mode < DFA_TC_OFF || cfg.tc_mode > DFA_TC_AUTO) {
-        fail(DFA_EINVAL, "bad server configuration");
-        return nullptr;
-    }
-    auto s = std::make_unique<Server>();
-    if (hipGetDevice(&s->device) != hipSuccess) {
-        fail(DFA_EDEVICE, "no HIP device");
-        return nullptr;
-    }
-    if (cfg.hbm_budget == 0) {
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-            fail(DFA_EDEVICE, "hipMemGetInfo failed");
+    try {
+        RelaxedCapture relaxed;
+        g_last_error.clear();
+        dfa_server_config cfg;
+        dfa_server_config_default(&cfg);
+        if (cfg_in) cfg = *cfg_in;
+        if (cfg.lanes == 0 || cfg.lanes > 16 || cfg.max_group == 0 || cfg.batch_round_budget < 3 ||
+            cfg.tc_mode < DFA_TC_OFF || cfg.tc_mode > DFA_TC_AUTO) {
+            fail(DFA_EINVAL, "bad server configuration");
             return nullptr;
         }
-        cfg.hbm_budget = free_b / 2;
+        auto s = std::make_unique<Server>();
+        if (hipGetDevice(&s->device) != hipSuccess) {
+            fail(DFA_EDEVICE, "no HIP device");
+            return nullptr;
+        }
+        if (cfg.hbm_budget == 0) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+                fail(DFA_EDEVICE, "hipMemGetInfo failed");
+                return nullptr;
+            }
+            cfg.hbm_budget = free_b / 2;
+        }
+        s->cfg = cfg;
+        {
+            Ctx *dc = nullptr;
+            if (get_ctx(dc) != DFA_OK) return nullptr;
+            CallScope lock(dc->mu);
+            if (init_ctx(*dc) != DFA_OK) return nullptr;
+            s->tune = dc->tune;
+        }
+        s->t_created = Clock::now();
+        try {
+            for (uint32_t i = 0; i < cfg.lanes; ++i) s->lanes.push_back(std::make_unique<Ctx>());
+            Server *raw = s.get();
+            for (uint32_t i = 0; i < cfg.lanes; ++i) s->workers.emplace_back(lane_main, raw, i);
+        } catch (const std::exception &e) {
+            // stop the lanes that did start before the server goes away
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->stopping = true;
+            }
+            s->cv_work.notify_all();
+            for (auto &t : s->workers) t.join();
+            for (auto &l : s->lanes) release_ctx(*l);
+            fail(DFA_ENOMEM, "starting the server lanes failed: %s", e.what());
+            return nullptr;
+        }
+        return reinterpret_cast<dfa_server *>(s.release());
+    } catch (const std::exception &e) {
+        fail(DFA_ENOMEM, "creating the server failed: %s", e.what());
+        return nullptr;
     }
-    s->cfg = cfg;
-    {
-        Ctx *dc = nullptr;
-        if (get_ctx(dc) != DFA_OK) return nullptr;
-        CallScope lock(dc->mu);
-        if (init_ctx(*dc) != DFA_OK) return nullptr;
-        s->tune = dc->tune;
-    }
-    s->t_created = Clock::now();
-    for (uint32_t i = 0; i < cfg.lanes; ++i) s->lanes.push_back(std::make_unique<Ctx>());
-    Server *raw = s.get();
-    for (uint32_t i = 0; i < cfg.lanes; ++i) s->workers.emplace_back(lane_main, raw, i);
-    return reinterpret_cast<dfa_server *>(s.release());
 }
 
 int dfa_server_submit(dfa_server *handle, const dfa_request *req, uint64_t *ticket) {
-    RelaxedCapture relaxed;  // page-locked staging may be allocated here
-    g_last_error.clear();
-    Server *s = reinterpret_cast<Server *>(handle);
-    if (!s || !req || !ticket) return fail(DFA_EINVAL, "NULL server, request or ticket");
-    if (req->kind != DFA_REQ_MINIMISE && req->kind != DFA_REQ_EQUIVALENT)
-        return fail(DFA_EINVAL, "unknown request kind %d", req->kind);
-    DFA_TRY(check_view(&req->a, "a"));
-    if (req->kind == DFA_REQ_EQUIVALENT) {
-        DFA_TRY(check_view(&req->b, "b"));
-        if (req->a.k != req->b.k) return fail(DFA_EINVAL, "alphabet sizes differ");
-    }
-    auto r = std::make_unique<ServedRequest>();
-    r->kind = req->kind;
-    const bool two = req->kind == DFA_REQ_EQUIVALENT;
-    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t da = static_cast<size_t>(req->a.n) * req->a.k * sizeof(uint32_t);
-    const size_t db = two ? static_cast<size_t>(req->b.n) * req->b.k * sizeof(uint32_t) : 0;
-    r->in_bytes = al(da) + al(req->a.n) + (two ? al(db) + al(req->b.n) : 0);
-    r->states = req->a.n + (two ? req->b.n : 0);
-    r->footprint = request_footprint(r->states, req->a.k, s->cfg.tc_mode != DFA_TC_OFF);
-    if (r->footprint > s->cfg.hbm_budget) {
+    return guarded([&]() -> int {
+        RelaxedCapture relaxed;  // page-locked staging may be allocated here
+        g_last_error.clear();
+        Server *s = reinterpret_cast<Server *>(handle);
+        if (!s || !req || !ticket) return fail(DFA_EINVAL, "NULL server, request or ticket");
+        if (req->kind != DFA_REQ_MINIMISE && req->kind != DFA_REQ_EQUIVALENT)
+            return fail(DFA_EINVAL, "unknown request kind %d", req->kind);
+        DFA_TRY(check_view(&req->a, "a"));
+        if (req->kind == DFA_REQ_EQUIVALENT) {
+            DFA_TRY(check_view(&req->b, "b"));
+            if (req->a.k != req->b.k) return fail(DFA_EINVAL, "alphabet sizes differ");
+        }
+        auto r = std::make_unique<ServedRequest>();
+        r->kind = req->kind;
+        const bool two = req->kind == DFA_REQ_EQUIVALENT;
+        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+        const size_t da = static_cast<size_t>(req->a.n) * req->a.k * sizeof(uint32_t);
+        const size_t db = two ? static_cast<size_t>(req->b.n) * req->b.k * sizeof(uint32_t) : 0;
+        r->in_bytes = al(da) + al(req->a.n) + (two ? al(db) + al(req->b.n) : 0);
+        r->states = req->a.n + (two ? req->b.n : 0);
+        r->footprint = request_footprint(r->states, req->a.k, s->cfg.tc_mode != DFA_TC_OFF);
+        if (r->footprint > s->cfg.hbm_budget) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->rejected++;
+            return fail(DFA_ENOMEM, "request needs ~%zu bytes of device memory, budget is %zu",
+                        r->footprint, s->cfg.hbm_budget);
+        }
+        // the inputs are copied now (page-locked, so the lane's upload is an
+        // asynchronous DMA), so the caller may free them on return
+        r->off_acc_a = al(da);
+        r->off_delta_b = r->off_acc_a + al(req->a.n);
+        r->off_acc_b = r->off_delta_b + al(db);
+        uint8_t *host = static_cast<uint8_t *>(s->pinned.get(r->in_bytes, r->host_cls));
+        if (!host) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->rejected++;
+            return fail(DFA_ENOMEM, "page-locked host allocation of %zu bytes failed", r->in_bytes);
+        }
+        r->host_in = host;
+        parallel_copy(host, req->a.delta, da);
+        std::memcpy(host + r->off_acc_a, req->a.accepting, req->a.n);
+        r->a = req->a;
+        if (two) {
+            parallel_copy(host + r->off_delta_b, req->b.delta, db);
+            std::memcpy(host + r->off_acc_b, req->b.accepting, req->b.n);
+            r->b = req->b;
+        }
         std::lock_guard<std::mutex> lk(s->mu);
-        s->rejected++;
-        return fail(DFA_ENOMEM, "request needs ~%zu bytes of device memory, budget is %zu",
-                    r->footprint, s->cfg.hbm_budget);
-    }
-    // the inputs are copied now (page-locked, so the lane's upload is an
-    // asynchronous DMA), so the caller may free them on return
-    r->off_acc_a = al(da);
-    r->off_delta_b = r->off_acc_a + al(req->a.n);
-    r->off_acc_b = r->off_delta_b + al(db);
-    uint8_t *host = static_cast<uint8_t *>(s->pinned.get(r->in_bytes, r->host_cls));
-    if (!host) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->rejected++;
-        return fail(DFA_ENOMEM, "page-locked host allocation of %zu bytes failed", r->in_bytes);
-    }
-    r->host_in = host;
-    parallel_copy(host, req->a.delta, da);
-    std::memcpy(host + r->off_acc_a, req->a.accepting, req->a.n);
-    r->a = req->a;
-    if (two) {
-        parallel_copy(host + r->off_delta_b, req->b.delta, db);
-        std::memcpy(host + r->off_acc_b, req->b.accepting, req->b.n);
-        r->b = req->b;
-    }
-    std::lock_guard<std::mutex> lk(s->mu);
-    r->ticket = s->next_ticket++;
-    r->t_submit = Clock::now();
-    *ticket = r->ticket;
-    s->pending.push_back(r.get());
-    s->requests.emplace(r->ticket, std::move(r));
-    s->submitted++;
-    s->cv_work.notify_one();
-    return DFA_OK;
+        r->ticket = s->next_ticket++;
+        r->t_submit = Clock::now();
+        *ticket = r->ticket;
+        s->pending.push_back(r.get());
+        s->requests.emplace(r->ticket, std::move(r));
+        s->submitted++;
+        s->cv_work.notify_one();
+        return DFA_OK;
+    });
 }
 
 int dfa_server_poll(dfa_server *handle, uint64_t ticket, dfa_result *out) {
-    Server *s = reinterpret_cast<Server *>(handle);
-    if (!s || !out) return fail(DFA_EINVAL, "NULL server or result");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->requests.find(ticket);
-    if (it == s->requests.end()) return fail(DFA_EINVAL, "unknown ticket %llu",
-                                             static_cast<unsigned long long>(ticket));
-    if (!it->second->done) return DFA_EAGAIN;
-    fill_result(*it->second, out);
-    return DFA_OK;
+    return guarded([&]() -> int {
+        Server *s = reinterpret_cast<Server *>(handle);
+        if (!s || !out) return fail(DFA_EINVAL, "NULL server or result");
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->requests.find(ticket);
+        if (it == s->requests.end()) return fail(DFA_EINVAL, "unknown ticket %llu",
+                                                 static_cast<unsigned long long>(ticket));
+        if (!it->second->done) return DFA_EAGAIN;
+        fill_result(*it->second, out);
+        return DFA_OK;
+    });
 }
 
 int dfa_server_wait(dfa_server *handle, uint64_t ticket, dfa_result *out) {
-    Server *s = reinterpret_cast<Server *>(handle);
-    if (!s || !out) return fail(DFA_EINVAL, "NULL server or result");
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->requests.find(ticket);
-    if (it == s->requests.end()) return fail(DFA_EINVAL, "unknown ticket %llu",
-                                             static_cast<unsigned long long>(ticket));
-    ServedRequest *r = it->second.get();
-    s->cv_done.wait(lk, [&] { return r->done; });
-    fill_result(*r, out);
-    return DFA_OK;
+    return guarded([&]() -> int {
+        Server *s = reinterpret_cast<Server *>(handle);
+        if (!s || !out) return fail(DFA_EINVAL, "NULL server or result");
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->requests.find(ticket);
+        if (it == s->requests.end()) return fail(DFA_EINVAL, "unknown ticket %llu",
+                                                 static_cast<unsigned long long>(ticket));
+        ServedRequest *r = it->second.get();
+        s->cv_done.wait(lk, [&] { return r->done; });
+        fill_result(*r, out);
+        return DFA_OK;
+    });
 }
 
 int dfa_result_release(dfa_server *handle, uint64_t ticket) {
-    RelaxedCapture relaxed;
-    Server *s = reinterpret_cast<Server *>(handle);
-    if (!s) return fail(DFA_EINVAL, "NULL server");
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->requests.find(ticket);
-    if (it == s->requests.end() || !it->second->done)
-        return fail(DFA_EINVAL, "ticket %llu is unknown or not finished",
-                    static_cast<unsigned long long>(ticket));
-    if (it->second->blocks) s->pinned.put(it->second->blocks, it->second->blocks_cls);
-    s->requests.erase(it);
-    return DFA_OK;
+    return guarded([&]() -> int {
+        RelaxedCapture relaxed;
+        Server *s = reinterpret_cast<Server *>(handle);
+        if (!s) return fail(DFA_EINVAL, "NULL server");
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->requests.find(ticket);
+        if (it == s->requests.end() || !it->second->done)
+            return fail(DFA_EINVAL, "ticket %llu is unknown or not finished",
+                        static_cast<unsigned long long>(ticket));
+        if (it->second->blocks) s->pinned.put(it->second->blocks, it->second->blocks_cls);
+        s->requests.erase(it);
+        return DFA_OK;
+    });
 }
 
 int dfa_server_get_stats(dfa_server *handle, dfa_server_stats *out) {
-    Server *s = reinterpret_cast<Server *>(handle);
-    if (!s || !out) return fail(DFA_EINVAL, "NULL server or stats");
-    std::lock_guard<std::mutex> lk(s->mu);
-    std::memset(out, 0, sizeof *out);
-    out->submitted = s->submitted;
-    out->completed = s->completed;
-    out->rejected = s->rejected;
-    out->batched_groups = s->groups;
-    out->solo_runs = s->solo;
-    out->pending = s->pending.size();
-    out->hbm_in_use = s->in_use;
-    out->hbm_budget = s->cfg.hbm_budget;
-    std::vector<double> lat = s->latencies;
-    if (!lat.empty()) {
-        std::sort(lat.begin(), lat.end());
-        auto pct = [&](double p) {
-            size_t i = static_cast<size_t>(p * (lat.size() - 1) + 0.5);
-            return lat[std::min(i, lat.size() - 1)];
-        };
-        out->p50_ms = pct(0.50);
-        out->p99_ms = pct(0.99);
-        double sum = 0;
-        for (double v : lat) sum += v;
-        out->mean_ms = sum / lat.size();
-    }
-    out->uptime_s = std::chrono::duration<double>(Clock::now() - s->t_created).count();
-    out->requests_per_s = out->uptime_s > 0 ? s->completed / out->uptime_s : 0.0;
-    return DFA_OK;
+    return guarded([&]() -> int {
+        Server *s = reinterpret_cast<Server *>(handle);
+        if (!s || !out) return fail(DFA_EINVAL, "NULL server or stats");
+        std::lock_guard<std::mutex> lk(s->mu);
+        std::memset(out, 0, sizeof *out);
+        out->submitted = s->submitted;
+        out->completed = s->completed;
+        out->rejected = s->rejected;
+        out->batched_groups = s->groups;
+        out->solo_runs = s->solo;
+        out->pending = s->pending.size();
+        out->hbm_in_use = s->in_use;
+        out->hbm_budget = s->cfg.hbm_budget;
+        std::vector<double> lat = s->latencies;
+        if (!lat.empty()) {
+            std::sort(lat.begin(), lat.end());
+            auto pct = [&](double p) {
+                size_t i = static_cast<size_t>(p * (lat.size() - 1) + 0.5);
+                return lat[std::min(i, lat.size() - 1)];
+            };
+            out->p50_ms = pct(0.50);
+            out->p99_ms = pct(0.99);
+            double sum = 0;
+            for (double v : lat) sum += v;
+            out->mean_ms = sum / lat.size();
+        }
+        out->uptime_s = std::chrono::duration<double>(Clock::now() - s->t_created).count();
+        out->requests_per_s = out->uptime_s > 0 ? s->completed / out->uptime_s : 0.0;
+        return DFA_OK;
+    });
 }
 
 void dfa_server_destroy(dfa_server *handle) {
-    RelaxedCapture relaxed;
-    Server *s = reinterpret_cast<Server *>(handle);
-    if (!s) return;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stopping = true;
-        for (ServedRequest *r : s->pending) {
-            r->status = DFA_ECANCELED;
-            r->t_start = Clock::now();
-            r->done = true;
-            r->t_done = r->t_start;
+    try {
+        RelaxedCapture relaxed;
+        Server *s = reinterpret_cast<Server *>(handle);
+        if (!s) return;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stopping = true;
+            for (ServedRequest *r : s->pending) {
+                r->status = DFA_ECANCELED;
+                r->t_start = Clock::now();
+                r->done = true;
+                r->t_done = r->t_start;
+            }
+            s->pending.clear();
         }
-        s->pending.clear();
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+        for (auto &t : s->workers) t.join();
+        (void)hipSetDevice(s->device);
+        for (auto &c : s->lanes) release_ctx(*c);
+        // host copies of cancelled requests and unreleased results go back to
+        // the pool, which the server frees
+        for (auto &kv : s->requests) {
+            if (kv.second->host_in) s->pinned.put(kv.second->host_in, kv.second->host_cls);
+            if (kv.second->blocks) s->pinned.put(kv.second->blocks, kv.second->blocks_cls);
+            kv.second->host_in = nullptr;
+            kv.second->blocks = nullptr;
+        }
+        delete s;
+    } catch (...) {
+        // nothing may cross the C ABI; what was not freed stays allocated
     }
-    s->cv_work.notify_all();
-    s->cv_done.notify_all();
-    for (auto &t : s->workers) t.join();
-    (void)hipSetDevice(s->device);
-    for (auto &c : s->lanes) release_ctx(*c);
-    // host copies of cancelled requests and unreleased results go back to
-    // the pool, which the server frees
-    for (auto &kv : s->requests) {
-        if (kv.second->host_in) s->pinned.put(kv.second->host_in, kv.second->host_cls);
-        if (kv.second->blocks) s->pinned.put(kv.second->blocks, kv.second->blocks_cls);
-        kv.second->host_in = nullptr;
-        kv.second->blocks = nullptr;
-    }
-    delete s;
 }
 
 }  // extern "C"
