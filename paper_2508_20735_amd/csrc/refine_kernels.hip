@@ -286,14 +286,19 @@ __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
 // signature (label of q, labels of its successors) packs exactly into one
 // word, which becomes the new label.  Labels are gathered from the byte copy
 // written by round 0 (small enough to stay in L2).  Distinct labels are
-// counted by first setters in a presence bitmap; each tile of kBlock states
-// first removes its own duplicates in an LDS set, so a frequent label costs
-// one bitmap access per tile, not one per state.
+// counted by first setters in a presence bitmap; a workgroup first removes
+// the duplicates among the tiles it handles in an LDS set, so a frequent
+// label costs about one bitmap access per workgroup, not one per state.
 constexpr uint32_t kLdsSlots = 2 * kBlock;
+// labels a workgroup remembers across its tiles; the set is emptied before a
+// tile once it is half full, so a tile (at most kBlock new labels) always
+// finds empty slots
+constexpr uint32_t kLabelSlots = 16 * kBlock;
 
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
-    __shared__ uint32_t lset[kLdsSlots];
+    __shared__ uint32_t lset[kLabelSlots];
+    __shared__ uint32_t lfill;
     if (p.ctl->done) return;
     const uint32_t r = p.ctl->round;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
@@ -302,10 +307,19 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
     const uint32_t tx = threadIdx.x;
     uint32_t fresh = 0;
     const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
+    for (uint32_t i = tx; i < kLabelSlots; i += kBlock) lset[i] = ~0u;
+    if (tx == 0) lfill = 0;
+    __syncthreads();
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
-        for (uint32_t i = tx; i < kLdsSlots; i += kBlock) lset[i] = ~0u;
+        // every thread reads the fill before any thread of this tile inserts
+        const bool half_full = lfill > kLabelSlots / 2;
         __syncthreads();
+        if (half_full) {
+            for (uint32_t i = tx; i < kLabelSlots; i += kBlock) lset[i] = ~0u;
+            if (tx == 0) lfill = 0;
+            __syncthreads();
+        }
         const size_t q = base + tx;
         bool first = false;
         uint32_t key = 0;
@@ -327,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
             }
             Y[q] = key;
             // keys are < 2^kPackedMaxBits, so ~0u marks an empty LDS slot
-            uint32_t slot = (key * 0x9E3779B1u) >> 23;  // 9 bits
+            uint32_t slot = (key * 0x9E3779B1u) >> 20;  // 12 bits
             for (;;) {
                 const uint32_t e =
                     __hip_atomic_load(lset + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -336,11 +350,12 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
                     const uint32_t prev = atomicCAS(lset + slot, ~0u, key);
                     if (prev == ~0u) {
                         first = true;
+                        atomicAdd(&lfill, 1u);
                         break;
                     }
                     if (prev == key) break;
                 }
-                slot = (slot + 1) & (kLdsSlots - 1);
+                slot = (slot + 1) & (kLabelSlots - 1);
             }
         }
         if (first) {
