@@ -33,6 +33,28 @@ __device__ __forceinline__ size_t grid_stride() {
 // Workgroup sum of per-thread values, added with one atomic per workgroup to
 // one of kSpread counters (consecutive workgroups use different lines).
 // Every thread of the workgroup must call it.
+// The tiles (of `tile` states, covering n states) that this workgroup
+// handles, as first, end and step.  Workgroups are dispatched to the 8 XCDs
+// round-robin; with a grid that is a multiple of 8, each XCD takes one
+// contiguous eighth of the tiles, so in a union (whose transitions stay
+// inside each operand) the gathers of an XCD stay inside one operand, a
+// footprint half as large for its L2.  Other grids stride over all tiles.
+struct TileRange {
+    size_t first, end, step;
+};
+
+__device__ __forceinline__ TileRange xcd_tiles(size_t n, size_t tile) {
+    const size_t tiles = (n + tile - 1) / tile;
+    TileRange t{blockIdx.x, tiles, gridDim.x};
+    if (gridDim.x % 8 == 0) {
+        const size_t x = blockIdx.x % 8;
+        t.first = tiles * x / 8 + blockIdx.x / 8;
+        t.end = tiles * (x + 1) / 8;
+        t.step = gridDim.x / 8;
+    }
+    return t;
+}
+
 __device__ __forceinline__ void wg_add_spread(uint32_t *counters, int word, uint32_t v) {
     __shared__ uint32_t part[kBlock / 64];
 #pragma unroll

@@ -310,8 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
     for (uint32_t i = tx; i < kLabelSlots; i += kBlock) lset[i] = ~0u;
     if (tx == 0) lfill = 0;
     __syncthreads();
-    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
-         base += static_cast<size_t>(gridDim.x) * kBlock) {
+    // XCD-sliced tiles: in a union each XCD gathers the labels of one
+    // operand only, a footprint its own L2 holds
+    const TileRange tr = xcd_tiles(p.N, kBlock);
+    for (size_t t = tr.first; t < tr.end; t += tr.step) {
+        const size_t base = t * kBlock;
         // every thread reads the fill before any thread of this tile inserts
         const bool half_full = lfill > kLabelSlots / 2;
         __syncthreads();
@@ -567,8 +570,11 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
         const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
         // two states per thread, all independent loads of both issued before
         // their values are used
-        for (size_t base = static_cast<size_t>(blockIdx.x) * (2 * kBlock); base < p.N;
-             base += static_cast<size_t>(gridDim.x) * (2 * kBlock)) {
+        // XCD-sliced tiles of two kBlock-state halves (a union's successor
+        // ids are gathered from one operand per XCD)
+        const TileRange tr = xcd_tiles(p.N, 2 * kBlock);
+        for (size_t tile = tr.first; tile < tr.end; tile += tr.step) {
+            const size_t base = tile * (2 * kBlock);
             const size_t q[2] = {base + threadIdx.x, base + kBlock + threadIdx.x};
             bool act[2];
             uint32_t w0[2], t[2][KC], w[2][KC];
