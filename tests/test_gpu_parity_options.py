@@ -130,3 +130,23 @@ def test_large_alphabets(k):
     blocks, _, _, _ = B.minimise_batch([d, big], tc="off")
     np.testing.assert_array_equal(blocks[0], hb)
     np.testing.assert_array_equal(blocks[1], hb2)
+
+
+@pytest.mark.parametrize("n,k", [(2047, 2), (6139, 4), (130972, 3), (2 * 1024 * 1024 + 3, 4)])
+def test_xcd_sliced_tiles(n, k):
+    """Grids that are multiples of 8 give each XCD a contiguous share of the
+    tiles (ragged shares and a ragged last tile here; the label rounds' grid
+    is capped at 2,048 and the round kernels' at 8,192), others stride over
+    all tiles: Moore's partition and round count, and the equivalence
+    verdicts on unions of twice the size, both label rounds included."""
+    d = W.random_dfa(n, k, 0.3, 31 + k)
+    res = B.minimise(d.delta, d.accepting, tc="off")
+    block, nb, rounds, changing = oracle.moore(d.delta, d.accepting)
+    np.testing.assert_array_equal(res.block, block)
+    assert (res.stats["num_blocks"], res.stats["rounds"], res.stats["changing_rounds"]) == \
+        (nb, rounds, changing)
+    perm, _ = W.permuted_copy(d, 32 + k)
+    mut, _ = W.mutate_one(d, 33 + k)
+    assert B.equivalent(d, perm, tc="off")[0]
+    want = oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting, mut.start)
+    assert B.equivalent(d, mut, tc="off")[0] == want
