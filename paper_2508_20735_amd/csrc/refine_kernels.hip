@@ -637,9 +637,9 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
                     emit_key(p, Y, q[i], w0[i], w[i], KC, W, !all && p.grouping == 0, claims);
         }
     } else {
-        for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
-             base += static_cast<size_t>(gridDim.x) * kBlock) {
-            const size_t q = base + threadIdx.x;
+        const TileRange tr = xcd_tiles(p.N, kBlock);
+        for (size_t tile = tr.first; tile < tr.end; tile += tr.step) {
+            const size_t q = tile * kBlock + threadIdx.x;
             const bool valid = q < p.N;
             const uint32_t w0 = valid ? X[q] : 0u;
             bool act = valid;
