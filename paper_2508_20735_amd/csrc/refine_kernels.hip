@@ -48,18 +48,33 @@ __global__ __launch_bounds__(kBlock) void k_ingest(const uint32_t *__restrict__ 
                                                     uint32_t *err, uint32_t *nonid) {
     bool bad = false;
     unsigned long long moves = 0;  // letters 0..63 that move some state
-    for (size_t q = global_tid(); q < n; q += grid_stride()) {
-        const uint32_t *row = delta + q * k;
-        for (uint32_t a = 0; a < k; ++a) {
-            const uint32_t t = row[a];
-            bad |= t >= n;
-            if (t != q) {
-                if (a < 64)
-                    moves |= 1ull << a;
-                else if (nonid[a] == 0u)
-                    nonid[a] = 1u;
+    auto put = [&](size_t q, uint32_t a, uint32_t t) {
+        bad |= t >= n;
+        if (t != q) {
+            if (a < 64)
+                moves |= 1ull << a;
+            else if (nonid[a] == 0u)
+                nonid[a] = 1u;
+        }
+        cols[static_cast<size_t>(a) * N + offset + q] = t + toff;
+    };
+    // rows of a multiple of 4 letters at a 16-byte aligned address are read
+    // 16 bytes at a time (uniform over the grid)
+    if (k % 4 == 0 && (reinterpret_cast<uintptr_t>(delta) & 15u) == 0) {
+        for (size_t q = global_tid(); q < n; q += grid_stride()) {
+            const uint4 *row = reinterpret_cast<const uint4 *>(delta + q * k);
+            for (uint32_t a = 0; a < k; a += 4) {
+                const uint4 v = row[a / 4];
+                put(q, a, v.x);
+                put(q, a + 1, v.y);
+                put(q, a + 2, v.z);
+                put(q, a + 3, v.w);
             }
-            cols[static_cast<size_t>(a) * N + offset + q] = t + toff;
+        }
+    } else {
+        for (size_t q = global_tid(); q < n; q += grid_stride()) {
+            const uint32_t *row = delta + q * k;
+            for (uint32_t a = 0; a < k; ++a) put(q, a, row[a]);
         }
     }
     wave_set_flag(err, bad);
