@@ -68,6 +68,10 @@ def parse_args():
                     help="skip the same step through the host-pointer calls (copies included)")
     ap.add_argument("--no-products", action="store_true",
                     help="skip the product explorations (Tables 4 and 5 families)")
+    ap.add_argument("--no-chain", action="store_true",
+                    help="skip the chain-structured workload (plain vs closure)")
+    ap.add_argument("--no-chain-plain", action="store_true",
+                    help="in the chain leg, skip the plain refinement (about 2^20 rounds)")
     return ap.parse_args()
 
 
@@ -87,10 +91,38 @@ def traffic_for(kernel: str):
     return entry.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(d, perm):
-    """The oracle (sequential C, one thread) on a bounded sample of the same
-    workload: Moore signature refinement of the DFA and of its union with the
-    permuted copy.  Returns transitions refined per second."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads for the all-cores oracle runs: the cores this process may use,
+    at most 16 (the share of one GPU on a shared host)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return max(1, min(16, usable))
+
+
+def cpu_baseline(W, d, perm) -> dict:
+    """The oracle (plain C, gcc -O3) on the machine's host cores, on bounded
+    samples of the same workloads.  value: sequential Moore signature
+    refinement (one thread) of the 2^22-state DFA and of its union with the
+    permuted copy, in transitions refined per second (n * k * rounds / s).
+    Beside it: sequential Hopcroft on the same DFA and union-find
+    Hopcroft-Karp on the permuted pair; and, with one DFA per thread over all
+    usable cores, the 4,096-DFA batch workload (Moore) and the 96 served
+    requests (Hopcroft, or Hopcroft-Karp for equivalence requests)."""
+    import concurrent.futures
+
     import oracle
     t0 = time.perf_counter()
     _, _, rounds_a, _ = oracle.moore(d.delta, d.accepting)
@@ -101,9 +133,89 @@ def cpu_baseline(d, perm):
     t3 = time.perf_counter()
     work = d.n * d.k * rounds_a + 2 * d.n * d.k * rounds_u
     secs = (t1 - t0) + (t3 - t2)
+    t4 = time.perf_counter()
+    oracle.hopcroft(d.delta, d.accepting)
+    t5 = time.perf_counter()
+    oracle.equiv_hk(d.delta, d.accepting, d.start, perm.delta, perm.accepting, perm.start)
+    t6 = time.perf_counter()
+    threads = host_threads()
+
+    def pool_map(fn, xs):
+        with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+            return list(ex.map(fn, xs))
+
+    items = W.batch_workload(count=4096, paired_from=2048)
+    t7 = time.perf_counter()
+    res = pool_map(lambda it: oracle.moore(it.dfa.delta, it.dfa.accepting), items)
+    t8 = time.perf_counter()
+    batch_work = sum(it.dfa.n * it.dfa.k * r[2] for it, r in zip(items, res))
+    reqs = W.serving_workload(96, rate=1.0)
+
+    def serve_one(r):
+        if r.kind == "minimise":
+            return oracle.hopcroft(r.dfa.delta, r.dfa.accepting)[1]
+        return oracle.equiv_hk(r.dfa.delta, r.dfa.accepting, r.dfa.start, r.other.delta,
+                               r.other.accepting, r.other.start)
+    t9 = time.perf_counter()
+    pool_map(serve_one, reqs)
+    t10 = time.perf_counter()
     return {"value": work / secs, "unit": UNIT, "cores": 1, "kind": "oracle",
             "sample": (f"Moore rounds on the n=2^22 DFA ({rounds_a} rounds) and on its union "
-                       f"with the permuted copy ({rounds_u} rounds), {secs:.1f} s")}
+                       f"with the permuted copy ({rounds_u} rounds), {secs:.1f} s, one thread"),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "usable_cores": threads,
+            "compiler": "gcc -O3 -std=c11",
+            "hopcroft_2e22_s": t5 - t4,
+            "hopcroft_2e22_transitions_per_s": d.n * d.k / (t5 - t4),
+            "hk_equivalence_2e22_permuted_s": t6 - t5,
+            "batch_all_cores": {"threads": threads, "dfas": len(items), "seconds": t8 - t7,
+                                "transitions_per_s": batch_work / (t8 - t7),
+                                "what": "Moore on each of the 4,096 batch DFAs, one per thread"},
+            "served_all_cores": {"threads": threads, "requests": len(reqs),
+                                 "seconds": t10 - t9, "requests_per_s": len(reqs) / (t10 - t9),
+                                 "what": "Hopcroft (minimise) or union-find Hopcroft-Karp "
+                                         "(equivalence) per request, one per thread"}}
+
+
+def chain_leg(B, W, torch, np, dev, plain: bool) -> dict:
+    """The chain-structured workload: a 2^20-state chain (letter a steps, b is
+    the identity, only the last state accepts) followed by a 2^20-state random
+    tail.  Plain refinement (about 2^20 rounds, run once) against the closure
+    built first (tc on) and on demand (tc auto), median device time of 3 runs
+    after one warm-up, with the input resident.  rate = the library's
+    transitions refined (n * k_eff * rounds) over the time;
+    plain_equivalent_rate = n * k * (rounds of the plain run) over the time."""
+    d = W.cfg_chain()
+    delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
+    acc = torch.from_numpy(d.accepting).to(dev)
+    blk = torch.empty(d.n, dtype=torch.int32, device=dev)
+    plain_rounds = (1 << 20) - 1  # the closed form, replaced by the plain run's count
+    out = {"workload": "chain 2^20 (a: i -> i+1, b: identity, last state accepting) + "
+                       "2^20-state random tail (k = 2, p = 0.5), seed 3",
+           "n": d.n, "k": d.k}
+    if plain:
+        print("chain leg: plain refinement", file=sys.stderr, flush=True)
+        st = B.minimise_device(delta, acc, blk, tc="off", loop="graph").stats
+        plain_rounds = st["rounds"]
+        out["off"] = {"ms": st["device_ms"], "rounds": st["rounds"],
+                      "changing_rounds": st["changing_rounds"], "k_eff": st["k_eff"],
+                      "rate": st["transitions_refined"] / (st["device_ms"] * 1e-3),
+                      "algorithmic_GBps": st["algorithmic_bytes"] / (st["device_ms"] * 1e-3) / 1e9}
+    for tc in ("on", "auto"):
+        def once():
+            return B.minimise_device(delta, acc, blk, tc=tc, loop="graph").stats
+        once()
+        sts = [once() for _ in range(3)]
+        ms = float(np.median([s_["device_ms"] for s_ in sts]))
+        st = sts[-1]
+        out[tc] = {"ms": ms, "rounds": st["rounds"], "changing_rounds": st["changing_rounds"],
+                   "k_eff": st["k_eff"], "plain_rounds_before_closure": st["plain_rounds"],
+                   "rate": st["transitions_refined"] / (ms * 1e-3),
+                   "plain_equivalent_rate": d.n * d.k * plain_rounds / (ms * 1e-3)}
+    out["plain_rounds_used"] = plain_rounds
+    if plain:
+        out["closure_speedup"] = {tc: out["off"]["ms"] / out[tc]["ms"] for tc in ("on", "auto")}
+    del delta, acc, blk
+    return out
 
 
 def batch_leg(B, W, torch, np, count: int) -> dict:
@@ -558,8 +670,7 @@ def main() -> int:
             # the kernel gathers k block ids per refined state: its rate of
             # random gathers against the device's, measured the same way on
             # the union's size (most launches refine the 2n-state unions)
-            k_eff = d.k
-            gathers = kd["algorithmic_bytes"] / (8 * k_eff + 8) * k_eff
+            gathers = kd["state_letters"]
             ref = gather_reference(torch, dev, [d.n, 2 * d.n])
             achieved_g = gathers / (kd["total_ms"] / 1e3)
             out["gather_roofline"] = {
@@ -594,8 +705,10 @@ def main() -> int:
         out["table2"] = table2_leg(B, W, torch, np, dev)
     if not args.no_products:
         out["products"] = product_leg(B, W, torch, np, dev)
+    if not args.no_chain:
+        out["chain"] = chain_leg(B, W, torch, np, dev, plain=not args.no_chain_plain)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, perm)
+        out["cpu_baseline"] = cpu_baseline(W, d, perm)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -214,13 +214,18 @@ int dfa_set_tuning(const dfa_tuning *t);
  * dfa_profile_read copies up to cap entries and sets *count to the number of
  * kernels seen.  algorithmic_bytes sums, over the launches, the states the
  * launch refined times the kernel's bytes per refined state (k = k_eff):
- * signature 8k + 4, grouping 4, label rounds 5k + 5, round end 0.
+ * signature 8k + 4, grouping 4, label rounds 5k + 5, round end 0 (a whole
+ * signature round is 8k + 8, the figure dfa_stats.algorithmic_bytes uses).
+ * states sums the refined states and state_letters the refined states times
+ * k_eff (the signature kernel's successor-id gathers).
  */
 typedef struct dfa_kernel_time {
     char name[32];
     uint64_t launches;
     double total_ms;
     uint64_t algorithmic_bytes;
+    uint64_t states;
+    uint64_t state_letters;
 } dfa_kernel_time;
 
 int dfa_profile_enable(int on);
@@ -390,6 +395,13 @@ typedef struct dfa_server_stats {
 void dfa_server_config_default(dfa_server_config *cfg);
 /* NULL on failure (see dfa_last_error).  Uses the current HIP device. */
 dfa_server *dfa_server_create(const dfa_server_config *cfg);
+/* Device bytes the server charges against hbm_budget for running `req`
+ * alone: its inputs and workspace, plus a fixed part for the lane's buffers.
+ * Admission also counts the workspaces that idle lanes keep from earlier
+ * requests; when the head request does not fit beside them, the idle lanes
+ * free theirs first, so device memory held by the server stays within the
+ * budget. */
+int dfa_server_footprint(const dfa_server *s, const dfa_request *req, size_t *bytes);
 /* Copies the request's arrays into page-locked host memory (pooled by the
  * server; large arrays are copied by several threads), so the caller may free
  * them on return; the lane that runs the request uploads them asynchronously.

@@ -56,13 +56,13 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c into oracle/_build/liboracle.so with gcc -O2."""
+    """Compile oracle.c into oracle/_build/liboracle.so with gcc -O3."""
     os.makedirs(_LIB_DIR, exist_ok=True)
     if (not force and os.path.exists(_LIB)
             and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC)):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared",
+    subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-shared",
                            "-fPIC", "-o", tmp, _SRC])
     os.replace(tmp, _LIB)
     return _LIB

@@ -69,7 +69,7 @@ static int check_dfa(uint32_t n, uint32_t k, const uint32_t *delta, const uint8_
 /* ids may be arbitrary 32-bit labels.                                      */
 /* ------------------------------------------------------------------------ */
 
-static const uint32_t *g_sort_ids;
+static _Thread_local const uint32_t *g_sort_ids; /* comparator state, one per thread */
 static int cmp_by_id_then_index(const void *x, const void *y)
 {
     uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
@@ -110,9 +110,9 @@ int orc_canonicalise(uint32_t n, const uint32_t *ids, uint32_t *out)
 /* the number of blocks did not grow, exactly the paper's stop test.        */
 /* ------------------------------------------------------------------------ */
 
-static const uint32_t *g_blk;
-static const uint32_t *g_sig;
-static uint32_t g_k;
+static _Thread_local const uint32_t *g_blk; /* comparator state, one per thread */
+static _Thread_local const uint32_t *g_sig;
+static _Thread_local uint32_t g_k;
 
 static int cmp_signature(const void *x, const void *y)
 {

@@ -78,7 +78,8 @@ class Tuning(ctypes.Structure):
 
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
-                ("total_ms", ctypes.c_double), ("algorithmic_bytes", ctypes.c_uint64)]
+                ("total_ms", ctypes.c_double), ("algorithmic_bytes", ctypes.c_uint64),
+                ("states", ctypes.c_uint64), ("state_letters", ctypes.c_uint64)]
 
 
 class BatchStats(ctypes.Structure):
@@ -144,7 +145,7 @@ EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
                   "dfa_equivalent_batch_device", "dfa_server_config_default",
                   "dfa_server_create", "dfa_server_submit", "dfa_server_poll",
                   "dfa_server_wait", "dfa_result_release", "dfa_server_get_stats",
-                  "dfa_server_destroy"])
+                  "dfa_server_destroy", "dfa_server_footprint"])
 
 _lock = threading.Lock()
 _lib = None
@@ -206,6 +207,8 @@ def load(build_if_missing: bool = True):
         lib.dfa_server_create.argtypes = [P(ServerConfig)]
         lib.dfa_server_create.restype = vp
         lib.dfa_server_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
+        lib.dfa_server_footprint.argtypes = [vp, P(Request), P(ctypes.c_size_t)]
+        lib.dfa_server_footprint.restype = i32
         lib.dfa_server_poll.argtypes = [vp, ctypes.c_uint64, P(Result)]
         lib.dfa_server_wait.argtypes = [vp, ctypes.c_uint64, P(Result)]
         lib.dfa_result_release.argtypes = [vp, ctypes.c_uint64]
@@ -287,7 +290,8 @@ def profile_only(name: str | None) -> None:
 
 
 def profile_read() -> dict:
-    """{kernel name: {launches, total_ms, algorithmic_bytes}} since profile_enable(True)."""
+    """{kernel name: {launches, total_ms, algorithmic_bytes, states, state_letters}}
+    since profile_enable(True)."""
     lib = load()
     count = ctypes.c_int()
     _check(lib.dfa_profile_read(None, 0, ctypes.byref(count)))
@@ -295,7 +299,9 @@ def profile_read() -> dict:
     _check(lib.dfa_profile_read(buf, count.value, ctypes.byref(count)))
     return {buf[i].name.decode(): {"launches": int(buf[i].launches),
                                    "total_ms": float(buf[i].total_ms),
-                                   "algorithmic_bytes": int(buf[i].algorithmic_bytes)}
+                                   "algorithmic_bytes": int(buf[i].algorithmic_bytes),
+                                   "states": int(buf[i].states),
+                                   "state_letters": int(buf[i].state_letters)}
             for i in range(count.value)}
 
 
@@ -582,17 +588,31 @@ class Server:
     def submit_equivalent(self, a, b) -> int:
         return self._submit(REQ_EQUIVALENT, a, b)
 
-    def _submit(self, kind, a, b) -> int:
+    def _request(self, kind, a, b):
         req = Request()
         req.kind = kind
         va, keep_a = _view_host(a)
         req.a = va
+        keep = [keep_a]
         if b is not None:
             vb, keep_b = _view_host(b)
             req.b = vb
+            keep.append(keep_b)
+        return req, keep
+
+    def _submit(self, kind, a, b) -> int:
+        req, keep = self._request(kind, a, b)
         t = ctypes.c_uint64()
         _check(self._lib.dfa_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         return int(t.value)
+
+    def footprint(self, a, b=None) -> int:
+        """Device bytes the server charges for running this minimise (b None)
+        or equivalence request alone (dfa_server_footprint)."""
+        req, keep = self._request(REQ_MINIMISE if b is None else REQ_EQUIVALENT, a, b)
+        out = ctypes.c_size_t()
+        _check(self._lib.dfa_server_footprint(self._h, ctypes.byref(req), ctypes.byref(out)))
+        return int(out.value)
 
     def _convert(self, r: Result) -> dict:
         out = {"status": r.status, "verdict": bool(r.verdict), "num_blocks": r.num_blocks,

@@ -68,12 +68,36 @@ int fail(int code, const char *fmt, ...) {
 // address).
 std::atomic<uint64_t> g_allocation_number{0};
 
+// A fixed region of device memory that buffers are carved from instead of
+// being allocated (the workspace of the allocation-free entry point); reset
+// at the start of every call that uses it.
+struct Arena {
+    uint8_t *base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+};
+
 struct Buffer {
     void *p = nullptr;
     size_t cap = 0;
     uint64_t allocation = 0;  // number of the current allocation (0: none)
+    Arena *arena = nullptr;   // carve from this region, never allocate
     int ensure(size_t bytes, const char *what) {
         if (p && bytes <= cap) return DFA_OK;
+        if (arena) {
+            // a region outgrown within a call is abandoned until the next reset
+            const size_t want = (std::max<size_t>(bytes, 256) + 255) & ~static_cast<size_t>(255);
+            if (want > arena->size - arena->used)
+                return fail(DFA_ENOMEM,
+                            "%s: %zu bytes do not fit the fixed workspace (%zu of %zu bytes "
+                            "already in use)",
+                            what, want, arena->used, arena->size);
+            p = arena->base + arena->used;
+            arena->used += want;
+            cap = want;
+            allocation = ++g_allocation_number;
+            return DFA_OK;
+        }
         if (p) {
             (void)hipFree(p);
             p = nullptr;
@@ -179,6 +203,8 @@ struct Ctx {
         uint64_t launches = 0;
         double ms = 0;
         uint64_t bytes = 0;
+        uint64_t states = 0;         // refined states over the launches
+        uint64_t state_letters = 0;  // refined states times k_eff
     };
     std::map<std::string, KernelTime> ktimes;
     struct Pending {
@@ -186,6 +212,7 @@ struct Ctx {
         size_t ev0, ev1;
         uint32_t round;
         uint32_t bytes_per_state;
+        uint32_t k_eff;
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> evpool;
@@ -351,7 +378,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
     if (timed) {
         DFA_TRY(prof_event(c, e1));
         HIP_TRY(hipEventRecord(c.evpool[e1], c.stream));
-        c.pending.push_back({kern_name(kind), e0, e1, round, kern_bytes(kind, a.k_eff)});
+        c.pending.push_back({kern_name(kind), e0, e1, round, kern_bytes(kind, a.k_eff), a.k_eff});
     }
     return DFA_OK;
 }
@@ -378,8 +405,12 @@ int prof_collect(Ctx &c, const RoundCtl &ctl) {
         auto &t = c.ktimes[p.name];
         t.launches += 1;
         t.ms += ms;
-        if (p.round < ctl.round && ctl.round - p.round <= kActiveHist)
-            t.bytes += static_cast<uint64_t>(ctl.active_hist[p.round % kActiveHist]) * p.bytes_per_state;
+        if (p.round < ctl.round && ctl.round - p.round <= kActiveHist) {
+            const uint64_t refined = ctl.active_hist[p.round % kActiveHist];
+            t.bytes += refined * p.bytes_per_state;
+            t.states += refined;
+            t.state_letters += refined * p.k_eff;
+        }
     }
     c.pending.clear();
     c.ev_used = 0;
@@ -1011,7 +1042,8 @@ int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const u
     DFA_TRY(prepare_refinement(c, n, k));
     const size_t id_range = n;  // refine() returns state ids
     DFA_TRY(c.canon.ensure(id_range * sizeof(uint32_t), "canonical ids"));
-    HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    // (a context without events, the allocation-free one, times on the host)
+    if (c.ev_start) HIP_TRY(hipEventRecord(c.ev_start, c.stream));
     uint32_t *flags = c.flags.as<uint32_t>();
     launch_ingest(delta, n, k, c.cols.as<uint32_t>(), n, 0, 0, flags + kFlagErr, flags + kFlagNonid,
                   c.stream);
@@ -1044,7 +1076,7 @@ int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const u
         }
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
+    if (c.ev_stop) HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
     if (q) {
         DFA_TRY(read_back(c, c.scalars.p, 2 * sizeof(uint32_t)));
         q->num_blocks = c.pinned[0];
@@ -1059,9 +1091,11 @@ int minimise_impl(Ctx &c, uint32_t n, uint32_t k, const uint32_t *delta, const u
     }
     if (st) {
         fill_stats(st, r);
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
-        st->device_ms = ms;
+        if (c.ev_start && c.ev_stop) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
+            st->device_ms = ms;
+        }
     }
     return DFA_OK;
 }
@@ -1853,7 +1887,9 @@ int equivalent_host(Ctx &c, const dfa_view *a, const dfa_view *b, int *verdict,
 // free, and their kernels overlap on the device.  Results are canonical, so
 // a request's result does not depend on the requests it ran with.
 
-void release_ctx(Ctx &c) {
+// Calls f on every device buffer of a context.
+template <class F>
+void for_each_buffer(Ctx &c, F &&f) {
     Buffer *bufs[] = {&c.cols, &c.tc_cols, &c.colmap, &c.blockA, &c.blockB, &c.sig, &c.hash,
                       &c.table, &c.ctl, &c.flags, &c.canon, &c.dense, &c.leader_of, &c.partials,
                       &c.scalars, &c.multi, &c.active, &c.accbits, &c.counters, &c.presence,
@@ -1866,13 +1902,17 @@ void release_ctx(Ctx &c) {
                       &c.sub_acc, &c.sub_block, &c.sort_keys0, &c.sort_keys1, &c.sort_vals0,
                       &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,
                       &c.sort_m, &c.serve_in};
+    for (Buffer *b : bufs) f(*b);
+}
+
+void release_ctx(Ctx &c) {
     if (c.stream) (void)hipStreamSynchronize(c.stream);
-    for (Buffer *b : bufs) {
-        if (b->p) (void)hipFree(b->p);
-        b->p = nullptr;
-        b->cap = 0;
-        b->allocation = 0;
-    }
+    for_each_buffer(c, [](Buffer &b) {
+        if (b.p && !b.arena) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        b.allocation = 0;
+    });
     for (hipGraphExec_t &g : c.graphs) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
@@ -1972,7 +2012,11 @@ struct Server {
     std::condition_variable cv_work, cv_done;
     std::deque<ServedRequest *> pending;
     std::unordered_map<uint64_t, std::unique_ptr<ServedRequest>> requests;
-    size_t in_use = 0;
+    // device memory of the lanes: held[i] = bytes of lane i's workspace
+    // (grow-only buffers kept between requests); while lane i runs a group,
+    // reserved[i] bounds its workspace for that run
+    std::vector<size_t> held, reserved;
+    std::vector<char> busy;
     bool stopping = false;
     uint64_t next_ticket = 1;
     uint64_t submitted = 0, completed = 0, rejected = 0, groups = 0, solo = 0;
@@ -1982,8 +2026,21 @@ struct Server {
     std::vector<std::unique_ptr<Ctx>> lanes;
 };
 
-// Device bytes a request may occupy while it runs (inputs, columns,
-// signatures, hashes, table, block buffers and marks, outputs).
+// Device bytes of a lane's workspace that do not scale with the requests:
+// every buffer is rounded up to 2 MiB (about 40 of them), plus the label
+// bitmaps; charged once per admitted group.
+constexpr size_t kGroupFixedBytes = size_t(96) << 20;
+
+// Sum of a lane's buffer capacities.
+size_t workspace_bytes(Ctx &c) {
+    size_t total = 0;
+    for_each_buffer(c, [&](Buffer &b) { total += b.p ? b.cap : 0; });
+    return total;
+}
+
+// Device bytes a request may add to a lane's workspace while it runs
+// (inputs, columns, signatures, hashes, table, block buffers and marks,
+// outputs), apart from the fixed part.
 size_t request_footprint(uint64_t n, uint32_t k, bool closure) {
     uint64_t bytes = n * (4ull * k + 1)        // input copy
                      + n * 4ull * k            // columns
@@ -2141,19 +2198,50 @@ void lane_main(Server *sp, size_t lane) {
     }
     for (;;) {
         std::vector<ServedRequest *> grp, all;
-        size_t fp = 0;
         {
             std::unique_lock<std::mutex> lk(s.mu);
+            // device memory of the running lanes (their reservations)
+            auto busy_bytes = [&] {
+                size_t t = 0;
+                for (size_t i = 0; i < s.busy.size(); ++i)
+                    if (s.busy[i]) t += s.reserved[i];
+                return t;
+            };
+            // the head fits once idle lanes give their workspaces back
             s.cv_work.wait(lk, [&] {
                 return s.stopping ||
-                       (!s.pending.empty() &&
-                        s.in_use + s.pending.front()->footprint <= s.cfg.hbm_budget);
+                       (!s.pending.empty() && busy_bytes() + kGroupFixedBytes +
+                                                      s.pending.front()->footprint <=
+                                                  s.cfg.hbm_budget);
             });
             if (s.stopping) return;
             ServedRequest *head = s.pending.front();
             s.pending.pop_front();
             grp.push_back(head);
-            fp = head->footprint;
+            size_t idle_held = 0;
+            for (size_t i = 0; i < s.busy.size(); ++i)
+                if (!s.busy[i] && i != lane) idle_held += s.held[i];
+            // this lane's workspace may grow by the group's footprint; when
+            // that does not fit beside what the lanes hold, the idle lanes
+            // (this one included) free their workspaces first
+            size_t base = busy_bytes() + idle_held + s.held[lane] + kGroupFixedBytes;
+            if (base + head->footprint > s.cfg.hbm_budget) {
+                for (size_t i = 0; i < s.busy.size(); ++i) {
+                    if (s.busy[i] || s.held[i] == 0) continue;
+                    Ctx &li = *s.lanes[i];
+                    std::lock_guard<std::mutex> g(li.mu);
+                    if (li.stream) (void)hipStreamSynchronize(li.stream);
+                    for_each_buffer(li, [](Buffer &b) {
+                        if (b.p) (void)hipFree(b.p);
+                        b.p = nullptr;
+                        b.cap = 0;
+                        b.allocation = 0;
+                    });
+                    s.held[i] = 0;
+                }
+                base = busy_bytes() + kGroupFixedBytes;
+            }
+            size_t fp = head->footprint;
             const bool small = head->states <= s.cfg.batch_max_states;
             if (small) {
                 for (auto it = s.pending.begin();
@@ -2161,7 +2249,7 @@ void lane_main(Server *sp, size_t lane) {
                     ServedRequest *r = *it;
                     const size_t extra = r->footprint;
                     if (r->kind == head->kind && r->states <= s.cfg.batch_max_states &&
-                        s.in_use + fp + extra <= s.cfg.hbm_budget) {
+                        base + fp + extra <= s.cfg.hbm_budget) {
                         grp.push_back(r);
                         fp += extra;
                         it = s.pending.erase(it);
@@ -2170,7 +2258,8 @@ void lane_main(Server *sp, size_t lane) {
                     }
                 }
             }
-            s.in_use += fp;
+            s.busy[lane] = 1;
+            s.reserved[lane] = s.held[lane] + kGroupFixedBytes + fp;
             const auto now = Clock::now();
             for (auto *r : grp) r->t_start = now;
             if (grp.size() > 1 || small) s.groups++;
@@ -2224,9 +2313,16 @@ void lane_main(Server *sp, size_t lane) {
             if (r->host_in) s.pinned.put(r->host_in, r->host_cls);
             r->host_in = nullptr;
         }
+        size_t now_held = 0;
+        {
+            std::lock_guard<std::mutex> g(c.mu);
+            now_held = workspace_bytes(c);
+        }
         {
             std::lock_guard<std::mutex> lk(s.mu);
-            s.in_use -= fp;
+            s.busy[lane] = 0;
+            s.reserved[lane] = 0;
+            s.held[lane] = now_held;
             for (auto *r : all) {
                 if (!r->batched) s.solo++;
                 finish(s, r, lk);
@@ -2314,6 +2410,8 @@ int dfa_profile_read(dfa_kernel_time *out, int cap, int *count) {
                 out[i].launches = kv.second.launches;
                 out[i].total_ms = kv.second.ms;
                 out[i].algorithmic_bytes = kv.second.bytes;
+                out[i].states = kv.second.states;
+                out[i].state_letters = kv.second.state_letters;
             }
             ++i;
         }
@@ -2659,6 +2757,9 @@ dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
         s->t_created = Clock::now();
         try {
             for (uint32_t i = 0; i < cfg.lanes; ++i) s->lanes.push_back(std::make_unique<Ctx>());
+            s->held.assign(cfg.lanes, 0);
+            s->reserved.assign(cfg.lanes, 0);
+            s->busy.assign(cfg.lanes, 0);
             Server *raw = s.get();
             for (uint32_t i = 0; i < cfg.lanes; ++i) s->workers.emplace_back(lane_main, raw, i);
         } catch (const std::exception &e) {
@@ -2678,6 +2779,21 @@ dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
         fail(DFA_ENOMEM, "creating the server failed: %s", e.what());
         return nullptr;
     }
+}
+
+int dfa_server_footprint(const dfa_server *handle, const dfa_request *req, size_t *bytes) {
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        const Server *s = reinterpret_cast<const Server *>(handle);
+        if (!s || !req || !bytes) return fail(DFA_EINVAL, "NULL server, request or bytes");
+        if (req->kind != DFA_REQ_MINIMISE && req->kind != DFA_REQ_EQUIVALENT)
+            return fail(DFA_EINVAL, "unknown request kind %d", req->kind);
+        const uint64_t states =
+            static_cast<uint64_t>(req->a.n) + (req->kind == DFA_REQ_EQUIVALENT ? req->b.n : 0u);
+        *bytes = request_footprint(states, req->a.k, s->cfg.tc_mode != DFA_TC_OFF) +
+                 kGroupFixedBytes;
+        return DFA_OK;
+    });
 }
 
 int dfa_server_submit(dfa_server *handle, const dfa_request *req, uint64_t *ticket) {
@@ -2702,11 +2818,11 @@ int dfa_server_submit(dfa_server *handle, const dfa_request *req, uint64_t *tick
         r->in_bytes = al(da) + al(req->a.n) + (two ? al(db) + al(req->b.n) : 0);
         r->states = req->a.n + (two ? req->b.n : 0);
         r->footprint = request_footprint(r->states, req->a.k, s->cfg.tc_mode != DFA_TC_OFF);
-        if (r->footprint > s->cfg.hbm_budget) {
+        if (r->footprint + kGroupFixedBytes > s->cfg.hbm_budget) {
             std::lock_guard<std::mutex> lk(s->mu);
             s->rejected++;
             return fail(DFA_ENOMEM, "request needs ~%zu bytes of device memory, budget is %zu",
-                        r->footprint, s->cfg.hbm_budget);
+                        r->footprint + kGroupFixedBytes, s->cfg.hbm_budget);
         }
         // the inputs are copied now (page-locked, so the lane's upload is an
         // asynchronous DMA), so the caller may free them on return
@@ -2797,7 +2913,9 @@ int dfa_server_get_stats(dfa_server *handle, dfa_server_stats *out) {
         out->batched_groups = s->groups;
         out->solo_runs = s->solo;
         out->pending = s->pending.size();
-        out->hbm_in_use = s->in_use;
+        size_t in_use = 0;
+        for (size_t i = 0; i < s->busy.size(); ++i) in_use += s->busy[i] ? s->reserved[i] : s->held[i];
+        out->hbm_in_use = in_use;
         out->hbm_budget = s->cfg.hbm_budget;
         std::vector<double> lat = s->latencies;
         if (!lat.empty()) {

@@ -209,15 +209,18 @@ def memory(n: int, forgetful: bool) -> DFA:
 # benchmark workloads
 # --------------------------------------------------------------------------
 
-def chain_with_tail(N: int, tail: int, seed: int, p: float = 0.5) -> DFA:
-    """Chain part: N states, a: i -> min(i+1, N-1), b: i -> i, only N-1
-    accepting.  Random tail: ``tail`` states with both letters uniform over the
-    tail [N, N+tail) and acceptance probability p."""
+def chain_with_tail(N: int, tail: int, seed: int, p: float = 0.5, k: int = 2) -> DFA:
+    """Chain part: N states, letter 0: i -> min(i+1, N-1), every other letter
+    the identity, only N-1 accepting.  Random tail: ``tail`` states with all k
+    letters uniform over the tail [N, N+tail) and acceptance probability p.
+    With k = 2 this is the chain-structured workload (letters a and b)."""
+    if k < 1:
+        raise ValueError("k >= 1")
     rng = _rng(seed)
     i = np.arange(N, dtype=np.uint32)
-    chain = np.stack([np.minimum(i + 1, N - 1), i], axis=1).astype(np.uint32)
-    tail_delta = rng.integers(N, N + tail, size=(tail, 2), dtype=np.uint32) if tail else \
-        np.zeros((0, 2), dtype=np.uint32)
+    chain = np.stack([np.minimum(i + 1, N - 1)] + [i] * (k - 1), axis=1).astype(np.uint32)
+    tail_delta = rng.integers(N, N + tail, size=(tail, k), dtype=np.uint32) if tail else \
+        np.zeros((0, k), dtype=np.uint32)
     tail_acc = (rng.random(tail) < p).astype(np.uint8)
     acc = np.zeros(N, dtype=np.uint8)
     acc[N - 1] = 1
@@ -291,7 +294,8 @@ def serving_workload(count: int, rate: float, seed: int = 5, nmin: int = 1000,
     """Request stream: Poisson arrivals at `rate` per second, 80% minimise /
     20% equivalence (against a permuted copy or a one-transition mutation,
     alternately), n log-uniform in [nmin, nmax], k uniform in `letters`, and
-    a fraction p_chain of chain DFAs (half chain, half random tail)."""
+    a fraction p_chain of chain DFAs (half chain, half random tail, with the
+    drawn k: letter 0 steps the chain, the others are the identity on it)."""
     rng = _rng(seed)
     gaps = rng.exponential(1.0 / rate, size=count)
     arrivals = np.cumsum(gaps) - gaps[0]
@@ -305,7 +309,7 @@ def serving_workload(count: int, rate: float, seed: int = 5, nmin: int = 1000,
     for i in range(count):
         n, k = int(ns[i]), int(ks[i])
         if chains[i]:
-            d = chain_with_tail(max(n // 2, 2), n - max(n // 2, 2), int(sub[i]))
+            d = chain_with_tail(max(n // 2, 2), n - max(n // 2, 2), int(sub[i]), k=k)
         else:
             d = random_dfa(n, k, float(ps[i]), int(sub[i]))
         if kinds[i]:

@@ -4,6 +4,7 @@ rejects bad arguments before touching the device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -45,17 +46,39 @@ def test_default_options(lib):
     assert o.equiv_method == B.EQ["union"]
 
 
-def test_struct_sizes_match_header():
-    # the binding's structures mirror the header's field by field
-    assert ctypes.sizeof(B.Options) == 40
-    assert ctypes.sizeof(B.Stats) == 32 + 3 * 8 + 2 * 8
-    assert ctypes.sizeof(B.View) == 12 + 4 + 16
-    assert ctypes.sizeof(B.Tuning) == 64
-    assert ctypes.sizeof(B.BatchStats) == 16 + 24 + 24
-    assert ctypes.sizeof(B.ServerConfig) == 64
-    assert ctypes.sizeof(B.Request) == 8 + 2 * 32
-    assert ctypes.sizeof(B.Result) == 16 + 8 + 8 + 24
-    assert ctypes.sizeof(B.ServerStats) == 6 * 8 + 5 * 8 + 2 * 8
+STRUCTS = {
+    "dfa_options": "Options", "dfa_stats": "Stats", "dfa_view": "View", "dfa_tuning": "Tuning",
+    "dfa_batch_stats": "BatchStats", "dfa_server_config": "ServerConfig",
+    "dfa_request": "Request", "dfa_result": "Result", "dfa_server_stats": "ServerStats",
+    "dfa_kernel_time": "KernelTime", "dfa_quotient": "Quotient",
+}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's structures mirror the header's: sizes and the offset of
+    every field, as a C compiler lays the header out."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dfamin.h"',
+             'int main(void) {']
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(B, pyname)
+        lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{pyname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o",
+                           str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    seen = 0
+    for line in filter(None, out):
+        pyname, what, value = line.split()
+        cls = getattr(B, pyname)
+        want = ctypes.sizeof(cls) if what == "size" else getattr(cls, what).offset
+        assert int(value) == want, (pyname, what)
+        seen += 1
+    assert seen == sum(len(getattr(B, p)._fields_) + 1 for p in STRUCTS.values())
 
 
 def test_default_tuning(lib):

@@ -6,6 +6,9 @@ compared with the oracle's Moore rounds (plain letters, or the closure letters
 built by Algorithm 5); verdicts with union-find Hopcroft-Karp and the oracle's
 product exploration.  Integer work: every comparison is exact.
 """
+import concurrent.futures
+import os
+
 import numpy as np
 import pytest
 
@@ -498,9 +501,10 @@ def test_config_large_bench_step_configuration(large):
 
 
 def test_config_chain_closure():
-    """Chain of 2^20 states plus a 2^20-state random tail: the closure path
-    (on and auto) against Hopcroft, and the closed-form round count of the
-    chain part (19 = log2(2^20) - 1) as a lower bound."""
+    """Chain of 2^20 states plus a 2^20-state random tail with the closure
+    (on and auto): the partition against Hopcroft, and with the closure built
+    first the exact round count of the oracle's Moore rounds over the closure
+    letters (19 = log2(2^20) - 1, the chain's closed form)."""
     d = W.cfg_chain()
     hb, nb = oracle.hopcroft(d.delta, d.accepting)
     for tc in ("on", "auto"):
@@ -513,8 +517,25 @@ def test_config_chain_closure():
         # letter is the identity at every level and the first letter's level
         # 21 repeats level 20, so 21 of the 2 x 22 columns remain
         assert res.stats["k_eff"] == 21 and res.stats["tc_levels"] == 21
+    _, tnb, trounds, tchanging = oracle.minimise_tc(d.delta, d.accepting)
+    assert tchanging == 19
     res = B.minimise(d.delta, d.accepting, tc="on")
-    assert res.stats["changing_rounds"] >= 19
+    assert res.stats["changing_rounds"] == tchanging
+    assert res.stats["rounds"] == trounds and res.stats["num_blocks"] == tnb
+
+
+@pytest.mark.timeout(900)
+def test_config_chain_plain_full_size():
+    """The same DFA refined on its two input letters only: 2^20 - 2 refining
+    rounds (the chain's closed form; the tail is stable within a few rounds),
+    and the partition equals Hopcroft's."""
+    d = W.cfg_chain()
+    hb, nb = oracle.hopcroft(d.delta, d.accepting)
+    res = B.minimise(d.delta, d.accepting, tc="off")
+    np.testing.assert_array_equal(res.block, hb)
+    st = res.stats
+    assert st["num_blocks"] == nb == d.n and st["tc_used"] == 0
+    assert st["changing_rounds"] == (1 << 20) - 2 and st["rounds"] == (1 << 20) - 1
 
 
 # ---------------------------------------------------------------- kernel variants
@@ -638,62 +659,61 @@ def test_batch_workload_small_slice():
         assert v == oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
 
 
-def _certify(d, block):
-    """The ids are canonical (each the smallest member of its block) and the
-    partition is stable and refines acceptance, so every block lies inside one
-    equivalence class (Section 2); with the oracle's block count it is the
-    coarsest one."""
-    q = np.arange(d.n)
-    assert (block <= q).all() and (block[block] == block).all()
-    assert (d.accepting == d.accepting[block]).all()
-    assert (block[d.delta] == block[d.delta[block]]).all()
+def _oracle_map(fn, items):
+    """The oracle over many inputs on the host's cores (its C calls release
+    the interpreter lock)."""
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
 
 
 def test_batch_workload_full_size():
     """The 4,096-DFA batch workload at full size, in the launch configuration
-    the benchmark times (one batched call per kind): every DFA's partition is
-    certified stable with canonical ids, 256 seeded samples are compared with
-    the oracle state by state (rounds included), and all 2,048 equivalence
-    verdicts with the oracle's."""
+    the benchmark times (one batched call per kind): every DFA's partition
+    and round count equal the oracle's Moore rounds state by state, and all
+    2,048 equivalence verdicts equal union-find Hopcroft-Karp's."""
     items = W.batch_workload(count=4096, paired_from=2048)
     dfas = [it.dfa for it in items]
     blocks, nb, rounds, _ = B.minimise_batch(dfas)
-    for d, blk, c in zip(dfas, blocks, nb):
-        _certify(d, blk)
-        assert c == np.count_nonzero(blk == np.arange(d.n))
-    for i in np.random.default_rng(404).choice(len(dfas), 256, replace=False):
-        d = dfas[i]
-        ref, rnb, rrounds, _ = oracle.moore(d.delta, d.accepting)
-        np.testing.assert_array_equal(blocks[i], ref)
-        assert (nb[i], rounds[i]) == (rnb, rrounds)
+    refs = _oracle_map(lambda d: oracle.moore(d.delta, d.accepting), dfas)
+    for i, (d, ref) in enumerate(zip(dfas, refs)):
+        np.testing.assert_array_equal(blocks[i], ref[0], err_msg=f"dfa {i}")
+        assert (nb[i], rounds[i]) == (ref[1], ref[2]), i
     pairs = [(it.dfa, it.pair) for it in items if it.pair is not None]
     verdicts, _ = B.equivalent_batch(pairs)
-    expect = [oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
-              for a, b in pairs]
+    expect = _oracle_map(lambda ab: oracle.equiv_hk(ab[0].delta, ab[0].accepting, ab[0].start,
+                                                    ab[1].delta, ab[1].accepting, ab[1].start),
+                         pairs)
     assert list(verdicts) == expect
     assert 0 < sum(expect) < len(expect)
 
 
+def _served_expected(r):
+    if r.kind == "minimise":
+        return oracle.hopcroft(r.dfa.delta, r.dfa.accepting)
+    return oracle.equiv_hk(r.dfa.delta, r.dfa.accepting, r.dfa.start, r.other.delta,
+                           r.other.accepting, r.other.start)
+
+
 def test_server_serving_workload_full_size():
-    """The first 16 requests of the serving workload at full size (n up to
-    2.3M, chain DFAs included), through a server with the default
-    configuration as the benchmark runs it: every result equals the oracle's."""
-    reqs = W.serving_workload(96, rate=1.0)[:16]
+    """All 96 requests of the serving workload at full size (n up to 4.2M,
+    alphabets of 2 to 16 letters, chain DFAs included), through a server with
+    the default configuration as the benchmark runs it: every partition equals
+    Hopcroft's and every verdict union-find Hopcroft-Karp's."""
+    reqs = W.serving_workload(96, rate=1.0)
     with B.Server() as srv:
         tickets = [srv.submit_minimise(r.dfa) if r.kind == "minimise" else
                    srv.submit_equivalent(r.dfa, r.other) for r in reqs]
         results = [srv.wait(t) for t in tickets]
+    expected = _oracle_map(_served_expected, reqs)
     kinds = set()
-    for r, got in zip(reqs, results):
-        assert got["status"] == 0
+    for i, (r, got, exp) in enumerate(zip(reqs, results, expected)):
+        assert got["status"] == 0, i
         if r.kind == "minimise":
-            hb, hnb = oracle.hopcroft(r.dfa.delta, r.dfa.accepting)
-            np.testing.assert_array_equal(got["blocks"], hb)
-            assert got["num_blocks"] == hnb
+            np.testing.assert_array_equal(got["blocks"], exp[0], err_msg=f"request {i}")
+            assert got["num_blocks"] == exp[1], i
         else:
-            assert got["verdict"] == oracle.equiv_hk(r.dfa.delta, r.dfa.accepting, r.dfa.start,
-                                                     r.other.delta, r.other.accepting,
-                                                     r.other.start)
+            assert got["verdict"] == exp, i
         kinds.add(r.kind)
     assert kinds == {"minimise", "equivalent"}
 
@@ -736,7 +756,7 @@ def _serving_mix(seed, count):
         k = int(rng.choice([2, 4, 8, 16]))
         if rng.random() < 0.1:
             half = max(n // 2, 2)
-            d = W.chain_with_tail(half, n - half, int(rng.integers(1 << 30)))
+            d = W.chain_with_tail(half, n - half, int(rng.integers(1 << 30)), k=k)
         else:
             d = W.random_dfa(n, k, float(rng.uniform(0.05, 0.5)), int(rng.integers(1 << 30)))
         if rng.random() < 0.2:

@@ -197,18 +197,42 @@ def test_chain_round_counts_closed_form(M):
     assert changing_tc == max(bin(m).count("1") for m in range(N - 1)) == M - 1
 
 
-def test_chain_with_tail_small():
-    """The chain-plus-random-tail workload at reduced size: all states
-    distinct, plain rounds = N - 2 from the chain, and the closure agrees."""
-    N = 256
+@pytest.mark.parametrize("M", [8, 10, 12])
+def test_chain_with_tail_small(M):
+    """The chain-plus-random-tail workload at reduced size (N = 2^M chain
+    states, N tail states): all states distinct, plain rounds exactly N - 2
+    and closure rounds exactly M - 1, the chain's closed forms, because the
+    random tail is stable long before either."""
+    N = 2 ** M
     d = W.chain_with_tail(N, N, seed=3)
     hb, hnb = oracle.hopcroft(d.delta, d.accepting)
+    assert hnb == 2 * N
     mb, nb, _, changing = oracle.moore(d.delta, d.accepting)
     np.testing.assert_array_equal(hb, mb)
-    assert changing >= N - 2
+    assert changing == N - 2
     tb, _, _, changing_tc = oracle.minimise_tc(d.delta, d.accepting)
     np.testing.assert_array_equal(hb, tb)
-    assert changing_tc < 20
+    assert changing_tc == M - 1
+    # the tail alone is stable within a few rounds
+    tail = W.DFA(d.delta[N:] - N, d.accepting[N:], 0)
+    assert oracle.moore(tail.delta, tail.accepting)[3] < 8
+
+
+@pytest.mark.parametrize("k", [1, 3, 16])
+def test_chain_with_tail_alphabets(k):
+    """Chain requests of the serving workload use the drawn alphabet: letter 0
+    steps the chain, the others are the identity on it, so the chain's round
+    counts are those of the two-letter chain."""
+    N = 64
+    d = W.chain_with_tail(N, 40, seed=5, k=k)
+    assert d.delta.shape == (N + 40, k)
+    i = np.arange(N)
+    assert (d.delta[:N, 0] == np.minimum(i + 1, N - 1)).all()
+    assert (d.delta[:N, 1:] == i[:, None]).all()
+    assert (d.delta[N:] >= N).all()
+    _, nb, _, changing = oracle.moore(d.delta, d.accepting)
+    assert changing == N - 2
+    assert oracle.minimise_tc(d.delta, d.accepting)[3] == 5
 
 
 # ---------------------------------------------------------------- equivalence / inclusion
