@@ -72,6 +72,9 @@ def parse_args():
                     help="skip the chain-structured workload (plain vs closure)")
     ap.add_argument("--no-chain-plain", action="store_true",
                     help="in the chain leg, skip the plain refinement (about 2^20 rounds)")
+    ap.add_argument("--only", choices=["batch", "served", "chain"],
+                    help="run only this leg (no timed step) and print its object: for "
+                         "profiling one leg under rocprofv3")
     return ap.parse_args()
 
 
@@ -497,18 +500,21 @@ def serve_leg(B, W, count: int) -> dict:
         else:
             B.equivalent(r.dfa, r.other)
 
-    def burst(srv):
+    def burst(srv, results=None):
         t0 = time.perf_counter()
         tickets = [submit(srv, r) for r in reqs]
         for t in tickets:
-            srv.wait(t)
+            res = srv.wait(t)
+            if results is not None:
+                results.append(res)
         return time.perf_counter() - t0
 
+    burst_res = []
     with B.Server() as srv:
         # a long-running server: one untimed pass warms its page-locked
         # input pool and the lanes' device workspaces
         burst(srv)
-        burst_s = burst(srv)
+        burst_s = burst(srv, burst_res)
     capacity = count / burst_s
     rate = 0.7 * capacity
     gaps = W._rng(55).exponential(1.0 / rate, size=count)
@@ -523,7 +529,8 @@ def serve_leg(B, W, count: int) -> dict:
             if delay > 0:
                 time.sleep(delay)
             tickets.append(submit(srv, r))
-        lat = [srv.wait(t)["latency_ms"] for t in tickets]
+        stream_res = [srv.wait(t) for t in tickets]
+        lat = [r_["latency_ms"] for r_ in stream_res]
         stream_s = time.perf_counter() - t0
     for r in reqs[:2]:
         plain_one(r)
@@ -539,7 +546,28 @@ def serve_leg(B, W, count: int) -> dict:
             "plain_requests_per_s": count / plain_s,
             "speedup": (count / burst_s) / (count / plain_s),
             "poisson_rate": rate, "p50_ms": pick(0.5), "p99_ms": pick(0.99),
-            "stream_requests_per_s": count / stream_s, "lanes": 4}
+            "stream_requests_per_s": count / stream_s, "lanes": 4,
+            "breakdown": {"stream": _served_breakdown(stream_res),
+                          "burst": _served_breakdown(burst_res)}}
+
+
+def _served_breakdown(results) -> dict:
+    """Where served requests spend their time: medians and means over the
+    requests of queue (submit -> start), input copies, device work and result
+    copy (a batched request reports its group's copies and device work), and
+    the device time of the distinct groups summed (each group counted once)."""
+    import statistics
+    parts = ("queue_ms", "h2d_ms", "device_ms", "d2h_ms", "service_ms", "latency_ms")
+    out = {}
+    for p in parts:
+        vals = [r[p] for r in results]
+        out[p] = {"median": statistics.median(vals), "mean": statistics.fmean(vals)}
+    groups = {(r["h2d_ms"], r["device_ms"], r["d2h_ms"]) for r in results}
+    out["distinct_groups"] = len(groups)
+    out["device_ms_sum_over_groups"] = sum(g[1] for g in groups)
+    out["h2d_ms_sum_over_groups"] = sum(g[0] for g in groups)
+    out["d2h_ms_sum_over_groups"] = sum(g[2] for g in groups)
+    return out
 
 
 def main() -> int:
@@ -562,6 +590,16 @@ def main() -> int:
     torch.cuda.set_device(0)
     B.load(build_if_missing=True)
     dev = torch.device("cuda:0")
+
+    if args.only:
+        if args.only == "batch":
+            leg = batch_leg(B, W, torch, np, args.batch_count)
+        elif args.only == "served":
+            leg = serve_leg(B, W, args.serve_requests)
+        else:
+            leg = chain_leg(B, W, torch, np, dev, plain=not args.no_chain_plain)
+        print(json.dumps({args.only: leg}), flush=True)
+        return 0
 
     d = W.cfg_large()
     perm, _ = W.permuted_copy(d, W.CFG_LARGE_PERM_SEED)

@@ -360,7 +360,9 @@ typedef struct dfa_server_config {
     uint32_t batch_max_states;   /* larger requests run alone (default 2^18) */
     uint32_t batch_round_budget; /* rounds of a batched refinement (>= 3, default 12) */
     int32_t tc_mode;             /* closure for requests run alone (default DFA_TC_AUTO) */
-    uint32_t reserved[9];
+    uint32_t paused;             /* 1: the lanes take no request until dfa_server_resume
+                                    (requests are still accepted and queued); default 0 */
+    uint32_t reserved[8];
 } dfa_server_config;
 
 typedef struct dfa_request {
@@ -382,6 +384,10 @@ typedef struct dfa_result {
     double queue_ms;          /* submit -> start */
     double service_ms;        /* start -> done (of its group) */
     double latency_ms;        /* submit -> done */
+    /* parts of service_ms, for the work the request ran in (its group's when
+     * batched): input copies to the device (HIP events), device work of the
+     * refinements (HIP events; a re-run alone included), result copy back */
+    double h2d_ms, device_ms, d2h_ms;
 } dfa_result;
 
 typedef struct dfa_server_stats {
@@ -390,6 +396,7 @@ typedef struct dfa_server_stats {
     double p50_ms, p99_ms, mean_ms; /* latency of completed requests */
     double uptime_s, requests_per_s;
     uint64_t hbm_in_use, hbm_budget;
+    uint64_t waiting_threads;       /* threads blocked in dfa_server_wait */
 } dfa_server_stats;
 
 void dfa_server_config_default(dfa_server_config *cfg);
@@ -409,12 +416,21 @@ int dfa_server_footprint(const dfa_server *s, const dfa_request *req, size_t *by
 int dfa_server_submit(dfa_server *s, const dfa_request *req, uint64_t *ticket);
 /* DFA_EAGAIN while the request runs or waits. */
 int dfa_server_poll(dfa_server *s, uint64_t ticket, dfa_result *out);
+/* Blocks until the request is done.  A thread may wait while another thread
+ * destroys the server: a request that had not started then returns with
+ * out->status = DFA_ECANCELED (and out->blocks = NULL), and
+ * dfa_server_destroy returns only after every such waiter has left. */
 int dfa_server_wait(dfa_server *s, uint64_t ticket, dfa_result *out);
+/* Lets the lanes of a server created with cfg.paused = 1 take requests. */
+int dfa_server_resume(dfa_server *s);
 /* Frees a finished request's result (the blocks pointer becomes invalid). */
 int dfa_result_release(dfa_server *s, uint64_t ticket);
 int dfa_server_get_stats(dfa_server *s, dfa_server_stats *out);
 /* Cancels waiting requests (status DFA_ECANCELED), waits for running ones,
- * frees the lanes.  Results not released are freed too. */
+ * frees the lanes' workspaces (their streams are kept by the library for
+ * later servers).  Results not released are freed too.  Apart from threads
+ * blocked in dfa_server_wait, no other call on the same server may run
+ * concurrently with it or follow it. */
 void dfa_server_destroy(dfa_server *s);
 
 /* Description of the last failure on the calling thread ("" if none). */

@@ -107,7 +107,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("lanes", ctypes.c_uint32),
                 ("max_group", ctypes.c_uint32), ("batch_max_states", ctypes.c_uint32),
                 ("batch_round_budget", ctypes.c_uint32), ("tc_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 9)]
+                ("paused", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 8)]
 
 
 class Request(ctypes.Structure):
@@ -120,7 +120,9 @@ class Result(ctypes.Structure):
                 ("num_blocks", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
                 ("blocks", ctypes.POINTER(ctypes.c_uint32)), ("n", ctypes.c_uint32),
                 ("batched", ctypes.c_uint32), ("queue_ms", ctypes.c_double),
-                ("service_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+                ("service_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("h2d_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("d2h_ms", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
@@ -130,7 +132,7 @@ class ServerStats(ctypes.Structure):
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("mean_ms", ctypes.c_double), ("uptime_s", ctypes.c_double),
                 ("requests_per_s", ctypes.c_double), ("hbm_in_use", ctypes.c_uint64),
-                ("hbm_budget", ctypes.c_uint64)]
+                ("hbm_budget", ctypes.c_uint64), ("waiting_threads", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -145,7 +147,7 @@ EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
                   "dfa_equivalent_batch_device", "dfa_server_config_default",
                   "dfa_server_create", "dfa_server_submit", "dfa_server_poll",
                   "dfa_server_wait", "dfa_result_release", "dfa_server_get_stats",
-                  "dfa_server_destroy", "dfa_server_footprint"])
+                  "dfa_server_destroy", "dfa_server_footprint", "dfa_server_resume"])
 
 _lock = threading.Lock()
 _lib = None
@@ -213,6 +215,7 @@ def load(build_if_missing: bool = True):
         lib.dfa_server_wait.argtypes = [vp, ctypes.c_uint64, P(Result)]
         lib.dfa_result_release.argtypes = [vp, ctypes.c_uint64]
         lib.dfa_server_get_stats.argtypes = [vp, P(ServerStats)]
+        lib.dfa_server_resume.argtypes = [vp]
         lib.dfa_server_destroy.argtypes = [vp]
         lib.dfa_server_destroy.restype = None
         lib.dfa_profile_enable.argtypes = [i32]
@@ -224,7 +227,8 @@ def load(build_if_missing: bool = True):
                    "dfa_profile_enable", "dfa_profile_read", "dfa_minimise_batch",
                    "dfa_minimise_batch_device", "dfa_equivalent_batch",
                    "dfa_equivalent_batch_device", "dfa_server_submit", "dfa_server_poll",
-                   "dfa_server_wait", "dfa_result_release", "dfa_server_get_stats"):
+                   "dfa_server_wait", "dfa_result_release", "dfa_server_get_stats",
+                   "dfa_server_resume"):
             getattr(lib, fn).restype = i32
         _lib = lib
         return lib
@@ -566,7 +570,7 @@ class Server:
 
     def __init__(self, hbm_budget: int = 0, lanes: int = 4, max_group: int = 512,
                  batch_max_states: int = 1 << 18, batch_round_budget: int = 12,
-                 tc: str = "auto"):
+                 tc: str = "auto", paused: bool = False):
         lib = load()
         cfg = ServerConfig()
         lib.dfa_server_config_default(ctypes.byref(cfg))
@@ -576,6 +580,7 @@ class Server:
         cfg.batch_max_states = batch_max_states
         cfg.batch_round_budget = batch_round_budget
         cfg.tc_mode = TC[tc]
+        cfg.paused = 1 if paused else 0
         h = lib.dfa_server_create(ctypes.byref(cfg))
         if not h:
             raise DfaError(DFA_EINVAL, lib.dfa_last_error().decode(errors="replace"))
@@ -617,7 +622,8 @@ class Server:
     def _convert(self, r: Result) -> dict:
         out = {"status": r.status, "verdict": bool(r.verdict), "num_blocks": r.num_blocks,
                "rounds": r.rounds, "batched": bool(r.batched), "queue_ms": r.queue_ms,
-               "service_ms": r.service_ms, "latency_ms": r.latency_ms, "blocks": None}
+               "service_ms": r.service_ms, "latency_ms": r.latency_ms, "h2d_ms": r.h2d_ms,
+               "device_ms": r.device_ms, "d2h_ms": r.d2h_ms, "blocks": None}
         if r.blocks:
             out["blocks"] = np.ctypeslib.as_array(r.blocks, shape=(r.n,)).copy()
         return out
@@ -641,6 +647,10 @@ class Server:
 
     def release(self, ticket: int) -> None:
         _check(self._lib.dfa_result_release(self._h, ticket))
+
+    def resume(self) -> None:
+        """Lets the lanes of a server created paused take requests."""
+        _check(self._lib.dfa_server_resume(self._h))
 
     def stats(self) -> dict:
         st = ServerStats()

@@ -179,6 +179,7 @@ struct Ctx {
         sort_runhead, sort_m;
     Buffer serve_in;  // server lanes: device copies of the running requests' inputs
     hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr;  // pruned minimisation, whole call
+    hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;  // server lanes: a group's input copies
     // waits on the stream sleep instead of spinning (server lanes, so that
     // waiting lanes leave the host cores to submissions)
     bool blocking_sync = false;
@@ -230,16 +231,52 @@ int get_ctx(Ctx *&out) {
     return DFA_OK;
 }
 
+// Streams are never destroyed: a context that goes away (a server lane)
+// returns its stream here and the next one takes it.  Destroying a stream
+// while another thread of the process synchronises the whole device (which
+// waits on every stream of the device) is a race the library cannot see
+// from its side, so it never does it.
+std::mutex g_stream_pool_mu;
+std::vector<hipStream_t> g_stream_pool[kMaxDevices];
+
+int take_stream(int dev, hipStream_t &out) {
+    {
+        std::lock_guard<std::mutex> g(g_stream_pool_mu);
+        auto &pool = g_stream_pool[dev];
+        if (!pool.empty()) {
+            out = pool.back();
+            pool.pop_back();
+            return DFA_OK;
+        }
+    }
+    // default priority; callers' streams are joined explicitly (join_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&out, hipStreamNonBlocking));
+    return DFA_OK;
+}
+
+void give_stream(int dev, hipStream_t st) {
+    if (!st || dev < 0 || dev >= kMaxDevices) return;
+    try {
+        std::lock_guard<std::mutex> g(g_stream_pool_mu);
+        g_stream_pool[dev].push_back(st);
+    } catch (...) {
+        // not pooled: the stream stays allocated until the process ends
+    }
+}
+
 int init_ctx(Ctx &c) {
     if (c.inited) return DFA_OK;
     HIP_TRY(hipGetDevice(&c.device));
-    // default priority; callers' streams are joined explicitly (join_stream)
-    HIP_TRY(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    if (c.device < 0 || c.device >= kMaxDevices)
+        return fail(DFA_EDEVICE, "device index %d out of range", c.device);
+    DFA_TRY(take_stream(c.device, c.stream));
     HIP_TRY(hipEventCreate(&c.ev_start));
     HIP_TRY(hipEventCreate(&c.ev_stop));
     HIP_TRY(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreate(&c.ev_p0));
     HIP_TRY(hipEventCreate(&c.ev_p1));
+    HIP_TRY(hipEventCreate(&c.ev_up0));
+    HIP_TRY(hipEventCreate(&c.ev_up1));
     HIP_TRY(hipEventCreateWithFlags(&c.ev_sync, hipEventBlockingSync | hipEventDisableTiming));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c.pinned), kPinnedWords * sizeof(uint32_t),
                           hipHostMallocDefault));
@@ -1927,6 +1964,9 @@ void release_ctx(Ctx &c) {
     if (c.ev_p0) (void)hipEventDestroy(c.ev_p0);
     if (c.ev_p1) (void)hipEventDestroy(c.ev_p1);
     c.ev_p0 = c.ev_p1 = nullptr;
+    if (c.ev_up0) (void)hipEventDestroy(c.ev_up0);
+    if (c.ev_up1) (void)hipEventDestroy(c.ev_up1);
+    c.ev_up0 = c.ev_up1 = nullptr;
     if (c.pinned) (void)hipHostFree(c.pinned);
     if (c.pinned_batch) (void)hipHostFree(c.pinned_batch);
     for (int i = 0; i < 2; ++i) {
@@ -1936,7 +1976,8 @@ void release_ctx(Ctx &c) {
         c.ring_ev[i] = nullptr;
         c.ring_recorded[i] = false;
     }
-    if (c.stream) (void)hipStreamDestroy(c.stream);
+    // the stream goes back to the pool (it was synchronised above)
+    give_stream(c.device, c.stream);
     c.ev_start = c.ev_stop = c.ev_in = nullptr;
     c.pinned = nullptr;
     c.pinned_batch = nullptr;
@@ -2001,6 +2042,9 @@ struct ServedRequest {
     bool batched = false;
     uint32_t *blocks = nullptr;  // minimisation result, page-locked (server pool)
     size_t blocks_cls = 0;
+    // time of the work it ran in (its group's, when batched): input copies,
+    // device work (refinements, a re-run alone included), result copy
+    double h2d_ms = 0, device_ms = 0, d2h_ms = 0;
 };
 
 struct Server {
@@ -2018,6 +2062,9 @@ struct Server {
     std::vector<size_t> held, reserved;
     std::vector<char> busy;
     bool stopping = false;
+    bool paused = false;   // lanes take no request until dfa_server_resume
+    uint32_t waiters = 0;  // threads inside dfa_server_wait (destroy waits for them)
+    std::condition_variable cv_left;  // a waiter left dfa_server_wait
     uint64_t next_ticket = 1;
     uint64_t submitted = 0, completed = 0, rejected = 0, groups = 0, solo = 0;
     std::vector<double> latencies;
@@ -2082,11 +2129,13 @@ void run_solo(Server &s, Ctx &c, ServedRequest *r) {
             if (!r->blocks)
                 r->status = fail(DFA_ENOMEM, "page-locked result buffer of %zu bytes", n * 4);
         }
+        const auto t0 = Clock::now();
         if (r->status == DFA_OK &&
             (hipMemcpyAsync(r->blocks, c.stage_block.p, n * sizeof(uint32_t),
                             hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
              stream_sync(c) != hipSuccess))
             r->status = fail(DFA_EDEVICE, "copy of the result failed");
+        r->d2h_ms += std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
         r->num_blocks = st.num_blocks;
         r->rounds = st.rounds;
     } else {
@@ -2095,6 +2144,7 @@ void run_solo(Server &s, Ctx &c, ServedRequest *r) {
         r->verdict = v;
         r->rounds = st.rounds;
     }
+    r->device_ms += st.device_ms;
     r->batched = false;
 }
 
@@ -2121,11 +2171,16 @@ void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
             rc = minimise_batch_impl(c, count, dev.data(), c.batch_out.as<uint32_t>(), nullptr,
                                      nb.data(), rounds.data(), o, &bs);
         if (rc == DFA_OK || rc == DFA_ELIMIT) {
+            const auto t0 = Clock::now();
             int rc2 = ensure_pinned_batch(c, total * sizeof(uint32_t));
-            if (rc2 == DFA_OK && hipMemcpyAsync(c.pinned_batch, c.batch_out.p,
-                                                total * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                                c.stream) == hipSuccess &&
-                stream_sync(c) == hipSuccess) {
+            const bool copied = rc2 == DFA_OK &&
+                                hipMemcpyAsync(c.pinned_batch, c.batch_out.p,
+                                               total * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                               c.stream) == hipSuccess &&
+                                stream_sync(c) == hipSuccess;
+            const double d2h = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+            for (auto *r : grp) r->d2h_ms += d2h;
+            if (copied) {
                 const uint32_t *src = reinterpret_cast<const uint32_t *>(c.pinned_batch);
                 uint64_t pos = 0;
                 for (uint32_t i = 0; i < count; ++i) {
@@ -2176,6 +2231,7 @@ void run_group(Server &s, Ctx &c, std::vector<ServedRequest *> &grp) {
             rc = DFA_OK;
         }
     }
+    for (auto *r : grp) r->device_ms += bs.device_ms;
     for (uint32_t i = 0; i < count; ++i) {
         if (rc != DFA_OK) {
             grp[i]->status = rc;
@@ -2210,7 +2266,7 @@ void lane_main(Server *sp, size_t lane) {
             // the head fits once idle lanes give their workspaces back
             s.cv_work.wait(lk, [&] {
                 return s.stopping ||
-                       (!s.pending.empty() && busy_bytes() + kGroupFixedBytes +
+                       (!s.paused && !s.pending.empty() && busy_bytes() + kGroupFixedBytes +
                                                       s.pending.front()->footprint <=
                                                   s.cfg.hbm_budget);
             });
@@ -2265,6 +2321,7 @@ void lane_main(Server *sp, size_t lane) {
             if (grp.size() > 1 || small) s.groups++;
         }
         all = grp;
+        bool uploaded = false;
         try {
             std::lock_guard<std::mutex> g(c.mu);
             g_last_error.clear();
@@ -2277,6 +2334,7 @@ void lane_main(Server *sp, size_t lane) {
                 for (auto *r : grp) r->status = DFA_ENOMEM;
             } else {
                 uint8_t *dev = c.serve_in.as<uint8_t>();
+                (void)hipEventRecord(c.ev_up0, c.stream);
                 for (auto *r : grp) {
                     if (hipMemcpyAsync(dev, r->host_in, r->in_bytes, hipMemcpyHostToDevice,
                                        c.stream) != hipSuccess) {
@@ -2293,6 +2351,8 @@ void lane_main(Server *sp, size_t lane) {
                     dev += r->in_bytes;
                     ready.push_back(r);
                 }
+                (void)hipEventRecord(c.ev_up1, c.stream);
+                uploaded = true;
             }
             grp.swap(ready);
             if (grp.size() == 1 && grp[0]->states > s.cfg.batch_max_states)
@@ -2309,6 +2369,11 @@ void lane_main(Server *sp, size_t lane) {
             }
         }
         (void)stream_sync(c);  // the input copies have completed
+        if (uploaded) {
+            float up_ms = 0.f;
+            if (hipEventElapsedTime(&up_ms, c.ev_up0, c.ev_up1) == hipSuccess)
+                for (auto *r : all) r->h2d_ms = up_ms;
+        }
         for (auto *r : all) {
             if (r->host_in) s.pinned.put(r->host_in, r->host_cls);
             r->host_in = nullptr;
@@ -2345,6 +2410,9 @@ void fill_result(const ServedRequest &r, dfa_result *out) {
     out->queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
     out->service_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_start).count();
     out->latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
+    out->h2d_ms = r.h2d_ms;
+    out->device_ms = r.device_ms;
+    out->d2h_ms = r.d2h_ms;
 }
 
 // Runs an entry point's body so that no C++ exception crosses the C ABI: a
@@ -2747,6 +2815,7 @@ dfa_server *dfa_server_create(const dfa_server_config *cfg_in) {
             cfg.hbm_budget = free_b / 2;
         }
         s->cfg = cfg;
+        s->paused = cfg.paused != 0;
         {
             Ctx *dc = nullptr;
             if (get_ctx(dc) != DFA_OK) return nullptr;
@@ -2879,8 +2948,27 @@ int dfa_server_wait(dfa_server *handle, uint64_t ticket, dfa_result *out) {
         if (it == s->requests.end()) return fail(DFA_EINVAL, "unknown ticket %llu",
                                                  static_cast<unsigned long long>(ticket));
         ServedRequest *r = it->second.get();
+        // dfa_server_destroy cancels waiting requests and then waits for
+        // every waiter to leave before it frees the server
+        ++s->waiters;
         s->cv_done.wait(lk, [&] { return r->done; });
         fill_result(*r, out);
+        // a cancelled request's result goes away with the server
+        if (r->status == DFA_ECANCELED) out->blocks = nullptr;
+        if (--s->waiters == 0) s->cv_left.notify_all();
+        return DFA_OK;
+    });
+}
+
+int dfa_server_resume(dfa_server *handle) {
+    return guarded([&]() -> int {
+        Server *s = reinterpret_cast<Server *>(handle);
+        if (!s) return fail(DFA_EINVAL, "NULL server");
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->paused = false;
+        }
+        s->cv_work.notify_all();
         return DFA_OK;
     });
 }
@@ -2917,6 +3005,7 @@ int dfa_server_get_stats(dfa_server *handle, dfa_server_stats *out) {
         for (size_t i = 0; i < s->busy.size(); ++i) in_use += s->busy[i] ? s->reserved[i] : s->held[i];
         out->hbm_in_use = in_use;
         out->hbm_budget = s->cfg.hbm_budget;
+        out->waiting_threads = s->waiters;
         std::vector<double> lat = s->latencies;
         if (!lat.empty()) {
             std::sort(lat.begin(), lat.end());
@@ -2955,6 +3044,13 @@ void dfa_server_destroy(dfa_server *handle) {
         s->cv_work.notify_all();
         s->cv_done.notify_all();
         for (auto &t : s->workers) t.join();
+        {
+            // threads blocked in dfa_server_wait have seen their request
+            // finish or be cancelled; the server is freed once they left
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_done.notify_all();
+            s->cv_left.wait(lk, [&] { return s->waiters == 0; });
+        }
         (void)hipSetDevice(s->device);
         for (auto &c : s->lanes) release_ctx(*c);
         // host copies of cancelled requests and unreleased results go back to

@@ -7,6 +7,7 @@ built by Algorithm 5); verdicts with union-find Hopcroft-Karp and the oracle's
 product exploration.  Integer work: every comparison is exact.
 """
 import concurrent.futures
+import ctypes
 import os
 
 import numpy as np
@@ -820,7 +821,9 @@ def test_server_round_budget_fallback_to_closure():
 
 
 def test_server_admission_and_errors():
-    with B.Server(lanes=1, hbm_budget=64 << 20) as srv:
+    # the budget holds a lane's fixed workspace (96 MiB) and a small request,
+    # not the 2^20-state, 8-letter one (with its closure about 1 GB)
+    with B.Server(lanes=1, hbm_budget=256 << 20) as srv:
         too_big = W.random_dfa(1 << 20, 8, 0.5, 1)
         with pytest.raises(B.DfaError) as e:
             srv.submit_minimise(too_big)
@@ -833,6 +836,48 @@ def test_server_admission_and_errors():
         r = srv.wait(srv.submit_minimise(good))
         np.testing.assert_array_equal(r["blocks"], oracle.hopcroft(good.delta, good.accepting)[0])
         assert srv.stats()["rejected"] == 1
+
+
+def test_server_paused_resume_and_cancel():
+    """A server created paused queues requests without running them.  After
+    resume they run as usual; requests still queued when the server is
+    destroyed are cancelled, and a thread blocked in wait on one of them
+    returns DFA_ECANCELED (destroy returns only after it left)."""
+    import threading
+    import time
+
+    dfas = [W.random_dfa(800 + 7 * i, 3, 0.3, 40 + i) for i in range(4)]
+    with B.Server(lanes=1, paused=True) as srv:
+        tickets = [srv.submit_minimise(d) for d in dfas[:2]]
+        time.sleep(0.05)
+        assert all(srv.poll(t) is None for t in tickets)  # nothing ran while paused
+        assert srv.stats()["completed"] == 0
+        srv.resume()
+        for d, t in zip(dfas[:2], tickets):
+            np.testing.assert_array_equal(srv.wait(t)["blocks"],
+                                          oracle.hopcroft(d.delta, d.accepting)[0])
+    srv = B.Server(lanes=2, paused=True)
+    tickets = [srv.submit_minimise(d) for d in dfas]
+    seen = {}
+
+    def waiter(t):
+        r = B.Result()
+        rc = srv._lib.dfa_server_wait(srv._h, t, ctypes.byref(r))
+        seen[t] = (rc, r.status, bool(r.blocks))
+
+    threads = [threading.Thread(target=waiter, args=(t,)) for t in tickets[1:3]]
+    for th in threads:
+        th.start()
+    deadline = time.time() + 30
+    while srv.stats()["waiting_threads"] < 2:  # nothing can run while paused
+        assert time.time() < deadline
+        time.sleep(0.005)
+    srv.close()
+    for th in threads:
+        th.join(timeout=60)
+        assert not th.is_alive()
+    for t in tickets[1:3]:
+        assert seen[t] == (B.DFA_OK, B.DFA_ECANCELED, False)
 
 
 @pytest.mark.parametrize("n,k", [(2 * 1024 * 1024 + 3, 5), (1 << 21, 4), ((1 << 21) - 1, 1)])
