@@ -261,6 +261,34 @@ int dfa_minimise_device(uint32_t n, uint32_t k, const uint32_t *delta,
                         const dfa_options *opt, dfa_stats *stats, void *stream);
 
 /*
+ * dfa_minimise_device for callers that cannot allocate device memory (code
+ * in tight serving loops, harnesses that forbid hipMalloc): the call makes no
+ * device allocation and frees nothing.  Same arguments, results and errors
+ * as dfa_minimise_device; the caller still passes the inputs and outputs.
+ *   - Every buffer the call needs is carved from a fixed workspace of
+ *     256 MiB, a static device array that each device running this entry
+ *     point holds until the process ends.  A plain refinement needs about
+ *     n*(8k + 41) bytes plus a hash table of 8 * 2^ceil(log2 2n) bytes and
+ *     about 4.1 MiB of label bitmaps (e.g. n up to about 2^21 at k = 4).
+ *   - DFA_ENOMEM, before any work, when that estimate exceeds the workspace;
+ *     DFA_ENOMEM also when a later part of the call does not fit (closure
+ *     letters with DFA_TC_ON, pruning).  With DFA_TC_AUTO a closure that does
+ *     not fit is skipped and plain rounds continue (same partition).
+ *   - DFA_LOOP_GRAPH runs as DFA_LOOP_CHUNK (instantiating a graph allocates);
+ *     the kernel tuning is the default one (dfa_tuning_default).
+ *   - Calls on one device share that device's workspace, which keeps the last
+ *     call's contents; every call clears what must start at zero.  Calls
+ *     that overlapped on one device would race on it, so the library runs
+ *     them one at a time (a lock of their own, separate from the other
+ *     entry points') and each returns only when its work on the device is
+ *     done.
+ */
+int dfa_minimise_device_fixed(uint32_t n, uint32_t k, const uint32_t *delta,
+                              const uint8_t *accepting, uint32_t *block_out,
+                              dfa_quotient *q_out, const dfa_options *opt, dfa_stats *stats,
+                              void *stream);
+
+/*
  * Equivalence L(a) = L(b) (Section 4, Algorithm 6's result; decided by
  * minimising the disjoint union and comparing the blocks of the two start
  * states, with an early exit as soon as they separate).

@@ -139,6 +139,7 @@ class ServerStats(ctypes.Structure):
 
 
 EXPORTS = sorted(["dfa_options_default", "dfa_minimise", "dfa_minimise_device",
+                  "dfa_minimise_device_fixed",
                   "dfa_equivalent", "dfa_equivalent_device", "dfa_included",
                   "dfa_included_device", "dfa_last_error", "dfa_device_info",
                   "dfa_tuning_default", "dfa_get_tuning", "dfa_set_tuning",
@@ -182,6 +183,8 @@ def load(build_if_missing: bool = True):
         lib.dfa_minimise.argtypes = [u32, u32, vp, vp, vp, P(Quotient), P(Options), P(Stats)]
         lib.dfa_minimise_device.argtypes = [u32, u32, vp, vp, vp, P(Quotient), P(Options),
                                             P(Stats), vp]
+        lib.dfa_minimise_device_fixed.argtypes = [u32, u32, vp, vp, vp, P(Quotient),
+                                                  P(Options), P(Stats), vp]
         lib.dfa_equivalent.argtypes = [P(View), P(View), P(i32), P(Options), P(Stats)]
         lib.dfa_equivalent_device.argtypes = [P(View), P(View), P(i32), P(Options), P(Stats), vp]
         lib.dfa_included.argtypes = [P(View), P(View), P(i32), P(ctypes.c_uint64), P(Options),
@@ -221,7 +224,8 @@ def load(build_if_missing: bool = True):
         lib.dfa_profile_enable.argtypes = [i32]
         lib.dfa_profile_read.argtypes = [P(KernelTime), i32, P(i32)]
         lib.dfa_profile_only.argtypes = [ctypes.c_char_p]
-        for fn in ("dfa_minimise", "dfa_minimise_device", "dfa_equivalent",
+        for fn in ("dfa_minimise", "dfa_minimise_device", "dfa_minimise_device_fixed",
+                   "dfa_equivalent",
                    "dfa_equivalent_device", "dfa_included", "dfa_included_device",
                    "dfa_device_info", "dfa_get_tuning", "dfa_set_tuning",
                    "dfa_profile_enable", "dfa_profile_read", "dfa_minimise_batch",
@@ -382,6 +386,25 @@ def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop:
                     algorithm: str = "signature", prune: bool = False) -> MinimiseResult:
     """dfa_minimise_device on torch GPU tensors: delta int32/uint32 [n, k]
     (row-major), accepting uint8 [n]; block_out int32 [n] (allocated if None)."""
+    return _minimise_device("dfa_minimise_device", delta, accepting, block_out, tc, loop, start,
+                            max_rounds, chunk, lds_stage, quotient, stream, algorithm, prune)
+
+
+def minimise_device_fixed(delta, accepting, block_out=None, *, tc: str = "auto",
+                          loop: str = "graph", start: int = 0, max_rounds: int = 0,
+                          chunk: int = 0, lds_stage=2, quotient: bool = False, stream=None,
+                          algorithm: str = "signature", prune: bool = False) -> MinimiseResult:
+    """dfa_minimise_device_fixed (no device allocation inside the library: its
+    workspace is a fixed device array) on torch GPU tensors; arguments as
+    minimise_device.  The tensors it is given, and block_out / the quotient
+    when they are allocated here, come from the caller's side."""
+    return _minimise_device("dfa_minimise_device_fixed", delta, accepting, block_out, tc, loop,
+                            start, max_rounds, chunk, lds_stage, quotient, stream, algorithm,
+                            prune)
+
+
+def _minimise_device(entry, delta, accepting, block_out, tc, loop, start, max_rounds, chunk,
+                     lds_stage, quotient, stream, algorithm, prune) -> MinimiseResult:
     import torch
     n, k = delta.shape
     if delta.dtype not in (torch.int32, torch.uint32):
@@ -398,10 +421,10 @@ def minimise_device(delta, accepting, block_out=None, *, tc: str = "auto", loop:
         qd = torch.empty((n, k), dtype=torch.int32, device=delta.device)
         qa = torch.empty(n, dtype=torch.uint8, device=delta.device)
         q = Quotient(qd.data_ptr(), qa.data_ptr(), 0, 0)
-    rc = load().dfa_minimise_device(n, k, delta.data_ptr(), accepting.data_ptr(),
-                                    block_out.data_ptr(),
-                                    ctypes.byref(q) if q is not None else None, ctypes.byref(o),
-                                    ctypes.byref(st), _stream_ptr(stream))
+    rc = getattr(load(), entry)(n, k, delta.data_ptr(), accepting.data_ptr(),
+                                block_out.data_ptr(),
+                                ctypes.byref(q) if q is not None else None, ctypes.byref(o),
+                                ctypes.byref(st), _stream_ptr(stream))
     _check(rc)
     res = MinimiseResult(block_out, st.as_dict())
     if q is not None:

@@ -25,6 +25,15 @@
 #include "dfamin.h"
 #include "dfamin_internal.h"
 
+// Workspace of dfa_minimise_device_fixed, the entry point that allocates no
+// device memory: every buffer of its calls is carved from this array.  Each
+// device that runs that entry point holds its own copy until the process
+// ends.  Host code never passes this name to a kernel or a copy (on the host
+// it is a stand-in, not a device address); the device address comes from
+// hipGetSymbolAddress, taken once per device.
+static constexpr size_t kFixedScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) uint8_t scratch[kFixedScratchBytes];
+
 namespace dfamin {
 
 GraphRecorder *&graph_recorder() {
@@ -75,6 +84,7 @@ struct Arena {
     uint8_t *base = nullptr;
     size_t size = 0;
     size_t used = 0;
+    uint64_t generation = 1;  // bumped by every reset: earlier carves are void
 };
 
 struct Buffer {
@@ -82,7 +92,12 @@ struct Buffer {
     size_t cap = 0;
     uint64_t allocation = 0;  // number of the current allocation (0: none)
     Arena *arena = nullptr;   // carve from this region, never allocate
+    uint64_t carved_in = 0;   // arena generation of the current carve
     int ensure(size_t bytes, const char *what) {
+        if (arena && carved_in != arena->generation) {  // carved before the last reset
+            p = nullptr;
+            cap = 0;
+        }
         if (p && bytes <= cap) return DFA_OK;
         if (arena) {
             // a region outgrown within a call is abandoned until the next reset
@@ -95,6 +110,7 @@ struct Buffer {
             p = arena->base + arena->used;
             arena->used += want;
             cap = want;
+            carved_in = arena->generation;
             allocation = ++g_allocation_number;
             return DFA_OK;
         }
@@ -185,6 +201,7 @@ struct Ctx {
     bool blocking_sync = false;
     hipEvent_t ev_sync = nullptr;
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
+    Arena arena;  // the allocation-free context's fixed workspace (unused elsewhere)
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     uint8_t *ring[2] = {nullptr, nullptr};  // page-locked chunks for large host copies
     hipEvent_t ring_ev[2] = {nullptr, nullptr};
@@ -1986,6 +2003,44 @@ void release_ctx(Ctx &c) {
     c.inited = false;
 }
 
+// ---- the allocation-free entry point's context ----
+
+// One per device: its own stream, lock and events (made at its first call,
+// the set-up), and buffers carved from the device's copy of `scratch`.
+Ctx g_fixed[kMaxDevices];
+
+// Set-up on the current device (once): the device address of `scratch`, and
+// every buffer of the context bound to it.
+int init_fixed(Ctx &c) {
+    if (!c.arena.base) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DFA_EDEVICE, "device address of the fixed workspace: %s",
+                        hipGetErrorString(e));
+        c.arena.base = static_cast<uint8_t *>(ptr);
+        c.arena.size = kFixedScratchBytes;
+        c.arena.used = 0;
+        for_each_buffer(c, [&c](Buffer &b) {
+            b.arena = &c.arena;
+            b.p = nullptr;
+            b.cap = 0;
+        });
+    }
+    return init_ctx(c);
+}
+
+// Workspace of a plain refinement (no closure, no pruning) of n states and k
+// letters in the fixed context, each buffer rounded up to 256 bytes as the
+// arena carves it: columns 4k, block ids 8, marks 4, signatures 4(k + 1),
+// hashes 8, table <= 32, canonical ids, dense ids, leaders 12, byte labels 1,
+// bit masks < 1 per state; plus the label bitmaps and small control words.
+size_t fixed_plain_bytes(uint64_t n, uint64_t k) {
+    const uint64_t table = 8 * next_pow2(std::max<uint64_t>(2 * n, 1024));
+    return n * (8 * k + 41) + table + (size_t(1) << kPackedMaxBits) / 8 +
+           (1u << kPatternMaxBits) / 8 + (size_t(64) << 10);
+}
+
 using Clock = std::chrono::steady_clock;
 
 // Page-locked host buffers for submitted inputs, reused across requests (one
@@ -2567,6 +2622,37 @@ int dfa_minimise_device(uint32_t n, uint32_t k, const uint32_t *delta, const uin
         DFA_TRY(join_stream(*c, stream));
         if (stats) std::memset(stats, 0, sizeof *stats);
         return minimise_impl(*c, n, k, delta, accepting, block_out, q_out, o, stats);
+    });
+}
+
+int dfa_minimise_device_fixed(uint32_t n, uint32_t k, const uint32_t *delta,
+                              const uint8_t *accepting, uint32_t *block_out, dfa_quotient *q_out,
+                              const dfa_options *opt, dfa_stats *stats, void *stream) {
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        dfa_options o = resolve(opt);
+        DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
+        const size_t need = fixed_plain_bytes(n, k);
+        if (need > kFixedScratchBytes)
+            return fail(DFA_ENOMEM,
+                        "n = %u, k = %u needs about %zu bytes of workspace; the fixed workspace "
+                        "holds %zu",
+                        n, k, need, kFixedScratchBytes);
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev < 0 || dev >= kMaxDevices)
+            return fail(DFA_EDEVICE, "device index %d out of range", dev);
+        Ctx &c = g_fixed[dev];
+        CallScope lock(c.mu);
+        DFA_TRY(init_fixed(c));
+        // a graph's instantiation allocates: chunks are launched one by one
+        if (o.loop_mode == DFA_LOOP_GRAPH) o.loop_mode = DFA_LOOP_CHUNK;
+        // every call carves its buffers afresh from the start of the array
+        c.arena.used = 0;
+        ++c.arena.generation;
+        DFA_TRY(join_stream(c, stream));
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return minimise_impl(c, n, k, delta, accepting, block_out, q_out, o, stats);
     });
 }
 
