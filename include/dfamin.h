@@ -181,9 +181,10 @@ void dfa_options_default(dfa_options *opt);
 
 /*
  * Kernel tuning of the current device (launch shapes and kernel variants; no
- * effect on results).  Set by the autotuner or by hand; read by every later
- * call on that device.  dfa_set_tuning returns DFA_EINVAL for out-of-range
- * values.
+ * effect on results).  Set by hand or by the package's autotuner (which
+ * measures candidate tunings on the caller's workload and keeps the fastest
+ * per device and workload shape); read by every later call on that device.
+ * dfa_set_tuning returns DFA_EINVAL for out-of-range values.
  */
 typedef struct dfa_tuning {
     uint32_t round_grid_cap; /* workgroups of the signature/grouping kernels (grid-stride
@@ -199,7 +200,12 @@ typedef struct dfa_tuning {
                                 low bits, so that distinct keys share hashes: slower, still
                                 exact (keys are always compared in full); for testing the
                                 collision paths of both groupings */
-    uint32_t reserved[10];
+    uint32_t batch_lds_states; /* batched calls: DFAs (equivalence: pairs) of at most this many
+                                  states and at most 16 letters are refined whole inside one
+                                  workgroup, ids and table in LDS; the others go through the
+                                  segmented refinement.  0 = never; at most 16384, and lowered
+                                  to what one workgroup's LDS holds on the device */
+    uint32_t reserved[9];
 } dfa_tuning;
 
 void dfa_tuning_default(dfa_tuning *t);

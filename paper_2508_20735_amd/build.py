@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libdfamin.so")
 SOURCES = ["api.hip", "refine_kernels.hip", "leader_kernels.hip", "reach_kernels.hip",
-           "sort_kernels.hip", "product_kernels.hip"]
+           "sort_kernels.hip", "product_kernels.hip", "batch_kernels.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -201,6 +201,7 @@ struct Ctx {
     bool blocking_sync = false;
     hipEvent_t ev_sync = nullptr;
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
+    Buffer small_jobs, small_results, small_ctl;  // batched small DFAs (one workgroup each)
     Arena arena;  // the allocation-free context's fixed workspace (unused elsewhere)
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     uint8_t *ring[2] = {nullptr, nullptr};  // page-locked chunks for large host copies
@@ -1667,57 +1668,153 @@ int check_views(uint32_t count, const dfa_view *v, const char *name) {
 
 // Batched minimisation on device views; out_dev receives the block ids,
 // part i at out_off[i].
+// Largest job (states) that goes to the one-workgroup path: the tuning's
+// limit, lowered to what one workgroup's LDS holds on this device.
+uint32_t small_cutoff(Ctx &c) {
+    uint32_t cut = std::min(c.tune.batch_lds_states, kSmallMaxStates);
+    if (!cut) return 0;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    // (plus the kernel's own few static words)
+    while (cut && static_cast<int>(small_refine_lds_bytes(cut)) + 256 > lds) cut >>= 1;
+    return cut;
+}
+
+// Queues the small jobs (one workgroup each, largest first); their results
+// are read back by finish_small_jobs after the stream is synchronised.
+int launch_small_jobs(Ctx &c, std::vector<SmallJob> &jobs, uint32_t slots, uint32_t *out_dev,
+                      uint32_t max_rounds) {
+    std::sort(jobs.begin(), jobs.end(), [](const SmallJob &x, const SmallJob &y) {
+        return x.na + x.nb > y.na + y.nb;
+    });
+    const uint32_t nmax = jobs.front().na + jobs.front().nb;
+    const uint32_t lds = small_refine_lds_bytes(nmax);
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
+    const int fit = small_refine_max_groups(lds, cus);
+    if (fit <= 0) return fail(DFA_EDEVICE, "no workgroup of %u LDS bytes fits the device", lds);
+    const uint32_t groups = std::min<uint32_t>(static_cast<uint32_t>(jobs.size()),
+                                               static_cast<uint32_t>(fit));
+    DFA_TRY(c.small_jobs.ensure(jobs.size() * sizeof(SmallJob), "small jobs"));
+    DFA_TRY(c.small_results.ensure(static_cast<size_t>(slots) * sizeof(SmallResult),
+                                   "small results"));
+    DFA_TRY(c.small_ctl.ensure(2 * sizeof(uint32_t), "small job counter"));
+    HIP_TRY(hipMemcpyAsync(c.small_jobs.p, jobs.data(), jobs.size() * sizeof(SmallJob),
+                           hipMemcpyHostToDevice, c.stream));
+    uint32_t *ctl = c.small_ctl.as<uint32_t>();
+    launch_small_refine(c.small_jobs.as<SmallJob>(), static_cast<uint32_t>(jobs.size()), groups,
+                        lds, ctl, out_dev, c.small_results.as<SmallResult>(), max_rounds, ctl + 1,
+                        c.stream);
+    HIP_TRY(hipGetLastError());
+    return DFA_OK;
+}
+
+// After the stream has been synchronised: the small jobs' results (indexed
+// by DFA / pair) and their target check.
+int finish_small_jobs(Ctx &c, uint32_t slots, std::vector<SmallResult> &res) {
+    res.resize(slots);
+    HIP_TRY(hipMemcpy(res.data(), c.small_results.p, slots * sizeof(SmallResult),
+                      hipMemcpyDeviceToHost));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, c.small_ctl.as<uint32_t>() + 1, sizeof err, hipMemcpyDeviceToHost));
+    if (err) return fail(DFA_EINVAL, "a transition target is >= n");
+    return DFA_OK;
+}
+
 int minimise_batch_impl(Ctx &c, uint32_t count, const dfa_view *views, uint32_t *out_dev,
                         const uint64_t *out_off, uint32_t *num_blocks, uint32_t *rounds,
                         const dfa_options &o, dfa_batch_stats *st) {
-    std::vector<Part> parts(count);
-    uint64_t off = 0, out = 0;
+    // small DFAs: one workgroup each; the others: one segmented refinement
+    const uint32_t cutoff = small_cutoff(c);
+    std::vector<Part> parts;
+    std::vector<uint32_t> large_of;  // DFA index of each segment
+    std::vector<SmallJob> small;
+    uint64_t off = 0, out = 0, total = 0;
     uint32_t kmax = 0;
     for (uint32_t i = 0; i < count; ++i) {
         const dfa_view &v = views[i];
-        Part &p = parts[i];
+        const uint64_t out_i = out_off ? out_off[i] : out;
+        out += v.n;
+        total += v.n;
+        if (v.n <= cutoff && v.k <= kSmallMaxK) {
+            SmallJob j;
+            std::memset(&j, 0, sizeof j);
+            j.delta_a = v.delta;
+            j.acc_a = v.accepting;
+            j.na = v.n;
+            j.k = v.k;
+            j.index = i;
+            j.out = out_i;
+            small.push_back(j);
+            continue;
+        }
+        Part p;
         std::memset(&p, 0, sizeof p);
         p.delta = v.delta;
         p.accepting = v.accepting;
         p.n = v.n;
         p.k = v.k;
         p.off = static_cast<uint32_t>(off);
-        p.seg = i;
+        p.seg = static_cast<uint32_t>(parts.size());
         p.start = v.start;
-        p.out = out_off ? out_off[i] : out;
-        out += v.n;
+        p.out = out_i;
         off += v.n;
         kmax = std::max(kmax, v.k);
         if (off >= 0xFFFFFFFFull) return fail(DFA_EINVAL, "total number of states must be < 2^32 - 1");
+        parts.push_back(p);
+        large_of.push_back(i);
     }
     HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    if (!small.empty()) DFA_TRY(launch_small_jobs(c, small, count, out_dev, o.max_rounds));
     RefineResult r;
     SegArgs g{};
     std::vector<uint32_t> blocks, changing;
-    DFA_TRY(refine_segments(c, parts, count, kmax, o, r, g, blocks, changing));
     const size_t N = off;
-    DFA_TRY(c.canon.ensure(N * sizeof(uint32_t), "canonical ids"));
-    // canonical ids go to the block buffer that does not hold the result
-    uint32_t *canon_ids = c.blockA.as<uint32_t>() == r.final_block ? c.blockB.as<uint32_t>()
-                                                                   : c.blockA.as<uint32_t>();
-    launch_canonicalise(r.final_block, N, N, c.canon.as<uint32_t>(), canon_ids, c.stream);
-    launch_part_output(g, N, canon_ids, out_dev, c.stream);
-    HIP_TRY(hipGetLastError());
+    if (!parts.empty()) {
+        DFA_TRY(refine_segments(c, parts, static_cast<uint32_t>(parts.size()), kmax, o, r, g,
+                                blocks, changing));
+        DFA_TRY(c.canon.ensure(N * sizeof(uint32_t), "canonical ids"));
+        // canonical ids go to the block buffer that does not hold the result
+        uint32_t *canon_ids = c.blockA.as<uint32_t>() == r.final_block ? c.blockB.as<uint32_t>()
+                                                                       : c.blockA.as<uint32_t>();
+        launch_canonicalise(r.final_block, N, N, c.canon.as<uint32_t>(), canon_ids, c.stream);
+        launch_part_output(g, N, canon_ids, out_dev, c.stream);
+        HIP_TRY(hipGetLastError());
+    }
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
     HIP_TRY(stream_sync(c));
-    uint64_t transitions = 0;
-    for (uint32_t i = 0; i < count; ++i) {
-        if (num_blocks) num_blocks[i] = blocks[i];
-        if (rounds) rounds[i] = changing[i] + 1;
-        transitions += static_cast<uint64_t>(views[i].n) * views[i].k * (changing[i] + 1);
+    std::vector<SmallResult> sres;
+    if (!small.empty()) DFA_TRY(finish_small_jobs(c, count, sres));
+    uint64_t transitions = 0, small_bytes = 0;
+    uint32_t joint_rounds = parts.empty() ? 0 : r.ctl.round;
+    bool limit = !parts.empty() && r.ctl.limit;
+    auto record = [&](uint32_t i, uint32_t nb, uint32_t ch) {
+        if (num_blocks) num_blocks[i] = nb;
+        if (rounds) rounds[i] = ch + 1;
+        transitions += static_cast<uint64_t>(views[i].n) * views[i].k * (ch + 1);
+    };
+    for (size_t j = 0; j < parts.size(); ++j) record(large_of[j], blocks[j], changing[j]);
+    for (const SmallJob &j : small) {
+        const SmallResult &sr = sres[j.index];
+        record(j.index, sr.num_blocks, sr.changing);
+        joint_rounds = std::max(joint_rounds, sr.rounds);
+        limit |= sr.limit != 0;
+        small_bytes += static_cast<uint64_t>(j.na) * sr.rounds * (8ull * j.k + 8ull);
     }
     if (st) {
-        fill_batch_stats(st, count, r, N, transitions);
+        fill_batch_stats(st, count, r, total, transitions);
+        st->rounds = joint_rounds;
+        if (parts.empty()) st->k_eff = 0;
+        st->algorithmic_bytes = (parts.empty() ? 0 : r.bytes) + small_bytes;
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
         st->device_ms = ms;
     }
-    if (r.ctl.limit)
+    if (limit)
         return fail(DFA_ELIMIT, "max_rounds (%u) reached before every partition was stable",
                     o.max_rounds);
     return DFA_OK;
@@ -1726,50 +1823,96 @@ int minimise_batch_impl(Ctx &c, uint32_t count, const dfa_view *views, uint32_t 
 int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_view *b,
                           int32_t *verdicts, const dfa_options &o, dfa_batch_stats *st,
                           uint32_t *rounds_out = nullptr) {
-    std::vector<Part> parts(2 * static_cast<size_t>(count));
-    uint64_t off = 0;
+    // small pairs: one workgroup each; the others: one segmented refinement
+    const uint32_t cutoff = small_cutoff(c);
+    std::vector<Part> parts;
+    std::vector<uint32_t> large_of;  // pair index of each segment
+    std::vector<SmallJob> small;
+    uint64_t off = 0, total = 0;
     uint32_t kmax = 0;
-    for (uint32_t i = 0; i < count; ++i)
+    for (uint32_t i = 0; i < count; ++i) {
+        total += static_cast<uint64_t>(a[i].n) + b[i].n;
+        if (static_cast<uint64_t>(a[i].n) + b[i].n <= cutoff && a[i].k <= kSmallMaxK) {
+            SmallJob j;
+            std::memset(&j, 0, sizeof j);
+            j.delta_a = a[i].delta;
+            j.acc_a = a[i].accepting;
+            j.delta_b = b[i].delta;
+            j.acc_b = b[i].accepting;
+            j.na = a[i].n;
+            j.nb = b[i].n;
+            j.k = a[i].k;
+            j.start_a = a[i].start;
+            j.start_b = b[i].start;
+            j.index = i;
+            small.push_back(j);
+            continue;
+        }
+        const uint32_t seg = static_cast<uint32_t>(large_of.size());
         for (int side = 0; side < 2; ++side) {
             const dfa_view &v = side ? b[i] : a[i];
-            Part &p = parts[2 * static_cast<size_t>(i) + side];
+            Part p;
             std::memset(&p, 0, sizeof p);
             p.delta = v.delta;
             p.accepting = v.accepting;
             p.n = v.n;
             p.k = v.k;
             p.off = static_cast<uint32_t>(off);
-            p.seg = i;
+            p.seg = seg;
             p.start = v.start;
             off += v.n;
             kmax = std::max(kmax, v.k);
             if (off >= 0xFFFFFFFFull)
                 return fail(DFA_EINVAL, "total number of states must be < 2^32 - 1");
+            parts.push_back(p);
         }
+        large_of.push_back(i);
+    }
     HIP_TRY(hipEventRecord(c.ev_start, c.stream));
+    if (!small.empty()) DFA_TRY(launch_small_jobs(c, small, count, nullptr, o.max_rounds));
     RefineResult r;
     SegArgs g{};
     std::vector<uint32_t> blocks, changing;
-    DFA_TRY(refine_segments(c, parts, count, kmax, o, r, g, blocks, changing));
-    DFA_TRY(c.batch_out.ensure(count * sizeof(int32_t), "verdicts"));
-    launch_pair_verdicts(g, r.final_block, c.batch_out.as<int32_t>(), c.stream);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(verdicts, c.batch_out.p, count * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           c.stream));
+    const uint32_t nseg = static_cast<uint32_t>(large_of.size());
+    std::vector<int32_t> seg_verdicts(nseg);
+    if (nseg) {
+        DFA_TRY(refine_segments(c, parts, nseg, kmax, o, r, g, blocks, changing));
+        DFA_TRY(c.batch_out.ensure(nseg * sizeof(int32_t), "verdicts"));
+        launch_pair_verdicts(g, r.final_block, c.batch_out.as<int32_t>(), c.stream);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(seg_verdicts.data(), c.batch_out.p, nseg * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, c.stream));
+    }
     HIP_TRY(hipEventRecord(c.ev_stop, c.stream));
     HIP_TRY(stream_sync(c));
-    if (rounds_out)
-        for (uint32_t i = 0; i < count; ++i) rounds_out[i] = changing[i] + 1;
+    std::vector<SmallResult> sres;
+    if (!small.empty()) DFA_TRY(finish_small_jobs(c, count, sres));
+    uint64_t transitions = 0, small_bytes = 0;
+    uint32_t joint_rounds = nseg ? r.ctl.round : 0;
+    bool limit = nseg && r.ctl.limit;
+    auto record = [&](uint32_t i, int32_t verdict, uint32_t ch) {
+        verdicts[i] = verdict;
+        if (rounds_out) rounds_out[i] = ch + 1;
+        transitions += (static_cast<uint64_t>(a[i].n) + b[i].n) * a[i].k * (ch + 1);
+    };
+    for (uint32_t j = 0; j < nseg; ++j) record(large_of[j], seg_verdicts[j], changing[j]);
+    for (const SmallJob &j : small) {
+        const SmallResult &sr = sres[j.index];
+        record(j.index, static_cast<int32_t>(sr.verdict), sr.changing);
+        joint_rounds = std::max(joint_rounds, sr.rounds);
+        limit |= sr.limit != 0;
+        small_bytes += (static_cast<uint64_t>(j.na) + j.nb) * sr.rounds * (8ull * j.k + 8ull);
+    }
     if (st) {
-        uint64_t transitions = 0;
-        for (uint32_t i = 0; i < count; ++i)
-            transitions += (static_cast<uint64_t>(a[i].n) + b[i].n) * a[i].k * (changing[i] + 1);
-        fill_batch_stats(st, count, r, off, transitions);
+        fill_batch_stats(st, count, r, total, transitions);
+        st->rounds = joint_rounds;
+        if (!nseg) st->k_eff = 0;
+        st->algorithmic_bytes = (nseg ? r.bytes : 0) + small_bytes;
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, c.ev_start, c.ev_stop));
         st->device_ms = ms;
     }
-    if (r.ctl.limit)
+    if (limit)
         return fail(DFA_ELIMIT, "max_rounds (%u) reached before every verdict was known",
                     o.max_rounds);
     return DFA_OK;
@@ -1955,7 +2098,8 @@ void for_each_buffer(Ctx &c, F &&f) {
                       &c.reach_qb, &c.reach_flags, &c.reach_dense, &c.reach_orig, &c.sub_delta,
                       &c.sub_acc, &c.sub_block, &c.sort_keys0, &c.sort_keys1, &c.sort_vals0,
                       &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,
-                      &c.sort_m, &c.serve_in};
+                      &c.sort_m, &c.serve_in, &c.small_jobs, &c.small_results,
+                      &c.small_ctl};
     for (Buffer *b : bufs) f(*b);
 }
 
@@ -2551,6 +2695,7 @@ void dfa_tuning_default(dfa_tuning *t) {
     t->label_rounds = 2;
     t->cached_probe = 1;
     t->chunk = 4;
+    t->batch_lds_states = 4096;
 }
 
 int dfa_get_tuning(dfa_tuning *t) {
@@ -2569,7 +2714,8 @@ int dfa_set_tuning(const dfa_tuning *t) {
     return guarded([&]() -> int {
         if (!t) return fail(DFA_EINVAL, "tuning is NULL");
         if (t->label_rounds > 2 || t->cached_probe > 1 || t->chunk == 0 || t->chunk > 4096 ||
-            t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24) || t->hash_bits > 63)
+            t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24) || t->hash_bits > 63 ||
+            t->batch_lds_states > kSmallMaxStates)
             return fail(DFA_EINVAL, "tuning value out of range");
         Ctx *c = nullptr;
         DFA_TRY(get_ctx(c));

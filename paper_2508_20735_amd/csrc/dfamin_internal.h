@@ -345,6 +345,34 @@ void launch_quotient_identity(const uint32_t *delta, const uint8_t *acc, uint32_
                               uint32_t start, uint32_t *qdelta, uint8_t *qacc, uint32_t *qstart,
                               hipStream_t s);
 
+// ---- small DFAs, one workgroup each (batch_kernels.hip) ----
+// A job: one DFA (nb == 0: minimisation, block ids to out_blocks + out) or
+// the disjoint union of two DFAs with the same k (equivalence: the verdict).
+// States are local: DFA a's are 0 .. na-1, DFA b's follow.
+constexpr uint32_t kSmallThreads = 256;  // threads of a job's workgroup
+constexpr uint32_t kSmallMaxK = 16;      // letters of a job
+constexpr uint32_t kSmallMaxStates = 16384;  // states of a job (ids are 16-bit)
+struct SmallJob {
+    const uint32_t *delta_a, *delta_b;  // device, row-major
+    const uint8_t *acc_a, *acc_b;
+    uint32_t na, nb, k, start_a, start_b;
+    uint32_t index;  // DFA or pair index in the call (results[index])
+    uint64_t out;    // minimisation: offset of the DFA's ids in out_blocks
+};
+struct SmallResult {
+    uint32_t num_blocks, rounds, changing, verdict, limit;
+};
+// LDS bytes of a job of n states (table of 2^ceil(log2 2n) >= 64 words and
+// two 16-bit id arrays).
+uint32_t small_refine_lds_bytes(uint32_t n);
+// Workgroups that fit on the device at once with that much LDS (0: none).
+int small_refine_max_groups(uint32_t lds_bytes, int device_cus);
+// Refines every job (largest first: jobs sorted by size, taken from a
+// counter); *err = 1 if some target is out of range; results[job.index].
+void launch_small_refine(const SmallJob *jobs, uint32_t njobs, uint32_t groups, uint32_t lds_bytes,
+                         uint32_t *next_job, uint32_t *out_blocks, SmallResult *results,
+                         uint32_t max_rounds, uint32_t *err, hipStream_t s);
+
 // ---- product exploration (product_kernels.hip) ----
 struct ProductArgs {
     const uint32_t *dA, *dB;   // row-major
