@@ -205,7 +205,9 @@ typedef struct dfa_tuning {
                                   workgroup, ids and table in LDS; the others go through the
                                   segmented refinement.  0 = never; at most 16384, and lowered
                                   to what one workgroup's LDS holds on the device */
-    uint32_t reserved[9];
+    uint32_t insert_pair;      /* 1 (default): the LDS-staged grouping kernel takes two states
+                                  per thread when k_eff is 1, 2, 3, 4 or 8; 0: one */
+    uint32_t reserved[8];
 } dfa_tuning;
 
 void dfa_tuning_default(dfa_tuning *t);

@@ -700,6 +700,7 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
     ra.round_grid_cap = c.tune.round_grid_cap;
     ra.pattern_grid_cap = c.tune.label_grid_cap;
     ra.cached_probe = c.tune.cached_probe;
+    ra.insert_pair = c.tune.insert_pair;
     ra.chg = c.chg.as<unsigned long long>();
     ra.chg_sum = c.chg_sum.as<unsigned long long>();
     ra.single = c.single.as<unsigned long long>();
@@ -2696,6 +2697,7 @@ void dfa_tuning_default(dfa_tuning *t) {
     t->cached_probe = 1;
     t->chunk = 4;
     t->batch_lds_states = 4096;
+    t->insert_pair = 1;
 }
 
 int dfa_get_tuning(dfa_tuning *t) {
@@ -2715,7 +2717,7 @@ int dfa_set_tuning(const dfa_tuning *t) {
         if (!t) return fail(DFA_EINVAL, "tuning is NULL");
         if (t->label_rounds > 2 || t->cached_probe > 1 || t->chunk == 0 || t->chunk > 4096 ||
             t->round_grid_cap > (1u << 24) || t->label_grid_cap > (1u << 24) || t->hash_bits > 63 ||
-            t->batch_lds_states > kSmallMaxStates)
+            t->batch_lds_states > kSmallMaxStates || t->insert_pair > 1)
             return fail(DFA_EINVAL, "tuning value out of range");
         Ctx *c = nullptr;
         DFA_TRY(get_ctx(c));

@@ -189,7 +189,7 @@ struct RoundArgs {
     uint32_t round_grid_cap;    // workgroups of the round kernels (0 = one per 256 states)
     uint32_t pattern_grid_cap;  // workgroups of the label rounds
     uint32_t cached_probe;      // probe the table with cached loads first
-    uint32_t pad;
+    uint32_t insert_pair;       // 1: LDS-staged grouping with two states per thread
     unsigned long long *chg;      // N/64 words
     unsigned long long *single;   // N/64 words, zero before the first round
     unsigned long long *touched;  // 2 * (N/64) words, zero before the first round

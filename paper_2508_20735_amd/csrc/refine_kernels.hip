@@ -255,27 +255,48 @@ __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
     uint32_t *__restrict__ out = p.blockB;
     unsigned long long seen_reg = 0;
     const ColPtrs<KC> colp(p.cols, p.colmap, p.N);
-    for (size_t q = global_tid(); q < p.N; q += grid_stride()) {
-        uint32_t label = acc_bit(p.accbits, static_cast<uint32_t>(q));
-        if constexpr (KC > 0) {
-            // all column entries first, then all acceptance bits
-            uint32_t t[KC];
-#pragma unroll
-            for (int j = 0; j < KC; ++j) t[j] = colp.c[j][q];
-#pragma unroll
-            for (int j = 0; j < KC; ++j) label |= acc_bit(p.accbits, t[j]) << (j + 1);
-        } else {
-            for (uint32_t j = 0; j < keff; ++j) {
-                const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
-                label |= acc_bit(p.accbits, t) << (j + 1);
-            }
-        }
+    auto emit = [&](size_t q, uint32_t label) {
         out[q] = label;
         if (p.lab8) p.lab8[q] = static_cast<uint8_t>(label);
         if (in_reg)
             seen_reg |= 1ull << label;
         else
             atomicOr(pres + (label >> 5), 1u << (label & 31));
+    };
+    if constexpr (KC > 0) {
+        // S states per thread and iteration, every load of one kind issued
+        // for all of them before any value is used (the round is bound by
+        // the latency of the column reads and the dependent bit gathers)
+        constexpr int S = 4;
+        for (size_t base = static_cast<size_t>(blockIdx.x) * (S * kBlock); base < p.N;
+             base += static_cast<size_t>(gridDim.x) * (S * kBlock)) {
+            size_t q[S];
+            uint32_t t[S][KC], label[S];
+#pragma unroll
+            for (int i = 0; i < S; ++i) q[i] = base + i * kBlock + threadIdx.x;
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+#pragma unroll
+                for (int j = 0; j < KC; ++j) t[i][j] = q[i] < p.N ? colp.c[j][q[i]] : 0u;
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                label[i] = q[i] < p.N ? acc_bit(p.accbits, static_cast<uint32_t>(q[i])) : 0u;
+#pragma unroll
+                for (int j = 0; j < KC; ++j) label[i] |= acc_bit(p.accbits, t[i][j]) << (j + 1);
+            }
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+                if (q[i] < p.N) emit(q[i], label[i]);
+        }
+    } else {
+        for (size_t q = global_tid(); q < p.N; q += grid_stride()) {
+            uint32_t label = acc_bit(p.accbits, static_cast<uint32_t>(q));
+            for (uint32_t j = 0; j < keff; ++j) {
+                const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
+                label |= acc_bit(p.accbits, t) << (j + 1);
+            }
+            emit(q, label);
+        }
     }
     if (in_reg) {
         seen_reg = wave_or64(seen_reg);
@@ -326,11 +347,16 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
     if (tx == 0) lfill = 0;
     __syncthreads();
     // XCD-sliced tiles: in a union each XCD gathers the labels of one
-    // operand only, a footprint its own L2 holds
-    const TileRange tr = xcd_tiles(p.N, kBlock);
+    // operand only, a footprint its own L2 holds.  A tile has 2 * kBlock
+    // states, two per thread, so that each thread has the loads of two
+    // states in flight (the round is bound by load latency).
+    constexpr int S = 2;
+    const TileRange tr = xcd_tiles(p.N, S * kBlock);
     for (size_t t = tr.first; t < tr.end; t += tr.step) {
-        const size_t base = t * kBlock;
-        // every thread reads the fill before any thread of this tile inserts
+        const size_t base = t * (S * kBlock);
+        // every thread reads the fill before any thread of this tile
+        // inserts; a tile adds at most S * kBlock labels, so a set at most
+        // half full always has empty slots for them
         const bool half_full = lfill > kLabelSlots / 2;
         __syncthreads();
         if (half_full) {
@@ -338,54 +364,70 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
             if (tx == 0) lfill = 0;
             __syncthreads();
         }
-        const size_t q = base + tx;
-        bool first = false;
-        uint32_t key = 0;
-        if (q < p.N) {
-            key = p.lab8[q];
-            if constexpr (KC > 0) {
-                // all column entries first, then all byte labels
-                uint32_t t[KC];
+        size_t q[S];
+        uint32_t key[S];
 #pragma unroll
-                for (int j = 0; j < KC; ++j) t[j] = colp.c[j][q];
+        for (int i = 0; i < S; ++i) q[i] = base + i * kBlock + tx;
+        if constexpr (KC > 0) {
+            // all column entries first, then all byte labels
+            uint32_t tt[S][KC];
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+#pragma unroll
+                for (int j = 0; j < KC; ++j) tt[i][j] = q[i] < p.N ? colp.c[j][q[i]] : 0u;
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                key[i] = q[i] < p.N ? p.lab8[q[i]] : 0u;
 #pragma unroll
                 for (int j = 0; j < KC; ++j)
-                    key |= static_cast<uint32_t>(p.lab8[t[j]]) << (bits * (j + 1));
-            } else {
+                    key[i] |= static_cast<uint32_t>(p.lab8[tt[i][j]]) << (bits * (j + 1));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                key[i] = 0;
+                if (q[i] >= p.N) continue;
+                key[i] = p.lab8[q[i]];
                 for (uint32_t j = 0; j < keff; ++j) {
-                    const uint32_t t = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q];
-                    key |= static_cast<uint32_t>(p.lab8[t]) << (bits * (j + 1));
+                    const uint32_t tj = p.cols[static_cast<size_t>(p.colmap[j]) * p.N + q[i]];
+                    key[i] |= static_cast<uint32_t>(p.lab8[tj]) << (bits * (j + 1));
                 }
             }
-            Y[q] = key;
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (q[i] >= p.N) continue;
+            Y[q[i]] = key[i];
             // keys are < 2^kPackedMaxBits, so ~0u marks an empty LDS slot
-            uint32_t slot = (key * 0x9E3779B1u) >> 20;  // 12 bits
+            uint32_t slot = (key[i] * 0x9E3779B1u) >> 20;  // 12 bits
+            bool first = false;
             for (;;) {
                 const uint32_t e =
                     __hip_atomic_load(lset + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (e == key) break;
+                if (e == key[i]) break;
                 if (e == ~0u) {
-                    const uint32_t prev = atomicCAS(lset + slot, ~0u, key);
+                    const uint32_t prev = atomicCAS(lset + slot, ~0u, key[i]);
                     if (prev == ~0u) {
                         first = true;
                         atomicAdd(&lfill, 1u);
                         break;
                     }
-                    if (prev == key) break;
+                    if (prev == key[i]) break;
                 }
                 slot = (slot + 1) & (kLabelSlots - 1);
             }
-        }
-        if (first) {
-            uint32_t *word = p.presence_packed + (key >> 5);
-            const uint32_t bit = 1u << (key & 31);
-            // a cached read may be stale, but bits are only ever set during
-            // the round: a bit it shows is set, and one it misses costs one
-            // atomic; frequent labels are filtered here (on the 2^22-state
-            // workload 72,299 labels cover 4.2M states, the top one 458K)
-            const uint32_t seen =
-                __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (!(seen & bit)) fresh += (atomicOr(word, bit) & bit) ? 0u : 1u;
+            if (first) {
+                uint32_t *word = p.presence_packed + (key[i] >> 5);
+                const uint32_t bit = 1u << (key[i] & 31);
+                // a cached read may be stale, but bits are only ever set
+                // during the round: a bit it shows is set, and one it misses
+                // costs one atomic; frequent labels are filtered here (on
+                // the 2^22-state workload 72,299 labels cover 4.2M states,
+                // the top one 458K)
+                const uint32_t seen =
+                    __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (!(seen & bit)) fresh += (atomicOr(word, bit) & bit) ? 0u : 1u;
+            }
         }
         __syncthreads();
     }
@@ -890,6 +932,154 @@ __device__ __forceinline__ void insert_lds_body(const InsParams &p) {
     wg_add_spread(p.counters, 3, blocks);
 }
 
+// The same grouping with two states per thread (tiles of 2 * kBlock
+// states) and the signature width known at compile time (KC = k_eff > 0):
+// the reads of both states' rows, their holders' rows and their hashes are
+// in flight together, and the probes of the two states' tile leaders are
+// issued one after the other without waiting in between (the kernel is
+// bound by the latency of these dependent random reads).
+template <int KC>
+__device__ __forceinline__ bool rows_equal_fixed(const uint32_t *__restrict__ sig, size_t a,
+                                                 size_t b) {
+    constexpr int W = KC + 1;
+    const uint32_t *ra = sig + a * W;
+    const uint32_t *rb = sig + b * W;
+    uint32_t va[W], vb[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        va[i] = ra[i];
+        vb[i] = rb[i];
+    }
+    bool eq = true;
+#pragma unroll
+    for (int i = 0; i < W; ++i) eq &= va[i] == vb[i];
+    return eq;
+}
+
+template <int KC>
+__device__ __forceinline__ void insert_lds2_body(const InsParams &p) {
+    constexpr int S = 2;
+    constexpr uint32_t kTile = S * kBlock;
+    constexpr uint32_t kSlots2 = 2 * kTile;
+    __shared__ unsigned long long ltab[kSlots2];
+    __shared__ uint32_t gid[kTile];
+    __shared__ uint32_t lsize[kTile];
+    if (p.ctl->done || !stage_in_lds(p)) return;
+    const uint32_t r = p.ctl->round;
+    const uint32_t epoch = r % kEpochs + 1;
+    const bool all = r <= p.ctl->all_active_until;
+    const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
+    uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
+    const uint32_t tx = threadIdx.x;
+    uint32_t blocks = 0, idle = 0, changed = 0;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kTile; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kTile) {
+        size_t q[S], first[S];
+        bool act[S];
+        uint32_t loc[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            loc[i] = i * kBlock + tx;
+            q[i] = base + loc[i];
+            first[i] = q[i] - lane_id();
+            const unsigned long long am = first[i] < p.N ? p.active[first[i] >> 6] : 0ull;
+            act[i] = q[i] < p.N && ((am >> lane_id()) & 1ull);
+            idle += (q[i] < p.N && !act[i]) ? 1u : 0u;
+        }
+        // whole tile idle: nothing to group (uniform across the workgroup)
+        if (__syncthreads_or(act[0] || act[1]) == 0) {
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+                if (lane_id() == 0 && first[i] < p.N) p.chg[first[i] >> 6] = 0ull;
+            continue;
+        }
+        uint32_t x[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) x[i] = act[i] ? X[q[i]] : 0u;
+        // the state holding its block's id kept it in the signature kernel;
+        // a member with the same key joins it directly, the others group in
+        // LDS first
+        bool joins[S], grp[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const bool cand = act[i] && !all && x[i] != q[i];
+            joins[i] = cand && rows_equal_fixed<KC>(p.sig, q[i], x[i]);
+        }
+        uint64_t h[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (joins[i]) {
+                Y[q[i]] = x[i];
+                mark_multi(p.multi, x[i], r + 1);
+            }
+            grp[i] = act[i] && !joins[i] && (all || x[i] != q[i]);
+            h[i] = grp[i] ? p.hash[q[i]] : 0;
+        }
+        for (uint32_t i = tx; i < kSlots2; i += kBlock) ltab[i] = kEmptyPair;
+#pragma unroll
+        for (int i = 0; i < S; ++i) lsize[loc[i]] = 0;
+        __syncthreads();
+        uint32_t lead[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            lead[i] = loc[i];
+            if (!grp[i]) continue;
+            const uint32_t ltag = static_cast<uint32_t>(h[i] >> 32);
+            uint32_t sl = static_cast<uint32_t>(h[i]) & (kSlots2 - 1);
+            for (;;) {
+                unsigned long long e =
+                    __hip_atomic_load(ltab + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (e == kEmptyPair) {
+                    const unsigned long long want =
+                        (static_cast<unsigned long long>(ltag) << 32) | loc[i];
+                    const unsigned long long prev = atomicCAS(ltab + sl, kEmptyPair, want);
+                    if (prev == kEmptyPair) break;
+                    e = prev;
+                }
+                if (static_cast<uint32_t>(e >> 32) == ltag) {
+                    const uint32_t other = static_cast<uint32_t>(e);
+                    if (rows_equal_fixed<KC>(p.sig, q[i], base + other)) {
+                        lead[i] = other;
+                        break;
+                    }
+                }
+                sl = (sl + 1) & (kSlots2 - 1);
+            }
+            atomicAdd(lsize + lead[i], 1u);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (!grp[i] || lead[i] != loc[i]) continue;
+            bool claimed = false;
+            const uint32_t id = find_or_claim(p.table, p.mask, epoch, h[i],
+                                              static_cast<uint32_t>(q[i]), p.sig, p.W,
+                                              p.cached_probe != 0, claimed);
+            gid[loc[i]] = id;
+            if (claimed) ++blocks;
+            if (!claimed || lsize[loc[i]] > 1) mark_multi(p.multi, id, r + 1);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            bool ch = false;
+            if (grp[i]) {
+                const uint32_t id = gid[lead[i]];
+                Y[q[i]] = id;
+                ch = id != x[i];
+            }
+            const unsigned long long cm = __ballot(ch);
+            store_changed(p.chg, p.chg_sum, p.N, r, first[i], cm);
+            changed += ch ? 1u : 0u;
+        }
+        __syncthreads();
+    }
+    wg_add_spread(p.counters, 0, blocks);
+    wg_add_spread(p.counters, 1, idle);
+    wg_add_spread(p.counters, 2, changed);
+    wg_add_spread(p.counters, 3, blocks);
+}
+
 // One workgroup: the round's block count (spread counters), the stop tests,
 // and the counter reset.
 __device__ __forceinline__ void round_end_body(RoundCtl *ctl, const uint32_t *blockA,
@@ -957,6 +1147,9 @@ __global__ __launch_bounds__(kBlock) void k_signature(SigParams p) {
 __global__ __launch_bounds__(kBlock) void k_insert(InsParams p) { insert_body(p); }
 
 __global__ __launch_bounds__(kBlock) void k_insert_lds(InsParams p) { insert_lds_body(p); }
+
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_insert_lds2(InsParams p) { insert_lds2_body<KC>(p); }
 
 __global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint32_t *blockA,
                                                        const uint32_t *blockB, uint32_t *counters,
@@ -1338,8 +1531,13 @@ SigParams sig_params(const RoundArgs &a) {
                      a.single,   a.touched,    a.chg_sum,  a.grouping, a.hash_bits};
 }
 
-unsigned round_grid(const RoundArgs &a, unsigned cap) {
-    return grid_for(a.N, cap ? cap : (1u << 30));
+// Workgroups of a round kernel whose workgroups take `tile` states at a
+// time, at most cap (0: no cap).
+unsigned round_grid(const RoundArgs &a, unsigned cap, size_t tile = kBlock) {
+    size_t g = (a.N + tile - 1) / tile;
+    if (g == 0) g = 1;
+    const size_t c = cap ? cap : (1u << 30);
+    return static_cast<unsigned>(g > c ? c : g);
 }
 
 InsParams ins_params(const RoundArgs &a) {
@@ -1481,7 +1679,18 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
     const InsParams ip = ins_params(a);
     // the two grouping variants; exactly one of them works in a given round
     // (lds_stage 2 decides on the device from the previous round)
-    if (a.lds_stage != 0) launch_kernel(k_insert_lds, grid, block, 0, s, ip);
+    if (a.lds_stage != 0) {
+        // two states per thread for the specialised signature widths
+        const dim3 grid2(round_grid(a, a.round_grid_cap, 2 * kBlock));
+        switch (a.insert_pair ? a.k_eff : 0u) {
+            case 1: launch_kernel(k_insert_lds2<1>, grid2, block, 0, s, ip); break;
+            case 2: launch_kernel(k_insert_lds2<2>, grid2, block, 0, s, ip); break;
+            case 3: launch_kernel(k_insert_lds2<3>, grid2, block, 0, s, ip); break;
+            case 4: launch_kernel(k_insert_lds2<4>, grid2, block, 0, s, ip); break;
+            case 8: launch_kernel(k_insert_lds2<8>, grid2, block, 0, s, ip); break;
+            default: launch_kernel(k_insert_lds, grid, block, 0, s, ip); break;
+        }
+    }
     if (a.lds_stage != 1) launch_kernel(k_insert, grid, block, 0, s, ip);
 }
 
