@@ -1548,7 +1548,8 @@ int ensure_pinned_batch(Ctx &c, size_t bytes) {
 }
 
 // parts (host vector, device pointers inside) -> device SegArgs.
-int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, size_t N, SegArgs &g) {
+int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, bool pairs, size_t N,
+                SegArgs &g) {
     const size_t tiles = (N + kBlock - 1) / kBlock;
     std::vector<uint32_t> tile_part(tiles);
     uint32_t p = 0;
@@ -1559,14 +1560,14 @@ int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, size_t N,
     }
     DFA_TRY(c.parts.ensure(parts.size() * sizeof(Part), "batch parts"));
     DFA_TRY(c.tile_part.ensure(tiles * sizeof(uint32_t), "batch tiles"));
-    DFA_TRY(c.seg_words.ensure((4 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t),
+    DFA_TRY(c.seg_words.ensure((5 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t),
                                "segment counters"));
     HIP_TRY(hipMemcpy(c.parts.p, parts.data(), parts.size() * sizeof(Part),
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c.tile_part.p, tile_part.data(), tiles * sizeof(uint32_t),
                       hipMemcpyHostToDevice));
     uint32_t *w = c.seg_words.as<uint32_t>();
-    HIP_TRY(hipMemsetAsync(w, 0, (4 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t), c.stream));
+    HIP_TRY(hipMemsetAsync(w, 0, (5 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t), c.stream));
     g.parts = c.parts.as<Part>();
     g.tile_part = c.tile_part.as<uint32_t>();
     g.nparts = static_cast<uint32_t>(parts.size());
@@ -1575,19 +1576,21 @@ int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, size_t N,
     g.seg_prev = w + nseg;
     g.seg_changing = w + 2 * static_cast<size_t>(nseg);
     g.seg_flags = w + 3 * static_cast<size_t>(nseg);
-    g.init_count = w + 4 * static_cast<size_t>(nseg);
+    g.seg_done = w + 4 * static_cast<size_t>(nseg);
+    g.init_count = w + 5 * static_cast<size_t>(nseg);
+    g.pairs = pairs ? 1u : 0u;
     return DFA_OK;
 }
 
 // Refines the union described by parts; fills per-segment block counts and
 // changing rounds (host vectors).
-int refine_segments(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, uint32_t kmax,
-                    const dfa_options &o, RefineResult &r, SegArgs &g,
+int refine_segments(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, bool pairs,
+                    uint32_t kmax, const dfa_options &o, RefineResult &r, SegArgs &g,
                     std::vector<uint32_t> &seg_blocks, std::vector<uint32_t> &seg_changing) {
     const Part &last = parts.back();
     const size_t N = static_cast<size_t>(last.off) + last.n;
     if (N >= 0xFFFFFFFFull) return fail(DFA_EINVAL, "total number of states must be < 2^32 - 1");
-    DFA_TRY(upload_plan(c, parts, nseg, N, g));
+    DFA_TRY(upload_plan(c, parts, nseg, pairs, N, g));
     DFA_TRY(prepare_refinement(c, N, kmax));
     uint32_t *flags = c.flags.as<uint32_t>();
     launch_ingest_parts(g, N, kmax, c.cols.as<uint32_t>(), flags + kFlagErr, flags + kFlagNonid,
@@ -1776,8 +1779,8 @@ int minimise_batch_impl(Ctx &c, uint32_t count, const dfa_view *views, uint32_t 
     std::vector<uint32_t> blocks, changing;
     const size_t N = off;
     if (!parts.empty()) {
-        DFA_TRY(refine_segments(c, parts, static_cast<uint32_t>(parts.size()), kmax, o, r, g,
-                                blocks, changing));
+        DFA_TRY(refine_segments(c, parts, static_cast<uint32_t>(parts.size()), false, kmax, o,
+                                r, g, blocks, changing));
         DFA_TRY(c.canon.ensure(N * sizeof(uint32_t), "canonical ids"));
         // canonical ids go to the block buffer that does not hold the result
         uint32_t *canon_ids = c.blockA.as<uint32_t>() == r.final_block ? c.blockB.as<uint32_t>()
@@ -1877,7 +1880,7 @@ int equivalent_batch_impl(Ctx &c, uint32_t count, const dfa_view *a, const dfa_v
     const uint32_t nseg = static_cast<uint32_t>(large_of.size());
     std::vector<int32_t> seg_verdicts(nseg);
     if (nseg) {
-        DFA_TRY(refine_segments(c, parts, nseg, kmax, o, r, g, blocks, changing));
+        DFA_TRY(refine_segments(c, parts, nseg, true, kmax, o, r, g, blocks, changing));
         DFA_TRY(c.batch_out.ensure(nseg * sizeof(int32_t), "verdicts"));
         launch_pair_verdicts(g, r.final_block, c.batch_out.as<int32_t>(), c.stream);
         HIP_TRY(hipGetLastError());

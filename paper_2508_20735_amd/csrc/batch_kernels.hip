@@ -14,7 +14,8 @@
 // Ids inside a round are the index of the state that first claimed its
 // signature's slot; the final ids are made canonical (smallest member) in
 // LDS.  The round counts are those of plain signature rounds from the
-// initial partition {F, Q \ F}, as in the segmented path.
+// initial partition {F, Q \ F}, as in the segmented path; a pair stops at the
+// round that separates its start states.
 #include "device_common.h"
 
 namespace dfamin {
@@ -176,6 +177,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_refine(const SmallJob *
             uint16_t *t = cur;
             cur = nxt;
             nxt = t;
+            // a pair is decided once its start states are separated (the
+            // refinement never merges them again)
+            if (J.nb && cur[J.start_a] != cur[J.na + J.start_b]) {
+                nxt = cur;
+                break;
+            }
             if (max_rounds && round >= max_rounds) {
                 limit = 1;
                 nxt = cur;  // the last round's ids

@@ -133,7 +133,11 @@ struct SegArgs {
     uint32_t *seg_prev;       // blocks per segment after the last round
     uint32_t *seg_changing;   // rounds that split a block of the segment
     uint32_t *seg_flags;      // acceptance classes per segment (bit 0/1)
+    uint32_t *seg_done;       // r + 1 once the segment is decided in round r (0 before):
+                              // its partition is stable, or (pairs) its two start states
+                              // were separated; its states are skipped from then on
     uint32_t *init_count;     // sum over segments of their class counts
+    uint32_t pairs;           // 1: segment s is the union of parts 2s and 2s + 1
 };
 
 // Transposes every part into cols (targets offset by the part's first
@@ -218,7 +222,10 @@ void launch_mark(const RoundArgs &a, hipStream_t s);
 // signature letters change).
 void launch_ctl_full(RoundCtl *ctl, hipStream_t s);
 // Per-segment block counts of the round, then the per-segment bookkeeping
-// (both no-ops once the refinement has stopped); run before the round end.
+// (all no-ops once the refinement has stopped); run before the round end.
+// A segment whose partition did not change, or a pair whose start states
+// separated, is decided: its states are marked as skipped (singleton bits)
+// and it takes part in no later round.
 void launch_seg_round(const RoundArgs &a, hipStream_t s);
 // The three launches of launch_round, separately (for kernel timing).
 void launch_signature(const RoundArgs &a, hipStream_t s);

@@ -1229,16 +1229,29 @@ __global__ __launch_bounds__(kBlock) void k_ingest_parts(SegArgs g, size_t N, ui
     }
 }
 
+// The classes present in each segment are gathered per tile in LDS (a tile
+// spans at most kBlock segments), then OR-ed into seg_flags once per tile and
+// segment: per-state atomics on one word per segment serialised.
 __global__ __launch_bounds__(kBlock) void k_init_parts(SegArgs g, size_t N,
                                                         uint32_t *__restrict__ block) {
-    for (size_t q = global_tid(); q < N; q += grid_stride()) {
-        const Part P = g.parts[find_part(g, q)];
-        const bool f = P.accepting[q - P.off] != 0;
-        block[q] = 2u * P.seg + (f ? 1u : 0u);
-        const uint32_t bit = f ? 1u : 2u;
-        uint32_t *w = g.seg_flags + P.seg;
-        if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) & bit))
-            atomicOr(w, bit);
+    __shared__ uint32_t lflag[kBlock];
+    __shared__ uint32_t seg_first;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        lflag[threadIdx.x] = 0;
+        if (threadIdx.x == 0) seg_first = g.parts[g.tile_part[base / kBlock]].seg;
+        __syncthreads();
+        const size_t q = base + threadIdx.x;
+        if (q < N) {
+            const Part P = g.parts[find_part(g, q)];
+            const bool f = P.accepting[q - P.off] != 0;
+            block[q] = 2u * P.seg + (f ? 1u : 0u);
+            atomicOr(lflag + (P.seg - seg_first), f ? 1u : 2u);
+        }
+        __syncthreads();
+        const uint32_t m = lflag[threadIdx.x];
+        if (m) atomicOr(g.seg_flags + seg_first + threadIdx.x, m);
+        __syncthreads();
     }
 }
 
@@ -1264,19 +1277,31 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(SegArgs g, size_t N, const
                                                        const uint32_t *blockA,
                                                        const uint32_t *blockB) {
     __shared__ uint32_t lcnt[kBlock];
-    __shared__ uint32_t seg_first;
+    __shared__ uint32_t seg_first, tile_live;
     if (ctl->done) return;
     const uint32_t r = ctl->round;
     const uint32_t *__restrict__ Y = (r & 1u) ? blockA : blockB;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
         lcnt[threadIdx.x] = 0;
-        if (threadIdx.x == 0) seg_first = g.parts[g.tile_part[base / kBlock]].seg;
+        if (threadIdx.x == 0) {
+            // a tile whose segments are all decided has nothing to count
+            uint32_t p = g.tile_part[base / kBlock];
+            seg_first = g.parts[p].seg;
+            uint32_t live = 0;
+            const size_t end = base + kBlock < N ? base + kBlock : N;
+            for (; p < g.nparts && g.parts[p].off < end; ++p) live |= g.seg_done[g.parts[p].seg] == 0u;
+            tile_live = live;
+        }
         __syncthreads();
+        if (!tile_live) {
+            __syncthreads();  // every thread has read tile_live
+            continue;
+        }
         const size_t q = base + threadIdx.x;
         if (q < N && Y[q] == q) {
             const uint32_t seg = g.parts[find_part(g, q)].seg;
-            atomicAdd(lcnt + (seg - seg_first), 1u);
+            if (g.seg_done[seg] == 0u) atomicAdd(lcnt + (seg - seg_first), 1u);
         }
         __syncthreads();
         const uint32_t c = lcnt[threadIdx.x];
@@ -1285,15 +1310,55 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(SegArgs g, size_t N, const
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_end(SegArgs g, const RoundCtl *ctl) {
+// Per-segment end of round: a segment whose block count did not change is
+// stable (its partition never changes again: the segments are disjoint), and
+// a pair whose start states got different ids is separated; either way the
+// segment is decided in this round.
+__global__ __launch_bounds__(kBlock) void k_seg_end(SegArgs g, const RoundCtl *ctl,
+                                                     const uint32_t *blockA,
+                                                     const uint32_t *blockB) {
     if (ctl->done) return;
+    const uint32_t r = ctl->round;
+    const uint32_t *__restrict__ Y = (r & 1u) ? blockA : blockB;
     for (size_t s = global_tid(); s < g.nseg; s += grid_stride()) {
+        if (g.seg_done[s]) continue;
         const uint32_t c = g.seg_cnt[s];
-        if (c != g.seg_prev[s]) {
-            g.seg_changing[s] += 1;
-            g.seg_prev[s] = c;
-        }
         g.seg_cnt[s] = 0;
+        if (c == g.seg_prev[s]) {
+            g.seg_done[s] = r + 1;
+            continue;
+        }
+        g.seg_changing[s] += 1;
+        g.seg_prev[s] = c;
+        if (g.pairs) {
+            const Part A = g.parts[2 * s], B = g.parts[2 * s + 1];
+            if (Y[A.off + A.start] != Y[B.off + B.start]) g.seg_done[s] = r + 1;
+        }
+    }
+}
+
+// The states of the segments decided in this round are marked as skipped in
+// the singleton bits (one workgroup per segment; the bits of a word shared
+// with a neighbouring segment are set atomically).
+__global__ __launch_bounds__(kBlock) void k_seg_freeze(SegArgs g, const RoundCtl *ctl,
+                                                        unsigned long long *single) {
+    if (ctl->done) return;
+    const uint32_t r = ctl->round;
+    for (size_t s = blockIdx.x; s < g.nseg; s += gridDim.x) {
+        if (g.seg_done[s] != r + 1) continue;
+        const Part first = g.parts[g.pairs ? 2 * s : s];
+        const Part last = g.parts[g.pairs ? 2 * s + 1 : s];
+        const size_t lo = first.off, hi = static_cast<size_t>(last.off) + last.n;
+        for (size_t w = (lo >> 6) + threadIdx.x; w <= ((hi - 1) >> 6); w += kBlock) {
+            const size_t b0 = w << 6;
+            unsigned long long m = ~0ull;
+            if (b0 < lo) m &= ~0ull << (lo - b0);
+            if (b0 + 64 > hi) m &= ~0ull >> (b0 + 64 - hi);
+            if (m == ~0ull)
+                single[w] = m;
+            else
+                atomicOr(single + w, m);
+        }
     }
 }
 
@@ -1598,7 +1663,9 @@ void launch_seg_round(const RoundArgs &a, hipStream_t s) {
     launch_kernel(k_seg_count, dim3(grid_for(a.N, kDefaultGridCap)), dim3(kBlock), 0, s,
                        a.seg, a.N, a.ctl, a.blockA, a.blockB);
     launch_kernel(k_seg_end, dim3(grid_for(a.seg.nseg, kDefaultGridCap)), dim3(kBlock), 0, s,
-                       a.seg, a.ctl);
+                       a.seg, a.ctl, a.blockA, a.blockB);
+    launch_kernel(k_seg_freeze, dim3(std::min<uint32_t>(a.seg.nseg, kDefaultGridCap)),
+                  dim3(kBlock), 0, s, a.seg, a.ctl, a.single);
 }
 
 void launch_part_output(const SegArgs &g, size_t N, const uint32_t *canon, uint32_t *out,
