@@ -207,7 +207,12 @@ typedef struct dfa_tuning {
                                   to what one workgroup's LDS holds on the device */
     uint32_t insert_pair;      /* 1 (default): the LDS-staged grouping kernel takes two states
                                   per thread when k_eff is 1, 2, 3, 4 or 8; 0: one */
-    uint32_t reserved[8];
+    uint32_t slice_min_states; /* single-DFA refinements of at least this many states (and at
+                                  most 2^24, k_eff 1..8 or 16, no closure, not the persistent
+                                  loop) bucket their edges by target slice once, and their
+                                  dense rounds in the first chunk gather successor ids through
+                                  slices held in LDS; 0 = never; default 2^20 */
+    uint32_t reserved[7];
 } dfa_tuning;
 
 void dfa_tuning_default(dfa_tuning *t);

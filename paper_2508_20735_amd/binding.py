@@ -71,7 +71,7 @@ class Tuning(ctypes.Structure):
                 ("label_rounds", ctypes.c_uint32), ("cached_probe", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("hash_bits", ctypes.c_uint32),
                 ("batch_lds_states", ctypes.c_uint32), ("insert_pair", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 8)]
+                ("slice_min_states", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

@@ -202,6 +202,7 @@ struct Ctx {
     hipEvent_t ev_sync = nullptr;
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     Buffer small_jobs, small_results, small_ctl;  // batched small DFAs (one workgroup each)
+    Buffer pb_tl, pb_src, pb_val, pb_off, pb_partials;  // edges bucketed by target slice
     Arena arena;  // the allocation-free context's fixed workspace (unused elsewhere)
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     uint8_t *ring[2] = {nullptr, nullptr};  // page-locked chunks for large host copies
@@ -356,7 +357,7 @@ int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
 
 enum class Kern {
     Mark, Signature, Insert, SortGroup, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove,
-    LeaderEnd
+    LeaderEnd, PbGather, SignaturePb
 };
 
 int prof_event(Ctx &c, size_t &idx) {
@@ -370,7 +371,10 @@ int prof_event(Ctx &c, size_t &idx) {
 }
 
 // Algorithmic bytes per refined state of each round kernel (k = k_eff):
-//   signature  4k (column entries) + 4 (own block id) + 4k (successor ids)
+//   signature  4k (column entries) + 4 (own block id) + 4k (successor ids);
+//              in rounds that gather through LDS slices the successor ids are
+//              charged to the gather pass (4k) and the rest (4k + 4) to the
+//              signature pass
 //   insert     4 (the new block id)
 //   pattern    4k (columns) + (k + 1) (acceptance of q and successors) + 4 (label)
 //   packed     4k (columns) + (k + 1) (byte labels) + 4 (label)
@@ -379,6 +383,8 @@ int prof_event(Ctx &c, size_t &idx) {
 uint32_t kern_bytes(Kern kind, uint32_t k_eff) {
     switch (kind) {
         case Kern::Signature: return 8 * k_eff + 4;
+        case Kern::PbGather: return 4 * k_eff;
+        case Kern::SignaturePb: return 4 * k_eff + 4;
         case Kern::Insert: return 4;
         case Kern::Pattern:
         case Kern::Packed: return 5 * k_eff + 5;
@@ -398,6 +404,8 @@ const char *kern_name(Kern kind) {
         case Kern::Packed: return "k_packed_round";
         case Kern::LeaderElect: return "k_leader_elect";
         case Kern::LeaderMove: return "k_leader_move";
+        case Kern::PbGather: return "k_pb_gather";
+        case Kern::SignaturePb: return "k_signature_pb";
         default: return "k_leader_end";
     }
 }
@@ -415,6 +423,8 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
         switch (kind) {
             case Kern::Mark: launch_mark(a, c.stream); break;
             case Kern::Signature: launch_signature(a, c.stream); break;
+            case Kern::PbGather: launch_pb_gather(a, c.stream); break;
+            case Kern::SignaturePb: launch_signature_pb(a, c.stream); break;
             case Kern::Insert: launch_insert(a, c.stream); break;
             case Kern::SortGroup: launch_sort_group(a, c.stream); break;
             case Kern::RoundEnd: launch_round_end(a, c.stream); break;
@@ -440,6 +450,10 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
 
 int launch_full_round(Ctx &c, const RoundArgs &a, uint32_t round) {
     DFA_TRY(launch_kern(c, Kern::Mark, a, round));
+    if (a.pb.nb) {
+        DFA_TRY(launch_kern(c, Kern::PbGather, a, round));
+        DFA_TRY(launch_kern(c, Kern::SignaturePb, a, round));
+    }
     DFA_TRY(launch_kern(c, Kern::Signature, a, round));
     DFA_TRY(launch_kern(c, a.grouping ? Kern::SortGroup : Kern::Insert, a, round));
     if (a.seg.nseg) launch_seg_round(a, c.stream);
@@ -460,7 +474,14 @@ int prof_collect(Ctx &c, const RoundCtl &ctl) {
         auto &t = c.ktimes[p.name];
         t.launches += 1;
         t.ms += ms;
-        if (p.round < ctl.round && ctl.round - p.round <= kActiveHist) {
+        // the signature kernel and the two slice passes stand in for each
+        // other round by round: only the path the round took is charged
+        const bool pb = ((ctl.pb_rounds >> (p.round % 64)) & 1ull) != 0;
+        const bool sig = std::strcmp(p.name, "k_signature") == 0;
+        const bool pass = std::strcmp(p.name, "k_pb_gather") == 0 ||
+                          std::strcmp(p.name, "k_signature_pb") == 0;
+        const bool did_work = !((sig && pb) || (pass && !pb));
+        if (did_work && p.round < ctl.round && ctl.round - p.round <= kActiveHist) {
             const uint64_t refined = ctl.active_hist[p.round % kActiveHist];
             t.bytes += refined * p.bytes_per_state;
             t.states += refined;
@@ -725,6 +746,44 @@ RoundArgs make_round_args(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff
 // and init kernels).  With state_ids, a partition that ends in label ids
 // (a stable partition found by a label round) gets one more table round,
 // which keeps the partition and turns the labels into state ids.
+// Buckets the edges by target slice when the refinement is large enough for
+// dense rounds to gain from gathering through LDS (dfa_tuning.slice_min_states)
+// and its signature width has a specialised kernel; pb.nb == 0 otherwise.
+// Not for segmented refinements, closure columns or the persistent loop.
+int build_slices(Ctx &c, const uint32_t *cols, size_t N, uint32_t k_eff, const dfa_options &o,
+                 bool excluded, PbArgs &pb) {
+    pb = PbArgs{};
+    const bool width = k_eff >= 1 && (k_eff <= 8 || k_eff == 16);
+    if (excluded || !width || o.loop_mode == DFA_LOOP_PERSISTENT || !c.tune.slice_min_states ||
+        N < c.tune.slice_min_states || N > (static_cast<size_t>(kPbMaxBuckets) << kPbSliceLog))
+        return DFA_OK;
+    const uint32_t nb = static_cast<uint32_t>((N + (1u << kPbSliceLog) - 1) >> kPbSliceLog);
+    const uint32_t ntiles = static_cast<uint32_t>((N + kPbTile - 1) / kPbTile);
+    const size_t E = N * k_eff;
+    const uint64_t L = static_cast<uint64_t>(nb) * ntiles;
+    DFA_TRY(c.pb_tl.ensure(E * sizeof(uint16_t), "slice targets"));
+    DFA_TRY(c.pb_src.ensure(E * sizeof(uint16_t), "slice sources"));
+    DFA_TRY(c.pb_val.ensure(E * sizeof(uint32_t), "slice values"));
+    // run lengths and starts, bucket starts; then the scan's chunk sums and
+    // bucket totals
+    DFA_TRY(c.pb_off.ensure((2 * L + nb + 1) * sizeof(uint32_t), "slice runs"));
+    DFA_TRY(c.pb_partials.ensure((pb_chunk_words(nb, ntiles) + nb) * sizeof(uint32_t),
+                                 "slice scan"));
+    pb.tl = c.pb_tl.as<uint16_t>();
+    pb.src = c.pb_src.as<uint16_t>();
+    pb.val = c.pb_val.as<uint32_t>();
+    pb.cnt = c.pb_off.as<uint32_t>();
+    pb.off = pb.cnt + L;
+    pb.bstart = pb.off + L;
+    pb.nb = nb;
+    pb.ntiles = ntiles;
+    uint32_t *csum = c.pb_partials.as<uint32_t>();
+    launch_pb_build(cols, c.colmap.as<uint32_t>(), N, k_eff, pb, csum,
+                    csum + pb_chunk_words(nb, ntiles), c.stream);
+    HIP_TRY(hipGetLastError());
+    return DFA_OK;
+}
+
 int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq, uint32_t eq_a,
            uint32_t eq_b, bool state_ids, RefineResult &res, const SegArgs *seg = nullptr) {
     res.N = static_cast<uint32_t>(N);
@@ -783,6 +842,9 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     DFA_TRY(c.sig.ensure(N * (k_eff + 1) * sizeof(uint32_t), "signatures"));
     DFA_TRY(c.hash.ensure(N * sizeof(uint64_t), "hashes"));
     const uint32_t grouping = (o.algorithm == DFA_ALGO_SORT && !seg) ? 1u : 0u;
+    // edges bucketed by target slice, for the dense rounds of the first chunk
+    PbArgs pb{};
+    DFA_TRY(build_slices(c, cols, N, k_eff, o, seg != nullptr || res.tc_used, pb));
     if (grouping) {
         const SortPlan pl = sort_plan(N);
         DFA_TRY(c.sort_keys0.ensure(N * sizeof(unsigned long long), "sort keys"));
@@ -825,8 +887,12 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     res.transitions = 0;
     res.bytes = 0;
     bool first = true;
+    bool first_chunk = true;
     for (;;) {
-        const RoundArgs ra = make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second, seg, grouping);
+        RoundArgs ra = make_round_args(c, cols, N, k_eff, cap, o.lds_stage, packed_second, seg, grouping);
+        // the dense rounds come first (the first table rounds); later chunks
+        // gather directly, so a long refinement pays nothing for the passes
+        if (first_chunk) ra.pb = pb;
         if (first) {
             // rounds 0 (and 1) run on their own: label rounds when the
             // signatures are short enough
@@ -846,6 +912,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         // rounds launched so far: the label rounds, then last_round onwards
         const uint32_t next_round = std::max(last_round, res.label_rounds ? res.label_rounds : 1u);
         DFA_TRY(run_chunk(c, ra, mode == DFA_LOOP_HOST ? 1u : chunk, mode, next_round));
+        first_chunk = false;
         DFA_TRY(read_back(c, ctl, sizeof(RoundCtl)));
         std::memcpy(&res.ctl, c.pinned, sizeof(RoundCtl));
         if (c.profiling) DFA_TRY(prof_collect(c, res.ctl));
@@ -2103,7 +2170,8 @@ void for_each_buffer(Ctx &c, F &&f) {
                       &c.sub_acc, &c.sub_block, &c.sort_keys0, &c.sort_keys1, &c.sort_vals0,
                       &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,
                       &c.sort_m, &c.serve_in, &c.small_jobs, &c.small_results,
-                      &c.small_ctl};
+                      &c.small_ctl, &c.pb_tl, &c.pb_src, &c.pb_val, &c.pb_off,
+                      &c.pb_partials};
     for (Buffer *b : bufs) f(*b);
 }
 
@@ -2701,6 +2769,7 @@ void dfa_tuning_default(dfa_tuning *t) {
     t->chunk = 4;
     t->batch_lds_states = 4096;
     t->insert_pair = 1;
+    t->slice_min_states = 1u << 20;
 }
 
 int dfa_get_tuning(dfa_tuning *t) {

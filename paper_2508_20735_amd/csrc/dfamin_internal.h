@@ -79,6 +79,7 @@ struct RoundCtl {
     uint32_t active_hist[kActiveHist];  // states refined by round r, at r % kActiveHist
     uint32_t gain_hist[kActiveHist];    // blocks added by round r, at r % kActiveHist
     uint32_t last_claims;               // blocks formed among the refined states
+    unsigned long long pb_rounds;       // bit r % 64: round r gathered through LDS slices
 };
 
 // ---- launchers (defined in refine_kernels.hip); all enqueue on `s` ----
@@ -163,6 +164,24 @@ struct SortBuffers {
     uint32_t *runhead;            // N: run head position of each sorted element
     uint32_t *m;                  // refined states this round (device)
 };
+// Successor-id gathers by target slices (a full round's gathers, served
+// from LDS).  Edges (state q, letter a) are bucketed once per refinement by
+// the slice of their target (kPbSliceLog bits: a slice's block ids fill a
+// workgroup's LDS); inside bucket b they sit by source tile (kPbTile states),
+// run (b, t) from off[t * nb + b], cnt[t * nb + b] edges long.
+constexpr uint32_t kPbSliceLog = 14;   // 16,384 states: 64 KB of ids in LDS (two workgroups per CU)
+constexpr uint32_t kPbTile = 2048;     // states of a source tile
+constexpr uint32_t kPbMaxBuckets = 1024;  // N <= 2^24
+constexpr uint32_t kPbChunk = 16;      // tiles per step of the run-start scan
+struct PbArgs {
+    uint16_t *tl;    // E: target within its slice
+    uint16_t *src;   // E: (source state - tile start) * k_eff + letter
+    uint32_t *val;   // E: the gathered block ids of the round
+    uint32_t *cnt;     // ntiles * nb run lengths, tile-major
+    uint32_t *off;     // ntiles * nb run starts in the edge list, tile-major
+    uint32_t *bstart;  // nb + 1 bucket starts (the edge list is bucket-major)
+    uint32_t nb, ntiles;  // nb == 0: gathers go directly to HBM
+};
 struct SortPlan {
     uint32_t sort_tiles, compact_tiles, hist_blocks, run_blocks;
     uint64_t hist_words, partial_words;
@@ -204,7 +223,16 @@ struct RoundArgs {
     uint32_t hash_bits;         // 0: full hashes; else only the low bits (collision tests)
     SortBuffers sort;           // grouping == 1
     SegArgs seg;                // nseg == 0: a single automaton
+    PbArgs pb;                  // nb > 0: dense rounds gather through slices in LDS
 };
+// Builds the buckets of PbArgs for the k_eff columns of `cols` (colmap):
+// needs pb.tl / pb.src (E = N * k_eff entries), pb.cnt and pb.off (ntiles *
+// nb each), pb.bstart (nb + 1), and scratch: `csum` (pb_chunk_words(nb,
+// ntiles) words) and `btot` (nb words); k_eff must be 1 to 8 or 16 and
+// N <= kPbMaxBuckets << kPbSliceLog.
+uint64_t pb_chunk_words(uint32_t nb, uint32_t ntiles);
+void launch_pb_build(const uint32_t *cols, const uint32_t *colmap, size_t N, uint32_t k_eff,
+                     const PbArgs &pb, uint32_t *csum, uint32_t *btot, hipStream_t s);
 // Grouping of the round by sorting (grouping == 1), in place of the table
 // kernels.
 void launch_sort_group(const RoundArgs &a, hipStream_t s);
@@ -227,7 +255,11 @@ void launch_ctl_full(RoundCtl *ctl, hipStream_t s);
 // separated, is decided: its states are marked as skipped (singleton bits)
 // and it takes part in no later round.
 void launch_seg_round(const RoundArgs &a, hipStream_t s);
-// The three launches of launch_round, separately (for kernel timing).
+// The launches of launch_round, separately (for kernel timing); the two
+// slice passes launch nothing without bucketed edges (pb.nb == 0) and do
+// nothing in rounds that gather directly.
+void launch_pb_gather(const RoundArgs &a, hipStream_t s);
+void launch_signature_pb(const RoundArgs &a, hipStream_t s);
 void launch_signature(const RoundArgs &a, hipStream_t s);
 void launch_insert(const RoundArgs &a, hipStream_t s);
 void launch_round_end(const RoundArgs &a, hipStream_t s);

@@ -201,6 +201,19 @@ __device__ __forceinline__ bool incremental_round(const RoundCtl &c, size_t N, u
 }
 
 
+// Whether this round's successor-id gathers go through the LDS slices
+// (edges bucketed for this refinement): the rounds that refine nearly every
+// state, i.e. the first table round, and non-incremental rounds with at most
+// three blocks per four states (fewer singletons than that leave too few
+// states to refine for a full pass over the edges).  Uniform over the grid.
+__device__ __forceinline__ bool pb_round(const PbArgs &pb, const RoundCtl &c, size_t N) {
+    if (!pb.nb || c.done) return false;
+    const uint32_t r = c.round;
+    if (r <= c.all_active_until) return true;
+    if (incremental_round(c, N, r)) return false;
+    return 4ull * c.prev_count < 3ull * N;
+}
+
 struct SigParams {
     const uint32_t *cols;
     const uint32_t *colmap;
@@ -226,7 +239,27 @@ struct SigParams {
     unsigned long long *chg_sum;
     uint32_t grouping;  // 1: sort grouping (no claims in the signature kernel)
     uint32_t hash_bits;  // 0: full key hashes; else only the low bits
+    // segmented refinements: the parts, so that a wave inside parts with
+    // fewer letters than k_eff skips the padding letters (nparts 0: none)
+    const Part *parts;
+    const uint32_t *tile_part;
+    uint32_t nparts;
+    PbArgs pb;  // nb > 0: dense rounds gather through LDS slices
 };
+
+// Letters a wave must read: in a segmented refinement, letters at or above
+// the largest alphabet of the parts that hold the wave's states are padding
+// (the identity, whose successor id is the state's own id, the leading
+// component of its key); k_eff otherwise.  Uniform across the wave.
+__device__ __forceinline__ uint32_t wave_letters(const SigParams &p, size_t first, uint32_t keff) {
+    if (!p.nparts || first >= p.N) return keff;
+    const size_t last = first + 63 < p.N ? first + 63 : p.N - 1;
+    uint32_t pi = p.tile_part[first / kBlock];
+    while (static_cast<size_t>(p.parts[pi].off) + p.parts[pi].n <= first) ++pi;
+    uint32_t k = 0;
+    for (; pi < p.nparts && p.parts[pi].off <= last; ++pi) k = k > p.parts[pi].k ? k : p.parts[pi].k;
+    return k < keff ? k : keff;
+}
 
 __device__ __forceinline__ uint64_t limit_hash(uint64_t h, uint32_t bits) {
     return bits ? (h & ((1ull << bits) - 1ull)) : h;
@@ -515,17 +548,23 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
         if constexpr (KC > 0) {
             // unconditional, straight-line loads (a state that needs none
             // reads state 0's): conditional loads sit in branches, across
-            // which the compiler waits for every load in flight
-            uint32_t t[S][KC];
+            // which the compiler waits for every load in flight.  Padding
+            // letters of a segmented refinement (the identity) never make
+            // members of a block differ, so they are not read (kw is uniform
+            // across the wave).
+            uint32_t t[S][KC], kw[S];
+#pragma unroll
+            for (int i = 0; i < S; ++i) kw[i] = wave_letters(p, q[i] - lane_id(), KC);
 #pragma unroll
             for (int i = 0; i < S; ++i)
 #pragma unroll
-                for (int j = 0; j < KC; ++j) t[i][j] = colp.c[j][s[i] ? 0 : q[i]];
+                for (int j = 0; j < KC; ++j) t[i][j] = j < kw[i] ? colp.c[j][s[i] ? 0 : q[i]] : 0u;
 #pragma unroll
             for (int i = 0; i < S; ++i) {
                 bool any = false;
 #pragma unroll
-                for (int j = 0; j < KC; ++j) any |= changed(t[i][j]);
+                for (int j = 0; j < KC; ++j)
+                    if (j < kw[i]) any |= changed(t[i][j]);
                 dirty[i] = !s[i] && any;
             }
         } else {
@@ -558,17 +597,22 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
 // learn whether their block is now a singleton (the marking kernel does this
 // in incremental rounds), and the wave's mask of refined states is stored.
 // Every lane of the wave must call it (ballots).
+// was_active: the state was refined in the previous round.  A state that is
+// refined in neither round already has its id in both block buffers (the
+// round that skipped it first copied it), so it needs no copy now.
 __device__ __forceinline__ bool select_state(const SigParams &p, size_t q, uint32_t w0, uint32_t r,
-                                             bool inc, const unsigned long long *T) {
+                                             bool inc, const unsigned long long *T,
+                                             bool &was_active) {
     const bool valid = q < p.N;
     const size_t first = q - lane_id();
     const size_t wd = first >> 6;
     const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
+    const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
+    was_active = ((aw >> lane_id()) & 1ull) != 0;
     bool s = !valid || ((sw >> lane_id()) & 1ull);
     if (!inc) {
-        const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
         // (a state whose id is another state's index shares its block)
-        if (!s && ((aw >> lane_id()) & 1ull)) s = w0 == q && p.multi[q] != r;
+        if (!s && was_active) s = w0 == q && p.multi[q] != r;
         const unsigned long long nsw = __ballot(s);
         if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
     }
@@ -611,7 +655,7 @@ __device__ __forceinline__ void emit_key(const SigParams &p, uint32_t *__restric
 // KC == 0: runtime k_eff, gathers issued in batches of 8.
 template <int KC>
 __device__ __forceinline__ void signature_body(const SigParams &p) {
-    if (p.ctl->done) return;
+    if (p.ctl->done || pb_round(p.pb, *p.ctl, p.N)) return;
     const uint32_t r = p.ctl->round;
     const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
@@ -645,13 +689,18 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
                     const unsigned long long am = __ballot(act[i]);
                     if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
                 } else {
-                    act[i] = select_state(p, q[i], w0[i], r, inc, T);
+                    bool was;
+                    act[i] = select_state(p, q[i], w0[i], r, inc, T, was);
                     if (q[i] < p.N && !act[i]) {
-                        Y[q[i]] = w0[i];
+                        if (was) Y[q[i]] = w0[i];
                         leaders += w0[i] == q[i] ? 1u : 0u;
                     }
                 }
             }
+            // letters this wave reads for each of its two states (padding
+            // letters of a segmented refinement are the state's own id)
+            const uint32_t kw[2] = {wave_letters(p, q[0] - lane_id(), KC),
+                                    wave_letters(p, q[1] - lane_id(), KC)};
             // waves where most lanes are refined load unconditionally (the
             // others reread the wave's first refined state, lines the wave
             // fetches anyway); sparse waves load per lane
@@ -673,20 +722,22 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < KC; ++j) t[i][j] = colp.c[j][qs[i]];
+                    for (int j = 0; j < KC; ++j) t[i][j] = j < kw[i] ? colp.c[j][qs[i]] : 0u;
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < KC; ++j) w[i][j] = X[t[i][j]];
+                    for (int j = 0; j < KC; ++j) w[i][j] = j < kw[i] ? X[t[i][j]] : w0[i];
             } else {
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < KC; ++j) t[i][j] = act[i] ? colp.c[j][q[i]] : 0u;
+                    for (int j = 0; j < KC; ++j)
+                        t[i][j] = act[i] && j < kw[i] ? colp.c[j][q[i]] : 0u;
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int j = 0; j < KC; ++j) w[i][j] = act[i] ? X[t[i][j]] : 0u;
+                    for (int j = 0; j < KC; ++j)
+                        w[i][j] = act[i] ? (j < kw[i] ? X[t[i][j]] : w0[i]) : 0u;
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -705,9 +756,10 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
                 const unsigned long long am = __ballot(act);
                 if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
             } else {
-                act = select_state(p, q, w0, r, inc, T);
+                bool was;
+                act = select_state(p, q, w0, r, inc, T, was);
                 if (valid && !act) {
-                    Y[q] = w0;
+                    if (was) Y[q] = w0;
                     leaders += w0 == q ? 1u : 0u;
                 }
             }
@@ -739,6 +791,455 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
                 ++claims;
             }
         }
+    }
+    wg_add_spread(p.counters, 0, leaders + claims);
+    wg_add_spread(p.counters, 3, claims);
+}
+
+// ---------------------------------------------------------------- gathers through LDS slices
+//
+// A dense round gathers k_eff block ids per state at random over the whole
+// id array, which runs at the device's random-gather rate (HBM / Infinity
+// Cache lines).  Here the gathers go through LDS instead.  Once per
+// refinement the edges (q, letter) are bucketed by the slice of their target
+// (2^kPbSliceLog states, whose ids fill 64 KB of LDS), and inside a bucket
+// by source tile.  In a dense round, pass A gives each bucket a workgroup
+// that loads its slice of the round's ids into LDS and streams the bucket's
+// edges, writing the gathered id of each edge next to it (coalesced).  Pass B
+// gives each source tile a workgroup that reads its runs from every bucket,
+// places the ids into the tile's keys in LDS, and then does what the
+// signature kernel does with them.  Both passes stream; the only random
+// accesses are to LDS.
+
+// States per thread whose successors are loaded together in the bucketing
+// kernels (a tile holds kPbTile / kBlock = 8 per thread).
+template <int KC>
+constexpr int kPbBatch = KC <= 4 ? 8 : (KC <= 8 ? 4 : 2);
+
+// Edge counts per (tile, bucket), tile-major: cnt[t * nb + b] is the length
+// of tile t's run in bucket b (one coalesced row per tile).
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_pb_count(const uint32_t *cols, const uint32_t *colmap,
+                                                      size_t N, uint32_t nb, uint32_t ntiles,
+                                                      uint32_t *cnt) {
+    __shared__ uint32_t hist[kPbMaxBuckets];
+    const ColPtrs<KC> colp(cols, colmap, N);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0;
+        __syncthreads();
+        const size_t base = static_cast<size_t>(t) * kPbTile;
+        // the loads of a batch of states go out before their atomics
+        for (uint32_t i0 = 0; i0 < kPbTile; i0 += kPbBatch<KC> * kBlock) {
+            uint32_t tg[kPbBatch<KC>][KC];
+#pragma unroll
+            for (int u = 0; u < kPbBatch<KC>; ++u) {
+                const size_t q = base + i0 + u * kBlock + threadIdx.x;
+#pragma unroll
+                for (int a = 0; a < KC; ++a) tg[u][a] = q < N ? colp.c[a][q] : ~0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kPbBatch<KC>; ++u)
+#pragma unroll
+                for (int a = 0; a < KC; ++a)
+                    if (tg[u][a] != ~0u) atomicAdd(hist + (tg[u][a] >> kPbSliceLog), 1u);
+        }
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
+            cnt[static_cast<size_t>(t) * nb + b] = hist[b];
+        __syncthreads();
+    }
+}
+
+// The edge list is bucket-major (bucket b's edges are contiguous, tile by
+// tile), while the counts are tile-major.  The run starts come from a scan
+// down each column of the count matrix, in three coalesced steps: column
+// sums over chunks of kPbChunk tiles, a scan of each column's chunk sums
+// (one wave per bucket) with the bucket totals scanned after it, and the
+// run starts of each chunk's tiles.
+__global__ __launch_bounds__(kBlock) void k_pb_colsum(const uint32_t *cnt, uint32_t nb,
+                                                       uint32_t ntiles, uint32_t *csum) {
+    const uint32_t c = blockIdx.x;
+    const uint32_t t0 = c * kPbChunk;
+    const uint32_t t1 = t0 + kPbChunk < ntiles ? t0 + kPbChunk : ntiles;
+    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
+        uint32_t sum = 0;
+        for (uint32_t t = t0; t < t1; ++t) sum += cnt[static_cast<size_t>(t) * nb + b];
+        csum[static_cast<size_t>(c) * nb + b] = sum;
+    }
+}
+
+// One wave per bucket: exclusive scan of the column's chunk sums in place,
+// and the bucket's edge count into btot[b].
+__global__ __launch_bounds__(kBlock) void k_pb_colscan(uint32_t *csum, uint32_t nb,
+                                                        uint32_t nchunks, uint32_t *btot) {
+    const uint32_t b = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    if (b >= nb) return;  // (uniform across the wave)
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nchunks; c0 += 64) {
+        const uint32_t c = c0 + lane_id();
+        const uint32_t v = c < nchunks ? csum[static_cast<size_t>(c) * nb + b] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane_id() >= static_cast<uint32_t>(d)) x += y;
+        }
+        if (c < nchunks) csum[static_cast<size_t>(c) * nb + b] = carry + x - v;
+        carry += __shfl(x, 63, 64);
+    }
+    if (lane_id() == 0) btot[b] = carry;
+}
+
+// One workgroup of 1024 threads (nb <= 1024): bucket starts, bstart[nb] =
+// the edge count.
+__global__ __launch_bounds__(1024) void k_pb_bscan(const uint32_t *btot, uint32_t nb,
+                                                    uint32_t *bstart) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t i = threadIdx.x;
+    const uint32_t v = i < nb ? btot[i] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane_id() >= static_cast<uint32_t>(d)) x += y;
+    }
+    if (lane_id() == 63) wsum[i / 64] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < i / 64; ++w) before += wsum[w];
+    if (i < nb) bstart[i] = before + x - v;
+    if (i == 1023) bstart[nb] = before + x;
+}
+
+// Run starts, tile-major: off[t * nb + b] = bucket b's start + the chunk's
+// scanned column sum + the runs of the chunk's earlier tiles in bucket b.
+__global__ __launch_bounds__(kBlock) void k_pb_apply(const uint32_t *cnt, const uint32_t *csum,
+                                                      const uint32_t *bstart, uint32_t nb,
+                                                      uint32_t ntiles, uint32_t *off) {
+    const uint32_t c = blockIdx.x;
+    const uint32_t t0 = c * kPbChunk;
+    const uint32_t t1 = t0 + kPbChunk < ntiles ? t0 + kPbChunk : ntiles;
+    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
+        uint32_t run = bstart[b] + csum[static_cast<size_t>(c) * nb + b];
+        for (uint32_t t = t0; t < t1; ++t) {
+            const size_t k = static_cast<size_t>(t) * nb + b;
+            off[k] = run;
+            run += cnt[k];
+        }
+    }
+}
+
+// Tile t's runs into LDS: rbase[b] = the start of its run in bucket b (in
+// the bucketed edge list), rstart[b] = the run's start in the tile's own edge
+// order (the runs back to back, bucket by bucket), rstart[nb] = the tile's
+// edge count.  Ends with a barrier.
+__device__ __forceinline__ void pb_tile_runs(const PbArgs &pb, uint32_t t, uint32_t *rstart,
+                                             uint32_t *rbase, uint32_t *wsum) {
+    const uint32_t tx = threadIdx.x;
+    const size_t row = static_cast<size_t>(t) * pb.nb;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < pb.nb; b0 += kBlock) {
+        const uint32_t b = b0 + tx;
+        uint32_t len = 0;
+        if (b < pb.nb) {
+            rbase[b] = pb.off[row + b];
+            len = pb.cnt[row + b];
+        }
+        uint32_t x = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane_id() >= static_cast<uint32_t>(d)) x += y;
+        }
+        if (lane_id() == 63) wsum[tx / 64] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (uint32_t w = 0; w < tx / 64; ++w) before += wsum[w];
+        if (b < pb.nb) rstart[b] = before + x - len;
+        uint32_t total = carry;
+        for (uint32_t w = 0; w < kBlock / 64; ++w) total += wsum[w];
+        __syncthreads();
+        carry = total;
+    }
+    if (tx == 0) rstart[pb.nb] = carry;
+    __syncthreads();
+}
+
+// Small alphabets (k_eff <= 4: the ids fit beside the tile's keys in LDS):
+// tile t's runs as one id per edge position instead of run starts to search.
+// rid[j] = the run (bucket) holding position j of the tile's edge order,
+// delta[b] = the start of run b in the edge list minus its start in the
+// tile's order (so position j sits at j + delta[rid[j]], modulo 2^32); if
+// lpos is given, lpos[b] = the run's start in the tile's order.  Each run is
+// filled by the thread that scans its length.  Returns the tile's edge
+// count; ends with a barrier.
+__device__ __forceinline__ uint32_t pb_tile_run_ids(const PbArgs &pb, uint32_t t, uint16_t *rid,
+                                                    uint32_t *delta, uint32_t *lpos,
+                                                    uint32_t *wsum, uint32_t *tot) {
+    const uint32_t tx = threadIdx.x;
+    const size_t row = static_cast<size_t>(t) * pb.nb;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < pb.nb; b0 += kBlock) {
+        const uint32_t b = b0 + tx;
+        uint32_t len = 0, at = 0;
+        if (b < pb.nb) {
+            at = pb.off[row + b];
+            len = pb.cnt[row + b];
+        }
+        uint32_t x = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane_id() >= static_cast<uint32_t>(d)) x += y;
+        }
+        if (lane_id() == 63) wsum[tx / 64] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (uint32_t w = 0; w < tx / 64; ++w) before += wsum[w];
+        if (b < pb.nb) {
+            const uint32_t start = before + x - len;
+            delta[b] = at - start;
+            if (lpos) lpos[b] = start;
+            for (uint32_t l = 0; l < len; ++l) rid[start + l] = static_cast<uint16_t>(b);
+        }
+        uint32_t total = carry;
+        for (uint32_t w = 0; w < kBlock / 64; ++w) total += wsum[w];
+        __syncthreads();
+        carry = total;
+    }
+    if (tx == 0) *tot = carry;
+    __syncthreads();
+    return *tot;
+}
+
+// The run holding position j of a tile's edge order (rstart[lo] <= j <
+// rstart[lo + 1]; empty runs are never chosen).
+__device__ __forceinline__ uint32_t pb_run_of(const uint32_t *rstart, uint32_t nb, uint32_t j) {
+    uint32_t lo = 0, hi = nb;  // rstart[lo] <= j < rstart[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (rstart[mid] <= j)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Places every edge of a tile into its run (order inside a run is free: an
+// edge carries its own source slot).  The tile's edges are first sorted by
+// bucket in LDS (its runs laid out back to back), then each run is written
+// out contiguously, so the stores coalesce instead of landing two bytes at a
+// time in hundreds of runs.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_pb_scatter(const uint32_t *cols, const uint32_t *colmap,
+                                                        size_t N, PbArgs pb) {
+    constexpr bool kIds = KC <= 4;
+    __shared__ uint32_t rs[kPbMaxBuckets + 1];           // run starts, or deltas
+    __shared__ uint32_t rb[kIds ? 1 : kPbMaxBuckets];    // run bases (search)
+    __shared__ uint16_t rid[kIds ? kPbTile * KC : 2];    // run ids (small alphabets)
+    __shared__ uint32_t lpos[kPbMaxBuckets];
+    __shared__ uint32_t wsum[kBlock / 64];
+    __shared__ uint32_t tot;
+    __shared__ uint16_t ltl[kPbTile * KC];
+    __shared__ uint16_t lsrc[kPbTile * KC];
+    const uint32_t tx = threadIdx.x;
+    const ColPtrs<KC> colp(cols, colmap, N);
+    for (uint32_t t = blockIdx.x; t < pb.ntiles; t += gridDim.x) {
+        uint32_t total;
+        if constexpr (kIds) {
+            total = pb_tile_run_ids(pb, t, rid, rs, lpos, wsum, &tot);
+        } else {
+            pb_tile_runs(pb, t, rs, rb, wsum);
+            for (uint32_t b = tx; b < pb.nb; b += kBlock) lpos[b] = rs[b];
+            total = rs[pb.nb];
+            __syncthreads();
+        }
+        const size_t base = static_cast<size_t>(t) * kPbTile;
+        // the loads of a batch of states go out before their atomics
+        for (uint32_t i0 = 0; i0 < kPbTile; i0 += kPbBatch<KC> * kBlock) {
+            uint32_t tg[kPbBatch<KC>][KC];
+#pragma unroll
+            for (int u = 0; u < kPbBatch<KC>; ++u) {
+                const size_t q = base + i0 + u * kBlock + tx;
+#pragma unroll
+                for (int a = 0; a < KC; ++a) tg[u][a] = q < N ? colp.c[a][q] : ~0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kPbBatch<KC>; ++u) {
+                const uint32_t i = i0 + u * kBlock + tx;
+#pragma unroll
+                for (int a = 0; a < KC; ++a) {
+                    if (tg[u][a] == ~0u) continue;
+                    const uint32_t e = atomicAdd(lpos + (tg[u][a] >> kPbSliceLog), 1u);
+                    ltl[e] = static_cast<uint16_t>(tg[u][a] & ((1u << kPbSliceLog) - 1u));
+                    lsrc[e] = static_cast<uint16_t>(i * KC + a);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t j = tx; j < total; j += kBlock) {
+            uint32_t e;
+            if constexpr (kIds) {
+                e = j + rs[rid[j]];
+            } else {
+                const uint32_t lo = pb_run_of(rs, pb.nb, j);
+                e = rb[lo] + (j - rs[lo]);
+            }
+            pb.tl[e] = ltl[j];
+            pb.src[e] = lsrc[j];
+        }
+        __syncthreads();
+    }
+}
+
+// Pass A: one or more workgroups per bucket; each loads the bucket's slice of
+// the round's ids into LDS and writes the gathered id of its share of the
+// bucket's edges.
+__global__ __launch_bounds__(kBlock) void k_pb_gather(SigParams p, uint32_t per_bucket) {
+    extern __shared__ uint32_t slice[];
+    if (!pb_round(p.pb, *p.ctl, p.N)) return;
+    const uint32_t r = p.ctl->round;
+    const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
+    const PbArgs &pb = p.pb;
+    constexpr uint32_t S = 1u << kPbSliceLog;
+    // (the round end reads the record only after this kernel has finished)
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        const_cast<RoundCtl *>(p.ctl)->pb_rounds |= 1ull << (r % 64);
+    for (uint32_t job = blockIdx.x; job < pb.nb * per_bucket; job += gridDim.x) {
+        const uint32_t b = job / per_bucket, part = job % per_bucket;
+        const size_t s0 = static_cast<size_t>(b) * S;
+        const uint32_t len = static_cast<uint32_t>(p.N - s0 < S ? p.N - s0 : S);
+        __syncthreads();  // the previous job's gathers are done with the slice
+        for (uint32_t i = threadIdx.x; i < len; i += kBlock) slice[i] = X[s0 + i];
+        __syncthreads();
+        const uint32_t lo = pb.bstart[b], hi = pb.bstart[b + 1];
+        const uint32_t chunk = (hi - lo + per_bucket - 1) / per_bucket;
+        const uint32_t a0 = lo + part * chunk;
+        const uint32_t a1 = a0 + chunk < hi ? a0 + chunk : hi;
+        // four edges per thread with 8-byte target and 16-byte value accesses,
+        // after a scalar head up to a multiple of four
+        const uint32_t al = (a0 + 3u) & ~3u;
+        const uint32_t v0 = al < a1 ? al : a1;
+        for (uint32_t e = a0 + threadIdx.x; e < v0; e += kBlock) pb.val[e] = slice[pb.tl[e]];
+        for (uint32_t e = v0 + 4 * threadIdx.x; e < a1; e += 4 * kBlock) {
+            if (e + 4 <= a1) {
+                const uint2 tv = *reinterpret_cast<const uint2 *>(pb.tl + e);
+                uint4 v;
+                v.x = slice[tv.x & 0xFFFFu];
+                v.y = slice[tv.x >> 16];
+                v.z = slice[tv.y & 0xFFFFu];
+                v.w = slice[tv.y >> 16];
+                *reinterpret_cast<uint4 *>(pb.val + e) = v;
+            } else {
+                for (uint32_t f = e; f < a1; ++f) pb.val[f] = slice[pb.tl[f]];
+            }
+        }
+    }
+}
+
+// Reads tile t's runs from every bucket (one flattened list, each edge's
+// run found by its id, or for wider alphabets by binary search over the run
+// starts) and places the gathered values into key[(state - tile start) * KC
+// + letter].  Ends with a barrier.
+template <int KC>
+struct PbRunsLds {
+    static constexpr bool kIds = KC <= 4;
+    uint32_t rs[kPbMaxBuckets + 1];         // run starts, or deltas
+    uint32_t rb[kIds ? 1 : kPbMaxBuckets];  // run bases (search)
+    uint16_t rid[kIds ? kPbTile * KC : 2];  // run ids (small alphabets)
+    uint32_t wsum[kBlock / 64];
+    uint32_t tot;
+};
+
+template <int KC>
+__device__ __forceinline__ void pb_tile_keys(const PbArgs &pb, uint32_t t, uint32_t *key,
+                                             PbRunsLds<KC> &L) {
+    const uint32_t tx = threadIdx.x;
+    uint32_t total;
+    if constexpr (PbRunsLds<KC>::kIds) {
+        total = pb_tile_run_ids(pb, t, L.rid, L.rs, nullptr, L.wsum, &L.tot);
+    } else {
+        pb_tile_runs(pb, t, L.rs, L.rb, L.wsum);
+        total = L.rs[pb.nb];
+    }
+    // eight edges per thread at a time: every run lookup first, then all
+    // their loads in flight together, then the LDS stores
+    constexpr int B = 8;
+    for (uint32_t j0 = 0; j0 < total; j0 += B * kBlock) {
+        uint32_t e[B];
+        bool ok[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t j = j0 + u * kBlock + tx;
+            ok[u] = j < total;
+            if constexpr (PbRunsLds<KC>::kIds) {
+                e[u] = ok[u] ? j + L.rs[L.rid[j]] : 0u;
+            } else {
+                const uint32_t lo = pb_run_of(L.rs, pb.nb, j);
+                e[u] = ok[u] ? L.rb[lo] + (j - L.rs[lo]) : 0u;
+            }
+        }
+        uint32_t sv[B], vv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            sv[u] = ok[u] ? pb.src[e[u]] : 0u;
+            vv[u] = ok[u] ? pb.val[e[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (ok[u]) key[sv[u]] = vv[u];
+    }
+    __syncthreads();
+}
+
+// Pass B: one workgroup per source tile of kPbTile states: the tile's keys
+// from the buckets, then what the signature kernel does with each state.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_signature_pb(SigParams p) {
+    __shared__ uint32_t key[kPbTile * KC];
+    __shared__ PbRunsLds<KC> runs;
+    if (!pb_round(p.pb, *p.ctl, p.N)) return;
+    const PbArgs &pb = p.pb;
+    const uint32_t r = p.ctl->round;
+    const uint32_t *__restrict__ X = (r & 1u) ? p.blockB : p.blockA;
+    uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
+    const bool all = r <= p.ctl->all_active_until;
+    const bool inc = !all && incremental_round(*p.ctl, p.N, r);
+    const size_t words = (p.N + 63) / 64;
+    const unsigned long long *__restrict__ T = p.touched + (r & 1u) * words;
+    constexpr size_t W = KC + 1;
+    uint32_t leaders = 0, claims = 0;
+    const uint32_t tx = threadIdx.x;
+    for (uint32_t t = blockIdx.x; t < pb.ntiles; t += gridDim.x) {
+        pb_tile_keys<KC>(pb, t, key, runs);
+        const size_t base = static_cast<size_t>(t) * kPbTile;
+        for (uint32_t i = tx; i < kPbTile; i += kBlock) {
+            const size_t q = base + i;
+            // (the whole wave takes part in the ballots below)
+            const uint32_t w0 = q < p.N ? X[q] : 0u;
+            bool act;
+            if (all) {
+                act = q < p.N;
+                const size_t first = q - lane_id();
+                const unsigned long long am = __ballot(act);
+                if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
+            } else {
+                bool was;
+                act = select_state(p, q, w0, r, inc, T, was);
+                if (q < p.N && !act) {
+                    if (was) Y[q] = w0;
+                    leaders += w0 == q ? 1u : 0u;
+                }
+            }
+            if (act) {
+                uint32_t w[KC];
+#pragma unroll
+                for (int a = 0; a < KC; ++a) w[a] = key[i * KC + a];
+                emit_key(p, Y, q, w0, w, KC, W, !all && p.grouping == 0, claims);
+            }
+        }
+        __syncthreads();  // the keys are done with before the next tile
     }
     wg_add_spread(p.counters, 0, leaders + claims);
     wg_add_spread(p.counters, 3, claims);
@@ -1593,7 +2094,9 @@ SigParams sig_params(const RoundArgs &a) {
                      a.blockB,   a.sig,        a.hash,     a.table,    a.table_cap,
                      a.multi,    a.active,     a.accbits,  a.presence, a.presence_packed,
                      a.lab8,     a.counters,   a.ctl,      a.cached_probe, a.chg,
-                     a.single,   a.touched,    a.chg_sum,  a.grouping, a.hash_bits};
+                     a.single,   a.touched,    a.chg_sum,  a.grouping, a.hash_bits,
+                     a.seg.nseg ? a.seg.parts : nullptr,      a.seg.nseg ? a.seg.tile_part : nullptr,
+                     a.seg.nseg ? a.seg.nparts : 0u, a.pb};
 }
 
 // Workgroups of a round kernel whose workgroups take `tile` states at a
@@ -1741,6 +2244,76 @@ void launch_signature(const RoundArgs &a, hipStream_t s) {
     }
 }
 
+// ---- gathers through LDS slices
+
+uint64_t pb_chunk_words(uint32_t nb, uint32_t ntiles) {
+    return static_cast<uint64_t>((ntiles + kPbChunk - 1) / kPbChunk) * nb;
+}
+
+namespace {
+
+template <int KC>
+void pb_build_k(const uint32_t *cols, const uint32_t *colmap, size_t N, const PbArgs &pb,
+                uint32_t *csum, uint32_t *btot, hipStream_t s) {
+    const dim3 tiles(std::min<uint32_t>(pb.ntiles, 8192u)), block(kBlock);
+    const uint32_t nchunks = (pb.ntiles + kPbChunk - 1) / kPbChunk;
+    launch_kernel(k_pb_count<KC>, tiles, block, 0, s, cols, colmap, N, pb.nb, pb.ntiles, pb.cnt);
+    launch_kernel(k_pb_colsum, dim3(nchunks), block, 0, s, pb.cnt, pb.nb, pb.ntiles, csum);
+    launch_kernel(k_pb_colscan, dim3((pb.nb + kBlock / 64 - 1) / (kBlock / 64)), block, 0, s,
+                  csum, pb.nb, nchunks, btot);
+    launch_kernel(k_pb_bscan, dim3(1), dim3(1024), 0, s, btot, pb.nb, pb.bstart);
+    launch_kernel(k_pb_apply, dim3(nchunks), block, 0, s, pb.cnt, csum, pb.bstart, pb.nb,
+                  pb.ntiles, pb.off);
+    launch_kernel(k_pb_scatter<KC>, tiles, block, 0, s, cols, colmap, N, pb);
+}
+
+}  // namespace
+
+void launch_pb_build(const uint32_t *cols, const uint32_t *colmap, size_t N, uint32_t k_eff,
+                     const PbArgs &pb, uint32_t *csum, uint32_t *btot, hipStream_t s) {
+    switch (k_eff) {
+        case 1: pb_build_k<1>(cols, colmap, N, pb, csum, btot, s); break;
+        case 2: pb_build_k<2>(cols, colmap, N, pb, csum, btot, s); break;
+        case 3: pb_build_k<3>(cols, colmap, N, pb, csum, btot, s); break;
+        case 4: pb_build_k<4>(cols, colmap, N, pb, csum, btot, s); break;
+        case 5: pb_build_k<5>(cols, colmap, N, pb, csum, btot, s); break;
+        case 6: pb_build_k<6>(cols, colmap, N, pb, csum, btot, s); break;
+        case 7: pb_build_k<7>(cols, colmap, N, pb, csum, btot, s); break;
+        case 8: pb_build_k<8>(cols, colmap, N, pb, csum, btot, s); break;
+        case 16: pb_build_k<16>(cols, colmap, N, pb, csum, btot, s); break;
+        default: break;  // the host only buckets these widths
+    }
+}
+
+void launch_pb_gather(const RoundArgs &a, hipStream_t s) {
+    if (!a.pb.nb) return;
+    const SigParams sp = sig_params(a);
+    // one workgroup per bucket (measured on MI355X with 2^23 states: one
+    // 64 KB slice per workgroup gathered 364 G ids/s; two or four workgroups
+    // per bucket, each loading the slice, 305 and 229; 128 KB slices 199)
+    const uint32_t per_bucket = 1u;
+    launch_kernel(k_pb_gather, dim3(a.pb.nb * per_bucket), dim3(kBlock),
+                  (1u << kPbSliceLog) * 4u, s, sp, per_bucket);
+}
+
+void launch_signature_pb(const RoundArgs &a, hipStream_t s) {
+    if (!a.pb.nb) return;
+    const SigParams sp = sig_params(a);
+    const dim3 grid(a.pb.ntiles), block(kBlock);
+    switch (a.k_eff) {
+        case 1: launch_kernel(k_signature_pb<1>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_signature_pb<2>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_signature_pb<3>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_signature_pb<4>, grid, block, 0, s, sp); break;
+        case 5: launch_kernel(k_signature_pb<5>, grid, block, 0, s, sp); break;
+        case 6: launch_kernel(k_signature_pb<6>, grid, block, 0, s, sp); break;
+        case 7: launch_kernel(k_signature_pb<7>, grid, block, 0, s, sp); break;
+        case 8: launch_kernel(k_signature_pb<8>, grid, block, 0, s, sp); break;
+        case 16: launch_kernel(k_signature_pb<16>, grid, block, 0, s, sp); break;
+        default: break;
+    }
+}
+
 void launch_insert(const RoundArgs &a, hipStream_t s) {
     const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
     const InsParams ip = ins_params(a);
@@ -1782,6 +2355,8 @@ void launch_ctl_full(RoundCtl *ctl, hipStream_t s) {
 
 void launch_round(const RoundArgs &a, hipStream_t s) {
     launch_mark(a, s);
+    launch_pb_gather(a, s);
+    launch_signature_pb(a, s);
     launch_signature(a, s);
     if (a.grouping)
         launch_sort_group(a, s);
