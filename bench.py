@@ -78,6 +78,11 @@ def parse_args():
     return ap.parse_args()
 
 
+def note(msg: str) -> None:
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def traffic_for(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None when it is missing or the kernels changed since it was taken."""
@@ -88,7 +93,7 @@ def traffic_for(kernel: str):
         return None
     if t.get("kernel_source_sha1") != kernel_source_digest():
         return None
-    entry = t.get("kernels", {}).get(kernel)
+    entry = t.get("library_kernels", {}).get(kernel)
     if not entry:
         return None
     return entry.get("hbm_bytes_per_launch")
@@ -274,12 +279,50 @@ def batch_leg(B, W, torch, np, count: int) -> dict:
     tp = time.perf_counter() - t0
     if list(vb) != list(vp):
         raise RuntimeError("batched and plain equivalence verdicts differ")
-    return {"workload": f"{count} random DFAs, n log-uniform [64, 65536], k in 2..8, "
-                        f"{len(pairs)} equivalence pairs",
-            "states": total, "batched_ms": tb * 1e3, "plain_ms": tp * 1e3,
-            "speedup": tp / tb,
-            "batched_transitions_per_s": work_b / tb,
-            "plain_transitions_per_s": work_p / tp}
+    leg = {"workload": f"{count} random DFAs, n log-uniform [64, 65536], k in 2..8, "
+                       f"{len(pairs)} equivalence pairs",
+           "states": total, "batched_ms": tb * 1e3, "plain_ms": tp * 1e3,
+           "speedup": tp / tb,
+           "batched_transitions_per_s": work_b / tb,
+           "plain_transitions_per_s": work_p / tp}
+    leg["autotuned"] = autotuned_batch(B, torch, A, pairs, batched=batched, plain_s=tp)
+    return leg
+
+
+def autotuned_batch(B, torch, A, pairs, batched, plain_s) -> dict:
+    """The same batch under the tuning the package's autotuner picks for it
+    (coordinate descent over the batch tuning on this workload, a scratch
+    cache file), timed like the default one; the default tuning is restored
+    afterwards."""
+    import tempfile
+
+    from paper_2508_20735_amd import autotune as T
+    before = B.get_tuning()
+    space = {"batch_lds_states": [0, 2048, 4096, 8192], "round_grid_cap": [4096, 8192, 16384],
+             "chunk": [4, 8, 16]}
+    try:
+        with tempfile.TemporaryDirectory() as tmp:
+            res = T.autotune_batch([a[0] for a in A], [a[1] for a in A],
+                                   pairs=([A[i] for i, _ in pairs], [p for _, p in pairs]),
+                                   space=space, reps=2, path=os.path.join(tmp, "tuning.json"))
+        tunings = list(res.values())
+        # the minimisation's tuning for the whole step (the equivalence search
+        # starts from it and may move further)
+        B.set_tuning(**tunings[0]["tuning"])
+        batched()
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            work, _v = batched()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        return {"tuning": tunings[0]["tuning"], "searched": space,
+                "per_shape_device_ms": {k: v["device_ms"] for k, v in res.items()},
+                "batched_ms": t * 1e3, "speedup": plain_s / t,
+                "batched_transitions_per_s": work / t}
+    finally:
+        B.set_tuning(**before)
 
 
 def variants_leg(B, W, torch, np, dev, A_d, A_a, n, pairs) -> dict:
@@ -579,7 +622,7 @@ def main() -> int:
     args = parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent DFAs would shard one queue per GPU)", file=sys.stderr)
         return 2
 
@@ -632,6 +675,7 @@ def main() -> int:
                 + s2["transitions_refined"])
         return work, (r.stats, s1, s2, e2)
 
+    note("timed step")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -708,6 +752,7 @@ def main() -> int:
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom),
             "avg_launch_us": avg_s * 1e6, "launches": kd["launches"],
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "refined_states_per_s": kd["states"] / (kd["total_ms"] / 1e3),
         }
         if dom == "k_signature":
             # the kernel gathers k block ids per refined state: its rate of
@@ -727,6 +772,18 @@ def main() -> int:
                          "gathers); full-round launches in the kernel trace run at the "
                          "reference rate"),
             }
+        pbg = kernels.get("k_pb_gather")
+        if pbg and pbg["total_ms"] > 0 and pbg["state_letters"]:
+            # the dense rounds' successor-id gathers, served from slices of
+            # the id array held in LDS (edges bucketed by target slice)
+            out["slice_gather"] = {
+                "kernel": "k_pb_gather", "launches": pbg["launches"],
+                "achieved": pbg["state_letters"] / (pbg["total_ms"] / 1e3) / 1e9,
+                "unit": "G gathers/s",
+                "note": ("gathers of the rounds that took the slice path over the pass's "
+                         "time in the profiled steps (its no-op launches in other rounds "
+                         "included)"),
+            }
         out["kernels_profiled_steps"] = args.profile_steps
         out["kernels"] = {
             k: {"launches": v["launches"], "avg_us": v["total_ms"] / v["launches"] * 1e3,
@@ -735,22 +792,30 @@ def main() -> int:
                                      if v["total_ms"] else 0.0)}
             for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["total_ms"])}
     if not args.no_batch:
+        note("batched leg")
         out["batched"] = batch_leg(B, W, torch, np, args.batch_count)
     if not args.no_serve:
+        note("served leg")
         out["served"] = serve_leg(B, W, args.serve_requests)
     if not args.no_variants:
+        note("variants leg")
         out["variants"] = variants_leg(B, W, torch, np, dev, A_d, A_a, d.n,
                                        {"permuted": (d.start, P_d, P_a, perm.start),
                                         "mutated": (d.start, M_d, M_a, mut.start)})
     if not args.no_host_path:
+        note("host-path leg")
         out["host_path"] = host_path_leg(B, np, d, perm, mut)
     if not args.no_table2:
+        note("Table 2 leg")
         out["table2"] = table2_leg(B, W, torch, np, dev)
     if not args.no_products:
+        note("products leg")
         out["products"] = product_leg(B, W, torch, np, dev)
     if not args.no_chain:
+        note("chain leg")
         out["chain"] = chain_leg(B, W, torch, np, dev, plain=not args.no_chain_plain)
     if not args.no_cpu_baseline:
+        note("CPU baseline")
         out["cpu_baseline"] = cpu_baseline(W, d, perm)
     print(json.dumps(out), flush=True)
     return 0

@@ -24,8 +24,13 @@ import re
 import sys
 from collections import defaultdict
 
-ROUND_KERNELS = ("k_mark", "k_signature", "k_insert", "k_insert_lds", "k_round_end",
-                 "k_pattern_round", "k_packed_round")
+ROUND_KERNELS = ("k_mark", "k_signature", "k_insert", "k_insert_lds", "k_insert_lds2",
+                 "k_round_end", "k_pattern_round", "k_packed_round", "k_pb_gather",
+                 "k_signature_pb", "k_pb_count", "k_pb_scatter")
+# The library's per-kernel timing names a launch of the grouping step
+# "k_insert": one dispatch of an LDS-staged variant and one of the plain
+# kernel, of which exactly one does the round's work.
+LIBRARY_GROUPS = {"k_insert": ("k_insert_lds2", "k_insert_lds", "k_insert")}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -114,6 +119,24 @@ def traffic(fetch_dir: str, write_dir: str, copy_bytes: int) -> dict:
         out["kernels"][b] = {"launches": len(fv), "fetch_bytes_per_launch": f_avg,
                              "write_bytes_per_launch": w_avg,
                              "hbm_bytes_per_launch": f_avg + w_avg}
+    # per launch under the library's timing names (bench.py's "kernel")
+    lib = {}
+    for b, e in out["kernels"].items():
+        if not any(b in members for members in LIBRARY_GROUPS.values()):
+            lib[b] = dict(e)
+    for name, members in LIBRARY_GROUPS.items():
+        parts = [out["kernels"][m] for m in members if m in out["kernels"]]
+        if not parts:
+            continue
+        launches = max(p["launches"] for p in parts)
+        f_tot = sum(p["fetch_bytes_per_launch"] * p["launches"] for p in parts)
+        w_tot = sum(p["write_bytes_per_launch"] * p["launches"] for p in parts)
+        lib[name] = {"launches": launches, "fetch_bytes_per_launch": f_tot / launches,
+                     "write_bytes_per_launch": w_tot / launches,
+                     "hbm_bytes_per_launch": (f_tot + w_tot) / launches,
+                     "dispatches": {m: out["kernels"][m]["launches"]
+                                    for m in members if m in out["kernels"]}}
+    out["library_kernels"] = lib
     return out
 
 

@@ -79,12 +79,16 @@ def test_slices_on_unions(tuning_restore):
     assert B.equivalent(d, perm, tc="off")[0]
     want = oracle.equiv_hk(d.delta, d.accepting, d.start, mut.delta, mut.accepting, mut.start)
     assert B.equivalent(d, mut, tc="off")[0] == want
-    # the union's partition itself, through the minimisation of the union
-    ud, ua = oracle.union(d.delta, d.accepting, perm.delta, perm.accepting)
-    ref, nb, rounds, changing = oracle.moore(ud, ua)
-    res = B.minimise(ud, ua, tc="off")
-    np.testing.assert_array_equal(res.block, ref)
-    assert res.stats["rounds"] == rounds
+    # the unions' partitions themselves, through their minimisation: with the
+    # mutated copy, separations spread back from the mutation over many
+    # incremental rounds after the dense ones
+    for other in (perm, mut):
+        ud, ua = oracle.union(d.delta, d.accepting, other.delta, other.accepting)
+        ref, nb, rounds, changing = oracle.moore(ud, ua)
+        for loop in ("chunk", "graph", "host"):
+            res = B.minimise(ud, ua, tc="off", loop=loop)
+            np.testing.assert_array_equal(res.block, ref)
+            assert res.stats["rounds"] == rounds and res.stats["changing_rounds"] == changing
 
 
 def test_slices_kernel_timing_charges_one_path(tuning_restore):
