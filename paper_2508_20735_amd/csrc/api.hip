@@ -203,6 +203,7 @@ struct Ctx {
     Buffer parts, tile_part, seg_words, batch_in, batch_out;
     Buffer small_jobs, small_results, small_ctl;  // batched small DFAs (one workgroup each)
     Buffer pb_tl, pb_src, pb_val, pb_off, pb_partials;  // edges bucketed by target slice
+    Buffer segpat_table, segpat;  // round 0 of segmented refinements by acceptance patterns
     Arena arena;  // the allocation-free context's fixed workspace (unused elsewhere)
     uint8_t *pinned_batch = nullptr;  // host staging of batched inputs/outputs
     uint8_t *ring[2] = {nullptr, nullptr};  // page-locked chunks for large host copies
@@ -357,7 +358,7 @@ int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
 
 enum class Kern {
     Mark, Signature, Insert, SortGroup, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove,
-    LeaderEnd, PbGather, SignaturePb
+    LeaderEnd, PbGather, SignaturePb, SegPattern
 };
 
 int prof_event(Ctx &c, size_t &idx) {
@@ -376,7 +377,8 @@ int prof_event(Ctx &c, size_t &idx) {
 //              charged to the gather pass (4k) and the rest (4k + 4) to the
 //              signature pass
 //   insert     4 (the new block id)
-//   pattern    4k (columns) + (k + 1) (acceptance of q and successors) + 4 (label)
+//   pattern    4k (columns) + (k + 1) (acceptance of q and successors) + 4 (label);
+//              the same for round 0 of a segmented refinement by patterns
 //   packed     4k (columns) + (k + 1) (byte labels) + 4 (label)
 //   elect      per compared (non-leader) state: 4k (own columns) + 4k (the
 //              leader's columns) + 8k (the two successor ids per letter)
@@ -387,7 +389,8 @@ uint32_t kern_bytes(Kern kind, uint32_t k_eff) {
         case Kern::SignaturePb: return 4 * k_eff + 4;
         case Kern::Insert: return 4;
         case Kern::Pattern:
-        case Kern::Packed: return 5 * k_eff + 5;
+        case Kern::Packed:
+        case Kern::SegPattern: return 5 * k_eff + 5;
         case Kern::LeaderElect: return 16 * k_eff;
         default: return 0;
     }
@@ -405,6 +408,7 @@ const char *kern_name(Kern kind) {
         case Kern::LeaderElect: return "k_leader_elect";
         case Kern::LeaderMove: return "k_leader_move";
         case Kern::PbGather: return "k_pb_gather";
+        case Kern::SegPattern: return "k_seg_pattern";
         case Kern::SignaturePb: return "k_signature_pb";
         default: return "k_leader_end";
     }
@@ -424,6 +428,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
             case Kern::Mark: launch_mark(a, c.stream); break;
             case Kern::Signature: launch_signature(a, c.stream); break;
             case Kern::PbGather: launch_pb_gather(a, c.stream); break;
+            case Kern::SegPattern: launch_seg_pattern(a, c.stream); break;
             case Kern::SignaturePb: launch_signature_pb(a, c.stream); break;
             case Kern::Insert: launch_insert(a, c.stream); break;
             case Kern::SortGroup: launch_sort_group(a, c.stream); break;
@@ -875,6 +880,18 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         }
     }
     res.label_rounds = pattern_first + packed_second;
+    // segmented refinements: round 0 by acceptance patterns when the keys of
+    // all segments fit the pattern table
+    const uint32_t segpat_bits = k_eff + 1;
+    const bool segpat = seg && c.tune.label_rounds >= 1 && !grouping && !res.tc_used &&
+                        segpat_bits <= kSegPatMaxBits &&
+                        (static_cast<uint64_t>(seg->nseg) << segpat_bits) <= kSegPatMaxWords;
+    if (segpat) {
+        DFA_TRY(c.segpat_table.ensure((static_cast<size_t>(seg->nseg) << segpat_bits) *
+                                          sizeof(uint32_t),
+                                      "pattern table"));
+        DFA_TRY(c.segpat.ensure(N * sizeof(uint16_t), "patterns"));
+    }
     launch_ctl_reset(ctl, c.flags.as<uint32_t>() + kFlagClass, o.max_rounds, check_eq, eq_a, eq_b,
                      pattern_first, packed_second, seg ? seg->init_count : nullptr, c.stream);
 
@@ -893,11 +910,21 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         // the dense rounds come first (the first table rounds); later chunks
         // gather directly, so a long refinement pays nothing for the passes
         if (first_chunk) ra.pb = pb;
+        if (segpat && first) {
+            ra.segpat_table = c.segpat_table.as<uint32_t>();
+            ra.segpat = c.segpat.as<uint16_t>();
+            ra.segpat_bits = segpat_bits;
+        }
         if (first) {
             // rounds 0 (and 1) run on their own: label rounds when the
             // signatures are short enough
             if (pattern_first) {
                 DFA_TRY(launch_kern(c, Kern::Pattern, ra, 0));
+                DFA_TRY(launch_kern(c, Kern::RoundEnd, ra, 0));
+            } else if (ra.segpat_bits) {
+                DFA_TRY(launch_kern(c, Kern::Mark, ra, 0));
+                DFA_TRY(launch_kern(c, Kern::SegPattern, ra, 0));
+                launch_seg_round(ra, c.stream);
                 DFA_TRY(launch_kern(c, Kern::RoundEnd, ra, 0));
             } else {
                 DFA_TRY(launch_full_round(c, ra, 0));
@@ -1662,7 +1689,7 @@ int refine_segments(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, bool 
     uint32_t *flags = c.flags.as<uint32_t>();
     launch_ingest_parts(g, N, kmax, c.cols.as<uint32_t>(), flags + kFlagErr, flags + kFlagNonid,
                         c.stream);
-    launch_init_parts(g, N, c.blockA.as<uint32_t>(), c.stream);
+    launch_init_parts(g, N, c.blockA.as<uint32_t>(), c.accbits.as<unsigned long long>(), c.stream);
     HIP_TRY(hipGetLastError());
     dfa_options ob = o;
     if (ob.tc_mode == DFA_TC_AUTO) ob.tc_mode = DFA_TC_OFF;  // no closure on demand in batches
@@ -2171,7 +2198,7 @@ void for_each_buffer(Ctx &c, F &&f) {
                       &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,
                       &c.sort_m, &c.serve_in, &c.small_jobs, &c.small_results,
                       &c.small_ctl, &c.pb_tl, &c.pb_src, &c.pb_val, &c.pb_off,
-                      &c.pb_partials};
+                      &c.pb_partials, &c.segpat_table, &c.segpat};
     for (Buffer *b : bufs) f(*b);
 }
 

@@ -145,8 +145,10 @@ struct SegArgs {
 // state; letters >= part.k become the identity); err / nonid as launch_ingest.
 void launch_ingest_parts(const SegArgs &g, size_t N, uint32_t k, uint32_t *cols, uint32_t *err,
                          uint32_t *nonid, hipStream_t s);
-// Initial labels 2 * seg + accepting, per-segment classes, their total.
-void launch_init_parts(const SegArgs &g, size_t N, uint32_t *block, hipStream_t s);
+// Initial labels 2 * seg + accepting, acceptance bits (accbits, N/64 words),
+// per-segment classes, their total.
+void launch_init_parts(const SegArgs &g, size_t N, uint32_t *block, unsigned long long *accbits,
+                       hipStream_t s);
 // Writes every part's canonical block ids (local: global id - part offset)
 // to out + part.out.
 void launch_part_output(const SegArgs &g, size_t N, const uint32_t *canon, uint32_t *out,
@@ -224,7 +226,21 @@ struct RoundArgs {
     SortBuffers sort;           // grouping == 1
     SegArgs seg;                // nseg == 0: a single automaton
     PbArgs pb;                  // nb > 0: dense rounds gather through slices in LDS
+    // segmented refinements: round 0 by acceptance patterns (segpat_bits =
+    // k_eff + 1 > 0), with a table of nseg << segpat_bits words and one
+    // pattern per state
+    uint32_t *segpat_table;
+    uint16_t *segpat;
+    uint32_t segpat_bits;
 };
+// Largest pattern width (bits) and table (words) of the segmented pattern
+// round.
+constexpr uint32_t kSegPatMaxBits = 16;
+constexpr uint64_t kSegPatMaxWords = 1ull << 24;
+// Round 0 of a segmented refinement without the table: every state's key is
+// its segment and the acceptance of itself and its successors, and each key
+// takes its smallest state as the block id (segpat_bits > 0).
+void launch_seg_pattern(const RoundArgs &a, hipStream_t s);
 // Builds the buckets of PbArgs for the k_eff columns of `cols` (colmap):
 // needs pb.tl / pb.src (E = N * k_eff entries), pb.cnt and pb.off (ntiles *
 // nb each), pb.bstart (nb + 1), and scratch: `csum` (pb_chunk_words(nb,

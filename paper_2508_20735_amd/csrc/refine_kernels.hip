@@ -1734,7 +1734,8 @@ __global__ __launch_bounds__(kBlock) void k_ingest_parts(SegArgs g, size_t N, ui
 // spans at most kBlock segments), then OR-ed into seg_flags once per tile and
 // segment: per-state atomics on one word per segment serialised.
 __global__ __launch_bounds__(kBlock) void k_init_parts(SegArgs g, size_t N,
-                                                        uint32_t *__restrict__ block) {
+                                                        uint32_t *__restrict__ block,
+                                                        unsigned long long *accbits) {
     __shared__ uint32_t lflag[kBlock];
     __shared__ uint32_t seg_first;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < N;
@@ -1743,17 +1744,127 @@ __global__ __launch_bounds__(kBlock) void k_init_parts(SegArgs g, size_t N,
         if (threadIdx.x == 0) seg_first = g.parts[g.tile_part[base / kBlock]].seg;
         __syncthreads();
         const size_t q = base + threadIdx.x;
+        bool f = false;
         if (q < N) {
             const Part P = g.parts[find_part(g, q)];
-            const bool f = P.accepting[q - P.off] != 0;
+            f = P.accepting[q - P.off] != 0;
             block[q] = 2u * P.seg + (f ? 1u : 0u);
             atomicOr(lflag + (P.seg - seg_first), f ? 1u : 2u);
         }
+        const unsigned long long fm = __ballot(f);
+        if (lane_id() == 0 && q < N) accbits[q >> 6] = fm;
         __syncthreads();
         const uint32_t m = lflag[threadIdx.x];
         if (m) atomicOr(g.seg_flags + seg_first + threadIdx.x, m);
         __syncthreads();
     }
+}
+
+// Round 0 of a segmented refinement refines the initial labels 2 * segment
+// + accepting, so a state's key is its segment and the acceptance of the
+// state and of each successor (section 3.3, the first signature round): at
+// most 2^(k_eff + 1) keys per segment.  They index a table of nseg <<
+// (k_eff + 1) words in which each key keeps its smallest state (LDS minimum
+// per workgroup, then one atomicMin per key present in the workgroup); that
+// state becomes the block id of every state with the key.  The ids are then
+// state indices with the same partition as a table round's, so the rounds
+// after it run unchanged.  A padding letter of a part (the identity) gives
+// the state's own acceptance without a load.
+constexpr uint32_t kSegPatTile = 4 * kBlock;   // states per workgroup step
+constexpr uint32_t kSegPatLds = 4096;          // keys kept in LDS per step
+
+__global__ __launch_bounds__(kBlock) void k_segpat_min(SigParams p, SegArgs g,
+                                                        uint32_t *table, uint16_t *pat,
+                                                        uint32_t bits) {
+    __shared__ uint32_t lmin[kSegPatLds];
+    __shared__ uint32_t seg_first;
+    if (p.ctl->done || p.ctl->round != 0) return;
+    const size_t nkeys = static_cast<size_t>(g.nseg) << bits;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kSegPatTile; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kSegPatTile) {
+        for (uint32_t i = threadIdx.x; i < kSegPatLds; i += kBlock) lmin[i] = ~0u;
+        if (threadIdx.x == 0) seg_first = g.parts[g.tile_part[base / kBlock]].seg;
+        __syncthreads();
+        for (uint32_t u = 0; u < kSegPatTile / kBlock; ++u) {
+            const size_t q = base + u * kBlock + threadIdx.x;
+            if (q >= p.N) break;
+            const Part P = g.parts[find_part(g, q)];
+            const uint32_t own = static_cast<uint32_t>((p.accbits[q >> 6] >> (q & 63)) & 1ull);
+            uint32_t key = own;
+            // eight letters' loads at a time, then their acceptance bits
+            for (uint32_t a0 = 0; a0 < p.k_eff; a0 += 8) {
+                uint32_t t[8];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) {
+                    const uint32_t a = a0 + j;
+                    t[j] = (a < p.k_eff && p.colmap[a] < P.k)
+                               ? p.cols[static_cast<size_t>(p.colmap[a]) * p.N + q]
+                               : static_cast<uint32_t>(q);
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) {
+                    const uint32_t a = a0 + j;
+                    if (a >= p.k_eff) break;
+                    const uint32_t bit =
+                        t[j] == q ? own
+                                  : static_cast<uint32_t>((p.accbits[t[j] >> 6] >> (t[j] & 63)) & 1ull);
+                    key |= bit << (a + 1);
+                }
+            }
+            pat[q] = static_cast<uint16_t>(key);
+            const size_t local = (static_cast<size_t>(P.seg - seg_first) << bits) | key;
+            if (local < kSegPatLds)
+                atomicMin(lmin + local, static_cast<uint32_t>(q));
+            else
+                atomicMin(table + ((static_cast<size_t>(P.seg) << bits) | key),
+                          static_cast<uint32_t>(q));
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kSegPatLds; i += kBlock) {
+            const size_t k = (static_cast<size_t>(seg_first) << bits) + i;
+            if (lmin[i] != ~0u && k < nkeys) atomicMin(table + k, lmin[i]);
+        }
+        __syncthreads();
+    }
+}
+
+// Every state takes its key's smallest state as its block id; the round's
+// bookkeeping as the grouping kernels do it (refined-state masks, block
+// marks, changed-id bits and summary, the spread counters).
+__global__ __launch_bounds__(kBlock) void k_segpat_assign(SigParams p, SegArgs g,
+                                                           const uint32_t *table,
+                                                           const uint16_t *pat, uint32_t bits,
+                                                           uint32_t *multi) {
+    if (p.ctl->done || p.ctl->round != 0) return;
+    const uint32_t r = 0;
+    const uint32_t *__restrict__ X = p.blockA;
+    uint32_t *__restrict__ Y = p.blockB;
+    uint32_t blocks = 0, changed = 0;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
+         base += static_cast<size_t>(gridDim.x) * kBlock) {
+        const size_t q = base + threadIdx.x;
+        const bool valid = q < p.N;
+        bool ch = false;
+        if (valid) {
+            const uint32_t seg = g.parts[find_part(g, q)].seg;
+            const uint32_t id = table[(static_cast<size_t>(seg) << bits) | pat[q]];
+            Y[q] = id;
+            if (id == q)
+                ++blocks;
+            else
+                mark_multi(multi, id, r + 1);
+            ch = id != X[q];
+            changed += ch ? 1u : 0u;
+        }
+        const size_t first = q - lane_id();
+        const unsigned long long am = __ballot(valid);
+        if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
+        const unsigned long long cm = __ballot(ch);
+        store_changed(p.chg, p.chg_sum, p.N, r, first, cm);
+    }
+    wg_add_spread(p.counters, 0, blocks);
+    wg_add_spread(p.counters, 2, changed);
+    wg_add_spread(p.counters, 3, blocks);
 }
 
 // seg_prev[s] = classes of segment s; *init_count = their sum.
@@ -2156,10 +2267,25 @@ void launch_ingest_parts(const SegArgs &g, size_t N, uint32_t k, uint32_t *cols,
                        N, k, cols, err, nonid);
 }
 
-void launch_init_parts(const SegArgs &g, size_t N, uint32_t *block, hipStream_t s) {
+void launch_init_parts(const SegArgs &g, size_t N, uint32_t *block, unsigned long long *accbits,
+                       hipStream_t s) {
     launch_kernel(k_init_parts, dim3(grid_for(N, kDefaultGridCap)), dim3(kBlock), 0, s, g, N,
-                       block);
+                  block, accbits);
     launch_kernel(k_seg_init, dim3(grid_for(g.nseg, kDefaultGridCap)), dim3(kBlock), 0, s, g);
+}
+
+void launch_seg_pattern(const RoundArgs &a, hipStream_t s) {
+    if (!a.segpat_bits) return;
+    const SigParams sp = sig_params(a);
+    const size_t words = static_cast<size_t>(a.seg.nseg) << a.segpat_bits;
+    launch_kernel(k_fill_u32, dim3(grid_for(words, kDefaultGridCap)), dim3(kBlock), 0, s,
+                  a.segpat_table, words, ~0u);
+    launch_kernel(k_segpat_min, dim3(grid_for((a.N + kSegPatTile - 1) / kSegPatTile * kBlock,
+                                              kDefaultGridCap)),
+                  dim3(kBlock), 0, s, sp, a.seg, a.segpat_table, a.segpat, a.segpat_bits);
+    launch_kernel(k_segpat_assign, dim3(grid_for(a.N, kDefaultGridCap)), dim3(kBlock), 0, s, sp,
+                  a.seg, static_cast<const uint32_t *>(a.segpat_table),
+                  static_cast<const uint16_t *>(a.segpat), a.segpat_bits, a.multi);
 }
 
 void launch_seg_round(const RoundArgs &a, hipStream_t s) {
