@@ -96,9 +96,9 @@ extern "C" {
                                  the rounds on the device, its phases separated by grid
                                  barriers, and stops as soon as the partition is stable
                                  (the while-loop of Algorithms 2 and 4, Section 3, kept
-                                 on the device).  Single-DFA
-                                 calls with DFA_ALGO_SIGNATURE or DFA_ALGO_LEADER;
-                                 DFA_EINVAL with DFA_ALGO_SORT and in batched calls */
+                                 on the device).  Calls with DFA_ALGO_SIGNATURE
+                                 (single and batched) or DFA_ALGO_LEADER; DFA_EINVAL
+                                 with DFA_ALGO_SORT */
 
 typedef struct dfa_options {
     int32_t tc_mode;      /* DFA_TC_*, default DFA_TC_AUTO */

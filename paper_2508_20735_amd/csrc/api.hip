@@ -1151,8 +1151,6 @@ int check_batch_options(const dfa_options &o) {
     if (o.algorithm != DFA_ALGO_SIGNATURE)
         return fail(DFA_EINVAL, "batched calls run signature rounds only");
     if (o.prune) return fail(DFA_EINVAL, "batched calls partition every state (prune = 0)");
-    if (o.loop_mode == DFA_LOOP_PERSISTENT)
-        return fail(DFA_EINVAL, "batched calls run host, chunk or graph loops");
     if (o.equiv_method != DFA_EQ_UNION)
         return fail(DFA_EINVAL, "batched equivalence refines unions (equiv_method = DFA_EQ_UNION)");
     return DFA_OK;

@@ -255,10 +255,10 @@ void launch_sort_group(const RoundArgs &a, hipStream_t s);
 // One round: marking of the blocks to refine, signatures, grouping, the
 // round end.
 void launch_round(const RoundArgs &a, hipStream_t s);
-// Up to `rounds` rounds (table grouping, one DFA) in one cooperative launch
-// of at most as many workgroups as fit on the device together; stops early
-// once the partition is stable.  hipErrorInvalidValue for segmented or
-// sort-grouped rounds.
+// Up to `rounds` rounds (table grouping; one DFA, or the segments of a batch
+// with their per-segment bookkeeping) in one cooperative launch of at most as
+// many workgroups as fit on the device together; stops early once the
+// partition is stable.  hipErrorInvalidValue for sort-grouped rounds.
 hipError_t launch_rounds_persistent(const RoundArgs &a, uint32_t rounds, hipStream_t s);
 // The marking kernel alone (also clears the table every kEpochs rounds).
 void launch_mark(const RoundArgs &a, hipStream_t s);

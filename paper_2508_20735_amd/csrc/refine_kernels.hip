@@ -1658,32 +1658,6 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RoundCtl *ctl, const uint3
     round_end_body(ctl, blockA, blockB, counters, N);
 }
 
-// Persistent loop: up to `rounds` rounds inside one cooperative launch, the
-// phases of a round separated by grid barriers instead of kernel boundaries
-// (the barrier's release and acquire make each phase's writes visible to
-// every workgroup, on every XCD, before the next phase reads them).  Every
-// workgroup takes the same barriers: the stop flag is read right after a
-// barrier and written only by the round's last phase, between two barriers.
-// The grid must fit on the device at once (the cooperative launch refuses
-// more workgroups than can be resident together).
-template <int KC>
-__global__ __launch_bounds__(kBlock) void k_rounds_persistent(SigParams sp, InsParams ip,
-                                                               RoundCtl *ctl, uint32_t rounds) {
-    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-    for (uint32_t i = 0; i < rounds; ++i) {
-        if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        mark_body<KC>(sp);
-        grid.sync();
-        signature_body<KC>(sp);
-        grid.sync();
-        insert_lds_body(ip);
-        insert_body(ip);
-        grid.sync();
-        if (blockIdx.x == 0)
-            round_end_body(ctl, ip.blockA, ip.blockB, ip.counters, static_cast<uint32_t>(ip.N));
-        grid.sync();
-    }
-}
 
 // ---------------------------------------------------------------- segmented refinement
 
@@ -1885,9 +1859,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_init(SegArgs g) {
 // Blocks per segment after the round: the states that are their block's id
 // (a block's id is the state that first claimed its signature).  Counts are
 // aggregated per tile in LDS (a tile spans at most kBlock segments).
-__global__ __launch_bounds__(kBlock) void k_seg_count(SegArgs g, size_t N, const RoundCtl *ctl,
-                                                       const uint32_t *blockA,
-                                                       const uint32_t *blockB) {
+__device__ __forceinline__ void seg_count_body(const SegArgs &g, size_t N, const RoundCtl *ctl,
+                                               const uint32_t *blockA, const uint32_t *blockB) {
     __shared__ uint32_t lcnt[kBlock];
     __shared__ uint32_t seg_first, tile_live;
     if (ctl->done) return;
@@ -1926,9 +1899,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(SegArgs g, size_t N, const
 // stable (its partition never changes again: the segments are disjoint), and
 // a pair whose start states got different ids is separated; either way the
 // segment is decided in this round.
-__global__ __launch_bounds__(kBlock) void k_seg_end(SegArgs g, const RoundCtl *ctl,
-                                                     const uint32_t *blockA,
-                                                     const uint32_t *blockB) {
+__device__ __forceinline__ void seg_end_body(const SegArgs &g, const RoundCtl *ctl,
+                                             const uint32_t *blockA, const uint32_t *blockB) {
     if (ctl->done) return;
     const uint32_t r = ctl->round;
     const uint32_t *__restrict__ Y = (r & 1u) ? blockA : blockB;
@@ -1952,8 +1924,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_end(SegArgs g, const RoundCtl *c
 // The states of the segments decided in this round are marked as skipped in
 // the singleton bits (one workgroup per segment; the bits of a word shared
 // with a neighbouring segment are set atomically).
-__global__ __launch_bounds__(kBlock) void k_seg_freeze(SegArgs g, const RoundCtl *ctl,
-                                                        unsigned long long *single) {
+__device__ __forceinline__ void seg_freeze_body(const SegArgs &g, const RoundCtl *ctl,
+                                                unsigned long long *single) {
     if (ctl->done) return;
     const uint32_t r = ctl->round;
     for (size_t s = blockIdx.x; s < g.nseg; s += gridDim.x) {
@@ -1971,6 +1943,59 @@ __global__ __launch_bounds__(kBlock) void k_seg_freeze(SegArgs g, const RoundCtl
             else
                 atomicOr(single + w, m);
         }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_count(SegArgs g, size_t N, const RoundCtl *ctl,
+                                                       const uint32_t *blockA,
+                                                       const uint32_t *blockB) {
+    seg_count_body(g, N, ctl, blockA, blockB);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_end(SegArgs g, const RoundCtl *ctl,
+                                                     const uint32_t *blockA,
+                                                     const uint32_t *blockB) {
+    seg_end_body(g, ctl, blockA, blockB);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_freeze(SegArgs g, const RoundCtl *ctl,
+                                                        unsigned long long *single) {
+    seg_freeze_body(g, ctl, single);
+}
+
+// Persistent loop: up to `rounds` rounds inside one cooperative launch, the
+// phases of a round separated by grid barriers instead of kernel boundaries
+// (the barrier's release and acquire make each phase's writes visible to
+// every workgroup, on every XCD, before the next phase reads them).  Every
+// workgroup takes the same barriers: the stop flag is read right after a
+// barrier and written only by the round's last phase, between two barriers.
+// The grid must fit on the device at once (the cooperative launch refuses
+// more workgroups than can be resident together).
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_rounds_persistent(SigParams sp, InsParams ip,
+                                                               SegArgs g, RoundCtl *ctl,
+                                                               uint32_t rounds) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (uint32_t i = 0; i < rounds; ++i) {
+        if (__hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        mark_body<KC>(sp);
+        grid.sync();
+        signature_body<KC>(sp);
+        grid.sync();
+        insert_lds_body(ip);
+        insert_body(ip);
+        grid.sync();
+        if (g.nseg) {  // (uniform) the per-segment bookkeeping of the round
+            seg_count_body(g, ip.N, ctl, ip.blockA, ip.blockB);
+            grid.sync();
+            seg_end_body(g, ctl, ip.blockA, ip.blockB);
+            grid.sync();
+            seg_freeze_body(g, ctl, sp.single);
+            grid.sync();
+        }
+        if (blockIdx.x == 0)
+            round_end_body(ctl, ip.blockA, ip.blockB, ip.counters, static_cast<uint32_t>(ip.N));
+        grid.sync();
     }
 }
 
@@ -2493,7 +2518,7 @@ void launch_round(const RoundArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_rounds_persistent(const RoundArgs &a, uint32_t rounds, hipStream_t s) {
-    if (a.seg.nseg || a.grouping) return hipErrorInvalidValue;
+    if (a.grouping) return hipErrorInvalidValue;
     const void *kernel;
     switch (a.k_eff) {
         case 1: kernel = reinterpret_cast<const void *>(&k_rounds_persistent<1>); break;
@@ -2509,8 +2534,9 @@ hipError_t launch_rounds_persistent(const RoundArgs &a, uint32_t rounds, hipStre
     const unsigned grid = std::min(round_grid(a, a.round_grid_cap), fit);
     SigParams sp = sig_params(a);
     InsParams ip = ins_params(a);
+    SegArgs g = a.seg;
     RoundCtl *ctl = a.ctl;
-    void *args[] = {&sp, &ip, &ctl, &rounds};
+    void *args[] = {&sp, &ip, &g, &ctl, &rounds};
     return hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
 }
 

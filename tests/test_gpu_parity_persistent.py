@@ -134,3 +134,37 @@ def test_persistent_pruned():
     block, nb, nr = oracle.minimise_reachable(d.delta, d.accepting, 3)
     np.testing.assert_array_equal(res.block, block)
     assert res.stats["reachable"] == nr
+
+
+@pytest.mark.parametrize("cut", [0, 4096])
+def test_persistent_batches(cut):
+    """Batched calls in the persistent loop: the segmented rounds with their
+    per-segment bookkeeping inside the cooperative launch (cut-off 0: every
+    DFA segmented; 4096: the small ones in one workgroup each), against the
+    oracle's partitions and Moore rounds and Hopcroft-Karp verdicts."""
+    before = B.get_tuning()
+    try:
+        B.set_tuning(batch_lds_states=cut)
+        rng = np.random.default_rng(41)
+        dfas = [W.random_dfa(int(rng.integers(1, 20000)), int(rng.integers(1, 9)),
+                             float(rng.uniform(0.05, 0.6)), 300 + i) for i in range(40)]
+        dfas += [W.fibonacci(12), W.bitsplitter(8), W.chain_with_tail(500, 200, 4)]
+        print(f"persistent batch, cut-off {cut}: {len(dfas)} DFAs", flush=True)
+        for chunk in (0, 3):
+            blocks, nb, rounds, st = B.minimise_batch(dfas, tc="off", loop="persistent",
+                                                      chunk=chunk)
+            for i, d in enumerate(dfas):
+                ref, rnb, rrounds, _ = oracle.moore(d.delta, d.accepting)
+                np.testing.assert_array_equal(blocks[i], ref, err_msg=f"dfa {i}")
+                assert (nb[i], rounds[i]) == (rnb, rrounds), (i, d.n, d.k)
+        pairs = []
+        for i, d in enumerate(dfas):
+            other = (W.permuted_copy(d, i)[0] if i % 2 == 0 or d.n < 2
+                     else W.mutate_one(d, i)[0])
+            pairs.append((d, other))
+        verdicts, _ = B.equivalent_batch(pairs, tc="off", loop="persistent")
+        for (a, b), v in zip(pairs, verdicts):
+            assert v == oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting,
+                                        b.start)
+    finally:
+        B.set_tuning(**before)
