@@ -230,8 +230,9 @@ def batch_leg(B, W, torch, np, count: int) -> dict:
     """Batched vs plain on the same GPU: `count` random DFAs (n log-uniform in
     [64, 65536], k in 2..8, p in [0.05, 0.5]); the upper half also checked for
     equivalence (even: permuted copy, odd: one-transition mutation).  Batched =
-    one dfa_minimise_batch_device + one dfa_equivalent_batch_device call;
-    plain = one dfa_minimise_device / dfa_equivalent_device call per DFA/pair."""
+    one dfa_minimise_batch_device + one dfa_equivalent_batch_device call, the
+    operands packed in flat GPU tensors (PackedBatch); plain = one
+    dfa_minimise_device / dfa_equivalent_device call per DFA/pair."""
     dev = torch.device("cuda:0")
     items = W.batch_workload(count=count, paired_from=count // 2)
 
@@ -244,11 +245,15 @@ def batch_leg(B, W, torch, np, count: int) -> dict:
     total = sum(it.dfa.n for it in items)
     out = torch.empty(total, dtype=torch.int32, device=dev)
     blocks = [torch.empty(it.dfa.n, dtype=torch.int32, device=dev) for it in items]
+    # the batched calls take each operand list packed in two flat tensors
+    pack_all = B.PackedBatch.from_dfas([it.dfa for it in items])
+    pack_l = B.PackedBatch.from_dfas([items[i].dfa for i, _ in pairs])
+    pack_r = B.PackedBatch.from_dfas([it.pair for it in items if it.pair is not None])
     torch.cuda.synchronize()
 
     def batched():
-        nb, rounds, st = B.minimise_batch_device([a[0] for a in A], [a[1] for a in A], out)
-        v, st2 = B.equivalent_batch_device([A[i] for i, _ in pairs], [p for _, p in pairs])
+        nb, rounds, st = B.minimise_batch_device(pack_all, None, out)
+        v, st2 = B.equivalent_batch_device(pack_l, pack_r)
         return st["transitions_refined"] + st2["transitions_refined"], v
 
     def plain():

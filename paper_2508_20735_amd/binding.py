@@ -539,14 +539,76 @@ def minimise_batch(dfas, *, tc: str = "auto", loop: str = "graph", max_rounds: i
     return blocks, nb, rounds, st.as_dict()
 
 
-def minimise_batch_device(deltas, accs, out, *, tc: str = "auto", loop: str = "graph",
-                          lds_stage=2, stream=None):
-    """dfa_minimise_batch_device: deltas / accs are lists of GPU tensors, out a
-    GPU int32 tensor with room for all states (packed in order)."""
+_VIEW_NP = np.dtype({"names": ["n", "k", "start", "delta", "accepting"],
+                     "formats": [np.uint32, np.uint32, np.uint32, np.uint64, np.uint64],
+                     "offsets": [View.n.offset, View.k.offset, View.start.offset,
+                                 View.delta.offset, View.accepting.offset],
+                     "itemsize": ctypes.sizeof(View)})
+
+
+class PackedBatch:
+    """A batch of DFAs held in two flat GPU tensors: delta_flat (int32, the
+    row-major transition tables one after another, n_i * k_i entries each)
+    and acc_flat (uint8, the acceptance arrays one after another).  The
+    dfa_view array of the batched calls is computed in bulk from the sizes
+    (no per-DFA Python work), so a call on thousands of DFAs costs the
+    library's time, not the binding's."""
+
+    def __init__(self, delta_flat, acc_flat, ns, ks, starts=None):
+        ns = np.asarray(ns, dtype=np.uint64)
+        ks = np.asarray(ks, dtype=np.uint64)
+        count = len(ns)
+        if len(ks) != count or count == 0:
+            raise ValueError("ns and ks must be non-empty and of the same length")
+        if (ns == 0).any() or (ks == 0).any():
+            raise ValueError("every DFA needs at least one state and one letter")
+        cells = ns * ks
+        _check_device_tensor(delta_flat, str(delta_flat.dtype), int(cells.sum()), "delta_flat")
+        if str(delta_flat.dtype) not in ("torch.int32", "torch.uint32"):
+            raise ValueError("delta_flat must be an int32 tensor")
+        _check_device_tensor(acc_flat, "torch.uint8", int(ns.sum()), "acc_flat")
+        arr = np.zeros(count, dtype=_VIEW_NP)
+        arr["n"] = ns
+        arr["k"] = ks
+        arr["start"] = 0 if starts is None else np.asarray(starts, dtype=np.uint32)
+        arr["delta"] = delta_flat.data_ptr() + 4 * (np.cumsum(cells) - cells)
+        arr["accepting"] = acc_flat.data_ptr() + (np.cumsum(ns) - ns)
+        self._arr = arr
+        self._keep = (delta_flat, acc_flat)
+        self.views = (View * count).from_buffer(arr)
+        self.count = count
+        self.states = int(ns.sum())
+
+    @classmethod
+    def from_dfas(cls, dfas, device="cuda:0"):
+        """Packs host DFAs (objects with delta, accepting, start) onto the GPU."""
+        import torch
+        delta = np.concatenate([np.ascontiguousarray(d.delta, dtype=np.uint32).ravel()
+                                for d in dfas])
+        acc = np.concatenate([np.ascontiguousarray(d.accepting, dtype=np.uint8).ravel()
+                              for d in dfas])
+        dev = torch.device(device)
+        return cls(torch.from_numpy(delta.view(np.int32)).to(dev), torch.from_numpy(acc).to(dev),
+                   [d.delta.shape[0] for d in dfas], [d.delta.shape[1] for d in dfas],
+                   [d.start for d in dfas])
+
+
+def _batch_views(deltas, accs=None, starts=None):
+    if isinstance(deltas, PackedBatch):
+        return deltas.views, deltas.count
     count = len(deltas)
     views = (View * count)()
     for i, (d, a) in enumerate(zip(deltas, accs)):
-        views[i] = _view_device(d, a, 0)
+        views[i] = _view_device(d, a, 0 if starts is None else starts[i])
+    return views, count
+
+
+def minimise_batch_device(deltas, accs, out, *, tc: str = "auto", loop: str = "graph",
+                          lds_stage=2, stream=None):
+    """dfa_minimise_batch_device: deltas / accs are lists of GPU tensors (or
+    deltas a PackedBatch and accs None), out a GPU int32 tensor with room for
+    all states (packed in order)."""
+    views, count = _batch_views(deltas, accs)
     nb = np.empty(count, dtype=np.uint32)
     rounds = np.empty(count, dtype=np.uint32)
     o = options(tc, loop, 0, 0, 0, lds_stage)
@@ -572,12 +634,20 @@ def equivalent_batch(pairs, *, tc: str = "auto", loop: str = "graph", max_rounds
 
 
 def equivalent_batch_device(a_list, b_list, *, loop: str = "graph", lds_stage=2, stream=None):
-    """a_list / b_list: lists of (delta tensor, accepting tensor, start)."""
-    count = len(a_list)
-    va, vb = (View * count)(), (View * count)()
-    for i in range(count):
-        va[i] = _view_device(*a_list[i])
-        vb[i] = _view_device(*b_list[i])
+    """a_list / b_list: lists of (delta tensor, accepting tensor, start), or
+    two PackedBatch of the same count."""
+    if isinstance(a_list, PackedBatch) != isinstance(b_list, PackedBatch):
+        raise ValueError("both operand lists must be PackedBatch, or neither")
+    if isinstance(a_list, PackedBatch):
+        if a_list.count != b_list.count:
+            raise ValueError("the two PackedBatch must hold the same number of DFAs")
+        va, vb, count = a_list.views, b_list.views, a_list.count
+    else:
+        count = len(a_list)
+        va, vb = (View * count)(), (View * count)()
+        for i in range(count):
+            va[i] = _view_device(*a_list[i])
+            vb[i] = _view_device(*b_list[i])
     verdicts = np.empty(count, dtype=np.int32)
     o = options("auto", loop, 0, 0, 0, lds_stage)
     st = BatchStats()

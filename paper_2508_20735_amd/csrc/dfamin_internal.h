@@ -210,7 +210,7 @@ struct RoundArgs {
     uint32_t *presence_packed;  // 2^kPackedMaxBits bits, zero between calls
     uint8_t *lab8;       // round-0 labels as bytes (packed round 1 only)
     RoundCtl *ctl;
-    int lds_stage;              // 0 never, 1 always, 2 when the last round grouped >= 8 states per block
+    int lds_stage;              // 0 never, 1 and 2 (automatic) every round
     uint32_t round_grid_cap;    // workgroups of the round kernels (0 = one per 256 states)
     uint32_t pattern_grid_cap;  // workgroups of the label rounds
     uint32_t cached_probe;      // probe the table with cached loads first

@@ -2468,8 +2468,8 @@ void launch_signature_pb(const RoundArgs &a, hipStream_t s) {
 void launch_insert(const RoundArgs &a, hipStream_t s) {
     const dim3 grid(round_grid(a, a.round_grid_cap)), block(kBlock);
     const InsParams ip = ins_params(a);
-    // the two grouping variants; exactly one of them works in a given round
-    // (lds_stage 2 decides on the device from the previous round)
+    // the LDS-staged variants (lds_stage 1, and 2, which stages every round)
+    // or the direct one (0)
     if (a.lds_stage != 0) {
         // two states per thread for the specialised signature widths
         const dim3 grid2(round_grid(a, a.round_grid_cap, 2 * kBlock));
@@ -2481,8 +2481,9 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
             case 8: launch_kernel(k_insert_lds2<8>, grid2, block, 0, s, ip); break;
             default: launch_kernel(k_insert_lds, grid, block, 0, s, ip); break;
         }
+    } else {
+        launch_kernel(k_insert, grid, block, 0, s, ip);
     }
-    if (a.lds_stage != 1) launch_kernel(k_insert, grid, block, 0, s, ip);
 }
 
 void launch_mark(const RoundArgs &a, hipStream_t s) {

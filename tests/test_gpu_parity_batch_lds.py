@@ -153,3 +153,46 @@ def test_autotuned_batch_parity(tmp_path, cutoff_restore):
         np.testing.assert_array_equal(got[pos:pos + d.n], ref, err_msg=f"dfa {i}")
         assert (nb[i], rounds[i]) == (rnb, rrounds), i
         pos += d.n
+
+
+def test_packed_batch_matches_tensor_lists(cutoff_restore):
+    """PackedBatch (two flat tensors per operand list, views computed in bulk)
+    gives the same blocks, counts, rounds and verdicts as lists of tensors,
+    and both equal the oracle."""
+    import torch
+
+    B.set_tuning(batch_lds_states=1024)
+    dfas = _edge_dfas()
+    others = [W.permuted_copy(d, i)[0] if i % 2 == 0 or d.n < 2 else W.mutate_one(d, i)[0]
+              for i, d in enumerate(dfas)]
+    dev = torch.device("cuda:0")
+
+    def t(d):
+        return (torch.from_numpy(np.ascontiguousarray(d.delta).view(np.int32)).to(dev),
+                torch.from_numpy(d.accepting).to(dev), d.start)
+
+    lists = [t(d) for d in dfas]
+    total = sum(d.n for d in dfas)
+    out_a = torch.empty(total, dtype=torch.int32, device=dev)
+    out_b = torch.empty(total, dtype=torch.int32, device=dev)
+    nb_a, r_a, _ = B.minimise_batch_device([x[0] for x in lists], [x[1] for x in lists], out_a)
+    pack = B.PackedBatch.from_dfas(dfas)
+    assert pack.count == len(dfas) and pack.states == total
+    nb_b, r_b, _ = B.minimise_batch_device(pack, None, out_b)
+    assert torch.equal(out_a, out_b)
+    np.testing.assert_array_equal(nb_a, nb_b)
+    np.testing.assert_array_equal(r_a, r_b)
+    got = out_b.cpu().numpy()
+    off = 0
+    for i, d in enumerate(dfas):
+        ref, rnb, rrounds, _ = oracle.moore(d.delta, d.accepting)
+        np.testing.assert_array_equal(got[off:off + d.n], ref, err_msg=f"dfa {i}")
+        assert (nb_b[i], r_b[i]) == (rnb, rrounds)
+        off += d.n
+    v_lists, _ = B.equivalent_batch_device(lists, [t(o) for o in others])
+    v_pack, _ = B.equivalent_batch_device(pack, B.PackedBatch.from_dfas(others))
+    np.testing.assert_array_equal(v_lists, v_pack)
+    for (a, b), v in zip(zip(dfas, others), v_pack):
+        assert v == oracle.equiv_hk(a.delta, a.accepting, a.start, b.delta, b.accepting, b.start)
+    with pytest.raises(ValueError):
+        B.equivalent_batch_device(pack, lists)
