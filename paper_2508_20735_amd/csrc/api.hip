@@ -2383,15 +2383,21 @@ size_t workspace_bytes(Ctx &c) {
 
 // Device bytes a request may add to a lane's workspace while it runs
 // (inputs, columns, signatures, hashes, table, block buffers and marks,
-// outputs), apart from the fixed part.
+// outputs, the edges bucketed by target slice, a batch's round-0 patterns),
+// apart from the fixed part.
 size_t request_footprint(uint64_t n, uint32_t k, bool closure) {
+    const uint64_t slices = (n >> kPbSliceLog) + 1, tiles = n / kPbTile + 1;
     uint64_t bytes = n * (4ull * k + 1)        // input copy
                      + n * 4ull * k            // columns
                      + n * 4ull * (k + 1)      // signature rows
                      + n * 8ull                // hashes
                      + n * 32ull               // table (2n slots of 8 bytes, rounded up)
                      + n * 4ull * 6            // blocks A/B, marks, canonical ids, output, scratch
+                     + n * 8ull * k            // bucketed edges: target, source slot, gathered id
+                     + slices * tiles * 12ull  // run lengths and starts, scan sums
+                     + n * 2ull                // round-0 patterns (batches)
                      + (1u << 22);             // fixed buffers
+    if (k + 1 <= kSegPatMaxBits) bytes += 4ull << (k + 1);  // the request's pattern-table rows
     if (closure) {
         uint32_t L = floor_log2(std::max<uint64_t>(n, 1));
         bytes += n * 4ull * k * (L + 1);
