@@ -529,6 +529,28 @@ def gather_reference(torch, dev, sizes) -> dict:
     return out
 
 
+def probe_reference(torch, dev, slots: int, probes: int) -> float:
+    """Random 8-byte loads per second from a table of `slots` int64 words (the
+    size of the grouping kernel's hash table), as torch indexing reaches
+    them: `probes` random indices, median of 10 timed repetitions."""
+    table = torch.randint(0, 1 << 62, (slots,), dtype=torch.int64, device=dev)
+    idx = torch.randint(0, slots, (probes,), dtype=torch.int64, device=dev)
+    for _ in range(3):
+        table[idx]
+    times = []
+    for _ in range(10):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        table[idx]
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = sorted(times)[len(times) // 2]
+    del table, idx
+    return probes / (ms * 1e-3)
+
+
 def serve_leg(B, W, count: int) -> dict:
     """Served requests: n log-uniform in [1,000, 4,194,304], k in {2,4,8,16},
     80% minimise / 20% equivalence, 10% chain DFAs, host arrays.  First a
@@ -776,6 +798,22 @@ def main() -> int:
                          "incremental rounds included (their fixed per-state work has no "
                          "gathers); full-round launches in the kernel trace run at the "
                          "reference rate"),
+            }
+        if dom == "k_insert":
+            # every refined state that groups through the table probes it at
+            # a random slot at least once: the kernel's refined states per
+            # second against the device's random 8-byte load rate on a table
+            # of the unions' size (2^ceil(log2(2 * 2n)) slots) is a lower
+            # bound on the fraction of that rate it reaches
+            slots = 1 << (4 * d.n - 1).bit_length()
+            ref_probes = probe_reference(torch, dev, slots, 2 * d.n)
+            achieved_p = kd["states"] / (kd["total_ms"] / 1e3)
+            out["probe_roofline"] = {
+                "kernel": dom, "achieved": achieved_p / 1e9, "peak": ref_probes / 1e9,
+                "unit": "G random table probes/s (lower bound: one per refined state)",
+                "frac": achieved_p / ref_probes,
+                "reference": (f"torch index gather: {2 * d.n} random int64 loads from a "
+                              f"{slots}-slot table, median of 10"),
             }
         pbg = kernels.get("k_pb_gather")
         if pbg and pbg["total_ms"] > 0 and pbg["state_letters"]:

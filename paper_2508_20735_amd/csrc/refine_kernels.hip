@@ -600,19 +600,22 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
 // was_active: the state was refined in the previous round.  A state that is
 // refined in neither round already has its id in both block buffers (the
 // round that skipped it first copied it), so it needs no copy now.
-__device__ __forceinline__ bool select_state(const SigParams &p, size_t q, uint32_t w0, uint32_t r,
-                                             bool inc, const unsigned long long *T,
-                                             bool &was_active) {
+// sw, aw: the wave's singleton and refined-state words (as loaded here);
+// mq: multi[q] when the caller loaded it ahead (else ~0u: loaded here when
+// needed).
+__device__ __forceinline__ bool select_state_words(const SigParams &p, size_t q, uint32_t w0,
+                                                   uint32_t r, bool inc,
+                                                   const unsigned long long *T,
+                                                   unsigned long long sw, unsigned long long aw,
+                                                   uint32_t mq, bool &was_active) {
     const bool valid = q < p.N;
     const size_t first = q - lane_id();
     const size_t wd = first >> 6;
-    const unsigned long long sw = first < p.N ? p.single[wd] : ~0ull;
-    const unsigned long long aw = first < p.N ? p.active[wd] : 0ull;
     was_active = ((aw >> lane_id()) & 1ull) != 0;
     bool s = !valid || ((sw >> lane_id()) & 1ull);
     if (!inc) {
         // (a state whose id is another state's index shares its block)
-        if (!s && was_active) s = w0 == q && p.multi[q] != r;
+        if (!s && was_active) s = w0 == q && (mq != ~0u ? mq : p.multi[q]) != r;
         const unsigned long long nsw = __ballot(s);
         if (lane_id() == 0 && first < p.N && nsw != sw) p.single[wd] = nsw;
     }
@@ -620,6 +623,15 @@ __device__ __forceinline__ bool select_state(const SigParams &p, size_t q, uint3
     const unsigned long long am = __ballot(act);
     if (lane_id() == 0 && first < p.N) p.active[wd] = am;
     return act;
+}
+
+__device__ __forceinline__ bool select_state(const SigParams &p, size_t q, uint32_t w0, uint32_t r,
+                                             bool inc, const unsigned long long *T,
+                                             bool &was_active) {
+    const size_t first = q - lane_id();
+    const unsigned long long sw = first < p.N ? p.single[first >> 6] : ~0ull;
+    const unsigned long long aw = first < p.N ? p.active[first >> 6] : 0ull;
+    return select_state_words(p, q, w0, r, inc, T, sw, aw, ~0u, was_active);
 }
 
 // Writes the key row and hash of a refined state; a state that holds its
@@ -1211,13 +1223,29 @@ __global__ __launch_bounds__(kBlock) void k_signature_pb(SigParams p) {
     constexpr size_t W = KC + 1;
     uint32_t leaders = 0, claims = 0;
     const uint32_t tx = threadIdx.x;
+    constexpr int EP = kPbTile / kBlock;  // states per thread in a tile
     for (uint32_t t = blockIdx.x; t < pb.ntiles; t += gridDim.x) {
-        pb_tile_keys<KC>(pb, t, key, runs);
         const size_t base = static_cast<size_t>(t) * kPbTile;
-        for (uint32_t i = tx; i < kPbTile; i += kBlock) {
+        // the tile's own ids are loaded before its keys are assembled, so
+        // their latency overlaps that work instead of following it
+        uint32_t w0s[EP], mqs[EP];
+        unsigned long long sws[EP], aws[EP];
+#pragma unroll
+        for (int e = 0; e < EP; ++e) {
+            const size_t q = base + e * kBlock + tx;
+            const size_t first = q - lane_id();
+            w0s[e] = q < p.N ? X[q] : 0u;
+            sws[e] = (!all && first < p.N) ? p.single[first >> 6] : ~0ull;
+            aws[e] = (!all && first < p.N) ? p.active[first >> 6] : 0ull;
+            mqs[e] = (!all && !inc && q < p.N) ? p.multi[q] : ~0u;
+        }
+        pb_tile_keys<KC>(pb, t, key, runs);
+#pragma unroll
+        for (int e = 0; e < EP; ++e) {
+            const uint32_t i = e * kBlock + tx;
             const size_t q = base + i;
             // (the whole wave takes part in the ballots below)
-            const uint32_t w0 = q < p.N ? X[q] : 0u;
+            const uint32_t w0 = w0s[e];
             bool act;
             if (all) {
                 act = q < p.N;
@@ -1226,7 +1254,7 @@ __global__ __launch_bounds__(kBlock) void k_signature_pb(SigParams p) {
                 if (lane_id() == 0 && first < p.N) p.active[first >> 6] = am;
             } else {
                 bool was;
-                act = select_state(p, q, w0, r, inc, T, was);
+                act = select_state_words(p, q, w0, r, inc, T, sws[e], aws[e], mqs[e], was);
                 if (q < p.N && !act) {
                     if (was) Y[q] = w0;
                     leaders += w0 == q ? 1u : 0u;
