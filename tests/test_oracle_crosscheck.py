@@ -172,13 +172,65 @@ def test_closure_preserves_equivalence(seed):
     np.testing.assert_array_equal(hb, tb)
 
 
-@pytest.mark.parametrize("i", range(4, 12))
+def _closure_rounds_bruteforce(delta, acc):
+    """Changing rounds of signature refinement over a one-letter DFA extended
+    by the letters a^(2^j), j <= L = floor(log2 n) (Algorithm 5), from the
+    definition: after r rounds two states share a block iff no word of at
+    most r extended letters tells them apart, and such a word moves the DFA
+    by m steps at a cost of floor(m / 2^L) + popcount(m mod 2^L) letters.  So
+    the count is the largest, over pairs of states, of the smallest cost of
+    an m after which exactly one of them accepts (a round that splits
+    nothing leaves the partition stable, so the last splitting round is the
+    largest separation round).  Every distinguishable pair is told apart by
+    some m < n (cost <= L + 1), so m < (L + 2) * 2^L suffices.  Returns
+    (changing rounds, number of classes); pairs never told apart are
+    equivalent."""
+    n = len(acc)
+    L = n.bit_length() - 1
+    span = (L + 2) << L
+    pos = np.arange(n)
+    rows = np.empty((span, n), dtype=bool)
+    for m in range(span):
+        rows[m] = acc[pos] != 0
+        pos = delta[pos, 0]
+    m = np.arange(span)
+    low = m & ((1 << L) - 1)
+    cost = (m >> L) + np.array([bin(int(x)).count("1") for x in low])
+    big = np.iinfo(np.int64).max
+    best = 0
+    rep = np.arange(n)  # smallest equivalent state
+    for p in range(n - 1):
+        diff = rows[:, p][:, None] != rows[:, p + 1:]
+        c = np.where(diff, cost[:, None], big).min(axis=0)
+        same = np.nonzero(c == big)[0] + p + 1
+        rep[same] = np.minimum(rep[same], rep[p])
+        if (c < big).any():
+            best = max(best, int(c[c < big].max()))
+    return best, int((rep == np.arange(n)).sum())
+
+
+@pytest.mark.parametrize("i", range(4, 13))
 def test_closure_on_fibonacci(i):
     d = W.fibonacci(i)
     tb, nb, _, changing = oracle.minimise_tc(d.delta, d.accepting)
     assert nb == d.n
-    # the closure shortens the n - 2 plain rounds (Table 2, transPR column)
+    # the closure shortens the n - 2 plain rounds (Table 2, transPR column) to
+    # exactly the brute-force count
     assert changing < d.n - 2
+    assert (changing, nb) == _closure_rounds_bruteforce(d.delta, d.accepting)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_closure_rounds_one_letter_random(seed):
+    """The same definition on random one-letter DFAs (functional graphs with
+    random acceptance), minimal or not: the closure's changing rounds and its
+    number of blocks."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 120))
+    delta = rng.integers(0, n, (n, 1)).astype(np.uint32)
+    acc = (rng.random(n) < 0.4).astype(np.uint8)
+    _, nb, _, changing = oracle.minimise_tc(delta, acc)
+    assert (changing, nb) == _closure_rounds_bruteforce(delta, acc)
 
 
 @pytest.mark.parametrize("M", [3, 4, 6, 8, 10])
