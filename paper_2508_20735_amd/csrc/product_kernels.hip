@@ -4,26 +4,23 @@
 // HBM) and no transitive closure is maintained.  Inclusion L(A) <= L(B) is
 // refuted by a reached pair with p accepting in A and q rejecting in B;
 // equivalence by a pair with exactly one accepting side.
-#include "dfamin_internal.h"
+#include "device_common.h"
 
 namespace dfamin {
 namespace {
 
 constexpr unsigned long long kEmpty = ~0ull;
 
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-    x ^= x >> 30;
-    x *= 0xbf58476d1ce4e5b9ull;
-    x ^= x >> 27;
-    x *= 0x94d049bb133111ebull;
-    x ^= x >> 31;
-    return x;
+// Slot of a pair key: the library's key mixing over its two 32-bit halves.
+__device__ __forceinline__ uint64_t pair_hash(uint64_t key) {
+    return mix_final(mix_step(mix_step(kHashSeed, static_cast<uint32_t>(key >> 32)),
+                              static_cast<uint32_t>(key)));
 }
 
 // Inserts key; returns true if it was not present.
 __device__ __forceinline__ bool set_insert(unsigned long long *tab, uint64_t mask,
                                            unsigned long long key) {
-    uint64_t s = mix64(key) & mask;
+    uint64_t s = pair_hash(key) & mask;
     for (;;) {
         unsigned long long e = __hip_atomic_load(tab + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (e == key) return false;
