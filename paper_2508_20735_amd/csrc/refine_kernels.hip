@@ -553,8 +553,11 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
             // members of a block differ, so they are not read (kw is uniform
             // across the wave).
             uint32_t t[S][KC], kw[S];
+            // a wave whose states are all singletons (or frozen) marks
+            // nothing: it reads no letter (uniform across the wave)
 #pragma unroll
-            for (int i = 0; i < S; ++i) kw[i] = wave_letters(p, q[i] - lane_id(), KC);
+            for (int i = 0; i < S; ++i)
+                kw[i] = __ballot(!s[i]) ? wave_letters(p, q[i] - lane_id(), KC) : 0u;
 #pragma unroll
             for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -709,14 +712,15 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
                     }
                 }
             }
-            // letters this wave reads for each of its two states (padding
-            // letters of a segmented refinement are the state's own id)
-            const uint32_t kw[2] = {wave_letters(p, q[0] - lane_id(), KC),
-                                    wave_letters(p, q[1] - lane_id(), KC)};
             // waves where most lanes are refined load unconditionally (the
             // others reread the wave's first refined state, lines the wave
             // fetches anyway); sparse waves load per lane
             const unsigned long long am[2] = {__ballot(act[0]), __ballot(act[1])};
+            // letters this wave reads for each of its two states (padding
+            // letters of a segmented refinement are the state's own id; a
+            // wave with no refined state reads none)
+            const uint32_t kw[2] = {am[0] ? wave_letters(p, q[0] - lane_id(), KC) : 0u,
+                                    am[1] ? wave_letters(p, q[1] - lane_id(), KC) : 0u};
             const uint32_t nact = static_cast<uint32_t>(__popcll(am[0])) +
                                   static_cast<uint32_t>(__popcll(am[1]));
             if (nact >= 64) {
