@@ -200,7 +200,7 @@ struct Ctx {
     // waiting lanes leave the host cores to submissions)
     bool blocking_sync = false;
     hipEvent_t ev_sync = nullptr;
-    Buffer parts, tile_part, seg_words, batch_in, batch_out;
+    Buffer parts, tile_part, seg_words, batch_in, batch_out, tile_dead;
     Buffer small_jobs, small_results, small_ctl;  // batched small DFAs (one workgroup each)
     Buffer pb_tl, pb_src, pb_val, pb_off, pb_partials;  // edges bucketed by target slice
     Buffer segpat_table, segpat;  // round 0 of segmented refinements by acceptance patterns
@@ -1654,12 +1654,14 @@ int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, bool pair
     DFA_TRY(c.tile_part.ensure(tiles * sizeof(uint32_t), "batch tiles"));
     DFA_TRY(c.seg_words.ensure((5 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t),
                                "segment counters"));
+    DFA_TRY(c.tile_dead.ensure(tiles, "decided tiles"));
     HIP_TRY(hipMemcpy(c.parts.p, parts.data(), parts.size() * sizeof(Part),
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c.tile_part.p, tile_part.data(), tiles * sizeof(uint32_t),
                       hipMemcpyHostToDevice));
     uint32_t *w = c.seg_words.as<uint32_t>();
     HIP_TRY(hipMemsetAsync(w, 0, (5 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t), c.stream));
+    HIP_TRY(hipMemsetAsync(c.tile_dead.p, 0, tiles, c.stream));
     g.parts = c.parts.as<Part>();
     g.tile_part = c.tile_part.as<uint32_t>();
     g.nparts = static_cast<uint32_t>(parts.size());
@@ -1671,6 +1673,7 @@ int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, bool pair
     g.seg_done = w + 4 * static_cast<size_t>(nseg);
     g.init_count = w + 5 * static_cast<size_t>(nseg);
     g.pairs = pairs ? 1u : 0u;
+    g.tile_dead = c.tile_dead.as<uint8_t>();
     return DFA_OK;
 }
 
@@ -2196,7 +2199,7 @@ void for_each_buffer(Ctx &c, F &&f) {
                       &c.sort_vals1, &c.sort_hist, &c.sort_partials, &c.sort_runhead,
                       &c.sort_m, &c.serve_in, &c.small_jobs, &c.small_results,
                       &c.small_ctl, &c.pb_tl, &c.pb_src, &c.pb_val, &c.pb_off,
-                      &c.pb_partials, &c.segpat_table, &c.segpat};
+                      &c.pb_partials, &c.segpat_table, &c.segpat, &c.tile_dead};
     for (Buffer *b : bufs) f(*b);
 }
 

@@ -139,6 +139,7 @@ struct SegArgs {
                               // were separated; its states are skipped from then on
     uint32_t *init_count;     // sum over segments of their class counts
     uint32_t pairs;           // 1: segment s is the union of parts 2s and 2s + 1
+    uint8_t *tile_dead;       // per tile of kBlock states: 1 once all its segments are decided
 };
 
 // Transposes every part into cols (targets offset by the part's first

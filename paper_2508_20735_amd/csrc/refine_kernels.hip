@@ -1902,12 +1902,18 @@ __device__ __forceinline__ void seg_count_body(const SegArgs &g, size_t N, const
          base += static_cast<size_t>(gridDim.x) * kBlock) {
         lcnt[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
-            // a tile whose segments are all decided has nothing to count
-            uint32_t p = g.tile_part[base / kBlock];
-            seg_first = g.parts[p].seg;
+            // a tile whose segments are all decided has nothing to count (and
+            // never has again: a decided segment stays decided)
+            const size_t t = base / kBlock;
             uint32_t live = 0;
-            const size_t end = base + kBlock < N ? base + kBlock : N;
-            for (; p < g.nparts && g.parts[p].off < end; ++p) live |= g.seg_done[g.parts[p].seg] == 0u;
+            if (!g.tile_dead[t]) {
+                uint32_t p = g.tile_part[t];
+                seg_first = g.parts[p].seg;
+                const size_t end = base + kBlock < N ? base + kBlock : N;
+                for (; p < g.nparts && g.parts[p].off < end; ++p)
+                    live |= g.seg_done[g.parts[p].seg] == 0u;
+                if (!live) g.tile_dead[t] = 1;
+            }
             tile_live = live;
         }
         __syncthreads();
