@@ -2278,11 +2278,18 @@ int init_fixed(Ctx &c) {
 // letters in the fixed context, each buffer rounded up to 256 bytes as the
 // arena carves it: columns 4k, block ids 8, marks 4, signatures 4(k + 1),
 // hashes 8, table <= 32, canonical ids, dense ids, leaders 12, byte labels 1,
-// bit masks < 1 per state; plus the label bitmaps and small control words.
-size_t fixed_plain_bytes(uint64_t n, uint64_t k) {
+// bit masks < 1 per state; plus the label bitmaps and small control words;
+// with `slices`, the edges bucketed by target slice (8 bytes per edge, run
+// counts and starts).
+size_t fixed_plain_bytes(uint64_t n, uint64_t k, bool slices) {
     const uint64_t table = 8 * next_pow2(std::max<uint64_t>(2 * n, 1024));
-    return n * (8 * k + 41) + table + (size_t(1) << kPackedMaxBits) / 8 +
-           (1u << kPatternMaxBits) / 8 + (size_t(64) << 10);
+    uint64_t bytes = n * (8 * k + 41) + table + (size_t(1) << kPackedMaxBits) / 8 +
+                     (1u << kPatternMaxBits) / 8 + (size_t(64) << 10);
+    if (slices) {
+        const uint64_t nb = (n >> kPbSliceLog) + 1, tiles = n / kPbTile + 1;
+        bytes += n * 8 * k + nb * tiles * 12 + 6 * 256;
+    }
+    return bytes;
 }
 
 using Clock = std::chrono::steady_clock;
@@ -2886,12 +2893,6 @@ int dfa_minimise_device_fixed(uint32_t n, uint32_t k, const uint32_t *delta,
         g_last_error.clear();
         dfa_options o = resolve(opt);
         DFA_TRY(check_minimise(n, k, delta, accepting, block_out, q_out, o));
-        const size_t need = fixed_plain_bytes(n, k);
-        if (need > kFixedScratchBytes)
-            return fail(DFA_ENOMEM,
-                        "n = %u, k = %u needs about %zu bytes of workspace; the fixed workspace "
-                        "holds %zu",
-                        n, k, need, kFixedScratchBytes);
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
         if (dev < 0 || dev >= kMaxDevices)
@@ -2899,6 +2900,16 @@ int dfa_minimise_device_fixed(uint32_t n, uint32_t k, const uint32_t *delta,
         Ctx &c = g_fixed[dev];
         CallScope lock(c.mu);
         DFA_TRY(init_fixed(c));
+        // (the same rule as build_slices, with every letter counted)
+        const bool slices = c.tune.slice_min_states && n >= c.tune.slice_min_states &&
+                            n <= (static_cast<uint64_t>(kPbMaxBuckets) << kPbSliceLog) &&
+                            o.loop_mode != DFA_LOOP_PERSISTENT && o.tc_mode != DFA_TC_ON;
+        const size_t need = fixed_plain_bytes(n, k, slices);
+        if (need > kFixedScratchBytes)
+            return fail(DFA_ENOMEM,
+                        "n = %u, k = %u needs about %zu bytes of workspace; the fixed workspace "
+                        "holds %zu",
+                        n, k, need, kFixedScratchBytes);
         // a graph's instantiation allocates: chunks are launched one by one
         if (o.loop_mode == DFA_LOOP_GRAPH) o.loop_mode = DFA_LOOP_CHUNK;
         // every call carves its buffers afresh from the start of the array

@@ -2526,7 +2526,13 @@ void launch_insert(const RoundArgs &a, hipStream_t s) {
 
 void launch_mark(const RoundArgs &a, hipStream_t s) {
     const SigParams sp = sig_params(a);
-    const unsigned cap = a.round_grid_cap ? std::min(a.round_grid_cap, kMarkGridCap) : kMarkGridCap;
+    // every workgroup loads the changed-id summary into LDS, so the grid is
+    // capped; without the summary (too large for LDS) the cap is the round
+    // kernels'
+    const bool summary = summary_words(a.N) <= kSumLdsWords;
+    const unsigned cap = !summary ? a.round_grid_cap
+                         : a.round_grid_cap ? std::min(a.round_grid_cap, kMarkGridCap)
+                                            : kMarkGridCap;
     const dim3 grid(round_grid(a, cap)), block(kBlock);
     switch (a.k_eff) {
         case 1: launch_kernel(k_mark<1>, grid, block, 0, s, sp); break;
