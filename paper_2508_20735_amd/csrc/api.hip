@@ -2253,6 +2253,12 @@ void release_ctx(Ctx &c) {
 // the set-up), and buffers carved from the device's copy of `scratch`.
 Ctx g_fixed[kMaxDevices];
 
+// The tuning set for each device (dfa_set_tuning), which every call on the
+// device reads, whichever context runs it; the defaults until one is set.
+std::mutex g_tuning_mu;
+dfa_tuning g_tuning[kMaxDevices];
+bool g_tuning_set[kMaxDevices];
+
 // Set-up on the current device (once): the device address of `scratch`, and
 // every buffer of the context bound to it.
 int init_fixed(Ctx &c) {
@@ -2837,6 +2843,10 @@ int dfa_set_tuning(const dfa_tuning *t) {
         CallScope lock(c->mu);
         DFA_TRY(init_ctx(*c));
         c->tune = *t;
+        const int dev = static_cast<int>(c - g_ctx);
+        std::lock_guard<std::mutex> g(g_tuning_mu);
+        g_tuning[dev] = *t;
+        g_tuning_set[dev] = true;
         return DFA_OK;
     });
 }
@@ -2900,6 +2910,10 @@ int dfa_minimise_device_fixed(uint32_t n, uint32_t k, const uint32_t *delta,
         Ctx &c = g_fixed[dev];
         CallScope lock(c.mu);
         DFA_TRY(init_fixed(c));
+        {  // the device's tuning, as for every other call on it
+            std::lock_guard<std::mutex> g(g_tuning_mu);
+            if (g_tuning_set[dev]) c.tune = g_tuning[dev];
+        }
         // (the same rule as build_slices, with every letter counted)
         const bool slices = c.tune.slice_min_states && n >= c.tune.slice_min_states &&
                             n <= (static_cast<uint64_t>(kPbMaxBuckets) << kPbSliceLog) &&

@@ -78,3 +78,18 @@ def test_fixed_rejects_oversize_before_any_work():
     del delta, acc
     # still usable afterwards
     _compare(W.random_dfa(20_000, 3, 0.2, 34))
+
+
+def test_fixed_reads_the_device_tuning():
+    """The device's tuning (dfa_set_tuning) applies to the allocation-free
+    entry point as to every other call: without label rounds the chain's
+    closure is switched on at another round, and both entry points agree."""
+    B.load(build_if_missing=False)
+    before = B.get_tuning()
+    try:
+        B.set_tuning(label_rounds=0)
+        d = W.chain_with_tail(400, 210, 7)
+        for loop in ("host", "chunk"):
+            _compare(d, tc="auto", loop=loop)
+    finally:
+        B.set_tuning(**before)
