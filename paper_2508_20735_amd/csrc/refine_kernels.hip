@@ -1112,7 +1112,9 @@ __global__ __launch_bounds__(kBlock) void k_pb_scatter(const uint32_t *cols, con
 // Pass A: one or more workgroups per bucket; each loads the bucket's slice of
 // the round's ids into LDS and writes the gathered id of its share of the
 // bucket's edges.
-__global__ __launch_bounds__(kBlock) void k_pb_gather(SigParams p, uint32_t per_bucket) {
+constexpr uint32_t kPbGatherThreads = 1024;  // one workgroup of 16 waves per bucket
+
+__global__ __launch_bounds__(kPbGatherThreads) void k_pb_gather(SigParams p, uint32_t per_bucket) {
     extern __shared__ uint32_t slice[];
     if (!pb_round(p.pb, *p.ctl, p.N)) return;
     const uint32_t r = p.ctl->round;
@@ -1127,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void k_pb_gather(SigParams p, uint32_t per_
         const size_t s0 = static_cast<size_t>(b) * S;
         const uint32_t len = static_cast<uint32_t>(p.N - s0 < S ? p.N - s0 : S);
         __syncthreads();  // the previous job's gathers are done with the slice
-        for (uint32_t i = threadIdx.x; i < len; i += kBlock) slice[i] = X[s0 + i];
+        for (uint32_t i = threadIdx.x; i < len; i += kPbGatherThreads) slice[i] = X[s0 + i];
         __syncthreads();
         const uint32_t lo = pb.bstart[b], hi = pb.bstart[b + 1];
         const uint32_t chunk = (hi - lo + per_bucket - 1) / per_bucket;
@@ -1137,8 +1139,8 @@ __global__ __launch_bounds__(kBlock) void k_pb_gather(SigParams p, uint32_t per_
         // after a scalar head up to a multiple of four
         const uint32_t al = (a0 + 3u) & ~3u;
         const uint32_t v0 = al < a1 ? al : a1;
-        for (uint32_t e = a0 + threadIdx.x; e < v0; e += kBlock) pb.val[e] = slice[pb.tl[e]];
-        for (uint32_t e = v0 + 4 * threadIdx.x; e < a1; e += 4 * kBlock) {
+        for (uint32_t e = a0 + threadIdx.x; e < v0; e += kPbGatherThreads) pb.val[e] = slice[pb.tl[e]];
+        for (uint32_t e = v0 + 4 * threadIdx.x; e < a1; e += 4 * kPbGatherThreads) {
             if (e + 4 <= a1) {
                 const uint2 tv = *reinterpret_cast<const uint2 *>(pb.tl + e);
                 uint4 v;
@@ -2479,9 +2481,11 @@ void launch_pb_gather(const RoundArgs &a, hipStream_t s) {
     const SigParams sp = sig_params(a);
     // one workgroup per bucket (measured on MI355X with 2^23 states: one
     // 64 KB slice per workgroup gathered 364 G ids/s; two or four workgroups
-    // per bucket, each loading the slice, 305 and 229; 128 KB slices 199)
+    // per bucket, each loading the slice, 305 and 229; 128 KB slices 199),
+    // of 1,024 threads: two per CU then hold 32 waves instead of 8 (a 2^23-
+    // state union's dense round 87 -> 44 us)
     const uint32_t per_bucket = 1u;
-    launch_kernel(k_pb_gather, dim3(a.pb.nb * per_bucket), dim3(kBlock),
+    launch_kernel(k_pb_gather, dim3(a.pb.nb * per_bucket), dim3(kPbGatherThreads),
                   (1u << kPbSliceLog) * 4u, s, sp, per_bucket);
 }
 
