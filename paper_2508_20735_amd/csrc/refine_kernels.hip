@@ -831,6 +831,11 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
 // kernels (a tile holds kPbTile / kBlock = 8 per thread).
 template <int KC>
 constexpr int kPbBatch = KC <= 4 ? 8 : (KC <= 8 ? 4 : 2);
+// The scatter's workgroups are twice as wide: its LDS (the tile's edges)
+// allows two per CU, which then hold 16 waves instead of 8.
+constexpr uint32_t kPbScatterThreads = 2 * kBlock;
+template <int KC>
+constexpr int kPbScatterBatch = kPbBatch<KC> / 2;
 
 // Edge counts per (tile, bucket), tile-major: cnt[t * nb + b] is the length
 // of tile t's run in bucket b (one coalesced row per tile).
@@ -949,12 +954,13 @@ __global__ __launch_bounds__(kBlock) void k_pb_apply(const uint32_t *cnt, const 
 // the bucketed edge list), rstart[b] = the run's start in the tile's own edge
 // order (the runs back to back, bucket by bucket), rstart[nb] = the tile's
 // edge count.  Ends with a barrier.
+template <uint32_t NT = kBlock>
 __device__ __forceinline__ void pb_tile_runs(const PbArgs &pb, uint32_t t, uint32_t *rstart,
                                              uint32_t *rbase, uint32_t *wsum) {
     const uint32_t tx = threadIdx.x;
     const size_t row = static_cast<size_t>(t) * pb.nb;
     uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < pb.nb; b0 += kBlock) {
+    for (uint32_t b0 = 0; b0 < pb.nb; b0 += NT) {
         const uint32_t b = b0 + tx;
         uint32_t len = 0;
         if (b < pb.nb) {
@@ -973,7 +979,7 @@ __device__ __forceinline__ void pb_tile_runs(const PbArgs &pb, uint32_t t, uint3
         for (uint32_t w = 0; w < tx / 64; ++w) before += wsum[w];
         if (b < pb.nb) rstart[b] = before + x - len;
         uint32_t total = carry;
-        for (uint32_t w = 0; w < kBlock / 64; ++w) total += wsum[w];
+        for (uint32_t w = 0; w < NT / 64; ++w) total += wsum[w];
         __syncthreads();
         carry = total;
     }
@@ -989,13 +995,14 @@ __device__ __forceinline__ void pb_tile_runs(const PbArgs &pb, uint32_t t, uint3
 // lpos is given, lpos[b] = the run's start in the tile's order.  Each run is
 // filled by the thread that scans its length.  Returns the tile's edge
 // count; ends with a barrier.
+template <uint32_t NT = kBlock>
 __device__ __forceinline__ uint32_t pb_tile_run_ids(const PbArgs &pb, uint32_t t, uint16_t *rid,
                                                     uint32_t *delta, uint32_t *lpos,
                                                     uint32_t *wsum, uint32_t *tot) {
     const uint32_t tx = threadIdx.x;
     const size_t row = static_cast<size_t>(t) * pb.nb;
     uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < pb.nb; b0 += kBlock) {
+    for (uint32_t b0 = 0; b0 < pb.nb; b0 += NT) {
         const uint32_t b = b0 + tx;
         uint32_t len = 0, at = 0;
         if (b < pb.nb) {
@@ -1019,7 +1026,7 @@ __device__ __forceinline__ uint32_t pb_tile_run_ids(const PbArgs &pb, uint32_t t
             for (uint32_t l = 0; l < len; ++l) rid[start + l] = static_cast<uint16_t>(b);
         }
         uint32_t total = carry;
-        for (uint32_t w = 0; w < kBlock / 64; ++w) total += wsum[w];
+        for (uint32_t w = 0; w < NT / 64; ++w) total += wsum[w];
         __syncthreads();
         carry = total;
     }
@@ -1048,14 +1055,14 @@ __device__ __forceinline__ uint32_t pb_run_of(const uint32_t *rstart, uint32_t n
 // out contiguously, so the stores coalesce instead of landing two bytes at a
 // time in hundreds of runs.
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_pb_scatter(const uint32_t *cols, const uint32_t *colmap,
+__global__ __launch_bounds__(kPbScatterThreads) void k_pb_scatter(const uint32_t *cols, const uint32_t *colmap,
                                                         size_t N, PbArgs pb) {
     constexpr bool kIds = KC <= 4;
     __shared__ uint32_t rs[kPbMaxBuckets + 1];           // run starts, or deltas
     __shared__ uint32_t rb[kIds ? 1 : kPbMaxBuckets];    // run bases (search)
     __shared__ uint16_t rid[kIds ? kPbTile * KC : 2];    // run ids (small alphabets)
     __shared__ uint32_t lpos[kPbMaxBuckets];
-    __shared__ uint32_t wsum[kBlock / 64];
+    __shared__ uint32_t wsum[kPbScatterThreads / 64];
     __shared__ uint32_t tot;
     __shared__ uint16_t ltl[kPbTile * KC];
     __shared__ uint16_t lsrc[kPbTile * KC];
@@ -1064,26 +1071,26 @@ __global__ __launch_bounds__(kBlock) void k_pb_scatter(const uint32_t *cols, con
     for (uint32_t t = blockIdx.x; t < pb.ntiles; t += gridDim.x) {
         uint32_t total;
         if constexpr (kIds) {
-            total = pb_tile_run_ids(pb, t, rid, rs, lpos, wsum, &tot);
+            total = pb_tile_run_ids<kPbScatterThreads>(pb, t, rid, rs, lpos, wsum, &tot);
         } else {
-            pb_tile_runs(pb, t, rs, rb, wsum);
-            for (uint32_t b = tx; b < pb.nb; b += kBlock) lpos[b] = rs[b];
+            pb_tile_runs<kPbScatterThreads>(pb, t, rs, rb, wsum);
+            for (uint32_t b = tx; b < pb.nb; b += kPbScatterThreads) lpos[b] = rs[b];
             total = rs[pb.nb];
             __syncthreads();
         }
         const size_t base = static_cast<size_t>(t) * kPbTile;
         // the loads of a batch of states go out before their atomics
-        for (uint32_t i0 = 0; i0 < kPbTile; i0 += kPbBatch<KC> * kBlock) {
-            uint32_t tg[kPbBatch<KC>][KC];
+        for (uint32_t i0 = 0; i0 < kPbTile; i0 += kPbScatterBatch<KC> * kPbScatterThreads) {
+            uint32_t tg[kPbScatterBatch<KC>][KC];
 #pragma unroll
-            for (int u = 0; u < kPbBatch<KC>; ++u) {
-                const size_t q = base + i0 + u * kBlock + tx;
+            for (int u = 0; u < kPbScatterBatch<KC>; ++u) {
+                const size_t q = base + i0 + u * kPbScatterThreads + tx;
 #pragma unroll
                 for (int a = 0; a < KC; ++a) tg[u][a] = q < N ? colp.c[a][q] : ~0u;
             }
 #pragma unroll
-            for (int u = 0; u < kPbBatch<KC>; ++u) {
-                const uint32_t i = i0 + u * kBlock + tx;
+            for (int u = 0; u < kPbScatterBatch<KC>; ++u) {
+                const uint32_t i = i0 + u * kPbScatterThreads + tx;
 #pragma unroll
                 for (int a = 0; a < KC; ++a) {
                     if (tg[u][a] == ~0u) continue;
@@ -1094,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_pb_scatter(const uint32_t *cols, con
             }
         }
         __syncthreads();
-        for (uint32_t j = tx; j < total; j += kBlock) {
+        for (uint32_t j = tx; j < total; j += kPbScatterThreads) {
             uint32_t e;
             if constexpr (kIds) {
                 e = j + rs[rid[j]];
@@ -2455,7 +2462,7 @@ void pb_build_k(const uint32_t *cols, const uint32_t *colmap, size_t N, const Pb
     launch_kernel(k_pb_bscan, dim3(1), dim3(1024), 0, s, btot, pb.nb, pb.bstart);
     launch_kernel(k_pb_apply, dim3(nchunks), block, 0, s, pb.cnt, csum, pb.bstart, pb.nb,
                   pb.ntiles, pb.off);
-    launch_kernel(k_pb_scatter<KC>, tiles, block, 0, s, cols, colmap, N, pb);
+    launch_kernel(k_pb_scatter<KC>, tiles, dim3(kPbScatterThreads), 0, s, cols, colmap, N, pb);
 }
 
 }  // namespace
