@@ -358,7 +358,7 @@ int upload(Ctx &c, void *dev, const void *host, size_t bytes) {
 
 enum class Kern {
     Mark, Signature, Insert, SortGroup, RoundEnd, Pattern, Packed, LeaderElect, LeaderMove,
-    LeaderEnd, PbGather, SignaturePb, SegPattern
+    LeaderEnd, PbGather, SignaturePb, SegPattern, PackedPb
 };
 
 int prof_event(Ctx &c, size_t &idx) {
@@ -390,6 +390,7 @@ uint32_t kern_bytes(Kern kind, uint32_t k_eff) {
         case Kern::Insert: return 4;
         case Kern::Pattern:
         case Kern::Packed:
+        case Kern::PackedPb:
         case Kern::SegPattern: return 5 * k_eff + 5;
         case Kern::LeaderElect: return 16 * k_eff;
         default: return 0;
@@ -409,6 +410,7 @@ const char *kern_name(Kern kind) {
         case Kern::LeaderMove: return "k_leader_move";
         case Kern::PbGather: return "k_pb_gather";
         case Kern::SegPattern: return "k_seg_pattern";
+        case Kern::PackedPb: return "k_packed_pb";
         case Kern::SignaturePb: return "k_signature_pb";
         default: return "k_leader_end";
     }
@@ -429,6 +431,7 @@ int launch_kern(Ctx &c, Kern kind, const Args &a, uint32_t round) {
             case Kern::Signature: launch_signature(a, c.stream); break;
             case Kern::PbGather: launch_pb_gather(a, c.stream); break;
             case Kern::SegPattern: launch_seg_pattern(a, c.stream); break;
+            case Kern::PackedPb: launch_packed_pb(a, c.stream); break;
             case Kern::SignaturePb: launch_signature_pb(a, c.stream); break;
             case Kern::Insert: launch_insert(a, c.stream); break;
             case Kern::SortGroup: launch_sort_group(a, c.stream); break;
@@ -930,7 +933,8 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
                 DFA_TRY(launch_full_round(c, ra, 0));
             }
             if (packed_second) {
-                DFA_TRY(launch_kern(c, Kern::Packed, ra, 1));
+                // through the slices when the edges are bucketed (k_eff <= 4)
+                DFA_TRY(launch_kern(c, ra.pb.nb ? Kern::PackedPb : Kern::Packed, ra, 1));
                 DFA_TRY(launch_kern(c, Kern::RoundEnd, ra, 1));
             }
             HIP_TRY(hipGetLastError());

@@ -277,6 +277,9 @@ void launch_seg_round(const RoundArgs &a, hipStream_t s);
 // nothing in rounds that gather directly.
 void launch_pb_gather(const RoundArgs &a, hipStream_t s);
 void launch_signature_pb(const RoundArgs &a, hipStream_t s);
+// Round 1 (packed labels, k_eff <= 4) through the slices: the byte labels'
+// pass A, then the keys and the label count per source tile.
+void launch_packed_pb(const RoundArgs &a, hipStream_t s);
 void launch_signature(const RoundArgs &a, hipStream_t s);
 void launch_insert(const RoundArgs &a, hipStream_t s);
 void launch_round_end(const RoundArgs &a, hipStream_t s);

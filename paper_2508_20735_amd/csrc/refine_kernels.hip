@@ -1218,6 +1218,180 @@ __device__ __forceinline__ void pb_tile_keys(const PbArgs &pb, uint32_t t, uint3
     __syncthreads();
 }
 
+// Round 1 (packed labels) through the slices.  Pass A: the bucket's slice
+// of round-0 byte labels (16 KB) into LDS, one byte per edge written next to
+// it (the id array pb.val read as bytes).
+__global__ __launch_bounds__(kPbGatherThreads) void k_pb_gather8(SigParams p) {
+    __shared__ uint8_t slice[1u << kPbSliceLog];
+    if (p.ctl->done) return;
+    const PbArgs &pb = p.pb;
+    uint8_t *__restrict__ val8 = reinterpret_cast<uint8_t *>(pb.val);
+    constexpr uint32_t S = 1u << kPbSliceLog;
+    const uint32_t tx = threadIdx.x;
+    for (uint32_t b = blockIdx.x; b < pb.nb; b += gridDim.x) {
+        const size_t s0 = static_cast<size_t>(b) * S;
+        const uint32_t len = static_cast<uint32_t>(p.N - s0 < S ? p.N - s0 : S);
+        __syncthreads();  // the previous bucket's gathers are done with the slice
+        // (s0 is a multiple of 2^kPbSliceLog: four labels per aligned word)
+        for (uint32_t i = 4 * tx; i < len; i += 4 * kPbGatherThreads) {
+            if (i + 4 <= len) {
+                *reinterpret_cast<uint32_t *>(slice + i) =
+                    *reinterpret_cast<const uint32_t *>(p.lab8 + s0 + i);
+            } else {
+                for (uint32_t f = i; f < len; ++f) slice[f] = p.lab8[s0 + f];
+            }
+        }
+        __syncthreads();
+        const uint32_t lo = pb.bstart[b], hi = pb.bstart[b + 1];
+        const uint32_t al = (lo + 3u) & ~3u;
+        const uint32_t v0 = al < hi ? al : hi;
+        for (uint32_t e = lo + tx; e < v0; e += kPbGatherThreads) val8[e] = slice[pb.tl[e]];
+        for (uint32_t e = v0 + 4 * tx; e < hi; e += 4 * kPbGatherThreads) {
+            if (e + 4 <= hi) {
+                const uint2 tv = *reinterpret_cast<const uint2 *>(pb.tl + e);
+                const uint32_t v = static_cast<uint32_t>(slice[tv.x & 0xFFFFu]) |
+                                   static_cast<uint32_t>(slice[tv.x >> 16]) << 8 |
+                                   static_cast<uint32_t>(slice[tv.y & 0xFFFFu]) << 16 |
+                                   static_cast<uint32_t>(slice[tv.y >> 16]) << 24;
+                *reinterpret_cast<uint32_t *>(val8 + e) = v;
+            } else {
+                for (uint32_t f = e; f < hi; ++f) val8[f] = slice[pb.tl[f]];
+            }
+        }
+    }
+}
+
+// Pass B of round 1: tile t's byte labels from every bucket into
+// key8[(state - tile start) * KC + letter], as pb_tile_keys does with ids.
+// Ends with a barrier.
+template <int KC>
+__device__ __forceinline__ void pb_tile_keys8(const PbArgs &pb, uint32_t t, uint8_t *key8,
+                                              PbRunsLds<KC> &L) {
+    const uint32_t tx = threadIdx.x;
+    const uint8_t *__restrict__ val8 = reinterpret_cast<const uint8_t *>(pb.val);
+    uint32_t total;
+    if constexpr (PbRunsLds<KC>::kIds) {
+        total = pb_tile_run_ids(pb, t, L.rid, L.rs, nullptr, L.wsum, &L.tot);
+    } else {
+        pb_tile_runs(pb, t, L.rs, L.rb, L.wsum);
+        total = L.rs[pb.nb];
+    }
+    constexpr int B = 8;
+    for (uint32_t j0 = 0; j0 < total; j0 += B * kBlock) {
+        uint32_t e[B];
+        bool ok[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t j = j0 + u * kBlock + tx;
+            ok[u] = j < total;
+            if constexpr (PbRunsLds<KC>::kIds) {
+                e[u] = ok[u] ? j + L.rs[L.rid[j]] : 0u;
+            } else {
+                const uint32_t lo = pb_run_of(L.rs, pb.nb, j);
+                e[u] = ok[u] ? L.rb[lo] + (j - L.rs[lo]) : 0u;
+            }
+        }
+        uint32_t sv[B], vv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            sv[u] = ok[u] ? pb.src[e[u]] : 0u;
+            vv[u] = ok[u] ? val8[e[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (ok[u]) key8[sv[u]] = static_cast<uint8_t>(vv[u]);
+    }
+    __syncthreads();
+}
+
+// Pass B of round 1 (packed labels, k_eff <= 4): one workgroup per source
+// tile; the keys and the distinct-label count as k_packed_round computes
+// them, the tile's states taken 2 * kBlock at a time so that the LDS label
+// set (emptied when half full) always has room.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_packed_pb(SigParams p) {
+    __shared__ uint8_t key8[kPbTile * KC];
+    __shared__ PbRunsLds<KC> runs;
+    __shared__ uint32_t lset[kLabelSlots];
+    __shared__ uint32_t lfill;
+    if (p.ctl->done) return;
+    const PbArgs &pb = p.pb;
+    const uint32_t r = p.ctl->round;
+    uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
+    constexpr uint32_t bits = KC + 1;
+    constexpr int EP = kPbTile / kBlock;
+    const uint32_t tx = threadIdx.x;
+    uint32_t fresh = 0;
+    for (uint32_t i = tx; i < kLabelSlots; i += kBlock) lset[i] = ~0u;
+    if (tx == 0) lfill = 0;
+    __syncthreads();
+    for (uint32_t t = blockIdx.x; t < pb.ntiles; t += gridDim.x) {
+        const size_t base = static_cast<size_t>(t) * kPbTile;
+        uint32_t own[EP];
+#pragma unroll
+        for (int e = 0; e < EP; ++e) {
+            const size_t q = base + e * kBlock + tx;
+            own[e] = q < p.N ? p.lab8[q] : 0u;
+        }
+        pb_tile_keys8<KC>(pb, t, key8, runs);
+#pragma unroll
+        for (int e0 = 0; e0 < EP; e0 += 2) {
+            // every thread reads the same fill (the last step ended with a
+            // barrier, and so did the key assembly) before any thread
+            // inserts; a step adds at most 2 * kBlock labels to a set at
+            // most half full
+            const bool half_full = lfill > kLabelSlots / 2;
+            __syncthreads();
+            if (half_full) {
+                for (uint32_t i = tx; i < kLabelSlots; i += kBlock) lset[i] = ~0u;
+                if (tx == 0) lfill = 0;
+                __syncthreads();
+            }
+#pragma unroll
+            for (int e = e0; e < e0 + 2; ++e) {
+                const uint32_t i = e * kBlock + tx;
+                const size_t q = base + i;
+                if (q >= p.N) continue;
+                uint32_t key = own[e];
+#pragma unroll
+                for (int j = 0; j < KC; ++j)
+                    key |= static_cast<uint32_t>(key8[i * KC + j]) << (bits * (j + 1));
+                Y[q] = key;
+                uint32_t slot = (key * 0x9E3779B1u) >> 20;  // 12 bits: kLabelSlots
+                bool first = false;
+                for (;;) {
+                    const uint32_t v = __hip_atomic_load(lset + slot, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (v == key) break;
+                    if (v == ~0u) {
+                        const uint32_t prev = atomicCAS(lset + slot, ~0u, key);
+                        if (prev == ~0u) {
+                            first = true;
+                            atomicAdd(&lfill, 1u);
+                            break;
+                        }
+                        if (prev == key) break;
+                    }
+                    slot = (slot + 1) & (kLabelSlots - 1);
+                }
+                if (first) {
+                    uint32_t *word = p.presence_packed + (key >> 5);
+                    const uint32_t bit = 1u << (key & 31);
+                    const uint32_t seen =
+                        __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (!(seen & bit)) fresh += (atomicOr(word, bit) & bit) ? 0u : 1u;
+                }
+            }
+            // the step's inserts are done before any thread reads the fill
+            // for the next step (every thread must see the same fill: the
+            // emptying branch holds a barrier)
+            __syncthreads();
+        }
+    }
+    wg_add_spread(p.counters, 0, fresh);
+    wg_add_spread(p.counters, 3, fresh);
+}
+
 // Pass B: one workgroup per source tile of kPbTile states: the tile's keys
 // from the buckets, then what the signature kernel does with each state.
 template <int KC>
@@ -2494,6 +2668,22 @@ void launch_pb_gather(const RoundArgs &a, hipStream_t s) {
     const uint32_t per_bucket = 1u;
     launch_kernel(k_pb_gather, dim3(a.pb.nb * per_bucket), dim3(kPbGatherThreads),
                   (1u << kPbSliceLog) * 4u, s, sp, per_bucket);
+}
+
+void launch_packed_pb(const RoundArgs &a, hipStream_t s) {
+    if (!a.pb.nb) return;
+    const SigParams sp = sig_params(a);
+    launch_kernel(k_pb_gather8, dim3(a.pb.nb), dim3(kPbGatherThreads), 0, s, sp);
+    // one workgroup per tile (the kernel also takes fewer, each then keeping
+    // its label set over several tiles)
+    const dim3 grid(a.pb.ntiles), block(kBlock);
+    switch (a.k_eff) {
+        case 1: launch_kernel(k_packed_pb<1>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_packed_pb<2>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_packed_pb<3>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_packed_pb<4>, grid, block, 0, s, sp); break;
+        default: break;  // packed labels only for k_eff <= 4
+    }
 }
 
 void launch_signature_pb(const RoundArgs &a, hipStream_t s) {
