@@ -473,6 +473,29 @@ __global__ __launch_bounds__(kBlock) void k_packed_round(SigParams p) {
 // their block is now a singleton, and marks the blocks with a member whose
 // successor changed id in the last round.  It also clears the touched bitmap
 // of the next round.
+// Sets bit xi of the bitmap T for the lanes with `want` (every lane of the
+// wave calls it).  Lanes whose bits share a word are merged into one atomic:
+// in id order (chains, twins laid out in the same order) a wave's 64 marks
+// often fall into one word, and 64 atomics on one address serialise.  At most
+// two merges (the second only if the first merged several lanes); the lanes
+// left set their bits one by one.
+__device__ __forceinline__ void wave_mark_bit(unsigned long long *T, uint32_t xi, bool want) {
+    const uint32_t w = xi >> 6;
+    const unsigned long long bit = 1ull << (xi & 63);
+    unsigned long long pending = __ballot(want);
+    for (int pass = 0; pass < 2 && pending; ++pass) {
+        const int lead = __ffsll(pending) - 1;
+        const uint32_t lw = __shfl(w, lead, 64);
+        const bool mine = ((pending >> lane_id()) & 1ull) && w == lw;
+        const unsigned long long grp = __ballot(mine);
+        const unsigned long long v = wave_or64(mine ? bit : 0ull);
+        if (static_cast<int>(lane_id()) == lead) atomicOr(T + lw, v);
+        pending &= ~grp;
+        if (__popcll(grp) < 2) break;
+    }
+    if ((pending >> lane_id()) & 1ull) atomicOr(T + w, bit);
+}
+
 template <int KC>
 __device__ __forceinline__ void mark_body(const SigParams &p) {
     if (p.ctl->done) return;
@@ -588,9 +611,8 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
         }
 #pragma unroll
         for (int i = 0; i < S; ++i) {
-            if (!dirty[i]) continue;
-            const uint32_t xi = was_active[i] ? x[i] : X[q[i]];
-            atomicOr(T + (xi >> 6), 1ull << (xi & 63));
+            const uint32_t xi = dirty[i] ? (was_active[i] ? x[i] : X[q[i]]) : 0u;
+            wave_mark_bit(T, xi, dirty[i]);
         }
     }
 }
