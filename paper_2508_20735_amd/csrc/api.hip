@@ -1658,7 +1658,9 @@ int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, bool pair
     DFA_TRY(c.tile_part.ensure(tiles * sizeof(uint32_t), "batch tiles"));
     DFA_TRY(c.seg_words.ensure((5 * static_cast<size_t>(nseg) + 1) * sizeof(uint32_t),
                                "segment counters"));
-    DFA_TRY(c.tile_dead.ensure(tiles, "decided tiles"));
+    // flags, then (2-byte aligned) the holder counts of decided tiles
+    const size_t lead_at = (tiles + 1) & ~static_cast<size_t>(1);
+    DFA_TRY(c.tile_dead.ensure(lead_at + 2 * tiles, "decided tiles"));
     HIP_TRY(hipMemcpy(c.parts.p, parts.data(), parts.size() * sizeof(Part),
                       hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c.tile_part.p, tile_part.data(), tiles * sizeof(uint32_t),
@@ -1678,6 +1680,7 @@ int upload_plan(Ctx &c, const std::vector<Part> &parts, uint32_t nseg, bool pair
     g.init_count = w + 5 * static_cast<size_t>(nseg);
     g.pairs = pairs ? 1u : 0u;
     g.tile_dead = c.tile_dead.as<uint8_t>();
+    g.tile_lead = reinterpret_cast<uint16_t *>(c.tile_dead.as<uint8_t>() + lead_at);
     return DFA_OK;
 }
 

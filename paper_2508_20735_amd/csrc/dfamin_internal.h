@@ -140,6 +140,8 @@ struct SegArgs {
     uint32_t *init_count;     // sum over segments of their class counts
     uint32_t pairs;           // 1: segment s is the union of parts 2s and 2s + 1
     uint8_t *tile_dead;       // per tile of kBlock states: 1 once all its segments are decided
+    uint16_t *tile_lead;      // per tile: states holding their block's id, written when the
+                              // tile is found decided (its ids never change again)
 };
 
 // Transposes every part into cols (targets offset by the part's first

@@ -245,7 +245,37 @@ struct SigParams {
     const uint32_t *tile_part;
     uint32_t nparts;
     PbArgs pb;  // nb > 0: dense rounds gather through LDS slices
+    // segmented refinements: decided tiles and their holders (else null)
+    const uint8_t *tile_dead;
+    const uint16_t *tile_lead;
 };
+
+// Segmented refinements: whether every kBlock-state tile of [base, base + n)
+// (base a multiple of kBlock, base < N) holds only decided segments.  Their
+// ids never change again and both block buffers hold them, so every round
+// kernel skips them.  Uniform across the workgroup.
+__device__ __forceinline__ bool tiles_dead(const uint8_t *dead, size_t N, size_t base,
+                                           uint32_t n) {
+    if (!dead) return false;
+    const size_t end = base + n < N ? base + n : N;
+    for (size_t t = base / kBlock; t * kBlock < end; ++t)
+        if (!dead[t]) return false;
+    return true;
+}
+
+// The states of those tiles that hold their block's id (the block count
+// includes them every round).
+__device__ __forceinline__ uint32_t dead_holders(const uint16_t *lead, size_t N, size_t base,
+                                                 uint32_t n) {
+    const size_t end = base + n < N ? base + n : N;
+    uint32_t h = 0;
+    for (size_t t = base / kBlock; t * kBlock < end; ++t) h += lead[t];
+    return h;
+}
+
+__device__ __forceinline__ uint32_t states_in(size_t N, size_t base, uint32_t n) {
+    return static_cast<uint32_t>((base + n < N ? base + n : N) - base);
+}
 
 // Letters a wave must read: in a segmented refinement, letters at or above
 // the largest alphabet of the parts that hold the wave's states are padding
@@ -537,6 +567,7 @@ __device__ __forceinline__ void mark_body(const SigParams &p) {
     constexpr int S = 4;
     for (size_t base = static_cast<size_t>(blockIdx.x) * (S * kBlock); base < p.N;
          base += static_cast<size_t>(gridDim.x) * (S * kBlock)) {
+        if (tiles_dead(p.tile_dead, p.N, base, S * kBlock)) continue;
         size_t q[S];
         unsigned long long sw[S], aw[S];
         bool s[S], was_active[S];
@@ -713,6 +744,10 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
         const TileRange tr = xcd_tiles(p.N, 2 * kBlock);
         for (size_t tile = tr.first; tile < tr.end; tile += tr.step) {
             const size_t base = tile * (2 * kBlock);
+            if (tiles_dead(p.tile_dead, p.N, base, 2 * kBlock)) {
+                if (threadIdx.x == 0) leaders += dead_holders(p.tile_lead, p.N, base, 2 * kBlock);
+                continue;
+            }
             const size_t q[2] = {base + threadIdx.x, base + kBlock + threadIdx.x};
             bool act[2];
             uint32_t w0[2], t[2][KC], w[2][KC];
@@ -785,6 +820,10 @@ __device__ __forceinline__ void signature_body(const SigParams &p) {
     } else {
         const TileRange tr = xcd_tiles(p.N, kBlock);
         for (size_t tile = tr.first; tile < tr.end; tile += tr.step) {
+            if (tiles_dead(p.tile_dead, p.N, tile * kBlock, kBlock)) {
+                if (threadIdx.x == 0) leaders += dead_holders(p.tile_lead, p.N, tile * kBlock, kBlock);
+                continue;
+            }
             const size_t q = tile * kBlock + threadIdx.x;
             const bool valid = q < p.N;
             const uint32_t w0 = valid ? X[q] : 0u;
@@ -1500,6 +1539,7 @@ struct InsParams {
     int lds_stage;
     unsigned long long *chg;
     unsigned long long *chg_sum;
+    const uint8_t *tile_dead;  // segmented refinements: decided tiles (else null)
 };
 
 // Stores a wave's changed-id mask and sets the summary bits of its groups
@@ -1535,6 +1575,10 @@ __device__ __forceinline__ void insert_body(const InsParams &p) {
     uint32_t blocks = 0, idle = 0, changed = 0;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
+        if (tiles_dead(p.tile_dead, p.N, base, kBlock)) {
+            if (threadIdx.x == 0) idle += states_in(p.N, base, kBlock);
+            continue;
+        }
         const size_t q = base + threadIdx.x;
         const size_t first = base + (threadIdx.x & ~63u);
         const unsigned long long am = first < p.N ? p.active[first >> 6] : 0ull;
@@ -1591,6 +1635,10 @@ __device__ __forceinline__ void insert_lds_body(const InsParams &p) {
     uint32_t blocks = 0, idle = 0, changed = 0;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kBlock; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kBlock) {
+        if (tiles_dead(p.tile_dead, p.N, base, kBlock)) {
+            if (tx == 0) idle += states_in(p.N, base, kBlock);
+            continue;
+        }
         const size_t q = base + tx;
         const size_t first = base + (tx & ~63u);
         const unsigned long long am = first < p.N ? p.active[first >> 6] : 0ull;
@@ -1712,6 +1760,10 @@ __device__ __forceinline__ void insert_lds2_body(const InsParams &p) {
     uint32_t blocks = 0, idle = 0, changed = 0;
     for (size_t base = static_cast<size_t>(blockIdx.x) * kTile; base < p.N;
          base += static_cast<size_t>(gridDim.x) * kTile) {
+        if (tiles_dead(p.tile_dead, p.N, base, kTile)) {
+            if (tx == 0) idle += states_in(p.N, base, kTile);
+            continue;
+        }
         size_t q[S], first[S];
         bool act[S];
         uint32_t loc[S];
@@ -2099,7 +2151,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_init(SegArgs g) {
 __device__ __forceinline__ void seg_count_body(const SegArgs &g, size_t N, const RoundCtl *ctl,
                                                const uint32_t *blockA, const uint32_t *blockB) {
     __shared__ uint32_t lcnt[kBlock];
-    __shared__ uint32_t seg_first, tile_live;
+    __shared__ uint32_t seg_first, tile_live, tile_dies, holders;
     if (ctl->done) return;
     const uint32_t r = ctl->round;
     const uint32_t *__restrict__ Y = (r & 1u) ? blockA : blockB;
@@ -2110,19 +2162,35 @@ __device__ __forceinline__ void seg_count_body(const SegArgs &g, size_t N, const
             // a tile whose segments are all decided has nothing to count (and
             // never has again: a decided segment stays decided)
             const size_t t = base / kBlock;
-            uint32_t live = 0;
+            uint32_t live = 0, dies = 0;
             if (!g.tile_dead[t]) {
                 uint32_t p = g.tile_part[t];
                 seg_first = g.parts[p].seg;
                 const size_t end = base + kBlock < N ? base + kBlock : N;
                 for (; p < g.nparts && g.parts[p].off < end; ++p)
                     live |= g.seg_done[g.parts[p].seg] == 0u;
-                if (!live) g.tile_dead[t] = 1;
+                dies = !live;
             }
             tile_live = live;
+            tile_dies = dies;
+            holders = 0;
         }
         __syncthreads();
         if (!tile_live) {
+            if (tile_dies) {
+                // the round kernels skip the tile from the next round on and
+                // count its block holders from here: the states of its
+                // segments were refined for the last time two rounds ago, and
+                // the round after that copied their ids into both buffers
+                const size_t q = base + threadIdx.x;
+                const unsigned long long hm = __ballot(q < N && Y[q] == q);
+                if (lane_id() == 0 && hm) atomicAdd(&holders, static_cast<uint32_t>(__popcll(hm)));
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    g.tile_lead[base / kBlock] = static_cast<uint16_t>(holders);
+                    g.tile_dead[base / kBlock] = 1;
+                }
+            }
             __syncthreads();  // every thread has read tile_live
             continue;
         }
@@ -2475,7 +2543,9 @@ SigParams sig_params(const RoundArgs &a) {
                      a.lab8,     a.counters,   a.ctl,      a.cached_probe, a.chg,
                      a.single,   a.touched,    a.chg_sum,  a.grouping, a.hash_bits,
                      a.seg.nseg ? a.seg.parts : nullptr,      a.seg.nseg ? a.seg.tile_part : nullptr,
-                     a.seg.nseg ? a.seg.nparts : 0u, a.pb};
+                     a.seg.nseg ? a.seg.nparts : 0u, a.pb,
+                     a.seg.nseg ? a.seg.tile_dead : nullptr,
+                     a.seg.nseg ? a.seg.tile_lead : nullptr};
 }
 
 // Workgroups of a round kernel whose workgroups take `tile` states at a
@@ -2490,7 +2560,8 @@ unsigned round_grid(const RoundArgs &a, unsigned cap, size_t tile = kBlock) {
 InsParams ins_params(const RoundArgs &a) {
     return InsParams{a.sig,    a.hash,   a.N,     a.k_eff + 1, a.table,    a.table_cap - 1,
                      a.blockA, a.blockB, a.multi, a.active,    a.counters, a.ctl,
-                     a.cached_probe, a.lds_stage, a.chg, a.chg_sum};
+                     a.cached_probe, a.lds_stage, a.chg, a.chg_sum,
+                     a.seg.nseg ? a.seg.tile_dead : nullptr};
 }
 
 // Workgroups of the persistent loop: no more than fit on the device at once.
