@@ -805,11 +805,11 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     DFA_TRY(c.single.ensure(words64 * sizeof(unsigned long long), "singleton bits"));
     DFA_TRY(c.touched.ensure(2 * words64 * sizeof(unsigned long long), "touched-block bits"));
     DFA_TRY(c.chg_sum.ensure(2 * sum_words * sizeof(unsigned long long), "changed-wave summary"));
-    // label rounds: the packed-label bitmap too when k letters could use it
+    // label rounds: the packed-label map too when k letters could use it
     // (identity letters, known after the readback, only make k_eff smaller)
     const bool packed_possible = !seg && (k + 1) * (k + 1) <= kPackedMaxBits;
     if (packed_possible)
-        DFA_TRY(c.presence_packed.ensure((size_t(1) << kPackedMaxBits) / 8, "label bitmap"));
+        DFA_TRY(c.presence_packed.ensure(kLabelMapBytes, "label map"));
     {
         ZeroList z{};
         DFA_TRY(zero_add(z, c.table, cap * sizeof(unsigned long long)));
@@ -817,7 +817,7 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
         DFA_TRY(zero_add(z, c.touched, 2 * words64 * sizeof(unsigned long long)));
         DFA_TRY(zero_add(z, c.chg_sum, 2 * sum_words * sizeof(unsigned long long)));
         if (packed_possible)
-            DFA_TRY(zero_add(z, c.presence_packed, (size_t(1) << kPackedMaxBits) / 8));
+            DFA_TRY(zero_add(z, c.presence_packed, kLabelMapBytes));
         launch_zero(z, c.stream);
         HIP_TRY(hipGetLastError());
     }
@@ -877,8 +877,8 @@ int refine(Ctx &c, size_t N, uint32_t k, const dfa_options &o, uint32_t check_eq
     if (packed_second) {
         DFA_TRY(c.lab8.ensure(N, "byte labels"));
         if (!packed_possible) {  // not cleared above
-            DFA_TRY(c.presence_packed.ensure((size_t(1) << kPackedMaxBits) / 8, "label bitmap"));
-            HIP_TRY(hipMemsetAsync(c.presence_packed.p, 0, (size_t(1) << kPackedMaxBits) / 8,
+            DFA_TRY(c.presence_packed.ensure(kLabelMapBytes, "label map"));
+            HIP_TRY(hipMemsetAsync(c.presence_packed.p, 0, kLabelMapBytes,
                                    c.stream));
         }
     }
@@ -2291,12 +2291,12 @@ int init_fixed(Ctx &c) {
 // letters in the fixed context, each buffer rounded up to 256 bytes as the
 // arena carves it: columns 4k, block ids 8, marks 4, signatures 4(k + 1),
 // hashes 8, table <= 32, canonical ids, dense ids, leaders 12, byte labels 1,
-// bit masks < 1 per state; plus the label bitmaps and small control words;
+// bit masks < 1 per state; plus the label maps and small control words;
 // with `slices`, the edges bucketed by target slice (8 bytes per edge, run
 // counts and starts).
 size_t fixed_plain_bytes(uint64_t n, uint64_t k, bool slices) {
     const uint64_t table = 8 * next_pow2(std::max<uint64_t>(2 * n, 1024));
-    uint64_t bytes = n * (8 * k + 41) + table + (size_t(1) << kPackedMaxBits) / 8 +
+    uint64_t bytes = n * (8 * k + 41) + table + kLabelMapBytes +
                      (1u << kPatternMaxBits) / 8 + (size_t(64) << 10);
     if (slices) {
         const uint64_t nb = (n >> kPbSliceLog) + 1, tiles = n / kPbTile + 1;
@@ -2419,6 +2419,7 @@ size_t request_footprint(uint64_t n, uint32_t k, bool closure) {
                      + n * 8ull * k            // bucketed edges: target, source slot, gathered id
                      + slices * tiles * 12ull  // run lengths and starts, scan sums
                      + n * 2ull                // round-0 patterns (batches)
+                     + kLabelMapBytes          // the packed round's label map
                      + (1u << 22);             // fixed buffers
     if (k + 1 <= kSegPatMaxBits) bytes += 4ull << (k + 1);  // the request's pattern-table rows
     if (closure) {

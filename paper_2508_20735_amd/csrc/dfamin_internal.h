@@ -40,6 +40,8 @@ constexpr int kSpread = 64;        // per-round counters, one per 128-byte line
 constexpr int kSpreadStride = 32;  // uint32 words between two counters
 constexpr uint32_t kPatternMaxBits = 17;  // first round by bit patterns if k_eff + 1 <= 17
 constexpr uint32_t kPackedMaxBits = 25;   // round 1 by packed labels if (k_eff + 1)^2 <= 25
+// the packed round's label map: one byte per possible label
+constexpr size_t kLabelMapBytes = size_t(1) << kPackedMaxBits;
 // Changed-id summary: one bit per group of 2^kSumShift consecutive states,
 // set when a state of the group changed its id in the round; 64 groups per
 // word.  Incremental marking holds up to kSumLdsWords words in LDS.
@@ -210,7 +212,7 @@ struct RoundArgs {
     const unsigned long long *accbits;
     uint32_t *counters;  // kSpread * kSpreadStride words, zero between rounds
     uint32_t *presence;  // 2^kPatternMaxBits bits, zero between calls
-    uint32_t *presence_packed;  // 2^kPackedMaxBits bits, zero between calls
+    uint32_t *presence_packed;  // label map, kLabelMapBytes bytes, zero when a refinement starts
     uint8_t *lab8;       // round-0 labels as bytes (packed round 1 only)
     RoundCtl *ctl;
     int lds_stage;              // 0 never, 1 and 2 (automatic) every round

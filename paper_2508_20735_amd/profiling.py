@@ -27,13 +27,14 @@ from collections import defaultdict
 ROUND_KERNELS = ("k_mark", "k_signature", "k_insert", "k_insert_lds", "k_insert_lds2",
                  "k_round_end", "k_pattern_round", "k_packed_round", "k_pb_gather",
                  "k_signature_pb", "k_pb_count", "k_pb_scatter", "k_pb_gather8",
-                 "k_packed_pb")
+                 "k_packed_pb", "k_count_labels")
 # The library's per-kernel timing names a launch of the grouping step
 # "k_insert": one dispatch of an LDS-staged variant and one of the plain
 # kernel, of which exactly one does the round's work.  "k_packed_pb" is the
-# packed label round through slices: the byte gather, then the round.
+# packed label round through slices: the byte gather, the round, and the
+# count of the labels it marked.
 LIBRARY_GROUPS = {"k_insert": ("k_insert_lds2", "k_insert_lds", "k_insert"),
-                  "k_packed_pb": ("k_pb_gather8", "k_packed_pb")}
+                  "k_packed_pb": ("k_pb_gather8", "k_packed_pb", "k_count_labels")}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
