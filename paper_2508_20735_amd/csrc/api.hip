@@ -2393,8 +2393,9 @@ struct Server {
 };
 
 // Device bytes of a lane's workspace that do not scale with the requests:
-// every buffer is rounded up to 2 MiB (about 40 of them), plus the label
-// bitmaps; charged once per admitted group.
+// every buffer is rounded up to 2 MiB (about 40 of them), plus the pattern
+// bitmap; charged once per admitted group (each request's footprint also
+// counts the packed round's label map).
 constexpr size_t kGroupFixedBytes = size_t(96) << 20;
 
 // Sum of a lane's buffer capacities.

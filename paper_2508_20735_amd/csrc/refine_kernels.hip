@@ -385,9 +385,10 @@ __global__ __launch_bounds__(kBlock) void k_pattern_round(SigParams p) {
 // signature (label of q, labels of its successors) packs exactly into one
 // word, which becomes the new label.  Labels are gathered from the byte copy
 // written by round 0 (small enough to stay in L2).  Distinct labels are
-// counted by first setters in a presence bitmap; a workgroup first removes
-// the duplicates among the tiles it handles in an LDS set, so a frequent
-// label costs about one bitmap access per workgroup, not one per state.
+// marked in a map of one byte per label and counted by a pass over it; a
+// workgroup first removes the duplicates among the tiles it handles in an
+// LDS set, so a frequent label costs about one store per workgroup, not one
+// per state.
 constexpr uint32_t kLdsSlots = 2 * kBlock;
 // labels a workgroup remembers across its tiles; the set is emptied before a
 // tile once it is half full, so a tile (at most kBlock new labels) always
