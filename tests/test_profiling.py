@@ -46,3 +46,24 @@ def test_short_and_base_names():
     n = "void dfamin::(anonymous namespace)::k_pb_scatter<16>(unsigned int const*, ...)"
     assert P.short_name(n) == "k_pb_scatter<16>"
     assert P.base_name(n) == "k_pb_scatter"
+
+
+def test_packed_slice_round_is_one_library_launch(tmp_path):
+    """The packed label round through slices is three dispatches (byte
+    gather, round, label count) under one timing name, k_packed_pb."""
+    copy = "__amd_rocclr_copyBuffer"
+    g8 = "void dfamin::(anonymous namespace)::k_pb_gather8(dfamin::(anonymous namespace)::SigParams)"
+    pk = "void dfamin::(anonymous namespace)::k_packed_pb<4>(dfamin::(anonymous namespace)::SigParams)"
+    cnt = "void dfamin::(anonymous namespace)::k_count_labels(dfamin::(anonymous namespace)::SigParams)"
+    fetch = [(copy, 512), (g8, 40), (pk, 200), (cnt, 16384), (g8, 60), (pk, 300), (cnt, 16384)]
+    write = [(copy, 1024), (g8, 10), (pk, 20), (cnt, 0), (g8, 30), (pk, 40), (cnt, 0)]
+    _write(str(tmp_path / "f"), "FETCH_SIZE", fetch)
+    _write(str(tmp_path / "w"), "WRITE_SIZE", write)
+    out = P.traffic(str(tmp_path / "f"), str(tmp_path / "w"), 1 << 20)
+    lib = out["library_kernels"]
+    assert set(lib) == {"k_packed_pb"}
+    e = lib["k_packed_pb"]
+    assert e["launches"] == 2
+    assert e["dispatches"] == {"k_pb_gather8": 2, "k_packed_pb": 2, "k_count_labels": 2}
+    assert e["fetch_bytes_per_launch"] == (40 + 200 + 16384 + 60 + 300 + 16384) * 1024 * 2 / 2
+    assert e["write_bytes_per_launch"] == (10 + 20 + 30 + 40) * 1024 / 2
