@@ -55,8 +55,9 @@ __device__ __forceinline__ TileRange xcd_tiles(size_t n, size_t tile) {
     return t;
 }
 
+template <uint32_t NT = kBlock>  // threads of the workgroup
 __device__ __forceinline__ void wg_add_spread(uint32_t *counters, int word, uint32_t v) {
-    __shared__ uint32_t part[kBlock / 64];
+    __shared__ uint32_t part[NT / 64];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     __syncthreads();
@@ -65,7 +66,7 @@ __device__ __forceinline__ void wg_add_spread(uint32_t *counters, int word, uint
     if (threadIdx.x == 0) {
         uint32_t s = 0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+        for (int w = 0; w < static_cast<int>(NT / 64); ++w) s += part[w];
         if (s) atomicAdd(counters + (blockIdx.x % kSpread) * kSpreadStride + word, s);
     }
 }

@@ -1194,6 +1194,12 @@ __global__ __launch_bounds__(kPbScatterThreads) void k_pb_scatter(const uint32_t
 // the round's ids into LDS and writes the gathered id of its share of the
 // bucket's edges.
 constexpr uint32_t kPbGatherThreads = 1024;  // one workgroup of 16 waves per bucket
+// pass B: threads of a tile's workgroup (measured on MI355X, bench step:
+// 512 threads 6.97 ms, 256 7.03, 1024 7.28: three workgroups per CU by LDS,
+// so 24 waves instead of 12, while 1,024 threads leave two states per thread)
+constexpr uint32_t kPbSigThreads = 512;
+// the packed round's pass B (bench step 6.96 -> 6.88 ms against 256 threads)
+constexpr uint32_t kPbPackedThreads = 512;
 
 __global__ __launch_bounds__(kPbGatherThreads) void k_pb_gather(SigParams p, uint32_t per_bucket) {
     extern __shared__ uint32_t slice[];
@@ -1241,38 +1247,38 @@ __global__ __launch_bounds__(kPbGatherThreads) void k_pb_gather(SigParams p, uin
 // run found by its id, or for wider alphabets by binary search over the run
 // starts) and places the gathered values into key[(state - tile start) * KC
 // + letter].  Ends with a barrier.
-template <int KC>
+template <int KC, uint32_t NT = kBlock>  // NT: threads of the workgroup
 struct PbRunsLds {
     static constexpr bool kIds = KC <= 4;
     uint32_t rs[kPbMaxBuckets + 1];         // run starts, or deltas
     uint32_t rb[kIds ? 1 : kPbMaxBuckets];  // run bases (search)
     uint16_t rid[kIds ? kPbTile * KC : 2];  // run ids (small alphabets)
-    uint32_t wsum[kBlock / 64];
+    uint32_t wsum[NT / 64];
     uint32_t tot;
 };
 
-template <int KC>
+template <int KC, uint32_t NT = kBlock>
 __device__ __forceinline__ void pb_tile_keys(const PbArgs &pb, uint32_t t, uint32_t *key,
-                                             PbRunsLds<KC> &L) {
+                                             PbRunsLds<KC, NT> &L) {
     const uint32_t tx = threadIdx.x;
     uint32_t total;
-    if constexpr (PbRunsLds<KC>::kIds) {
-        total = pb_tile_run_ids(pb, t, L.rid, L.rs, nullptr, L.wsum, &L.tot);
+    if constexpr (PbRunsLds<KC, NT>::kIds) {
+        total = pb_tile_run_ids<NT>(pb, t, L.rid, L.rs, nullptr, L.wsum, &L.tot);
     } else {
-        pb_tile_runs(pb, t, L.rs, L.rb, L.wsum);
+        pb_tile_runs<NT>(pb, t, L.rs, L.rb, L.wsum);
         total = L.rs[pb.nb];
     }
     // eight edges per thread at a time: every run lookup first, then all
     // their loads in flight together, then the LDS stores
     constexpr int B = 8;
-    for (uint32_t j0 = 0; j0 < total; j0 += B * kBlock) {
+    for (uint32_t j0 = 0; j0 < total; j0 += B * NT) {
         uint32_t e[B];
         bool ok[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const uint32_t j = j0 + u * kBlock + tx;
+            const uint32_t j = j0 + u * NT + tx;
             ok[u] = j < total;
-            if constexpr (PbRunsLds<KC>::kIds) {
+            if constexpr (PbRunsLds<KC, NT>::kIds) {
                 e[u] = ok[u] ? j + L.rs[L.rid[j]] : 0u;
             } else {
                 const uint32_t lo = pb_run_of(L.rs, pb.nb, j);
@@ -1338,27 +1344,27 @@ __global__ __launch_bounds__(kPbGatherThreads) void k_pb_gather8(SigParams p) {
 // Pass B of round 1: tile t's byte labels from every bucket into
 // key8[(state - tile start) * KC + letter], as pb_tile_keys does with ids.
 // Ends with a barrier.
-template <int KC>
+template <int KC, uint32_t NT = kBlock>
 __device__ __forceinline__ void pb_tile_keys8(const PbArgs &pb, uint32_t t, uint8_t *key8,
-                                              PbRunsLds<KC> &L) {
+                                              PbRunsLds<KC, NT> &L) {
     const uint32_t tx = threadIdx.x;
     const uint8_t *__restrict__ val8 = reinterpret_cast<const uint8_t *>(pb.val);
     uint32_t total;
-    if constexpr (PbRunsLds<KC>::kIds) {
-        total = pb_tile_run_ids(pb, t, L.rid, L.rs, nullptr, L.wsum, &L.tot);
+    if constexpr (PbRunsLds<KC, NT>::kIds) {
+        total = pb_tile_run_ids<NT>(pb, t, L.rid, L.rs, nullptr, L.wsum, &L.tot);
     } else {
-        pb_tile_runs(pb, t, L.rs, L.rb, L.wsum);
+        pb_tile_runs<NT>(pb, t, L.rs, L.rb, L.wsum);
         total = L.rs[pb.nb];
     }
     constexpr int B = 8;
-    for (uint32_t j0 = 0; j0 < total; j0 += B * kBlock) {
+    for (uint32_t j0 = 0; j0 < total; j0 += B * NT) {
         uint32_t e[B];
         bool ok[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const uint32_t j = j0 + u * kBlock + tx;
+            const uint32_t j = j0 + u * NT + tx;
             ok[u] = j < total;
-            if constexpr (PbRunsLds<KC>::kIds) {
+            if constexpr (PbRunsLds<KC, NT>::kIds) {
                 e[u] = ok[u] ? j + L.rs[L.rid[j]] : 0u;
             } else {
                 const uint32_t lo = pb_run_of(L.rs, pb.nb, j);
@@ -1382,10 +1388,10 @@ __device__ __forceinline__ void pb_tile_keys8(const PbArgs &pb, uint32_t t, uint
 // tile; the keys and the distinct-label count as k_packed_round computes
 // them, the tile's states taken 2 * kBlock at a time so that the LDS label
 // set (emptied when half full) always has room.
-template <int KC>
-__global__ __launch_bounds__(kBlock) void k_packed_pb(SigParams p) {
+template <int KC, uint32_t NT>
+__global__ __launch_bounds__(NT) void k_packed_pb(SigParams p) {
     __shared__ uint8_t key8[kPbTile * KC];
-    __shared__ PbRunsLds<KC> runs;
+    __shared__ PbRunsLds<KC, NT> runs;
     __shared__ uint32_t lset[kLabelSlots];
     __shared__ uint32_t lfill;
     if (p.ctl->done) return;
@@ -1393,9 +1399,10 @@ __global__ __launch_bounds__(kBlock) void k_packed_pb(SigParams p) {
     const uint32_t r = p.ctl->round;
     uint32_t *__restrict__ Y = (r & 1u) ? p.blockA : p.blockB;
     constexpr uint32_t bits = KC + 1;
-    constexpr int EP = kPbTile / kBlock;
+    constexpr int EP = kPbTile / NT;
+    static_assert(2 * NT <= kLabelSlots / 2, "a step's labels must fit a half-empty label set");
     const uint32_t tx = threadIdx.x;
-    for (uint32_t i = tx; i < kLabelSlots; i += kBlock) lset[i] = ~0u;
+    for (uint32_t i = tx; i < kLabelSlots; i += NT) lset[i] = ~0u;
     if (tx == 0) lfill = 0;
     __syncthreads();
     for (uint32_t t = blockIdx.x; t < pb.ntiles; t += gridDim.x) {
@@ -1403,26 +1410,26 @@ __global__ __launch_bounds__(kBlock) void k_packed_pb(SigParams p) {
         uint32_t own[EP];
 #pragma unroll
         for (int e = 0; e < EP; ++e) {
-            const size_t q = base + e * kBlock + tx;
+            const size_t q = base + e * NT + tx;
             own[e] = q < p.N ? p.lab8[q] : 0u;
         }
-        pb_tile_keys8<KC>(pb, t, key8, runs);
+        pb_tile_keys8<KC, NT>(pb, t, key8, runs);
 #pragma unroll
         for (int e0 = 0; e0 < EP; e0 += 2) {
             // every thread reads the same fill (the last step ended with a
             // barrier, and so did the key assembly) before any thread
-            // inserts; a step adds at most 2 * kBlock labels to a set at
+            // inserts; a step adds at most 2 * NT labels to a set at
             // most half full
             const bool half_full = lfill > kLabelSlots / 2;
             __syncthreads();
             if (half_full) {
-                for (uint32_t i = tx; i < kLabelSlots; i += kBlock) lset[i] = ~0u;
+                for (uint32_t i = tx; i < kLabelSlots; i += NT) lset[i] = ~0u;
                 if (tx == 0) lfill = 0;
                 __syncthreads();
             }
 #pragma unroll
             for (int e = e0; e < e0 + 2; ++e) {
-                const uint32_t i = e * kBlock + tx;
+                const uint32_t i = e * NT + tx;
                 const size_t q = base + i;
                 if (q >= p.N) continue;
                 uint32_t key = own[e];
@@ -1459,10 +1466,10 @@ __global__ __launch_bounds__(kBlock) void k_packed_pb(SigParams p) {
 
 // Pass B: one workgroup per source tile of kPbTile states: the tile's keys
 // from the buckets, then what the signature kernel does with each state.
-template <int KC>
-__global__ __launch_bounds__(kBlock) void k_signature_pb(SigParams p) {
+template <int KC, uint32_t NT>
+__global__ __launch_bounds__(NT) void k_signature_pb(SigParams p) {
     __shared__ uint32_t key[kPbTile * KC];
-    __shared__ PbRunsLds<KC> runs;
+    __shared__ PbRunsLds<KC, NT> runs;
     if (!pb_round(p.pb, *p.ctl, p.N)) return;
     const PbArgs &pb = p.pb;
     const uint32_t r = p.ctl->round;
@@ -1475,7 +1482,7 @@ __global__ __launch_bounds__(kBlock) void k_signature_pb(SigParams p) {
     constexpr size_t W = KC + 1;
     uint32_t leaders = 0, claims = 0;
     const uint32_t tx = threadIdx.x;
-    constexpr int EP = kPbTile / kBlock;  // states per thread in a tile
+    constexpr int EP = kPbTile / NT;  // states per thread in a tile
     for (uint32_t t = blockIdx.x; t < pb.ntiles; t += gridDim.x) {
         const size_t base = static_cast<size_t>(t) * kPbTile;
         // the tile's own ids are loaded before its keys are assembled, so
@@ -1484,17 +1491,17 @@ __global__ __launch_bounds__(kBlock) void k_signature_pb(SigParams p) {
         unsigned long long sws[EP], aws[EP];
 #pragma unroll
         for (int e = 0; e < EP; ++e) {
-            const size_t q = base + e * kBlock + tx;
+            const size_t q = base + e * NT + tx;
             const size_t first = q - lane_id();
             w0s[e] = q < p.N ? X[q] : 0u;
             sws[e] = (!all && first < p.N) ? p.single[first >> 6] : ~0ull;
             aws[e] = (!all && first < p.N) ? p.active[first >> 6] : 0ull;
             mqs[e] = (!all && !inc && q < p.N) ? p.multi[q] : ~0u;
         }
-        pb_tile_keys<KC>(pb, t, key, runs);
+        pb_tile_keys<KC, NT>(pb, t, key, runs);
 #pragma unroll
         for (int e = 0; e < EP; ++e) {
-            const uint32_t i = e * kBlock + tx;
+            const uint32_t i = e * NT + tx;
             const size_t q = base + i;
             // (the whole wave takes part in the ballots below)
             const uint32_t w0 = w0s[e];
@@ -1521,8 +1528,8 @@ __global__ __launch_bounds__(kBlock) void k_signature_pb(SigParams p) {
         }
         __syncthreads();  // the keys are done with before the next tile
     }
-    wg_add_spread(p.counters, 0, leaders + claims);
-    wg_add_spread(p.counters, 3, claims);
+    wg_add_spread<NT>(p.counters, 0, leaders + claims);
+    wg_add_spread<NT>(p.counters, 3, claims);
 }
 
 // ---------------------------------------------------------------- grouping
@@ -2774,31 +2781,33 @@ void launch_packed_pb(const RoundArgs &a, hipStream_t s) {
     launch_kernel(k_pb_gather8, dim3(a.pb.nb), dim3(kPbGatherThreads), 0, s, sp);
     // one workgroup per tile (the kernel also takes fewer, each then keeping
     // its label set over several tiles)
-    const dim3 grid(a.pb.ntiles), block(kBlock);
+    constexpr uint32_t NT = kPbPackedThreads;
+    const dim3 grid(a.pb.ntiles), block(NT);
     switch (a.k_eff) {
-        case 1: launch_kernel(k_packed_pb<1>, grid, block, 0, s, sp); break;
-        case 2: launch_kernel(k_packed_pb<2>, grid, block, 0, s, sp); break;
-        case 3: launch_kernel(k_packed_pb<3>, grid, block, 0, s, sp); break;
-        case 4: launch_kernel(k_packed_pb<4>, grid, block, 0, s, sp); break;
+        case 1: launch_kernel(k_packed_pb<1, NT>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_packed_pb<2, NT>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_packed_pb<3, NT>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_packed_pb<4, NT>, grid, block, 0, s, sp); break;
         default: break;  // packed labels only for k_eff <= 4
     }
-    launch_kernel(k_count_labels, dim3(1024), block, 0, s, sp);
+    launch_kernel(k_count_labels, dim3(1024), dim3(kBlock), 0, s, sp);
 }
 
 void launch_signature_pb(const RoundArgs &a, hipStream_t s) {
     if (!a.pb.nb) return;
     const SigParams sp = sig_params(a);
-    const dim3 grid(a.pb.ntiles), block(kBlock);
+    constexpr uint32_t NT = kPbSigThreads;
+    const dim3 grid(a.pb.ntiles), block(NT);
     switch (a.k_eff) {
-        case 1: launch_kernel(k_signature_pb<1>, grid, block, 0, s, sp); break;
-        case 2: launch_kernel(k_signature_pb<2>, grid, block, 0, s, sp); break;
-        case 3: launch_kernel(k_signature_pb<3>, grid, block, 0, s, sp); break;
-        case 4: launch_kernel(k_signature_pb<4>, grid, block, 0, s, sp); break;
-        case 5: launch_kernel(k_signature_pb<5>, grid, block, 0, s, sp); break;
-        case 6: launch_kernel(k_signature_pb<6>, grid, block, 0, s, sp); break;
-        case 7: launch_kernel(k_signature_pb<7>, grid, block, 0, s, sp); break;
-        case 8: launch_kernel(k_signature_pb<8>, grid, block, 0, s, sp); break;
-        case 16: launch_kernel(k_signature_pb<16>, grid, block, 0, s, sp); break;
+        case 1: launch_kernel(k_signature_pb<1, NT>, grid, block, 0, s, sp); break;
+        case 2: launch_kernel(k_signature_pb<2, NT>, grid, block, 0, s, sp); break;
+        case 3: launch_kernel(k_signature_pb<3, NT>, grid, block, 0, s, sp); break;
+        case 4: launch_kernel(k_signature_pb<4, NT>, grid, block, 0, s, sp); break;
+        case 5: launch_kernel(k_signature_pb<5, NT>, grid, block, 0, s, sp); break;
+        case 6: launch_kernel(k_signature_pb<6, NT>, grid, block, 0, s, sp); break;
+        case 7: launch_kernel(k_signature_pb<7, NT>, grid, block, 0, s, sp); break;
+        case 8: launch_kernel(k_signature_pb<8, NT>, grid, block, 0, s, sp); break;
+        case 16: launch_kernel(k_signature_pb<16, NT>, grid, block, 0, s, sp); break;
         default: break;
     }
 }
